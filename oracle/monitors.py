@@ -1,0 +1,115 @@
+"""Monitors of the cavity run (oracle; test infrastructure only).
+
+* ``residual``        -- Sec. 2.2 (iii), Eq. 6: relative L2 change of the
+                         velocity field over 100 steps, denominator at the
+                         earlier time; +inf when that denominator is zero.
+* ``stream_function`` -- Psi with Psi = 0 on the bottom wall and
+                         dPsi/dy = -u_x (so the clockwise primary vortex has
+                         Psi > 0, the sign of Tables 1-2), midpoint rule on
+                         site centres, lattice units.
+* ``probe``           -- velocity at an observing point (Sec. 3.3) given in
+                         units of the cavity width L, bilinear over site
+                         centres ((i + 1/2) / Nx), clamped to the outermost
+                         centres.
+* ``centreline``      -- u_x on the vertical line x = L/2 and u_y on the
+                         horizontal line y = H/2 (Figs. 1-2), averaging the two
+                         central columns / rows when the count is even.
+* ``vortex_extrema``  -- the primary vortex (max Psi) and the two bottom
+                         corner vortices (min Psi in each bottom quadrant), with
+                         centre positions in units of L, as in Tables 1-2.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def mass(rho):
+    """Sum of rho over all sites, exactly rounded (math.fsum)."""
+    return math.fsum(np.asarray(rho, dtype=np.float64).ravel().tolist())
+
+
+def residual(ux_new, uy_new, ux_old, uy_old):
+    """Eq. 6 with (u_x, u_y)(t) = *_old and (u_x, u_y)(t + 100) = *_new."""
+    num = math.fsum(((np.asarray(ux_new) - ux_old) ** 2
+                     + (np.asarray(uy_new) - uy_old) ** 2).ravel().tolist())
+    den = math.fsum((np.asarray(ux_old) ** 2
+                     + np.asarray(uy_old) ** 2).ravel().tolist())
+    if den == 0.0:
+        return math.inf
+    return math.sqrt(num / den)
+
+
+def stream_function(ux):
+    """Psi[y, x] = -(sum_{y' < y} u_x[y', x] + u_x[y, x] / 2) (lattice units)."""
+    ux = np.asarray(ux, dtype=np.float64)
+    below = np.zeros_like(ux)
+    below[1:] = np.cumsum(ux, axis=0)[:-1]
+    return -(below + 0.5 * ux)
+
+
+def _bilinear(field, X, Y):
+    ny, nx = field.shape
+    X = min(max(X, 0.0), nx - 1.0)
+    Y = min(max(Y, 0.0), ny - 1.0)
+    i0 = min(int(math.floor(X)), max(nx - 2, 0))
+    j0 = min(int(math.floor(Y)), max(ny - 2, 0))
+    i1 = min(i0 + 1, nx - 1)
+    j1 = min(j0 + 1, ny - 1)
+    tx = X - i0
+    ty = Y - j0
+    return ((1 - tx) * (1 - ty) * field[j0, i0] + tx * (1 - ty) * field[j0, i1]
+            + (1 - tx) * ty * field[j1, i0] + tx * ty * field[j1, i1])
+
+
+def probe(rho, ux, uy, points):
+    """(rho, u_x, u_y) at each point (x, y), coordinates in units of L = Nx.
+
+    Site (i, j) has its centre at ((i + 1/2)/Nx, (j + 1/2)/Nx)."""
+    nx = np.asarray(rho).shape[1]
+    out = []
+    for (px, py) in points:
+        X = px * nx - 0.5
+        Y = py * nx - 0.5
+        out.append([_bilinear(np.asarray(rho), X, Y),
+                    _bilinear(np.asarray(ux), X, Y),
+                    _bilinear(np.asarray(uy), X, Y)])
+    return np.array(out, dtype=np.float64)
+
+
+def centreline(ux, uy):
+    """(u_x along x = L/2 as a function of y, u_y along y = H/2 as a function
+    of x); central two columns/rows averaged for even counts."""
+    ux = np.asarray(ux)
+    uy = np.asarray(uy)
+    ny, nx = ux.shape
+    if nx % 2 == 0:
+        u_vert = 0.5 * (ux[:, nx // 2 - 1] + ux[:, nx // 2])
+    else:
+        u_vert = ux[:, nx // 2].copy()
+    if ny % 2 == 0:
+        v_horz = 0.5 * (uy[ny // 2 - 1, :] + uy[ny // 2, :])
+    else:
+        v_horz = uy[ny // 2, :].copy()
+    return u_vert, v_horz
+
+
+def vortex_extrema(psi, nx):
+    """Primary vortex = global max of Psi; lower-left / lower-right vortices =
+    min of Psi over the bottom-left / bottom-right quarter (x < W/2 or
+    x >= W/2, y < W/2).  Positions are site centres in units of L = Nx.
+    Returns a dict of (value, x, y)."""
+    psi = np.asarray(psi)
+    ny = psi.shape[0]
+    res = {}
+    j, i = np.unravel_index(int(np.argmax(psi)), psi.shape)
+    res["primary"] = (float(psi[j, i]), (i + 0.5) / nx, (j + 0.5) / nx)
+    hy = min(ny, nx // 2)
+    for name, xs in (("lower_left", slice(0, nx // 2)),
+                     ("lower_right", slice(nx // 2, nx))):
+        sub = psi[:hy, xs]
+        jj, ii = np.unravel_index(int(np.argmin(sub)), sub.shape)
+        ii += xs.start
+        res[name] = (float(psi[jj, ii]), (ii + 0.5) / nx, (jj + 0.5) / nx)
+    return res

@@ -1,0 +1,84 @@
+"""Brute-force twin of ``oracle.d2q9`` (test infrastructure only).
+
+Pure-Python loops over sites and directions, written in *push* form from the
+same definitions (arXiv 2211.05009, Sec. 2.1 Eqs. 1-3 and 5): every site
+collides its own populations, then sends each one along its link; a population
+whose link would end outside the cavity is reflected by the wall it meets
+(half-way bounce-back, moving-wall term -6 w_i rho_w c_i.u_w with rho_w = 1;
+the lid owns links through the top corners).  It shares no code with the
+vectorised oracle on purpose: the two are compared on tiny lattices.
+
+Only for lattices of a few dozen sites.
+"""
+from __future__ import annotations
+
+# Written out independently of oracle.d2q9 (no import from it).
+_VEL = ((0, 0), (1, 0), (0, 1), (-1, 0), (0, -1),
+        (1, 1), (-1, 1), (-1, -1), (1, -1))
+_WGT_NUM = (4, 1, 1, 1, 1, 1, 1, 1, 1)
+_WGT_DEN = (9, 9, 9, 9, 9, 36, 36, 36, 36)
+
+
+def _reverse(i):
+    cx, cy = _VEL[i]
+    return _VEL.index((-cx, -cy))
+
+
+def _feq_site(rho, ux, uy, wgt, one):
+    out = []
+    three = 3 * one
+    for (cx, cy), w in zip(_VEL, wgt):
+        cu = cx * ux + cy * uy
+        out.append(w * rho * (one + three * cu + (9 * one / 2) * cu * cu
+                              - (three / 2) * (ux * ux + uy * uy)))
+    return out
+
+
+def naive_steps(f, tau, u_lid, nsteps, num=float):
+    """Advance ``f`` (nested lists or array, [9][ny][nx]) by ``nsteps``
+    applications of Eq. 1 in the closed cavity; returns nested lists.
+
+    ``num`` is the number type every quantity is converted to: ``float`` for
+    IEEE FP64, or ``fractions.Fraction`` for exact rational arithmetic (then
+    ``f``, ``tau`` and ``u_lid`` should be given as exact values)."""
+    ny = len(f[0])
+    nx = len(f[0][0])
+    one = num(1)
+    wgt = [num(a) / num(b) for a, b in zip(_WGT_NUM, _WGT_DEN)]
+    tau = num(tau)
+    u_lid = num(u_lid)
+    cur = [[[num(f[i][y][x]) for x in range(nx)] for y in range(ny)]
+           for i in range(9)]
+    for _ in range(nsteps):
+        nxt = [[[None] * nx for _ in range(ny)] for _ in range(9)]
+        for y in range(ny):
+            for x in range(nx):
+                # collision at (x, y)
+                pops = [cur[i][y][x] for i in range(9)]
+                rho = num(0)
+                jx = num(0)
+                jy = num(0)
+                for i in range(9):
+                    rho += pops[i]
+                    jx += _VEL[i][0] * pops[i]
+                    jy += _VEL[i][1] * pops[i]
+                ux = jx / rho
+                uy = jy / rho
+                eq = _feq_site(rho, ux, uy, wgt, one)
+                post = [pops[i] - (pops[i] - eq[i]) / tau for i in range(9)]
+                # push every population along its link
+                for i in range(9):
+                    cx, cy = _VEL[i]
+                    tx, ty = x + cx, y + cy
+                    if 0 <= tx < nx and 0 <= ty < ny:
+                        nxt[i][ty][tx] = post[i]
+                        continue
+                    # reflected back into (x, y) as the reverse direction
+                    if ty >= ny:
+                        wall_u = u_lid        # lid first: corners belong to it
+                    else:
+                        wall_u = num(0)       # bottom and side walls at rest
+                    r = _reverse(i)
+                    nxt[r][y][x] = post[i] - 6 * wgt[i] * one * (cx * wall_u)
+        cur = nxt
+    return cur

@@ -1,0 +1,74 @@
+"""Pins of the oracle's monitors (Eq. 6 residual, probes, stream function)."""
+import math
+
+import numpy as np
+
+from oracle import monitors
+
+
+def test_residual_definition():
+    """Eq. 6: relative L2 change of (u_x, u_y) over 100 steps, denominator at
+    the earlier time."""
+    ux0 = np.full((3, 4), 0.2)
+    uy0 = np.zeros((3, 4))
+    assert math.isclose(monitors.residual(1.1 * ux0, uy0, ux0, uy0), 0.1, rel_tol=1e-14)
+    # a pure rotation of every vector by 90 degrees: |du|^2 = 2 |u|^2
+    assert math.isclose(monitors.residual(-uy0, ux0, ux0, uy0), math.sqrt(2), rel_tol=1e-14)
+    assert monitors.residual(ux0, uy0, np.zeros((3, 4)), uy0) == math.inf
+    assert monitors.residual(ux0, uy0, ux0, uy0) == 0.0
+
+
+def test_stream_function_of_uniform_and_couette_flow():
+    """Psi = 0 on the bottom wall, dPsi/dy = -u_x, midpoint rule on site
+    centres: uniform u_x = a gives Psi = -a (y + 1/2); the Couette profile
+    u_x = U (y + 1/2)/H gives Psi = -U/H ((y + 1/2)^2/2 + 1/8)."""
+    ny, nx = 7, 3
+    y = np.arange(ny)[:, None] + np.zeros((1, nx))
+    psi = monitors.stream_function(np.full((ny, nx), 0.3))
+    assert np.allclose(psi, -0.3 * (y + 0.5), atol=1e-15, rtol=0)
+    U, H = 0.1, ny
+    psi = monitors.stream_function(U * (y + 0.5) / H)
+    assert np.allclose(psi, -U / H * ((y + 0.5) ** 2 / 2 + 1 / 8), atol=1e-15, rtol=0)
+
+
+def test_vortex_extrema_locates_planted_extrema():
+    """Primary = global max of Psi; lower-left / lower-right = min over the
+    bottom quarter on each side; positions are site centres in units of L."""
+    nx, ny = 20, 24
+    psi = np.zeros((ny, nx))
+    psi[15, 11] = 0.12
+    psi[2, 1] = -1e-4
+    psi[3, 17] = -2e-3
+    psi[20, 3] = -5.0      # above the bottom quarter: not a corner vortex
+    ext = monitors.vortex_extrema(psi, nx)
+    assert ext["primary"] == (0.12, 11.5 / nx, 15.5 / nx)
+    assert ext["lower_left"] == (-1e-4, 1.5 / nx, 2.5 / nx)
+    assert ext["lower_right"] == (-2e-3, 17.5 / nx, 3.5 / nx)
+
+
+def test_probe_is_exact_on_linear_fields_and_on_site_centres():
+    """Bilinear interpolation over site centres reproduces a linear field
+    exactly inside the centre hull, returns the site value at a centre, and
+    clamps to the outermost centres outside it."""
+    nx, ny = 10, 6
+    X, Y = np.meshgrid(np.arange(nx) + 0.5, np.arange(ny) + 0.5)
+    field = 0.3 + 0.02 * X - 0.05 * Y
+    pts = [(0.37, 0.21), (0.5, 0.3), (0.91, 0.52)]
+    out = monitors.probe(field, field, 2 * field, pts)
+    for (px, py), row in zip(pts, out):
+        exp = 0.3 + 0.02 * px * nx - 0.05 * py * nx
+        assert math.isclose(row[0], exp, rel_tol=1e-14)
+        assert math.isclose(row[2], 2 * exp, rel_tol=1e-14)
+    rnd = np.random.default_rng(0).uniform(size=(ny, nx))
+    val = monitors.probe(rnd, rnd, rnd, [((3 + 0.5) / nx, (2 + 0.5) / nx)])[0, 0]
+    assert val == rnd[2, 3]
+    corner = monitors.probe(rnd, rnd, rnd, [(0.0, 0.0), (1.0, 5.0)])
+    assert corner[0, 0] == rnd[0, 0] and corner[1, 0] == rnd[-1, -1]
+
+
+def test_centreline_even_and_odd():
+    ux = np.arange(12.0).reshape(3, 4)
+    uy = np.arange(12.0).reshape(3, 4) * 2
+    u, v = monitors.centreline(ux, uy)
+    assert np.array_equal(u, 0.5 * (ux[:, 1] + ux[:, 2]))
+    assert np.array_equal(v, uy[1])
