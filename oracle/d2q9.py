@@ -113,7 +113,30 @@ def collide(f, tau, force=(0.0, 0.0)):
     return fs
 
 
-def stream(fs, u_lid=0.0, periodic_x=False, periodic_y=False, u_bottom=0.0):
+def _links(nx, ny, periodic_x, periodic_y):
+    """For each direction i: where each destination's population comes from.
+
+    Returns a list of (inside, ys_in, xs_in, wall, ys, xs) with ``inside``
+    the destinations whose source (x - c_ix, y - c_iy) is a lattice site
+    (after periodic wrapping), ``ys_in, xs_in`` those sources, ``wall`` the
+    destinations whose link crosses a wall, and ``ys, xs`` the source row and
+    column of every link (row >= ny: the lid, < 0: the bottom)."""
+    yy, xx = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    links = []
+    for i in range(9):
+        xs = xx - C[i, 0]
+        ys = yy - C[i, 1]
+        if periodic_x:
+            xs = np.mod(xs, nx)
+        if periodic_y:
+            ys = np.mod(ys, ny)
+        inside = (xs >= 0) & (xs < nx) & (ys >= 0) & (ys < ny)
+        links.append((inside, ys[inside], xs[inside], ~inside, ys, xs))
+    return links
+
+
+def stream(fs, u_lid=0.0, periodic_x=False, periodic_y=False, u_bottom=0.0,
+           links=None):
     """Streaming half of Eq. 1 plus the wall treatment.
 
     Destination (x, y) receives population i from (x - c_ix, y - c_iy).  If
@@ -125,19 +148,12 @@ def stream(fs, u_lid=0.0, periodic_x=False, periodic_y=False, u_bottom=0.0):
     x = Nx are at rest.  The lid is tested first, so the top corner links
     belong to the lid."""
     _, ny, nx = fs.shape
-    yy, xx = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    if links is None:
+        links = _links(nx, ny, periodic_x, periodic_y)
     out = np.empty_like(fs)
     for i in range(9):
-        xs = xx - C[i, 0]
-        ys = yy - C[i, 1]
-        if periodic_x:
-            xs = np.mod(xs, nx)
-        if periodic_y:
-            ys = np.mod(ys, ny)
-        inside = (xs >= 0) & (xs < nx) & (ys >= 0) & (ys < ny)
-        out[i][inside] = fs[i][ys[inside], xs[inside]]
-
-        wall = ~inside
+        inside, ys_in, xs_in, wall, ys, xs = links[i]
+        out[i][inside] = fs[i][ys_in, xs_in]
         if not np.any(wall):
             continue
         j = OPP[i]
@@ -181,6 +197,7 @@ class Cavity:
         self.periodic_y = bool(periodic_y)
         self.force = (float(force[0]), float(force[1]))
         self.t = 0
+        self._links = None
         # Initial state (Sec. 2.2 (i)): rho = 1, u = 0, f = f^eq.  With walls
         # half a link outside the lattice there are no wall sites, so every
         # site starts at rest; the lid acts through the wall treatment.
@@ -204,8 +221,10 @@ class Cavity:
 
     # -- time stepping ----------------------------------------------------
     def stream(self, fs):
+        if self._links is None:
+            self._links = _links(self.nx, self.ny, self.periodic_x, self.periodic_y)
         return stream(fs, self.u_lid, self.periodic_x, self.periodic_y,
-                      self.u_bottom)
+                      self.u_bottom, self._links)
 
     def step(self, n=1):
         """Apply Eq. 1 (collide, then stream with the wall treatment) n times."""
