@@ -1,0 +1,231 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) D2Q9 lattice-BGK lid-driven cavity
+ * library.
+ *
+ * The method is that of Xiang & Shi, "Flow Simulation of Lid-Driven
+ * Rectangular Cavity by Using Lattice Boltzmann Method" (arXiv 2211.05009):
+ *   - Sec. 2.1 Eq. 1: BGK evolution, collide then stream, one lattice link
+ *     per step;
+ *   - Sec. 2.1 Eq. 2: second-order equilibrium, c_s^2 = 1/3, D2Q9 weights
+ *     4/9, 1/9, 1/36;
+ *   - Sec. 2.1 Eq. 3: rho and rho u as moments of the populations;
+ *   - Sec. 2.1 Eq. 5 with Sec. 1's Re = U L / nu (L = cavity width):
+ *     tau = 3 U Nx / Re + 1/2 in lattice units (dx = dt = c = 1, Sec. 3);
+ *   - Sec. 2.2 (i): start from rest, rho = 1, f = f^eq;
+ *   - Sec. 2.2 (iii) Eq. 6: relative L2 change of u over 100 steps;
+ *   - Sec. 3.3: velocity at observing points, positions in units of L.
+ * Walls: half-way bounce-back on the three resting walls and the
+ * moving-wall bounce-back term -6 w rho_w (c . u_w), rho_w = 1, on the lid
+ * (the paper's own non-equilibrium-extrapolation scheme, Sec. 2.2 (ii), is
+ * not this library's boundary).  Links through the two top corners belong
+ * to the lid.
+ *
+ * Lattice: Nx sites along the lid, Ny sites up; site (x, y), y = 0 at the
+ * bottom.  Host arrays exchanged through this ABI are row-major [ny][nx]
+ * doubles (populations: [9][ny][nx]), velocity order
+ *   0:(0,0) 1:(1,0) 2:(0,1) 3:(-1,0) 4:(0,-1) 5:(1,1) 6:(-1,1) 7:(-1,-1)
+ *   8:(1,-1).
+ *
+ * Conventions for every function:
+ *   - returns LBM_OK (0) or a negative error code, never aborts or throws;
+ *     lbm_last_error() then holds a message (thread-local);
+ *   - a handle is used by one host thread at a time; distinct handles are
+ *     independent;
+ *   - pointers named *_host are caller-owned host memory, *_dev caller-owned
+ *     device memory on the handle's device; the library keeps no reference
+ *     to them after the call returns;
+ *   - work is issued on the handle's HIP stream (its own by default, see
+ *     lbm_set_stream); every function that returns data to the host
+ *     synchronises that stream before returning.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,     /* bad argument (the message names it) */
+  LBM_ENOMEM = -2,     /* device or host allocation failed */
+  LBM_EDEVICE = -3,    /* a HIP runtime call failed */
+  LBM_EUNSTABLE = -4,  /* a monitor went non-finite; state kept for inspection */
+  LBM_EIO = -5,        /* checkpoint file could not be read or written */
+  LBM_ESTATE = -6      /* checkpoint does not match the handle */
+};
+
+/* Storage precision of the populations. */
+enum {
+  LBM_F64 = 0,          /* f stored and collided in FP64 */
+  LBM_F32_SHIFTED = 1   /* g = f - w stored and collided in FP32; moments,
+                           mass, residual, probes, Psi reduced in FP64 */
+};
+
+typedef struct lbm_cavity *lbm_t;
+
+typedef struct {
+  int nx, ny;           /* sites along the lid / up */
+  int pitch;            /* elements per stored row (nx rounded up to 64) */
+  int dtype;            /* LBM_F64 or LBM_F32_SHIFTED */
+  double re, u_lid;     /* Reynolds number, lid speed */
+  double tau, omega;    /* relaxation time (Eq. 5) and 1/tau */
+  int64_t steps_done;   /* applications of Eq. 1 since the last (re)start */
+  size_t device_bytes;  /* device memory held by the handle */
+} lbm_info_t;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *lbm_last_error(void);
+
+/* Library version string. */
+const char *lbm_version(void);
+
+/*
+ * Create a cavity of nx x ny sites at Reynolds number re (Sec. 1 definition,
+ * L = nx) with lid speed u_lid, at rest (Sec. 2.2 (i)): rho = 1, u = 0.
+ * tau = 3 u_lid nx / re + 1/2 (Eq. 5).
+ * Errors: LBM_EINVAL if nx or ny < 2, nx > 65536, ny > 65536, re <= 0 or not
+ * finite, tau <= 1/2, |u_lid| >= 1/sqrt(3), out == NULL, unknown dtype;
+ * LBM_ENOMEM / LBM_EDEVICE on device failure.  The handle owns its device
+ * memory until lbm_destroy.
+ */
+int lbm_create(int nx, int ny, double re, double u_lid, int dtype, lbm_t *out);
+
+/* Same, with tau given directly (tau > 1/2).  re is reported as
+ * 3 u_lid nx / (tau - 1/2) (infinite if u_lid = 0). */
+int lbm_create_tau(int nx, int ny, double tau, double u_lid, int dtype,
+                   lbm_t *out);
+
+/* Free the handle and its device memory.  NULL is a no-op. */
+int lbm_destroy(lbm_t h);
+
+/* Issue all further work of h on hip_stream (a hipStream_t, e.g. the
+ * current stream of the caller's framework); NULL returns to the handle's
+ * own stream.  The caller's stream stays caller-owned and must outlive its
+ * use by h.  Pending work of h is finished before the switch. */
+int lbm_set_stream(lbm_t h, void *hip_stream);
+
+/* Handle parameters. */
+int lbm_info(lbm_t h, lbm_info_t *info);
+
+/*
+ * Execution options (do not change results):
+ *   LBM_OPT_USE_GRAPH     1 (default): aligned 100-step chunks are replayed
+ *                         from a captured HIP graph; 0: launched one by one.
+ *   LBM_OPT_STEP_VARIANT  index of the step kernel's tile shape, in
+ *                         [0, LBM_OPT_NUM_VARIANTS); picked by lbm_autotune.
+ *   LBM_OPT_NUM_VARIANTS  read-only: number of tile shapes.
+ * LBM_EINVAL for an unknown option or an out-of-range value.
+ */
+enum { LBM_OPT_USE_GRAPH = 1, LBM_OPT_STEP_VARIANT = 2, LBM_OPT_NUM_VARIANTS = 3 };
+int lbm_set_option(lbm_t h, int option, int64_t value);
+int lbm_get_option(lbm_t h, int option, int64_t *value);
+
+/*
+ * Advance n >= 0 steps of Eq. 1 with the wall treatment above.  At every
+ * step count t that is a multiple of 100 the monitors run: total mass and
+ * the Eq. 6 residual against the velocity field of step t - 100.  If probes
+ * are configured (lbm_probe_config) they are recorded every `every` steps.
+ * Returns after the work has finished; LBM_EUNSTABLE if the last monitor
+ * (or the final state's mass) is not finite.
+ */
+int lbm_step(lbm_t h, int64_t n);
+
+/* Number of steps applied since creation or the last lbm_set_populations /
+ * lbm_init_fields / lbm_load. */
+int lbm_steps_done(lbm_t h, int64_t *t);
+
+/*
+ * Density and velocity (Eq. 3) at the current step, each [ny][nx] doubles.
+ * A NULL output is skipped.  _host writes host memory, _dev device memory.
+ */
+int lbm_moments(lbm_t h, double *rho_host, double *ux_host, double *uy_host);
+int lbm_moments_device(lbm_t h, double *rho_dev, double *ux_dev,
+                       double *uy_dev);
+
+/*
+ * (rho, u_x, u_y) at npts observing points (Sec. 3.3) now.  xy_host holds
+ * npts pairs (x, y) in units of the cavity width L; each is interpolated
+ * bilinearly between site centres ((i + 1/2)/nx, (j + 1/2)/nx) and clamped
+ * to the outermost centres.  out_host receives npts triples.
+ * LBM_EINVAL if npts < 1 or npts > 4096, or a coordinate is not finite.
+ */
+int lbm_probe(lbm_t h, int npts, const double *xy_host, double *out_host);
+
+/*
+ * Record a probe time series on the device: from the next step on, every
+ * `every` steps (a divisor or a multiple of 100), write (rho, u_x, u_y) at
+ * the npts points into a ring of `capacity` records.  npts = 0 stops
+ * recording.  Reconfiguring clears the ring.
+ */
+int lbm_probe_config(lbm_t h, int npts, const double *xy_host, int every,
+                     int64_t capacity);
+
+/*
+ * Copy the recorded series, oldest first, into buf_host (room for
+ * max_records records of 1 + 3 npts doubles: the step number, then the
+ * npts triples).  *n_records receives the number copied (at most
+ * min(max_records, capacity) of the most recent ones).
+ */
+int lbm_probe_read(lbm_t h, double *buf_host, int64_t max_records,
+                   int64_t *n_records);
+
+/* Total mass sum_x rho(x) now, accumulated in FP64. */
+int lbm_mass(lbm_t h, double *mass);
+
+/*
+ * Eq. 6 residual from the most recent monitor: sqrt(sum |u(t) - u(t-100)|^2
+ * / sum |u(t-100)|^2).  *at_step receives t (-1 if no monitor has run).
+ * The residual is +inf when the denominator is zero or when the reference
+ * field was not taken exactly 100 steps before t.
+ */
+int lbm_residual(lbm_t h, double *residual, int64_t *at_step);
+
+/*
+ * Stream function Psi [ny][nx] (lattice units, host): Psi = 0 on the bottom
+ * wall, dPsi/dy = -u_x, midpoint rule on site centres, so the clockwise
+ * primary vortex has Psi > 0 (the sign of Tables 1-2).  Divide by
+ * u_lid * nx for the normalisation of Table 1.
+ */
+int lbm_stream_function(lbm_t h, double *psi_host);
+
+/*
+ * Replace the state by the populations f(t) [9][ny][nx] (host, the
+ * distribution before the collision of Eq. 1).  The step counter restarts
+ * at 0 and the residual reference is reset.  For LBM_F32_SHIFTED the stored
+ * value is f - w rounded to FP32.
+ */
+int lbm_set_populations(lbm_t h, const double *f_host);
+
+/*
+ * Read the stored post-collision populations f*(t) = f - (f - f^eq)/tau
+ * (the right-hand side of Eq. 1 at step t), [9][ny][nx] doubles (host).
+ * Their moments rho, rho u equal those of f(t).
+ */
+int lbm_get_populations(lbm_t h, double *fstar_host);
+
+/*
+ * Warm start: f = f^eq(rho, u) from fields [ny][nx] (host).  If
+ * renormalise_mass is non-zero, rho is first scaled so that the total mass
+ * is nx * ny (that of the rest state).  Step counter restarts at 0.
+ */
+int lbm_init_fields(lbm_t h, const double *rho_host, const double *ux_host,
+                    const double *uy_host, int renormalise_mass);
+
+/*
+ * Checkpoint: write / read a header (magic, version, nx, ny, dtype, steps,
+ * tau, u_lid) followed by the raw stored populations.  Restoring gives a
+ * bitwise-identical continuation.  LBM_EIO on file errors, LBM_ESTATE if
+ * the file's lattice or dtype differs from the handle's.
+ */
+int lbm_save(lbm_t h, const char *path);
+int lbm_load(lbm_t h, const char *path);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

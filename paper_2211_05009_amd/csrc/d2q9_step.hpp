@@ -1,0 +1,141 @@
+// d2q9_step.hpp -- the fused D2Q9 lattice-BGK step for gfx950.
+//
+// One launch applies Eq. 1 of arXiv 2211.05009 (Sec. 2.1) once to every
+// site, in pull form: each site gathers the post-collision populations of
+// its neighbours (the streaming half of Eq. 1), replaces the links that
+// cross a wall by the half-way bounce-back reflection (the lid adds the
+// moving-wall term -6 w rho_w c.u_w, rho_w = 1), forms rho and rho u
+// (Eq. 3), relaxes toward the equilibrium of Eq. 2 with omega = 1/tau
+// (Eq. 5), and stores the post-collision populations into the other buffer.
+// The stored state is therefore always f*(t), the right-hand side of Eq. 1.
+//
+// Layout: structure of arrays, nine planes of ny rows x pitch elements,
+// pitch = nx rounded up to 64, plane i at element offset i * plane.  A
+// 64-lane wavefront covers 64 consecutive x of one row: every load and
+// store of a plane is one contiguous 256 B (FP32) or 512 B (FP64) run.
+//
+// Storage variants:
+//   double, SHIFT = false : f itself in FP64.
+//   float,  SHIFT = true  : g = f - w in FP32.  The rest state is g = 0, so
+//                           the rounding error scales with the deviation
+//                           from rest instead of with w.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// D2Q9 weights (Sec. 2.1, below Eq. 2).
+#define LBM_W0 (4.0 / 9.0)
+#define LBM_WA (1.0 / 9.0)
+#define LBM_WD (1.0 / 36.0)
+
+// Map the hardware's round-robin block -> XCD assignment (block L runs on
+// XCD L % 8) onto contiguous tile ranges, so each XCD's L2 serves one band
+// of rows and the rows shared by neighbouring tiles are fetched once.
+__device__ __forceinline__ int xcd_tile(int L, int nb) {
+  const int k = L & 7, q = nb >> 3, r = nb & 7;
+  return k * q + (k < r ? k : r) + (L >> 3);
+}
+
+template <typename T>
+struct StepParams {
+  const T *__restrict__ src;
+  T *__restrict__ dst;
+  int nx, ny, pitch;
+  int plane;        // elements per population plane
+  int tiles_x;      // tiles along x (64 sites each)
+  T omega;          // 1 / tau
+  T u6;             // u_lid / 6: the moving-wall term for links 7 and 8
+};
+
+// Collide one site.  f[0..8] in: populations after streaming (or their
+// shift g = f - w); out: post-collision values.
+template <typename T, bool SHIFT>
+__device__ __forceinline__ void bgk_collide(T (&f)[9], T omega) {
+  const T one = T(1);
+  // Eq. 3
+  T s = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+  const T jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+  const T jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+  // SHIFT: s is the density deviation rho - 1 (the weights sum to 1)
+  const T rho = SHIFT ? one + s : s;
+  const T rinv = one / rho;
+  const T ux = jx * rinv, uy = jy * rinv;
+  const T usq = T(1.5) * (ux * ux + uy * uy);
+  // Eq. 2: w rho (1 + 3 cu + 4.5 cu^2 - 1.5 u^2).  In SHIFT form the
+  // equilibrium shift is w (rho - 1 + rho (3 cu + 4.5 cu^2 - 1.5 u^2)).
+  const T base = SHIFT ? s : rho;            // the "1" part times rho, less w
+  const T w0 = T(LBM_W0), wa = T(LBM_WA), wd = T(LBM_WD);
+  const T r0 = w0 * rho, ra = wa * rho, rd = wd * rho;
+  const T b0 = w0 * base, ba = wa * base, bd = wd * base;
+
+  T feq;
+  feq = b0 - r0 * usq;
+  f[0] += omega * (feq - f[0]);
+  {  // axis pairs (1,3) and (2,4)
+    const T sx = ra * (T(4.5) * ux * ux - usq), ax = ra * (T(3) * ux);
+    const T sy = ra * (T(4.5) * uy * uy - usq), ay = ra * (T(3) * uy);
+    f[1] += omega * ((ba + sx + ax) - f[1]);
+    f[3] += omega * ((ba + sx - ax) - f[3]);
+    f[2] += omega * ((ba + sy + ay) - f[2]);
+    f[4] += omega * ((ba + sy - ay) - f[4]);
+  }
+  {  // diagonal pairs (5,7) and (6,8)
+    const T p = ux + uy, m = uy - ux;
+    const T sp = rd * (T(4.5) * p * p - usq), ap = rd * (T(3) * p);
+    const T sm = rd * (T(4.5) * m * m - usq), am = rd * (T(3) * m);
+    f[5] += omega * ((bd + sp + ap) - f[5]);
+    f[7] += omega * ((bd + sp - ap) - f[7]);
+    f[6] += omega * ((bd + sm + am) - f[6]);
+    f[8] += omega * ((bd + sm - am) - f[8]);
+  }
+}
+
+// Gather the nine populations arriving at site (x, y) at offset o = y*pitch+x
+// (streaming half of Eq. 1 plus the walls).  Links whose source lies outside
+// read the reverse population of the same site; the lid row (y = ny-1) adds
+// -u/6 to link 7 and +u/6 to link 8 (corner links included).
+template <typename T>
+__device__ __forceinline__ void pull(const T *__restrict__ s, int plane,
+                                     int pitch, int o, bool xl, bool xr,
+                                     bool yb, bool yt, T u6, T (&f)[9]) {
+  const int P = plane;
+  f[0] = s[o];
+  f[1] = s[xl ? (P + o - 1) : (3 * P + o)];
+  f[2] = s[yb ? (2 * P + o - pitch) : (4 * P + o)];
+  f[3] = s[xr ? (3 * P + o + 1) : (P + o)];
+  f[4] = s[yt ? (4 * P + o + pitch) : (2 * P + o)];
+  f[5] = s[(xl && yb) ? (5 * P + o - 1 - pitch) : (7 * P + o)];
+  f[6] = s[(xr && yb) ? (6 * P + o + 1 - pitch) : (8 * P + o)];
+  f[7] = s[(xr && yt) ? (7 * P + o + 1 + pitch) : (5 * P + o)];
+  f[8] = s[(xl && yt) ? (8 * P + o - 1 + pitch) : (6 * P + o)];
+  if (!yt) {       // lid: moving-wall term, u_w = (u_lid, 0)
+    f[7] -= u6;
+    f[8] += u6;
+  }
+}
+
+// One step over a tile of 64 x (BY * RY) sites; block = 64 x BY threads,
+// each thread handles RY rows spaced BY apart.
+template <typename T, bool SHIFT, int BY, int RY>
+__global__ __launch_bounds__(64 * BY) void k_step(StepParams<T> p) {
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
+  const int x = tx * 64 + threadIdx.x;
+  if (x >= p.nx) return;
+  const bool xl = x > 0, xr = x < p.nx - 1;
+#pragma unroll
+  for (int r = 0; r < RY; ++r) {
+    const int y = ty * (BY * RY) + r * BY + threadIdx.y;
+    if (y >= p.ny) return;
+    const int o = y * p.pitch + x;
+    T f[9];
+    pull<T>(p.src, p.plane, p.pitch, o, xl, xr, y > 0, y < p.ny - 1, p.u6, f);
+    bgk_collide<T, SHIFT>(f, p.omega);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) p.dst[i * p.plane + o] = f[i];
+  }
+}
+
+}  // namespace lbm

@@ -1,0 +1,785 @@
+// lbm.hip -- C ABI and host runtime of the D2Q9 lid-driven cavity library
+// (declarations and contracts in include/lbm.h).
+//
+// Runtime structure per handle:
+//   * two population buffers (A/B ping-pong); buf[cur] holds f*(t);
+//   * a 100-step chunk (the monitor cadence of Sec. 2.2 (iii)) is captured
+//     once per start buffer into a HIP graph: 100 step kernels, then the
+//     FP64 monitor reduction (mass and Eq. 6 sums), plus probe records when
+//     their cadence divides 100; lbm_step replays it; steps that do not
+//     fill an aligned chunk are launched one by one;
+//   * FP64 scratch for moments / probes / population transfers, allocated on
+//     first use.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "d2q9_monitor.hpp"
+#include "d2q9_step.hpp"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPC(call)                                                          \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      return fail(e_ == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE,     \
+                  "%s failed: %s", #call, hipGetErrorString(e_));           \
+  } while (0)
+
+constexpr int kChunk = 100;   // monitor cadence (Eq. 6 compares t and t-100)
+
+}  // namespace
+
+// ---------------------------------------------------------------- variants
+// Step kernel variants: tile 64 x (BY*RY) sites, block 64 x BY threads.
+struct VariantDesc {
+  int by, ry;
+};
+static const VariantDesc kVariants[] = {{4, 1}, {4, 2}, {4, 4}, {8, 1},
+                                        {2, 4}, {1, 8}, {8, 2}, {16, 1}};
+static const int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+
+template <typename T, bool S, int BY, int RY>
+static hipError_t launch_step_t(const lbm_cavity *h, const void *src, void *dst,
+                                hipStream_t st) {
+  StepParams<T> p;
+  p.src = (const T *)src;
+  p.dst = (T *)dst;
+  p.nx = h->nx;
+  p.ny = h->ny;
+  p.pitch = h->pitch;
+  p.plane = h->plane;
+  p.tiles_x = (h->nx + 63) / 64;
+  p.omega = (T)h->omega;
+  p.u6 = (T)(h->u_lid / 6.0);
+  const int tiles_y = (h->ny + BY * RY - 1) / (BY * RY);
+  hipLaunchKernelGGL((k_step<T, S, BY, RY>), dim3(p.tiles_x * tiles_y),
+                     dim3(64, BY), 0, st, p);
+  return hipGetLastError();
+}
+
+template <typename T, bool S>
+static hipError_t launch_step_variant(const lbm_cavity *h, int v, const void *src,
+                                      void *dst, hipStream_t st) {
+  switch (v) {
+    case 0: return launch_step_t<T, S, 4, 1>(h, src, dst, st);
+    case 1: return launch_step_t<T, S, 4, 2>(h, src, dst, st);
+    case 2: return launch_step_t<T, S, 4, 4>(h, src, dst, st);
+    case 3: return launch_step_t<T, S, 8, 1>(h, src, dst, st);
+    case 4: return launch_step_t<T, S, 2, 4>(h, src, dst, st);
+    case 5: return launch_step_t<T, S, 1, 8>(h, src, dst, st);
+    case 6: return launch_step_t<T, S, 8, 2>(h, src, dst, st);
+    default: return launch_step_t<T, S, 16, 1>(h, src, dst, st);
+  }
+}
+
+static hipError_t launch_step(const lbm_cavity *h, const void *src, void *dst,
+                              hipStream_t st) {
+  if (h->dtype == LBM_F64)
+    return launch_step_variant<double, false>(h, h->variant, src, dst, st);
+  return launch_step_variant<float, true>(h, h->variant, src, dst, st);
+}
+
+// ------------------------------------------------------------ small kernels
+static Geometry geom(const lbm_cavity *h) {
+  Geometry g;
+  g.nx = h->nx;
+  g.ny = h->ny;
+  g.pitch = h->pitch;
+  g.plane = h->plane;
+  return g;
+}
+
+template <typename T, bool S>
+static hipError_t launch_monitor_t(const lbm_cavity *h, const void *src,
+                                   bool update, double *out, hipStream_t st) {
+  const int n = h->nx * h->ny;
+  const int blocks = std::min(kRedBlocks, (n + kRedThreads - 1) / kRedThreads);
+  if (update)
+    hipLaunchKernelGGL((k_monitor<T, S, true>), dim3(blocks), dim3(kRedThreads), 0,
+                       st, (const T *)src, geom(h), h->uref, h->partials);
+  else
+    hipLaunchKernelGGL((k_monitor<T, S, false>), dim3(blocks), dim3(kRedThreads),
+                       0, st, (const T *)src, geom(h), h->uref, h->partials);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedThreads), 0, st, h->partials,
+                     blocks, out);
+  return hipGetLastError();
+}
+
+static hipError_t launch_monitor(const lbm_cavity *h, const void *src, bool update,
+                                 double *out, hipStream_t st) {
+  if (h->dtype == LBM_F64) return launch_monitor_t<double, false>(h, src, update, out, st);
+  return launch_monitor_t<float, true>(h, src, update, out, st);
+}
+
+static hipError_t launch_probe_ring(const lbm_cavity *h, const void *src,
+                                    hipStream_t st) {
+  if (h->dtype == LBM_F64)
+    hipLaunchKernelGGL((k_probe_ring<double, false>), dim3(1), dim3(256), 0, st,
+                       (const double *)src, geom(h), h->probe_xy, h->probe_n,
+                       h->probe_ring, (long long)h->probe_cap, h->probe_count);
+  else
+    hipLaunchKernelGGL((k_probe_ring<float, true>), dim3(1), dim3(256), 0, st,
+                       (const float *)src, geom(h), h->probe_xy, h->probe_n,
+                       h->probe_ring, (long long)h->probe_cap, h->probe_count);
+  return hipGetLastError();
+}
+
+static int ensure_tmp(lbm_cavity *h, size_t doubles) {
+  if (h->tmp_doubles >= doubles) return LBM_OK;
+  if (h->tmp) HIPC(hipFree(h->tmp));
+  h->tmp = nullptr;
+  h->tmp_doubles = 0;
+  HIPC(hipMalloc(&h->tmp, doubles * sizeof(double)));
+  h->tmp_doubles = doubles;
+  return LBM_OK;
+}
+
+static bool probe_every_ok(int every) {
+  return every > 0 && (kChunk % every == 0 || every % kChunk == 0);
+}
+
+static void drop_graphs(lbm_cavity *h) {
+  for (int c = 0; c < 2; ++c) {
+    if (h->graph[c]) (void)hipGraphExecDestroy(h->graph[c]);
+    h->graph[c] = nullptr;
+  }
+}
+
+// Issue one 100-step chunk starting from buf[c] on stream st (either
+// directly or under capture).  Ends with the monitor on buf[c].
+static hipError_t issue_chunk(lbm_cavity *h, int c, hipStream_t st) {
+  int cur = c;
+  for (int k = 1; k <= kChunk; ++k) {
+    hipError_t e = launch_step(h, h->buf[cur], h->buf[1 - cur], st);
+    if (e != hipSuccess) return e;
+    cur = 1 - cur;
+    if (h->probe_n > 0 && h->probe_every <= kChunk && k % h->probe_every == 0) {
+      e = launch_probe_ring(h, h->buf[cur], st);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return launch_monitor(h, h->buf[cur], true, h->mon_dev, st);
+}
+
+static int build_graph(lbm_cavity *h, int c) {
+  hipGraph_t g = nullptr;
+  HIPC(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = issue_chunk(h, c, h->cap_stream);
+  hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return fail(LBM_EDEVICE, "graph capture failed: %s",
+                hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  e = hipGraphInstantiate(&h->graph[c], g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    h->graph[c] = nullptr;
+    return fail(LBM_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+  }
+  return LBM_OK;
+}
+
+// Reference field of Eq. 6 := current u; restart the step counter.
+static int reset_counters(lbm_cavity *h) {
+  h->t = 0;
+  h->snap_t = 0;
+  h->mon_t = -1;
+  h->last_res = INFINITY;
+  h->last_mass = NAN;
+  h->probe_n = 0;
+  drop_graphs(h);
+  hipError_t e = launch_monitor(h, h->buf[h->cur], true, h->aux_dev, h->stream);
+  if (e != hipSuccess) return fail(LBM_EDEVICE, "monitor launch: %s", hipGetErrorString(e));
+  return LBM_OK;
+}
+
+template <typename T, bool S>
+static void launch_moments_t(lbm_cavity *h, double *r, double *u, double *v) {
+  const int n = h->nx * h->ny;
+  hipLaunchKernelGGL((k_moments<T, S>), dim3((n + 255) / 256), dim3(256), 0, h->stream,
+                     (const T *)h->buf[h->cur], geom(h), r, u, v);
+}
+
+// ------------------------------------------------------------------- C ABI
+extern "C" {
+
+const char *lbm_last_error(void) { return g_err.c_str(); }
+
+const char *lbm_version(void) { return "mi355x-lbm 0.1 (gfx950)"; }
+
+static int create_impl(int nx, int ny, double tau, double re, double u_lid,
+                       int dtype, lbm_t *out) {
+  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nx < 2 || ny < 2 || nx > 65536 || ny > 65536)
+    return fail(LBM_EINVAL, "lattice %d x %d outside [2, 65536]", nx, ny);
+  if (dtype != LBM_F64 && dtype != LBM_F32_SHIFTED)
+    return fail(LBM_EINVAL, "unknown dtype %d", dtype);
+  if (!std::isfinite(u_lid) || std::fabs(u_lid) >= 1.0 / std::sqrt(3.0))
+    return fail(LBM_EINVAL, "|u_lid| = %g must be below c_s = 1/sqrt(3)", u_lid);
+  if (!std::isfinite(tau) || !(tau > 0.5))
+    return fail(LBM_EINVAL, "tau = %.17g must exceed 1/2", tau);
+  const int pitch = (nx + 63) / 64 * 64;
+  const long long plane = (long long)pitch * ny;
+  if (plane * 9 >= (1LL << 31))
+    return fail(LBM_EINVAL, "lattice too large for 32-bit element offsets");
+
+  lbm_cavity *h = new (std::nothrow) lbm_cavity();
+  if (!h) return fail(LBM_ENOMEM, "host allocation");
+  h->nx = nx;
+  h->ny = ny;
+  h->pitch = pitch;
+  h->plane = (int)plane;
+  h->dtype = dtype;
+  h->re = re;
+  h->u_lid = u_lid;
+  h->tau = tau;
+  h->omega = 1.0 / tau;
+  h->variant = 0;
+  h->use_graph = 1;
+  const size_t esz = dtype == LBM_F64 ? 8 : 4;
+  h->buf_bytes = (size_t)plane * 9 * esz;
+  int rc = LBM_OK;
+  auto bail = [&](int code) {
+    lbm_destroy(h);
+    return code;
+  };
+  hipError_t e;
+#define TRY(call)                                                              \
+  do {                                                                         \
+    e = (call);                                                                \
+    if (e != hipSuccess)                                                       \
+      return bail(fail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE,    \
+                       "%s failed: %s", #call, hipGetErrorString(e)));         \
+  } while (0)
+  TRY(hipGetDevice(&h->device));
+  TRY(hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking));
+  h->stream = h->own_stream;
+  TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  for (int c = 0; c < 2; ++c) {
+    TRY(hipMalloc(&h->buf[c], h->buf_bytes));
+    TRY(hipMemsetAsync(h->buf[c], 0, h->buf_bytes, h->stream));
+  }
+  TRY(hipMalloc(&h->uref, sizeof(double2) * (size_t)nx * ny));
+  TRY(hipMalloc(&h->partials, sizeof(double) * kRedBlocks * kNumSums));
+  TRY(hipMalloc(&h->mon_dev, sizeof(double) * 4));
+  TRY(hipMalloc(&h->aux_dev, sizeof(double) * 4));
+  TRY(hipHostMalloc(&h->mon_host, sizeof(double) * 8, hipHostMallocDefault));
+  h->cur = 0;
+  const int total = pitch * ny;
+  if (dtype == LBM_F64)
+    hipLaunchKernelGGL((k_init_eq<double, false>), dim3((total + 255) / 256), dim3(256),
+                       0, h->stream, (double *)h->buf[0], geom(h), nullptr, nullptr,
+                       nullptr, 1.0);
+  else
+    hipLaunchKernelGGL((k_init_eq<float, true>), dim3((total + 255) / 256), dim3(256), 0,
+                       h->stream, (float *)h->buf[0], geom(h), nullptr, nullptr,
+                       nullptr, 1.0);
+  TRY(hipGetLastError());
+  rc = reset_counters(h);
+  if (rc != LBM_OK) return bail(rc);
+  TRY(hipStreamSynchronize(h->stream));
+#undef TRY
+  *out = h;
+  return LBM_OK;
+}
+
+int lbm_create(int nx, int ny, double re, double u_lid, int dtype, lbm_t *out) {
+  if (!(re > 0.0) || !std::isfinite(re))
+    return fail(LBM_EINVAL, "re = %g must be positive and finite", re);
+  const double tau = 3.0 * u_lid * nx / re + 0.5;   // Eq. 5, nu = U L / Re
+  if (!(tau > 0.5))
+    return fail(LBM_EINVAL, "tau = 3 u nx / re + 1/2 = %.17g must exceed 1/2", tau);
+  return create_impl(nx, ny, tau, re, u_lid, dtype, out);
+}
+
+int lbm_create_tau(int nx, int ny, double tau, double u_lid, int dtype, lbm_t *out) {
+  const double re = (tau > 0.5 && u_lid != 0.0) ? 3.0 * u_lid * nx / (tau - 0.5)
+                                                 : INFINITY;
+  return create_impl(nx, ny, tau, re, u_lid, dtype, out);
+}
+
+int lbm_destroy(lbm_t h) {
+  if (!h) return LBM_OK;
+  drop_graphs(h);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  for (int c = 0; c < 2; ++c)
+    if (h->buf[c]) (void)hipFree(h->buf[c]);
+  if (h->uref) (void)hipFree(h->uref);
+  if (h->partials) (void)hipFree(h->partials);
+  if (h->mon_dev) (void)hipFree(h->mon_dev);
+  if (h->aux_dev) (void)hipFree(h->aux_dev);
+  if (h->mon_host) (void)hipHostFree(h->mon_host);
+  if (h->tmp) (void)hipFree(h->tmp);
+  if (h->probe_xy) (void)hipFree(h->probe_xy);
+  if (h->probe_ring) (void)hipFree(h->probe_ring);
+  if (h->probe_count) (void)hipFree(h->probe_count);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  if (h->own_stream) (void)hipStreamDestroy(h->own_stream);
+  delete h;
+  return LBM_OK;
+}
+
+int lbm_set_stream(lbm_t h, void *hip_stream) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  HIPC(hipStreamSynchronize(h->stream));
+  h->stream = hip_stream ? (hipStream_t)hip_stream : h->own_stream;
+  return LBM_OK;
+}
+
+int lbm_info(lbm_t h, lbm_info_t *info) {
+  if (!h || !info) return fail(LBM_EINVAL, "NULL argument");
+  info->nx = h->nx;
+  info->ny = h->ny;
+  info->pitch = h->pitch;
+  info->dtype = h->dtype;
+  info->re = h->re;
+  info->u_lid = h->u_lid;
+  info->tau = h->tau;
+  info->omega = h->omega;
+  info->steps_done = h->t;
+  info->device_bytes = 2 * h->buf_bytes + sizeof(double2) * (size_t)h->nx * h->ny +
+                       h->tmp_doubles * sizeof(double);
+  return LBM_OK;
+}
+
+int lbm_set_option(lbm_t h, int option, int64_t value) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  switch (option) {
+    case LBM_OPT_USE_GRAPH:
+      h->use_graph = value ? 1 : 0;
+      return LBM_OK;
+    case LBM_OPT_STEP_VARIANT:
+      if (value < 0 || value >= kNumVariants)
+        return fail(LBM_EINVAL, "variant %lld outside [0, %d)", (long long)value,
+                    kNumVariants);
+      if (h->variant != (int)value) drop_graphs(h);
+      h->variant = (int)value;
+      return LBM_OK;
+    default:
+      return fail(LBM_EINVAL, "unknown option %d", option);
+  }
+}
+
+int lbm_get_option(lbm_t h, int option, int64_t *value) {
+  if (!h || !value) return fail(LBM_EINVAL, "NULL argument");
+  switch (option) {
+    case LBM_OPT_USE_GRAPH: *value = h->use_graph; return LBM_OK;
+    case LBM_OPT_STEP_VARIANT: *value = h->variant; return LBM_OK;
+    case LBM_OPT_NUM_VARIANTS: *value = kNumVariants; return LBM_OK;
+    default: return fail(LBM_EINVAL, "unknown option %d", option);
+  }
+}
+
+// Host bookkeeping after a monitor at step t: the Eq. 6 reference is valid
+// only if it was taken exactly 100 steps earlier.
+static void note_monitor(lbm_cavity *h) {
+  h->mon_valid = (h->snap_t == h->t - kChunk);
+  h->snap_t = h->t;
+  h->mon_t = h->t;
+}
+
+int lbm_step(lbm_t h, int64_t n) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (n < 0) return fail(LBM_EINVAL, "n = %lld < 0", (long long)n);
+  if (n == 0) return LBM_OK;
+  bool monitored = false;
+  hipError_t e;
+  while (n > 0) {
+    const bool aligned = (h->t % kChunk) == 0;
+    if (aligned && n >= kChunk) {
+      if (h->use_graph) {
+        if (!h->graph[h->cur]) {
+          int rc = build_graph(h, h->cur);
+          if (rc != LBM_OK) return rc;
+        }
+        HIPC(hipGraphLaunch(h->graph[h->cur], h->stream));
+      } else {
+        e = issue_chunk(h, h->cur, h->stream);
+        if (e != hipSuccess) return fail(LBM_EDEVICE, "launch: %s", hipGetErrorString(e));
+      }
+      h->t += kChunk;
+      n -= kChunk;
+      note_monitor(h);
+      monitored = true;
+      if (h->probe_n > 0 && h->probe_every > kChunk && h->t % h->probe_every == 0) {
+        e = launch_probe_ring(h, h->buf[h->cur], h->stream);
+        if (e != hipSuccess) return fail(LBM_EDEVICE, "probe: %s", hipGetErrorString(e));
+      }
+      continue;
+    }
+    // single steps up to the next chunk boundary
+    e = launch_step(h, h->buf[h->cur], h->buf[1 - h->cur], h->stream);
+    if (e != hipSuccess) return fail(LBM_EDEVICE, "step launch: %s", hipGetErrorString(e));
+    h->cur = 1 - h->cur;
+    h->t += 1;
+    n -= 1;
+    if (h->probe_n > 0 && h->t % h->probe_every == 0) {
+      e = launch_probe_ring(h, h->buf[h->cur], h->stream);
+      if (e != hipSuccess) return fail(LBM_EDEVICE, "probe: %s", hipGetErrorString(e));
+    }
+    if (h->t % kChunk == 0) {
+      e = launch_monitor(h, h->buf[h->cur], true, h->mon_dev, h->stream);
+      if (e != hipSuccess) return fail(LBM_EDEVICE, "monitor: %s", hipGetErrorString(e));
+      note_monitor(h);
+      monitored = true;
+    }
+  }
+  if (monitored) {
+    HIPC(hipMemcpyAsync(h->mon_host, h->mon_dev, 3 * sizeof(double),
+                        hipMemcpyDeviceToHost, h->stream));
+  }
+  HIPC(hipStreamSynchronize(h->stream));
+  if (monitored) {
+    const double *m = h->mon_host;
+    h->last_mass = (double)h->nx * h->ny + m[0];
+    h->last_res = (h->mon_valid && m[2] > 0.0) ? std::sqrt(m[1] / m[2]) : INFINITY;
+    if (!std::isfinite(h->last_mass) || std::isnan(h->last_res))
+      return fail(LBM_EUNSTABLE, "non-finite monitor at step %lld (mass %g)",
+                  (long long)h->t, h->last_mass);
+  }
+  return LBM_OK;
+}
+
+int lbm_steps_done(lbm_t h, int64_t *t) {
+  if (!h || !t) return fail(LBM_EINVAL, "NULL argument");
+  *t = h->t;
+  return LBM_OK;
+}
+
+int lbm_moments_device(lbm_t h, double *rho, double *ux, double *uy) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (h->dtype == LBM_F64) launch_moments_t<double, false>(h, rho, ux, uy);
+  else launch_moments_t<float, true>(h, rho, ux, uy);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_moments(lbm_t h, double *rho, double *ux, double *uy) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  const size_t n = (size_t)h->nx * h->ny;
+  int rc = ensure_tmp(h, 3 * n);
+  if (rc) return rc;
+  double *d[3] = {rho ? h->tmp : nullptr, ux ? h->tmp + n : nullptr,
+                  uy ? h->tmp + 2 * n : nullptr};
+  if (h->dtype == LBM_F64) launch_moments_t<double, false>(h, d[0], d[1], d[2]);
+  else launch_moments_t<float, true>(h, d[0], d[1], d[2]);
+  HIPC(hipGetLastError());
+  double *outs[3] = {rho, ux, uy};
+  for (int k = 0; k < 3; ++k)
+    if (outs[k])
+      HIPC(hipMemcpyAsync(outs[k], d[k], n * sizeof(double), hipMemcpyDeviceToHost,
+                          h->stream));
+  HIPC(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_probe(lbm_t h, int npts, const double *xy, double *out) {
+  if (!h || !xy || !out) return fail(LBM_EINVAL, "NULL argument");
+  if (npts < 1 || npts > 4096) return fail(LBM_EINVAL, "npts = %d outside [1, 4096]", npts);
+  for (int i = 0; i < 2 * npts; ++i)
+    if (!std::isfinite(xy[i])) return fail(LBM_EINVAL, "probe coordinate %d not finite", i);
+  int rc = ensure_tmp(h, 5 * (size_t)npts);
+  if (rc) return rc;
+  HIPC(hipMemcpyAsync(h->tmp, xy, 2 * npts * sizeof(double), hipMemcpyHostToDevice,
+                      h->stream));
+  double *res = h->tmp + 2 * npts;
+  if (h->dtype == LBM_F64)
+    hipLaunchKernelGGL((k_probe<double, false>), dim3((npts + 255) / 256), dim3(256), 0,
+                       h->stream, (const double *)h->buf[h->cur], geom(h), h->tmp, npts, res);
+  else
+    hipLaunchKernelGGL((k_probe<float, true>), dim3((npts + 255) / 256), dim3(256), 0,
+                       h->stream, (const float *)h->buf[h->cur], geom(h), h->tmp, npts, res);
+  HIPC(hipGetLastError());
+  HIPC(hipMemcpyAsync(out, res, 3 * npts * sizeof(double), hipMemcpyDeviceToHost,
+                      h->stream));
+  HIPC(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_probe_config(lbm_t h, int npts, const double *xy, int every, int64_t capacity) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  HIPC(hipStreamSynchronize(h->stream));
+  drop_graphs(h);
+  if (npts == 0) {
+    h->probe_n = 0;
+    return LBM_OK;
+  }
+  if (!xy || npts < 0 || npts > 4096) return fail(LBM_EINVAL, "npts = %d outside [1, 4096]", npts);
+  if (!probe_every_ok(every))
+    return fail(LBM_EINVAL, "every = %d must divide 100 or be a multiple of 100", every);
+  if (capacity < 1 || capacity > (1LL << 26))
+    return fail(LBM_EINVAL, "capacity %lld outside [1, 2^26]", (long long)capacity);
+  for (int i = 0; i < 2 * npts; ++i)
+    if (!std::isfinite(xy[i])) return fail(LBM_EINVAL, "probe coordinate %d not finite", i);
+  if (h->probe_xy) HIPC(hipFree(h->probe_xy));
+  if (h->probe_ring) HIPC(hipFree(h->probe_ring));
+  if (!h->probe_count) HIPC(hipMalloc(&h->probe_count, sizeof(unsigned long long)));
+  h->probe_xy = nullptr;
+  h->probe_ring = nullptr;
+  h->probe_n = 0;
+  HIPC(hipMalloc(&h->probe_xy, 2 * npts * sizeof(double)));
+  HIPC(hipMalloc(&h->probe_ring, (size_t)capacity * 3 * npts * sizeof(double)));
+  HIPC(hipMemcpy(h->probe_xy, xy, 2 * npts * sizeof(double), hipMemcpyHostToDevice));
+  HIPC(hipMemset(h->probe_count, 0, sizeof(unsigned long long)));
+  h->probe_n = npts;
+  h->probe_every = every;
+  h->probe_cap = capacity;
+  // first recorded step: next multiple of `every` after now
+  h->probe_t0 = (h->t / every + 1) * every;
+  return LBM_OK;
+}
+
+int lbm_probe_read(lbm_t h, double *buf, int64_t max_records, int64_t *n_records) {
+  if (!h || !n_records) return fail(LBM_EINVAL, "NULL argument");
+  *n_records = 0;
+  if (!h->probe_ring || h->probe_n == 0) return LBM_OK;
+  if (max_records > 0 && !buf) return fail(LBM_EINVAL, "buf is NULL");
+  unsigned long long count = 0;
+  HIPC(hipStreamSynchronize(h->stream));
+  HIPC(hipMemcpy(&count, h->probe_count, sizeof count, hipMemcpyDeviceToHost));
+  const int64_t avail = std::min<int64_t>((int64_t)count, h->probe_cap);
+  const int64_t take = std::min<int64_t>(avail, max_records);
+  const int rec = 3 * h->probe_n;
+  std::vector<double> tmp((size_t)rec);
+  for (int64_t k = 0; k < take; ++k) {
+    const unsigned long long idx = count - take + k;      // record index
+    const int64_t slot = (int64_t)(idx % (unsigned long long)h->probe_cap);
+    HIPC(hipMemcpy(tmp.data(), h->probe_ring + slot * rec, rec * sizeof(double),
+                   hipMemcpyDeviceToHost));
+    double *dst = buf + k * (1 + rec);
+    dst[0] = (double)(h->probe_t0 + (int64_t)idx * h->probe_every);
+    std::memcpy(dst + 1, tmp.data(), rec * sizeof(double));
+  }
+  *n_records = take;
+  return LBM_OK;
+}
+
+int lbm_mass(lbm_t h, double *mass) {
+  if (!h || !mass) return fail(LBM_EINVAL, "NULL argument");
+  hipError_t e = launch_monitor(h, h->buf[h->cur], false, h->aux_dev, h->stream);
+  if (e != hipSuccess) return fail(LBM_EDEVICE, "monitor: %s", hipGetErrorString(e));
+  HIPC(hipMemcpyAsync(h->mon_host + 4, h->aux_dev, sizeof(double), hipMemcpyDeviceToHost,
+                      h->stream));
+  HIPC(hipStreamSynchronize(h->stream));
+  *mass = (double)h->nx * h->ny + h->mon_host[4];
+  return LBM_OK;
+}
+
+int lbm_residual(lbm_t h, double *residual, int64_t *at_step) {
+  if (!h || !residual) return fail(LBM_EINVAL, "NULL argument");
+  *residual = h->mon_t >= 0 ? h->last_res : INFINITY;
+  if (at_step) *at_step = h->mon_t;
+  return LBM_OK;
+}
+
+int lbm_stream_function(lbm_t h, double *psi) {
+  if (!h || !psi) return fail(LBM_EINVAL, "NULL argument");
+  const size_t n = (size_t)h->nx * h->ny;
+  int rc = ensure_tmp(h, n);
+  if (rc) return rc;
+  if (h->dtype == LBM_F64)
+    hipLaunchKernelGGL((k_psi<double, false>), dim3((h->nx + 255) / 256), dim3(256), 0,
+                       h->stream, (const double *)h->buf[h->cur], geom(h), h->tmp);
+  else
+    hipLaunchKernelGGL((k_psi<float, true>), dim3((h->nx + 255) / 256), dim3(256), 0,
+                       h->stream, (const float *)h->buf[h->cur], geom(h), h->tmp);
+  HIPC(hipGetLastError());
+  HIPC(hipMemcpyAsync(psi, h->tmp, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPC(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_set_populations(lbm_t h, const double *f) {
+  if (!h || !f) return fail(LBM_EINVAL, "NULL argument");
+  const size_t n = (size_t)h->nx * h->ny;
+  int rc = ensure_tmp(h, 9 * n);
+  if (rc) return rc;
+  HIPC(hipMemcpyAsync(h->tmp, f, 9 * n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  if (h->dtype == LBM_F64)
+    hipLaunchKernelGGL((k_set_pop<double, false>), dim3((n + 255) / 256), dim3(256), 0,
+                       h->stream, (double *)h->buf[h->cur], geom(h), h->tmp, h->omega);
+  else
+    hipLaunchKernelGGL((k_set_pop<float, true>), dim3((n + 255) / 256), dim3(256), 0,
+                       h->stream, (float *)h->buf[h->cur], geom(h), h->tmp, h->omega);
+  HIPC(hipGetLastError());
+  rc = reset_counters(h);
+  if (rc) return rc;
+  HIPC(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_get_populations(lbm_t h, double *f) {
+  if (!h || !f) return fail(LBM_EINVAL, "NULL argument");
+  const size_t n = (size_t)h->nx * h->ny;
+  int rc = ensure_tmp(h, 9 * n);
+  if (rc) return rc;
+  if (h->dtype == LBM_F64)
+    hipLaunchKernelGGL((k_get_pop<double, false>), dim3((n + 255) / 256), dim3(256), 0,
+                       h->stream, (const double *)h->buf[h->cur], geom(h), h->tmp);
+  else
+    hipLaunchKernelGGL((k_get_pop<float, true>), dim3((n + 255) / 256), dim3(256), 0,
+                       h->stream, (const float *)h->buf[h->cur], geom(h), h->tmp);
+  HIPC(hipGetLastError());
+  HIPC(hipMemcpyAsync(f, h->tmp, 9 * n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPC(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int lbm_init_fields(lbm_t h, const double *rho, const double *ux, const double *uy,
+                    int renormalise_mass) {
+  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  const size_t n = (size_t)h->nx * h->ny;
+  int rc = ensure_tmp(h, 3 * n);
+  if (rc) return rc;
+  const double *src[3] = {rho, ux, uy};
+  double *d[3] = {nullptr, nullptr, nullptr};
+  for (int k = 0; k < 3; ++k)
+    if (src[k]) {
+      d[k] = h->tmp + k * n;
+      HIPC(hipMemcpyAsync(d[k], src[k], n * sizeof(double), hipMemcpyHostToDevice,
+                          h->stream));
+    }
+  double scale = 1.0;
+  if (renormalise_mass && rho) {
+    // FP64 sum of rho on the device (same fixed-order reduction as the
+    // monitors), then scale so the total mass is nx * ny.
+    const int blocks = std::min(kRedBlocks, (int)((n + kRedThreads - 1) / kRedThreads));
+    hipLaunchKernelGGL(k_sum_dense, dim3(blocks), dim3(kRedThreads), 0, h->stream, d[0],
+                       (long long)n, h->partials);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedThreads), 0, h->stream, h->partials,
+                       blocks, h->aux_dev);
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(h->mon_host + 4, h->aux_dev, sizeof(double),
+                        hipMemcpyDeviceToHost, h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
+    const double total = h->mon_host[4];
+    if (!(total > 0.0) || !std::isfinite(total))
+      return fail(LBM_EINVAL, "sum of rho = %g cannot be renormalised", total);
+    scale = (double)n / total;
+  }
+  const int tot = h->pitch * h->ny;
+  if (h->dtype == LBM_F64)
+    hipLaunchKernelGGL((k_init_eq<double, false>), dim3((tot + 255) / 256), dim3(256), 0,
+                       h->stream, (double *)h->buf[h->cur], geom(h), d[0], d[1], d[2],
+                       scale);
+  else
+    hipLaunchKernelGGL((k_init_eq<float, true>), dim3((tot + 255) / 256), dim3(256), 0,
+                       h->stream, (float *)h->buf[h->cur], geom(h), d[0], d[1], d[2],
+                       scale);
+  HIPC(hipGetLastError());
+  rc = reset_counters(h);
+  if (rc) return rc;
+  HIPC(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+// Checkpoint file: header, stored populations of buf[cur], Eq. 6 reference.
+struct CkptHeader {
+  char magic[8];
+  int32_t version, nx, ny, pitch, dtype, pad;
+  int64_t t, snap_t, mon_t;
+  double tau, u_lid, last_res, last_mass;
+  uint64_t buf_bytes, uref_bytes;
+};
+
+int lbm_save(lbm_t h, const char *path) {
+  if (!h || !path) return fail(LBM_EINVAL, "NULL argument");
+  CkptHeader hd;
+  std::memset(&hd, 0, sizeof hd);
+  std::memcpy(hd.magic, "LBMD2Q9", 8);
+  hd.version = 1;
+  hd.nx = h->nx;
+  hd.ny = h->ny;
+  hd.pitch = h->pitch;
+  hd.dtype = h->dtype;
+  hd.t = h->t;
+  hd.snap_t = h->snap_t;
+  hd.mon_t = h->mon_t;
+  hd.tau = h->tau;
+  hd.u_lid = h->u_lid;
+  hd.last_res = h->last_res;
+  hd.last_mass = h->last_mass;
+  hd.buf_bytes = h->buf_bytes;
+  hd.uref_bytes = sizeof(double2) * (size_t)h->nx * h->ny;
+  std::vector<char> a(hd.buf_bytes), b(hd.uref_bytes);
+  HIPC(hipStreamSynchronize(h->stream));
+  HIPC(hipMemcpy(a.data(), h->buf[h->cur], hd.buf_bytes, hipMemcpyDeviceToHost));
+  HIPC(hipMemcpy(b.data(), h->uref, hd.uref_bytes, hipMemcpyDeviceToHost));
+  FILE *fp = std::fopen(path, "wb");
+  if (!fp) return fail(LBM_EIO, "cannot open %s for writing", path);
+  bool ok = std::fwrite(&hd, sizeof hd, 1, fp) == 1 &&
+            std::fwrite(a.data(), 1, a.size(), fp) == a.size() &&
+            std::fwrite(b.data(), 1, b.size(), fp) == b.size();
+  ok = (std::fclose(fp) == 0) && ok;
+  if (!ok) return fail(LBM_EIO, "short write to %s", path);
+  return LBM_OK;
+}
+
+int lbm_load(lbm_t h, const char *path) {
+  if (!h || !path) return fail(LBM_EINVAL, "NULL argument");
+  FILE *fp = std::fopen(path, "rb");
+  if (!fp) return fail(LBM_EIO, "cannot open %s", path);
+  CkptHeader hd;
+  if (std::fread(&hd, sizeof hd, 1, fp) != 1 || std::memcmp(hd.magic, "LBMD2Q9", 8) != 0 ||
+      hd.version != 1) {
+    std::fclose(fp);
+    return fail(LBM_EIO, "%s is not a checkpoint of this library", path);
+  }
+  if (hd.nx != h->nx || hd.ny != h->ny || hd.pitch != h->pitch || hd.dtype != h->dtype ||
+      hd.buf_bytes != h->buf_bytes ||
+      hd.uref_bytes != sizeof(double2) * (size_t)h->nx * h->ny) {
+    std::fclose(fp);
+    return fail(LBM_ESTATE, "checkpoint lattice %dx%d dtype %d does not match the handle",
+                hd.nx, hd.ny, hd.dtype);
+  }
+  std::vector<char> a(hd.buf_bytes), b(hd.uref_bytes);
+  const bool ok = std::fread(a.data(), 1, a.size(), fp) == a.size() &&
+                  std::fread(b.data(), 1, b.size(), fp) == b.size();
+  char extra;
+  const bool tail = std::fread(&extra, 1, 1, fp) == 0;
+  std::fclose(fp);
+  if (!ok || !tail) return fail(LBM_EIO, "%s is truncated or has trailing bytes", path);
+  HIPC(hipStreamSynchronize(h->stream));
+  HIPC(hipMemcpy(h->buf[h->cur], a.data(), a.size(), hipMemcpyHostToDevice));
+  HIPC(hipMemcpy(h->uref, b.data(), b.size(), hipMemcpyHostToDevice));
+  h->t = hd.t;
+  h->snap_t = hd.snap_t;
+  h->mon_t = hd.mon_t;
+  h->tau = hd.tau;
+  h->omega = 1.0 / hd.tau;
+  h->u_lid = hd.u_lid;
+  h->last_res = hd.last_res;
+  h->last_mass = hd.last_mass;
+  h->probe_n = 0;
+  drop_graphs(h);
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,345 @@
+"""ctypes binding of ``liblbm.so`` (declared in include/lbm.h).
+
+Argument marshalling only: every step of the lattice update, the monitors and
+the transfers run in the library's HIP kernels.  Functions keep the C names
+(``lbm_create``, ``lbm_step``, ...) and raise :class:`LbmError` on a non-zero
+return; :class:`Cavity` wraps a handle.  Host arrays are NumPy float64;
+device arrays and streams may be torch objects (``data_ptr()`` /
+``cuda_stream``), torch itself is not needed otherwise.
+
+The library must have been built (``python -m paper_2211_05009_amd.build``);
+importing this module without it raises ImportError: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblbm.so")
+
+LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_EIO, LBM_ESTATE = \
+    0, -1, -2, -3, -4, -5, -6
+LBM_F64, LBM_F32_SHIFTED = 0, 1
+LBM_OPT_USE_GRAPH, LBM_OPT_STEP_VARIANT, LBM_OPT_NUM_VARIANTS = 1, 2, 3
+DTYPES = {"f64": LBM_F64, "f32s": LBM_F32_SHIFTED}
+
+_ERRNAMES = {LBM_EINVAL: "LBM_EINVAL", LBM_ENOMEM: "LBM_ENOMEM",
+             LBM_EDEVICE: "LBM_EDEVICE", LBM_EUNSTABLE: "LBM_EUNSTABLE",
+             LBM_EIO: "LBM_EIO", LBM_ESTATE: "LBM_ESTATE"}
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRNAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+class lbm_info_t(ct.Structure):
+    _fields_ = [("nx", ct.c_int), ("ny", ct.c_int), ("pitch", ct.c_int),
+                ("dtype", ct.c_int), ("re", ct.c_double), ("u_lid", ct.c_double),
+                ("tau", ct.c_double), ("omega", ct.c_double),
+                ("steps_done", ct.c_int64), ("device_bytes", ct.c_size_t)]
+
+
+def _load():
+    # PyTorch ROCm wheels bundle their own HIP runtime under the same soname
+    # as ROCm's (libamdhip64.so.7).  Loading torch first makes that one
+    # runtime serve both torch and this library, so torch streams and device
+    # pointers handed to the library belong to the runtime that launches its
+    # kernels.  Without torch, ROCm's runtime is used.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2211_05009_amd.build` (no CPU fallback)")
+    return ct.CDLL(LIB_PATH)
+
+
+_lib = _load()
+_h = ct.c_void_p
+_dp = ct.POINTER(ct.c_double)
+_i64 = ct.c_int64
+
+# name -> argtypes (all return int unless listed in _RESTYPES)
+SIGNATURES = {
+    "lbm_last_error": [],
+    "lbm_version": [],
+    "lbm_create": [ct.c_int, ct.c_int, ct.c_double, ct.c_double, ct.c_int, ct.POINTER(_h)],
+    "lbm_create_tau": [ct.c_int, ct.c_int, ct.c_double, ct.c_double, ct.c_int, ct.POINTER(_h)],
+    "lbm_destroy": [_h],
+    "lbm_set_stream": [_h, ct.c_void_p],
+    "lbm_info": [_h, ct.POINTER(lbm_info_t)],
+    "lbm_set_option": [_h, ct.c_int, _i64],
+    "lbm_get_option": [_h, ct.c_int, ct.POINTER(_i64)],
+    "lbm_step": [_h, _i64],
+    "lbm_steps_done": [_h, ct.POINTER(_i64)],
+    "lbm_moments": [_h, ct.c_void_p, ct.c_void_p, ct.c_void_p],
+    "lbm_moments_device": [_h, ct.c_void_p, ct.c_void_p, ct.c_void_p],
+    "lbm_probe": [_h, ct.c_int, ct.c_void_p, ct.c_void_p],
+    "lbm_probe_config": [_h, ct.c_int, ct.c_void_p, ct.c_int, _i64],
+    "lbm_probe_read": [_h, ct.c_void_p, _i64, ct.POINTER(_i64)],
+    "lbm_mass": [_h, _dp],
+    "lbm_residual": [_h, _dp, ct.POINTER(_i64)],
+    "lbm_stream_function": [_h, ct.c_void_p],
+    "lbm_set_populations": [_h, ct.c_void_p],
+    "lbm_get_populations": [_h, ct.c_void_p],
+    "lbm_init_fields": [_h, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int],
+    "lbm_save": [_h, ct.c_char_p],
+    "lbm_load": [_h, ct.c_char_p],
+}
+_RESTYPES = {"lbm_last_error": ct.c_char_p, "lbm_version": ct.c_char_p}
+
+for _name, _args in SIGNATURES.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = _RESTYPES.get(_name, ct.c_int)
+
+
+def _check(rc):
+    if rc != LBM_OK:
+        raise LbmError(rc, _lib.lbm_last_error().decode())
+    return rc
+
+
+def _f64(a, shape):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {a.shape}")
+    return a
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ct.c_void_p)
+
+
+# ---------------------------------------------------------------- C names ---
+def lbm_last_error():
+    return _lib.lbm_last_error().decode()
+
+
+def lbm_version():
+    return _lib.lbm_version().decode()
+
+
+def lbm_create(nx, ny, re, u_lid, dtype):
+    h = _h()
+    _check(_lib.lbm_create(int(nx), int(ny), float(re), float(u_lid),
+                           DTYPES.get(dtype, dtype), ct.byref(h)))
+    return h
+
+
+def lbm_create_tau(nx, ny, tau, u_lid, dtype):
+    h = _h()
+    _check(_lib.lbm_create_tau(int(nx), int(ny), float(tau), float(u_lid),
+                               DTYPES.get(dtype, dtype), ct.byref(h)))
+    return h
+
+
+def lbm_destroy(h):
+    _check(_lib.lbm_destroy(h))
+
+
+def lbm_set_stream(h, stream):
+    """``stream``: a torch.cuda.Stream, a raw hipStream_t integer, or None."""
+    raw = getattr(stream, "cuda_stream", stream)
+    _check(_lib.lbm_set_stream(h, ct.c_void_p(raw) if raw else None))
+
+
+def lbm_info(h):
+    info = lbm_info_t()
+    _check(_lib.lbm_info(h, ct.byref(info)))
+    return {k: getattr(info, k) for k, _ in lbm_info_t._fields_}
+
+
+def lbm_set_option(h, option, value):
+    _check(_lib.lbm_set_option(h, int(option), int(value)))
+
+
+def lbm_get_option(h, option):
+    v = _i64()
+    _check(_lib.lbm_get_option(h, int(option), ct.byref(v)))
+    return v.value
+
+
+def lbm_step(h, n):
+    _check(_lib.lbm_step(h, int(n)))
+
+
+def lbm_steps_done(h):
+    t = _i64()
+    _check(_lib.lbm_steps_done(h, ct.byref(t)))
+    return t.value
+
+
+def lbm_moments(h, nx, ny):
+    rho, ux, uy = (np.empty((ny, nx)) for _ in range(3))
+    _check(_lib.lbm_moments(h, _ptr(rho), _ptr(ux), _ptr(uy)))
+    return rho, ux, uy
+
+
+def lbm_moments_device(h, rho, ux, uy):
+    """Device outputs: torch float64 tensors (or raw pointers / None)."""
+    ptrs = [None if a is None else ct.c_void_p(a.data_ptr() if hasattr(a, "data_ptr") else a)
+            for a in (rho, ux, uy)]
+    _check(_lib.lbm_moments_device(h, *ptrs))
+
+
+def lbm_probe(h, points):
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 2)
+    out = np.empty((pts.shape[0], 3))
+    _check(_lib.lbm_probe(h, pts.shape[0], _ptr(pts), _ptr(out)))
+    return out
+
+
+def lbm_probe_config(h, points, every, capacity):
+    if points is None or len(points) == 0:
+        _check(_lib.lbm_probe_config(h, 0, None, int(every), int(capacity)))
+        return
+    pts = np.ascontiguousarray(points, dtype=np.float64).reshape(-1, 2)
+    _check(_lib.lbm_probe_config(h, pts.shape[0], _ptr(pts), int(every), int(capacity)))
+
+
+def lbm_probe_read(h, npts, max_records):
+    buf = np.empty((max(int(max_records), 1), 1 + 3 * npts))
+    n = _i64()
+    _check(_lib.lbm_probe_read(h, _ptr(buf), int(max_records), ct.byref(n)))
+    return buf[:n.value]
+
+
+def lbm_mass(h):
+    m = ct.c_double()
+    _check(_lib.lbm_mass(h, ct.byref(m)))
+    return m.value
+
+
+def lbm_residual(h):
+    r = ct.c_double()
+    t = _i64()
+    _check(_lib.lbm_residual(h, ct.byref(r), ct.byref(t)))
+    return r.value, t.value
+
+
+def lbm_stream_function(h, nx, ny):
+    psi = np.empty((ny, nx))
+    _check(_lib.lbm_stream_function(h, _ptr(psi)))
+    return psi
+
+
+def lbm_set_populations(h, f, nx, ny):
+    f = _f64(f, (9, ny, nx))
+    _check(_lib.lbm_set_populations(h, _ptr(f)))
+
+
+def lbm_get_populations(h, nx, ny):
+    f = np.empty((9, ny, nx))
+    _check(_lib.lbm_get_populations(h, _ptr(f)))
+    return f
+
+
+def lbm_init_fields(h, rho, ux, uy, nx, ny, renormalise_mass=True):
+    arrs = [None if a is None else _f64(a, (ny, nx)) for a in (rho, ux, uy)]
+    _check(_lib.lbm_init_fields(h, *[_ptr(a) for a in arrs], int(bool(renormalise_mass))))
+
+
+def lbm_save(h, path):
+    _check(_lib.lbm_save(h, os.fsencode(path)))
+
+
+def lbm_load(h, path):
+    _check(_lib.lbm_load(h, os.fsencode(path)))
+
+
+# ------------------------------------------------------------ convenience ---
+class Cavity:
+    """A lid-driven cavity on the GPU (one library handle)."""
+
+    def __init__(self, nx, ny, re=None, u_lid=0.1, dtype="f64", tau=None):
+        self.nx, self.ny = int(nx), int(ny)
+        if tau is not None:
+            self.h = lbm_create_tau(nx, ny, tau, u_lid, dtype)
+        else:
+            self.h = lbm_create(nx, ny, re, u_lid, dtype)
+        self.npts = 0
+
+    def close(self):
+        if self.h:
+            lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def info(self):
+        return lbm_info(self.h)
+
+    @property
+    def steps_done(self):
+        return lbm_steps_done(self.h)
+
+    def step(self, n=1):
+        lbm_step(self.h, n)
+        return self
+
+    def moments(self):
+        return lbm_moments(self.h, self.nx, self.ny)
+
+    def moments_device(self, rho, ux, uy):
+        lbm_moments_device(self.h, rho, ux, uy)
+
+    def probe(self, points):
+        return lbm_probe(self.h, points)
+
+    def probe_config(self, points, every, capacity):
+        lbm_probe_config(self.h, points, every, capacity)
+        self.npts = 0 if points is None else len(points)
+
+    def probe_read(self, max_records):
+        return lbm_probe_read(self.h, self.npts, max_records)
+
+    def mass(self):
+        return lbm_mass(self.h)
+
+    def residual(self):
+        return lbm_residual(self.h)
+
+    def stream_function(self):
+        return lbm_stream_function(self.h, self.nx, self.ny)
+
+    def set_populations(self, f):
+        lbm_set_populations(self.h, f, self.nx, self.ny)
+
+    def get_populations(self):
+        return lbm_get_populations(self.h, self.nx, self.ny)
+
+    def init_fields(self, rho=None, ux=None, uy=None, renormalise_mass=True):
+        lbm_init_fields(self.h, rho, ux, uy, self.nx, self.ny, renormalise_mass)
+
+    def set_stream(self, stream):
+        lbm_set_stream(self.h, stream)
+
+    def set_option(self, option, value):
+        lbm_set_option(self.h, option, value)
+
+    def get_option(self, option):
+        return lbm_get_option(self.h, option)
+
+    def save(self, path):
+        lbm_save(self.h, path)
+
+    def load(self, path):
+        lbm_load(self.h, path)

@@ -1,0 +1,179 @@
+"""GPU parity: the HIP step against the CPU FP64 oracle, element by element.
+
+Bars (written in each test):
+  * FP64 storage: max |d rho| and max |d u| / U <= 1e-12 after up to 1000
+    steps; populations to 1e-12 as well.
+  * FP32 f - w storage: max |d u| <= 1e-5 U over a 1000-step horizon.
+Sizes span several 64-wide tiles and ragged tails; the full 500 x (500 Ar)
+lattices are checked one launch at a time (the oracle applies one step to the
+GPU's own state) and over 1000 steps at Ar = 0.4, Re = 8000.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from cavity_inputs import U_LID, random_shift
+from oracle import d2q9
+from oracle.d2q9 import W
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+F32_UTOL = 1e-5 * U_LID
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    from paper_2211_05009_amd import lbm as mod
+    return mod
+
+
+def oracle_from(f0, tau, u=U_LID):
+    ny, nx = f0.shape[1:]
+    o = d2q9.Cavity(nx, ny, tau=tau, u_lid=u)
+    o.set_state(f0)
+    return o
+
+
+def compare(gpu, orc, dtype, what=""):
+    """gpu, orc: Cavity objects at the same step."""
+    rg, uxg, uyg = gpu.moments()
+    ro, uxo, uyo = orc.moments()
+    du = max(np.max(np.abs(uxg - uxo)), np.max(np.abs(uyg - uyo)))
+    dr = np.max(np.abs(rg - ro))
+    if dtype == "f64":
+        assert dr <= F64_TOL, f"{what} rho {dr}"
+        assert du / U_LID <= F64_TOL, f"{what} u {du}"
+        fg = gpu.get_populations()
+        fo = orc.post_collision()
+        assert np.max(np.abs(fg - fo)) <= F64_TOL, what
+    else:
+        assert du <= F32_UTOL, f"{what} u {du}"
+        assert dr <= 1e-5, f"{what} rho {dr}"
+    return dr, du
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32s"])
+def test_first_step_from_rest_matches_closed_form(lbm, dtype):
+    """One step from rest: lid-row populations 7, 8 become 1/36 -+ U/6, all
+    else stays w (Eq. 1 with the moving-wall term); checked through the
+    stored post-collision state."""
+    c = lbm.Cavity(37, 29, tau=0.7, u_lid=U_LID, dtype=dtype)
+    c.step(1)
+    o = d2q9.Cavity(37, 29, tau=0.7, u_lid=U_LID).step(1)
+    tol = 1e-15 if dtype == "f64" else 2e-8
+    assert np.max(np.abs(c.get_populations() - o.post_collision())) <= tol
+    rho, ux, uy = c.moments()
+    assert np.max(np.abs(ux[-1] - U_LID / 3)) <= (1e-16 if dtype == "f64" else 1e-8)
+    assert np.max(np.abs(ux[:-1])) == 0.0
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32s"])
+def test_parity_from_rest_64(lbm, dtype):
+    """64 x 64 cavity, Re = 100, 1000 steps from rest (graph chunks)."""
+    c = lbm.Cavity(64, 64, re=100.0, u_lid=U_LID, dtype=dtype)
+    o = d2q9.Cavity(64, 64, re=100.0, u_lid=U_LID)
+    for k in range(4):
+        c.step(250)
+        o.step(250)
+        compare(c, o, dtype, f"t={o.t}")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32s"])
+@pytest.mark.parametrize("nx,ny,tau,seed", [(2, 2, 0.8, 1), (3, 70, 0.6, 2),
+                                            (65, 3, 0.9, 3), (130, 67, 0.51875, 4),
+                                            (200, 129, 1.2, 5), (64, 64, 0.55, 6)])
+def test_parity_random_state(lbm, dtype, nx, ny, tau, seed):
+    """Random low-Mach state, ragged lattices, 257 steps (two graph chunks and
+    57 single launches), several relaxation times."""
+    f0 = W[:, None, None] + random_shift(nx, ny, seed)
+    c = lbm.Cavity(nx, ny, tau=tau, u_lid=U_LID, dtype=dtype)
+    c.set_populations(f0)
+    o = oracle_from(f0, tau)
+    compare(c, o, dtype, "t=0")
+    c.step(257)
+    o.step(257)
+    compare(c, o, dtype, "t=257")
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32s"])
+def test_variants_graph_and_direct_launch_agree_bitwise(lbm, dtype):
+    """Every tile shape and both launch paths compute the same per-site
+    arithmetic, so their results agree bit for bit."""
+    nx, ny = 131, 77
+    f0 = W[:, None, None] + random_shift(nx, ny, 7)
+    ref = None
+    c = lbm.Cavity(nx, ny, tau=0.56, u_lid=U_LID, dtype=dtype)
+    nvar = c.get_option(lbm.LBM_OPT_NUM_VARIANTS)
+    for v in range(nvar):
+        for graph in (1, 0):
+            c.set_option(lbm.LBM_OPT_STEP_VARIANT, v)
+            c.set_option(lbm.LBM_OPT_USE_GRAPH, graph)
+            c.set_populations(f0)
+            c.step(230)
+            f = c.get_populations()
+            if ref is None:
+                ref = f
+            assert np.array_equal(f, ref), (v, graph)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32s"])
+@pytest.mark.parametrize("ar", [0.4, 1.0, 2.0])
+def test_full_size_single_launch(lbm, dtype, ar):
+    """500 x (500 Ar): one launch of the step, as timed by the benchmark
+    (after a 100-step graph chunk), against one oracle step applied to the
+    GPU's own stored state."""
+    nx, ny = 500, int(round(500 * ar))
+    tau = d2q9.relaxation_time(nx, 8000.0, U_LID)
+    c = lbm.Cavity(nx, ny, re=8000.0, u_lid=U_LID, dtype=dtype)
+    c.set_populations(W[:, None, None] + random_shift(nx, ny, 11))
+    c.step(100)                                   # one captured chunk
+    fs = c.get_populations()                      # f*(100)
+    c.step(1)                                     # one direct launch
+    o = d2q9.Cavity(nx, ny, tau=tau, u_lid=U_LID)
+    f101 = o.stream(fs)
+    o.set_state(f101, t=101)
+    ref = o.post_collision()
+    got = c.get_populations()
+    if dtype == "f64":
+        assert np.max(np.abs(got - ref)) <= 1e-15
+    else:
+        # one FP32 step from an exactly representable state: each stored
+        # value passes through ~10 FP32 operations on numbers no larger than
+        # the largest shift |f - w|, so the bound is 16 ulps of that shift
+        gmax = np.max(np.abs(ref - W[:, None, None]))
+        assert np.max(np.abs(got - ref)) <= 16 * 2.0 ** -24 * gmax
+
+
+@pytest.fixture(scope="module")
+def re8000_oracle():
+    """Oracle run: 500 x 200 (Ar = 0.4), Re = 8000, 1000 steps from rest."""
+    o = d2q9.Cavity(500, 200, re=8000.0, u_lid=U_LID)
+    o.step(1000)
+    return o
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32s"])
+def test_full_size_1000_steps_re8000(lbm, dtype, re8000_oracle):
+    c = lbm.Cavity(500, 200, re=8000.0, u_lid=U_LID, dtype=dtype)
+    c.step(1000)
+    dr, du = compare(c, re8000_oracle, dtype, "500x200 Re=8000 t=1000")
+    print(f"{dtype}: max|drho| {dr:.3e}  max|du|/U {du / U_LID:.3e}")
+
+
+def test_mass_conservation_long_run(lbm):
+    """20,000 steps of the 64 x 64, Re = 100 cavity.  FP64 storage drifts
+    only by the rounding of sum_i f^eq_i (~1e-16 of the mass per step, as in
+    the oracle).  FP32 f - w storage conserves mass only to its own rounding:
+    at steady state the same roundings of the stored shifts repeat every step
+    and add up linearly (measured 7.5e-9 of the mass after 20,000 steps); the
+    bound allows 13x that."""
+    for dtype, tol in (("f64", 5e-12), ("f32s", 1e-7)):
+        c = lbm.Cavity(64, 64, re=100.0, u_lid=U_LID, dtype=dtype)
+        m0 = c.mass()
+        assert m0 == 64 * 64
+        c.step(20000)
+        drift = abs(c.mass() - m0) / m0
+        print(f"{dtype}: relative mass drift after 20000 steps {drift:.3e}")
+        assert drift <= tol, dtype
