@@ -120,9 +120,29 @@ int lbm_info(lbm_t h, lbm_info_t *info);
  *   LBM_OPT_NUM_VARIANTS  read-only: number of tile shapes.
  * LBM_EINVAL for an unknown option or an out-of-range value.
  */
-enum { LBM_OPT_USE_GRAPH = 1, LBM_OPT_STEP_VARIANT = 2, LBM_OPT_NUM_VARIANTS = 3 };
+enum {
+  LBM_OPT_USE_GRAPH = 1,
+  LBM_OPT_STEP_VARIANT = 2,
+  LBM_OPT_NUM_VARIANTS = 3,
+  LBM_OPT_GRAPH_STEPS = 4  /* batches only: steps per captured graph, a
+                              multiple of 100 in [100, 100000] (default 1000) */
+};
 int lbm_set_option(lbm_t h, int option, int64_t value);
 int lbm_get_option(lbm_t h, int option, int64_t *value);
+
+/*
+ * Tile-shape autotuner: time every step-kernel tile shape over `chunks`
+ * 100-step chunks (1 <= chunks <= 10000) with HIP events on the handle's
+ * stream, keep the fastest (LBM_OPT_STEP_VARIANT) and leave the state, step
+ * counter and monitors exactly as before the call.  Must be called at a
+ * multiple of 100 steps.  If use_cache is non-zero and the file named by the
+ * environment variable LBM_TUNE_CACHE holds an entry for this device,
+ * storage type and lattice, that entry is applied without timing
+ * (*ms_per_step = NaN); a timed result is appended to that file.  Outputs
+ * may be NULL.  The shapes give bit-identical results.
+ */
+int lbm_autotune(lbm_t h, int chunks, int use_cache, int *best_variant,
+                 double *ms_per_step);
 
 /*
  * Advance n >= 0 steps of Eq. 1 with the wall treatment above.  At every
@@ -223,6 +243,69 @@ int lbm_init_fields(lbm_t h, const double *rho_host, const double *ux_host,
  */
 int lbm_save(lbm_t h, const char *path);
 int lbm_load(lbm_t h, const char *path);
+
+/* ------------------------------------------------------------------------
+ * Batched sweep: many cavities of uneven size advanced by one launch per
+ * step (the Re x Ar sweep of Sec. 3.3 / Fig. 17 as one job).
+ *
+ * All cavities share the lid speed and storage type; cavity k has its own
+ * nx[k] x ny[k] lattice and Reynolds number re[k] (tau_k = 3 u nx_k / re_k
+ * + 1/2).  Each cavity evolves exactly as a single cavity created with the
+ * same arguments (bit for bit: the per-site arithmetic is the same).
+ * Steps are applied to the *active* cavities; inactive ones keep their state
+ * and step count.  Monitors (mass, Eq. 6) run per cavity every 100 batch
+ * steps; aligned runs of LBM_OPT_GRAPH_STEPS steps replay a HIP graph.
+ * Cavity indices k are 0-based; out-of-range k gives LBM_EINVAL.
+ * ---------------------------------------------------------------------- */
+typedef struct lbm_batch *lbm_batch_t;
+
+/* Errors as lbm_create, per cavity; 1 <= n <= 4096; the total storage must
+ * stay below 2^31 elements per buffer. */
+int lbm_batch_create(int n, const int *nx, const int *ny, const double *re,
+                     double u_lid, int dtype, lbm_batch_t *out);
+int lbm_batch_destroy(lbm_batch_t b);
+int lbm_batch_set_stream(lbm_batch_t b, void *hip_stream);
+int lbm_batch_set_option(lbm_batch_t b, int option, int64_t value);
+int lbm_batch_get_option(lbm_batch_t b, int option, int64_t *value);
+
+/* Advance every active cavity n >= 0 steps.  With a threshold set, a cavity
+ * whose Eq. 6 residual is below it at a monitor becomes inactive at the next
+ * multiple of 100 steps (checked after each captured chunk).  Stops early
+ * when no cavity is active.  LBM_EUNSTABLE if a monitor is not finite. */
+int lbm_batch_step(lbm_batch_t b, int64_t n);
+
+/* Residual threshold for automatic deactivation (0 = off, the default). */
+int lbm_batch_set_threshold(lbm_batch_t b, double residual);
+
+/* Switch cavity k on or off; only at a multiple of 100 batch steps. */
+int lbm_batch_set_active(lbm_batch_t b, int k, int active);
+
+/* Per-cavity state: steps applied to it, last Eq. 6 residual (+inf if none
+ * or not valid), the step of that monitor (-1 if none), active flag.
+ * NULL outputs are skipped. */
+int lbm_batch_status(lbm_batch_t b, int k, int64_t *steps_done,
+                     double *residual, int64_t *residual_step, int *active);
+
+/* As the single-cavity calls, for cavity k (host buffers [ny_k][nx_k] or
+ * [9][ny_k][nx_k] doubles). */
+int lbm_batch_mass(lbm_batch_t b, int k, double *mass);
+int lbm_batch_moments(lbm_batch_t b, int k, double *rho_host, double *ux_host,
+                      double *uy_host);
+int lbm_batch_get_populations(lbm_batch_t b, int k, double *fstar_host);
+int lbm_batch_set_populations(lbm_batch_t b, int k, const double *f_host);
+int lbm_batch_init_fields(lbm_batch_t b, int k, const double *rho_host,
+                          const double *ux_host, const double *uy_host,
+                          int renormalise_mass);
+
+/* Number of cavities, total sites, batch steps applied, device bytes held. */
+int lbm_batch_info(lbm_batch_t b, int *n, int64_t *total_sites,
+                   int64_t *steps_done, size_t *device_bytes);
+
+/* Autotuner of the batch kernel's tile shape; as lbm_autotune with `chunks`
+ * captured graphs of LBM_OPT_GRAPH_STEPS steps per shape (1..1000).  Must be
+ * called at a multiple of 100 steps; the cavities' states are restored. */
+int lbm_batch_autotune(lbm_batch_t b, int chunks, int use_cache,
+                       int *best_variant, double *ms_per_step);
 
 #ifdef __cplusplus
 }

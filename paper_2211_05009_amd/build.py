@@ -18,8 +18,9 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbm.so")
 ARCH = "gfx950"
 
-SOURCES = ["lbm.hip"]
-DEPS = ["lbm.hip", "lbm_internal.h", "d2q9_step.hpp", "d2q9_monitor.hpp"]
+SOURCES = ["lbm.hip", "lbm_batch.hip"]
+DEPS = ["lbm.hip", "lbm_batch.hip", "lbm_internal.h", "d2q9_step.hpp",
+        "d2q9_monitor.hpp", "d2q9_batch.hpp"]
 
 
 def hipcc() -> str:

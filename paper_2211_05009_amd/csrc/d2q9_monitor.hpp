@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kRedThreads) void k_monitor(
 }
 
 // Per-block partial sums of a dense FP64 array (first slot of each triple).
-__global__ __launch_bounds__(kRedThreads) void k_sum_dense(
+static __global__ __launch_bounds__(kRedThreads) void k_sum_dense(
     const double *__restrict__ a, long long n, double *__restrict__ partials) {
   double acc[kNumSums] = {0.0, 0.0, 0.0};
   for (long long k = blockIdx.x * (long long)kRedThreads + threadIdx.x; k < n;
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(kRedThreads) void k_sum_dense(
 }
 
 // Single block: add nparts partial triples in a fixed order.
-__global__ __launch_bounds__(kRedThreads) void k_finalize(
+static __global__ __launch_bounds__(kRedThreads) void k_finalize(
     const double *__restrict__ partials, int nparts, double *__restrict__ out) {
   double acc[kNumSums] = {0.0, 0.0, 0.0};
   for (int b = threadIdx.x; b < nparts; b += kRedThreads)

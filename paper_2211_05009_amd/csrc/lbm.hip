@@ -16,6 +16,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -27,31 +28,55 @@
 
 using namespace lbm;
 
-namespace {
+thread_local std::string g_lbm_err;
 
-thread_local std::string g_err;
-
-int fail(int code, const char *fmt, ...) {
+int lbm_fail(int code, const char *fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
   vsnprintf(buf, sizeof buf, fmt, ap);
   va_end(ap);
-  g_err = buf;
+  g_lbm_err = buf;
   return code;
 }
 
-#define HIPC(call)                                                          \
-  do {                                                                      \
-    hipError_t e_ = (call);                                                 \
-    if (e_ != hipSuccess)                                                   \
-      return fail(e_ == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE,     \
-                  "%s failed: %s", #call, hipGetErrorString(e_));           \
-  } while (0)
+// ------------------------------------------------------------ tune cache
+std::string tune_key(const char *kind, int dtype, long long a, long long b) {
+  char arch[64] = "unknown";
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    std::snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
+    for (char *c = arch; *c; ++c)
+      if (*c == ' ' || *c == ':') *c = '_';
+  }
+  char buf[192];
+  std::snprintf(buf, sizeof buf, "%s|%s|%s|%lld|%lld", arch, kind,
+                dtype == LBM_F64 ? "f64" : "f32s", a, b);
+  return buf;
+}
 
-constexpr int kChunk = 100;   // monitor cadence (Eq. 6 compares t and t-100)
+int tune_cache_lookup(const std::string &key) {
+  const char *path = std::getenv("LBM_TUNE_CACHE");
+  if (!path || !*path) return -1;
+  FILE *fp = std::fopen(path, "r");
+  if (!fp) return -1;
+  char k[256];
+  int v = -1, found = -1;
+  while (std::fscanf(fp, "%255s %d", k, &v) == 2)
+    if (key == k) found = v;             // the last entry wins
+  std::fclose(fp);
+  return found;
+}
 
-}  // namespace
+void tune_cache_store(const std::string &key, int variant) {
+  const char *path = std::getenv("LBM_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE *fp = std::fopen(path, "a");
+  if (!fp) return;
+  std::fprintf(fp, "%s %d\n", key.c_str(), variant);
+  std::fclose(fp);
+}
 
 // ---------------------------------------------------------------- variants
 // Step kernel variants: tile 64 x (BY*RY) sites, block 64 x BY threads.
@@ -192,14 +217,14 @@ static int build_graph(lbm_cavity *h, int c) {
   hipError_t e2 = hipStreamEndCapture(h->cap_stream, &g);
   if (e != hipSuccess || e2 != hipSuccess) {
     if (g) (void)hipGraphDestroy(g);
-    return fail(LBM_EDEVICE, "graph capture failed: %s",
+    return lbm_fail(LBM_EDEVICE, "graph capture failed: %s",
                 hipGetErrorString(e != hipSuccess ? e : e2));
   }
   e = hipGraphInstantiate(&h->graph[c], g, nullptr, nullptr, 0);
   (void)hipGraphDestroy(g);
   if (e != hipSuccess) {
     h->graph[c] = nullptr;
-    return fail(LBM_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    return lbm_fail(LBM_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
   }
   return LBM_OK;
 }
@@ -214,7 +239,7 @@ static int reset_counters(lbm_cavity *h) {
   h->probe_n = 0;
   drop_graphs(h);
   hipError_t e = launch_monitor(h, h->buf[h->cur], true, h->aux_dev, h->stream);
-  if (e != hipSuccess) return fail(LBM_EDEVICE, "monitor launch: %s", hipGetErrorString(e));
+  if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "monitor launch: %s", hipGetErrorString(e));
   return LBM_OK;
 }
 
@@ -228,29 +253,29 @@ static void launch_moments_t(lbm_cavity *h, double *r, double *u, double *v) {
 // ------------------------------------------------------------------- C ABI
 extern "C" {
 
-const char *lbm_last_error(void) { return g_err.c_str(); }
+const char *lbm_last_error(void) { return g_lbm_err.c_str(); }
 
 const char *lbm_version(void) { return "mi355x-lbm 0.1 (gfx950)"; }
 
 static int create_impl(int nx, int ny, double tau, double re, double u_lid,
                        int dtype, lbm_t *out) {
-  if (!out) return fail(LBM_EINVAL, "out is NULL");
+  if (!out) return lbm_fail(LBM_EINVAL, "out is NULL");
   *out = nullptr;
   if (nx < 2 || ny < 2 || nx > 65536 || ny > 65536)
-    return fail(LBM_EINVAL, "lattice %d x %d outside [2, 65536]", nx, ny);
+    return lbm_fail(LBM_EINVAL, "lattice %d x %d outside [2, 65536]", nx, ny);
   if (dtype != LBM_F64 && dtype != LBM_F32_SHIFTED)
-    return fail(LBM_EINVAL, "unknown dtype %d", dtype);
+    return lbm_fail(LBM_EINVAL, "unknown dtype %d", dtype);
   if (!std::isfinite(u_lid) || std::fabs(u_lid) >= 1.0 / std::sqrt(3.0))
-    return fail(LBM_EINVAL, "|u_lid| = %g must be below c_s = 1/sqrt(3)", u_lid);
+    return lbm_fail(LBM_EINVAL, "|u_lid| = %g must be below c_s = 1/sqrt(3)", u_lid);
   if (!std::isfinite(tau) || !(tau > 0.5))
-    return fail(LBM_EINVAL, "tau = %.17g must exceed 1/2", tau);
+    return lbm_fail(LBM_EINVAL, "tau = %.17g must exceed 1/2", tau);
   const int pitch = (nx + 63) / 64 * 64;
   const long long plane = (long long)pitch * ny;
   if (plane * 9 >= (1LL << 31))
-    return fail(LBM_EINVAL, "lattice too large for 32-bit element offsets");
+    return lbm_fail(LBM_EINVAL, "lattice too large for 32-bit element offsets");
 
   lbm_cavity *h = new (std::nothrow) lbm_cavity();
-  if (!h) return fail(LBM_ENOMEM, "host allocation");
+  if (!h) return lbm_fail(LBM_ENOMEM, "host allocation");
   h->nx = nx;
   h->ny = ny;
   h->pitch = pitch;
@@ -274,7 +299,7 @@ static int create_impl(int nx, int ny, double tau, double re, double u_lid,
   do {                                                                         \
     e = (call);                                                                \
     if (e != hipSuccess)                                                       \
-      return bail(fail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE,    \
+      return bail(lbm_fail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE,    \
                        "%s failed: %s", #call, hipGetErrorString(e)));         \
   } while (0)
   TRY(hipGetDevice(&h->device));
@@ -311,10 +336,10 @@ static int create_impl(int nx, int ny, double tau, double re, double u_lid,
 
 int lbm_create(int nx, int ny, double re, double u_lid, int dtype, lbm_t *out) {
   if (!(re > 0.0) || !std::isfinite(re))
-    return fail(LBM_EINVAL, "re = %g must be positive and finite", re);
+    return lbm_fail(LBM_EINVAL, "re = %g must be positive and finite", re);
   const double tau = 3.0 * u_lid * nx / re + 0.5;   // Eq. 5, nu = U L / Re
   if (!(tau > 0.5))
-    return fail(LBM_EINVAL, "tau = 3 u nx / re + 1/2 = %.17g must exceed 1/2", tau);
+    return lbm_fail(LBM_EINVAL, "tau = 3 u nx / re + 1/2 = %.17g must exceed 1/2", tau);
   return create_impl(nx, ny, tau, re, u_lid, dtype, out);
 }
 
@@ -346,14 +371,14 @@ int lbm_destroy(lbm_t h) {
 }
 
 int lbm_set_stream(lbm_t h, void *hip_stream) {
-  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!h) return lbm_fail(LBM_EINVAL, "handle is NULL");
   HIPC(hipStreamSynchronize(h->stream));
   h->stream = hip_stream ? (hipStream_t)hip_stream : h->own_stream;
   return LBM_OK;
 }
 
 int lbm_info(lbm_t h, lbm_info_t *info) {
-  if (!h || !info) return fail(LBM_EINVAL, "NULL argument");
+  if (!h || !info) return lbm_fail(LBM_EINVAL, "NULL argument");
   info->nx = h->nx;
   info->ny = h->ny;
   info->pitch = h->pitch;
@@ -369,30 +394,30 @@ int lbm_info(lbm_t h, lbm_info_t *info) {
 }
 
 int lbm_set_option(lbm_t h, int option, int64_t value) {
-  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!h) return lbm_fail(LBM_EINVAL, "handle is NULL");
   switch (option) {
     case LBM_OPT_USE_GRAPH:
       h->use_graph = value ? 1 : 0;
       return LBM_OK;
     case LBM_OPT_STEP_VARIANT:
       if (value < 0 || value >= kNumVariants)
-        return fail(LBM_EINVAL, "variant %lld outside [0, %d)", (long long)value,
+        return lbm_fail(LBM_EINVAL, "variant %lld outside [0, %d)", (long long)value,
                     kNumVariants);
       if (h->variant != (int)value) drop_graphs(h);
       h->variant = (int)value;
       return LBM_OK;
     default:
-      return fail(LBM_EINVAL, "unknown option %d", option);
+      return lbm_fail(LBM_EINVAL, "unknown option %d", option);
   }
 }
 
 int lbm_get_option(lbm_t h, int option, int64_t *value) {
-  if (!h || !value) return fail(LBM_EINVAL, "NULL argument");
+  if (!h || !value) return lbm_fail(LBM_EINVAL, "NULL argument");
   switch (option) {
     case LBM_OPT_USE_GRAPH: *value = h->use_graph; return LBM_OK;
     case LBM_OPT_STEP_VARIANT: *value = h->variant; return LBM_OK;
     case LBM_OPT_NUM_VARIANTS: *value = kNumVariants; return LBM_OK;
-    default: return fail(LBM_EINVAL, "unknown option %d", option);
+    default: return lbm_fail(LBM_EINVAL, "unknown option %d", option);
   }
 }
 
@@ -405,8 +430,8 @@ static void note_monitor(lbm_cavity *h) {
 }
 
 int lbm_step(lbm_t h, int64_t n) {
-  if (!h) return fail(LBM_EINVAL, "handle is NULL");
-  if (n < 0) return fail(LBM_EINVAL, "n = %lld < 0", (long long)n);
+  if (!h) return lbm_fail(LBM_EINVAL, "handle is NULL");
+  if (n < 0) return lbm_fail(LBM_EINVAL, "n = %lld < 0", (long long)n);
   if (n == 0) return LBM_OK;
   bool monitored = false;
   hipError_t e;
@@ -421,7 +446,7 @@ int lbm_step(lbm_t h, int64_t n) {
         HIPC(hipGraphLaunch(h->graph[h->cur], h->stream));
       } else {
         e = issue_chunk(h, h->cur, h->stream);
-        if (e != hipSuccess) return fail(LBM_EDEVICE, "launch: %s", hipGetErrorString(e));
+        if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "launch: %s", hipGetErrorString(e));
       }
       h->t += kChunk;
       n -= kChunk;
@@ -429,23 +454,23 @@ int lbm_step(lbm_t h, int64_t n) {
       monitored = true;
       if (h->probe_n > 0 && h->probe_every > kChunk && h->t % h->probe_every == 0) {
         e = launch_probe_ring(h, h->buf[h->cur], h->stream);
-        if (e != hipSuccess) return fail(LBM_EDEVICE, "probe: %s", hipGetErrorString(e));
+        if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "probe: %s", hipGetErrorString(e));
       }
       continue;
     }
     // single steps up to the next chunk boundary
     e = launch_step(h, h->buf[h->cur], h->buf[1 - h->cur], h->stream);
-    if (e != hipSuccess) return fail(LBM_EDEVICE, "step launch: %s", hipGetErrorString(e));
+    if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "step launch: %s", hipGetErrorString(e));
     h->cur = 1 - h->cur;
     h->t += 1;
     n -= 1;
     if (h->probe_n > 0 && h->t % h->probe_every == 0) {
       e = launch_probe_ring(h, h->buf[h->cur], h->stream);
-      if (e != hipSuccess) return fail(LBM_EDEVICE, "probe: %s", hipGetErrorString(e));
+      if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "probe: %s", hipGetErrorString(e));
     }
     if (h->t % kChunk == 0) {
       e = launch_monitor(h, h->buf[h->cur], true, h->mon_dev, h->stream);
-      if (e != hipSuccess) return fail(LBM_EDEVICE, "monitor: %s", hipGetErrorString(e));
+      if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "monitor: %s", hipGetErrorString(e));
       note_monitor(h);
       monitored = true;
     }
@@ -460,20 +485,107 @@ int lbm_step(lbm_t h, int64_t n) {
     h->last_mass = (double)h->nx * h->ny + m[0];
     h->last_res = (h->mon_valid && m[2] > 0.0) ? std::sqrt(m[1] / m[2]) : INFINITY;
     if (!std::isfinite(h->last_mass) || std::isnan(h->last_res))
-      return fail(LBM_EUNSTABLE, "non-finite monitor at step %lld (mass %g)",
+      return lbm_fail(LBM_EUNSTABLE, "non-finite monitor at step %lld (mass %g)",
                   (long long)h->t, h->last_mass);
   }
   return LBM_OK;
 }
 
+int lbm_autotune(lbm_t h, int chunks, int use_cache, int *best_variant, double *ms_per_step) {
+  if (!h) return lbm_fail(LBM_EINVAL, "handle is NULL");
+  if (chunks < 1 || chunks > 10000)
+    return lbm_fail(LBM_EINVAL, "chunks = %d outside [1, 10000]", chunks);
+  if (h->t % kChunk != 0) return lbm_fail(LBM_EINVAL, "autotune only at a multiple of 100 steps");
+  const std::string key = tune_key("single", h->dtype, h->nx, h->ny);
+  const int cached = use_cache ? tune_cache_lookup(key) : -1;
+  if (cached >= 0 && cached < kNumVariants) {
+    if (best_variant) *best_variant = cached;
+    if (ms_per_step) *ms_per_step = NAN;
+    return lbm_set_option(h, LBM_OPT_STEP_VARIANT, cached);
+  }
+  const size_t uref_bytes = sizeof(double2) * (size_t)h->nx * h->ny;
+  void *save_f = nullptr, *save_u = nullptr;
+  HIPC(hipStreamSynchronize(h->stream));
+  HIPC(hipMalloc(&save_f, h->buf_bytes));
+  hipError_t e = hipMalloc(&save_u, uref_bytes);
+  if (e != hipSuccess) {
+    (void)hipFree(save_f);
+    return lbm_fail(LBM_ENOMEM, "autotune scratch: %s", hipGetErrorString(e));
+  }
+  const int cur0 = h->cur;
+  auto restore = [&]() -> hipError_t {
+    hipError_t r = hipMemcpyAsync(h->buf[cur0], save_f, h->buf_bytes, hipMemcpyDeviceToDevice,
+                                  h->stream);
+    if (r == hipSuccess)
+      r = hipMemcpyAsync(h->uref, save_u, uref_bytes, hipMemcpyDeviceToDevice, h->stream);
+    return r;
+  };
+  e = hipMemcpyAsync(save_f, h->buf[cur0], h->buf_bytes, hipMemcpyDeviceToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(save_u, h->uref, uref_bytes, hipMemcpyDeviceToDevice, h->stream);
+  const int64_t t0 = h->t, snap0 = h->snap_t, mon0 = h->mon_t;
+  const bool valid0 = h->mon_valid;
+  const double res0 = h->last_res, mass0 = h->last_mass;
+  const int probe_n0 = h->probe_n;
+  h->probe_n = 0;                 // no probe records during the trials
+  drop_graphs(h);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = LBM_OK;
+  double best_ms = INFINITY;
+  int best = h->variant;
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  for (int v = 0; v < kNumVariants && e == hipSuccess && rc == LBM_OK; ++v) {
+    rc = lbm_set_option(h, LBM_OPT_STEP_VARIANT, v);
+    if (rc == LBM_OK) rc = lbm_step(h, kChunk);           // warm-up and capture
+    if (rc != LBM_OK) break;
+    e = hipEventRecord(e0, h->stream);
+    if (e == hipSuccess) rc = lbm_step(h, (int64_t)chunks * kChunk);
+    if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    const double per_step = ms / ((double)chunks * kChunk);
+    if (rc == LBM_OK && e == hipSuccess && per_step < best_ms) {
+      best_ms = per_step;
+      best = v;
+    }
+    h->cur = cur0;
+    if (e == hipSuccess) e = restore();
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  h->cur = cur0;
+  if (e == hipSuccess) e = restore();
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  (void)hipFree(save_f);
+  (void)hipFree(save_u);
+  h->t = t0;
+  h->snap_t = snap0;
+  h->mon_t = mon0;
+  h->mon_valid = valid0;
+  h->last_res = res0;
+  h->last_mass = mass0;
+  h->probe_n = probe_n0;
+  drop_graphs(h);
+  if (rc != LBM_OK) return rc;
+  if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "autotune: %s", hipGetErrorString(e));
+  rc = lbm_set_option(h, LBM_OPT_STEP_VARIANT, best);
+  if (rc) return rc;
+  tune_cache_store(key, best);
+  if (best_variant) *best_variant = best;
+  if (ms_per_step) *ms_per_step = best_ms;
+  return LBM_OK;
+}
+
 int lbm_steps_done(lbm_t h, int64_t *t) {
-  if (!h || !t) return fail(LBM_EINVAL, "NULL argument");
+  if (!h || !t) return lbm_fail(LBM_EINVAL, "NULL argument");
   *t = h->t;
   return LBM_OK;
 }
 
 int lbm_moments_device(lbm_t h, double *rho, double *ux, double *uy) {
-  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!h) return lbm_fail(LBM_EINVAL, "handle is NULL");
   if (h->dtype == LBM_F64) launch_moments_t<double, false>(h, rho, ux, uy);
   else launch_moments_t<float, true>(h, rho, ux, uy);
   HIPC(hipGetLastError());
@@ -482,7 +594,7 @@ int lbm_moments_device(lbm_t h, double *rho, double *ux, double *uy) {
 }
 
 int lbm_moments(lbm_t h, double *rho, double *ux, double *uy) {
-  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!h) return lbm_fail(LBM_EINVAL, "handle is NULL");
   const size_t n = (size_t)h->nx * h->ny;
   int rc = ensure_tmp(h, 3 * n);
   if (rc) return rc;
@@ -501,10 +613,10 @@ int lbm_moments(lbm_t h, double *rho, double *ux, double *uy) {
 }
 
 int lbm_probe(lbm_t h, int npts, const double *xy, double *out) {
-  if (!h || !xy || !out) return fail(LBM_EINVAL, "NULL argument");
-  if (npts < 1 || npts > 4096) return fail(LBM_EINVAL, "npts = %d outside [1, 4096]", npts);
+  if (!h || !xy || !out) return lbm_fail(LBM_EINVAL, "NULL argument");
+  if (npts < 1 || npts > 4096) return lbm_fail(LBM_EINVAL, "npts = %d outside [1, 4096]", npts);
   for (int i = 0; i < 2 * npts; ++i)
-    if (!std::isfinite(xy[i])) return fail(LBM_EINVAL, "probe coordinate %d not finite", i);
+    if (!std::isfinite(xy[i])) return lbm_fail(LBM_EINVAL, "probe coordinate %d not finite", i);
   int rc = ensure_tmp(h, 5 * (size_t)npts);
   if (rc) return rc;
   HIPC(hipMemcpyAsync(h->tmp, xy, 2 * npts * sizeof(double), hipMemcpyHostToDevice,
@@ -524,20 +636,20 @@ int lbm_probe(lbm_t h, int npts, const double *xy, double *out) {
 }
 
 int lbm_probe_config(lbm_t h, int npts, const double *xy, int every, int64_t capacity) {
-  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!h) return lbm_fail(LBM_EINVAL, "handle is NULL");
   HIPC(hipStreamSynchronize(h->stream));
   drop_graphs(h);
   if (npts == 0) {
     h->probe_n = 0;
     return LBM_OK;
   }
-  if (!xy || npts < 0 || npts > 4096) return fail(LBM_EINVAL, "npts = %d outside [1, 4096]", npts);
+  if (!xy || npts < 0 || npts > 4096) return lbm_fail(LBM_EINVAL, "npts = %d outside [1, 4096]", npts);
   if (!probe_every_ok(every))
-    return fail(LBM_EINVAL, "every = %d must divide 100 or be a multiple of 100", every);
+    return lbm_fail(LBM_EINVAL, "every = %d must divide 100 or be a multiple of 100", every);
   if (capacity < 1 || capacity > (1LL << 26))
-    return fail(LBM_EINVAL, "capacity %lld outside [1, 2^26]", (long long)capacity);
+    return lbm_fail(LBM_EINVAL, "capacity %lld outside [1, 2^26]", (long long)capacity);
   for (int i = 0; i < 2 * npts; ++i)
-    if (!std::isfinite(xy[i])) return fail(LBM_EINVAL, "probe coordinate %d not finite", i);
+    if (!std::isfinite(xy[i])) return lbm_fail(LBM_EINVAL, "probe coordinate %d not finite", i);
   if (h->probe_xy) HIPC(hipFree(h->probe_xy));
   if (h->probe_ring) HIPC(hipFree(h->probe_ring));
   if (!h->probe_count) HIPC(hipMalloc(&h->probe_count, sizeof(unsigned long long)));
@@ -557,10 +669,10 @@ int lbm_probe_config(lbm_t h, int npts, const double *xy, int every, int64_t cap
 }
 
 int lbm_probe_read(lbm_t h, double *buf, int64_t max_records, int64_t *n_records) {
-  if (!h || !n_records) return fail(LBM_EINVAL, "NULL argument");
+  if (!h || !n_records) return lbm_fail(LBM_EINVAL, "NULL argument");
   *n_records = 0;
   if (!h->probe_ring || h->probe_n == 0) return LBM_OK;
-  if (max_records > 0 && !buf) return fail(LBM_EINVAL, "buf is NULL");
+  if (max_records > 0 && !buf) return lbm_fail(LBM_EINVAL, "buf is NULL");
   unsigned long long count = 0;
   HIPC(hipStreamSynchronize(h->stream));
   HIPC(hipMemcpy(&count, h->probe_count, sizeof count, hipMemcpyDeviceToHost));
@@ -582,9 +694,9 @@ int lbm_probe_read(lbm_t h, double *buf, int64_t max_records, int64_t *n_records
 }
 
 int lbm_mass(lbm_t h, double *mass) {
-  if (!h || !mass) return fail(LBM_EINVAL, "NULL argument");
+  if (!h || !mass) return lbm_fail(LBM_EINVAL, "NULL argument");
   hipError_t e = launch_monitor(h, h->buf[h->cur], false, h->aux_dev, h->stream);
-  if (e != hipSuccess) return fail(LBM_EDEVICE, "monitor: %s", hipGetErrorString(e));
+  if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "monitor: %s", hipGetErrorString(e));
   HIPC(hipMemcpyAsync(h->mon_host + 4, h->aux_dev, sizeof(double), hipMemcpyDeviceToHost,
                       h->stream));
   HIPC(hipStreamSynchronize(h->stream));
@@ -593,14 +705,14 @@ int lbm_mass(lbm_t h, double *mass) {
 }
 
 int lbm_residual(lbm_t h, double *residual, int64_t *at_step) {
-  if (!h || !residual) return fail(LBM_EINVAL, "NULL argument");
+  if (!h || !residual) return lbm_fail(LBM_EINVAL, "NULL argument");
   *residual = h->mon_t >= 0 ? h->last_res : INFINITY;
   if (at_step) *at_step = h->mon_t;
   return LBM_OK;
 }
 
 int lbm_stream_function(lbm_t h, double *psi) {
-  if (!h || !psi) return fail(LBM_EINVAL, "NULL argument");
+  if (!h || !psi) return lbm_fail(LBM_EINVAL, "NULL argument");
   const size_t n = (size_t)h->nx * h->ny;
   int rc = ensure_tmp(h, n);
   if (rc) return rc;
@@ -617,7 +729,7 @@ int lbm_stream_function(lbm_t h, double *psi) {
 }
 
 int lbm_set_populations(lbm_t h, const double *f) {
-  if (!h || !f) return fail(LBM_EINVAL, "NULL argument");
+  if (!h || !f) return lbm_fail(LBM_EINVAL, "NULL argument");
   const size_t n = (size_t)h->nx * h->ny;
   int rc = ensure_tmp(h, 9 * n);
   if (rc) return rc;
@@ -636,7 +748,7 @@ int lbm_set_populations(lbm_t h, const double *f) {
 }
 
 int lbm_get_populations(lbm_t h, double *f) {
-  if (!h || !f) return fail(LBM_EINVAL, "NULL argument");
+  if (!h || !f) return lbm_fail(LBM_EINVAL, "NULL argument");
   const size_t n = (size_t)h->nx * h->ny;
   int rc = ensure_tmp(h, 9 * n);
   if (rc) return rc;
@@ -654,7 +766,7 @@ int lbm_get_populations(lbm_t h, double *f) {
 
 int lbm_init_fields(lbm_t h, const double *rho, const double *ux, const double *uy,
                     int renormalise_mass) {
-  if (!h) return fail(LBM_EINVAL, "handle is NULL");
+  if (!h) return lbm_fail(LBM_EINVAL, "handle is NULL");
   const size_t n = (size_t)h->nx * h->ny;
   int rc = ensure_tmp(h, 3 * n);
   if (rc) return rc;
@@ -681,7 +793,7 @@ int lbm_init_fields(lbm_t h, const double *rho, const double *ux, const double *
     HIPC(hipStreamSynchronize(h->stream));
     const double total = h->mon_host[4];
     if (!(total > 0.0) || !std::isfinite(total))
-      return fail(LBM_EINVAL, "sum of rho = %g cannot be renormalised", total);
+      return lbm_fail(LBM_EINVAL, "sum of rho = %g cannot be renormalised", total);
     scale = (double)n / total;
   }
   const int tot = h->pitch * h->ny;
@@ -710,7 +822,7 @@ struct CkptHeader {
 };
 
 int lbm_save(lbm_t h, const char *path) {
-  if (!h || !path) return fail(LBM_EINVAL, "NULL argument");
+  if (!h || !path) return lbm_fail(LBM_EINVAL, "NULL argument");
   CkptHeader hd;
   std::memset(&hd, 0, sizeof hd);
   std::memcpy(hd.magic, "LBMD2Q9", 8);
@@ -733,30 +845,30 @@ int lbm_save(lbm_t h, const char *path) {
   HIPC(hipMemcpy(a.data(), h->buf[h->cur], hd.buf_bytes, hipMemcpyDeviceToHost));
   HIPC(hipMemcpy(b.data(), h->uref, hd.uref_bytes, hipMemcpyDeviceToHost));
   FILE *fp = std::fopen(path, "wb");
-  if (!fp) return fail(LBM_EIO, "cannot open %s for writing", path);
+  if (!fp) return lbm_fail(LBM_EIO, "cannot open %s for writing", path);
   bool ok = std::fwrite(&hd, sizeof hd, 1, fp) == 1 &&
             std::fwrite(a.data(), 1, a.size(), fp) == a.size() &&
             std::fwrite(b.data(), 1, b.size(), fp) == b.size();
   ok = (std::fclose(fp) == 0) && ok;
-  if (!ok) return fail(LBM_EIO, "short write to %s", path);
+  if (!ok) return lbm_fail(LBM_EIO, "short write to %s", path);
   return LBM_OK;
 }
 
 int lbm_load(lbm_t h, const char *path) {
-  if (!h || !path) return fail(LBM_EINVAL, "NULL argument");
+  if (!h || !path) return lbm_fail(LBM_EINVAL, "NULL argument");
   FILE *fp = std::fopen(path, "rb");
-  if (!fp) return fail(LBM_EIO, "cannot open %s", path);
+  if (!fp) return lbm_fail(LBM_EIO, "cannot open %s", path);
   CkptHeader hd;
   if (std::fread(&hd, sizeof hd, 1, fp) != 1 || std::memcmp(hd.magic, "LBMD2Q9", 8) != 0 ||
       hd.version != 1) {
     std::fclose(fp);
-    return fail(LBM_EIO, "%s is not a checkpoint of this library", path);
+    return lbm_fail(LBM_EIO, "%s is not a checkpoint of this library", path);
   }
   if (hd.nx != h->nx || hd.ny != h->ny || hd.pitch != h->pitch || hd.dtype != h->dtype ||
       hd.buf_bytes != h->buf_bytes ||
       hd.uref_bytes != sizeof(double2) * (size_t)h->nx * h->ny) {
     std::fclose(fp);
-    return fail(LBM_ESTATE, "checkpoint lattice %dx%d dtype %d does not match the handle",
+    return lbm_fail(LBM_ESTATE, "checkpoint lattice %dx%d dtype %d does not match the handle",
                 hd.nx, hd.ny, hd.dtype);
   }
   std::vector<char> a(hd.buf_bytes), b(hd.uref_bytes);
@@ -765,7 +877,7 @@ int lbm_load(lbm_t h, const char *path) {
   char extra;
   const bool tail = std::fread(&extra, 1, 1, fp) == 0;
   std::fclose(fp);
-  if (!ok || !tail) return fail(LBM_EIO, "%s is truncated or has trailing bytes", path);
+  if (!ok || !tail) return lbm_fail(LBM_EIO, "%s is truncated or has trailing bytes", path);
   HIPC(hipStreamSynchronize(h->stream));
   HIPC(hipMemcpy(h->buf[h->cur], a.data(), a.size(), hipMemcpyHostToDevice));
   HIPC(hipMemcpy(h->uref, b.data(), b.size(), hipMemcpyHostToDevice));

@@ -1,0 +1,783 @@
+// lbm_batch.hip -- batched sweep of uneven cavities and the tile-shape
+// autotuner (contracts in include/lbm.h).
+//
+// A batch owns one pair of buffers holding every cavity.  One kernel launch
+// advances all active cavities by one step (k_step_batch over a tile table);
+// a chunk of `graph_steps` steps (default 1000, a multiple of the 100-step
+// monitor cadence) with the per-cavity FP64 monitors after every 100 steps is
+// captured once into a HIP graph and replayed.  Cavities whose Eq. 6
+// residual falls below a threshold drop out of the tile table at a chunk
+// boundary.  Chunk boundaries are reached at even step counts only, so the
+// current buffer of every cavity, active or not, is buf[0] there.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "d2q9_batch.hpp"
+#include "d2q9_monitor.hpp"
+#include "d2q9_step.hpp"
+#include "lbm_internal.h"
+
+using namespace lbm;
+
+struct lbm_batch {
+  int n = 0, dtype = 0;
+  double u_lid = 0;
+  std::vector<int> nx, ny, pitch, plane, base, uref_off;
+  std::vector<double> re, tau;
+  size_t elems = 0, buf_bytes = 0;
+  void *buf[2] = {nullptr, nullptr};
+  int cur = 0;
+  void *desc = nullptr;                 // CavityDesc<T>[n]
+  int4 *tiles = nullptr;                // step tiles of active cavities
+  int ntiles = 0, tiles_cap = 0;
+  int4 *mtiles = nullptr;               // 64 x 4 monitor tiles of active cavities
+  int nmtiles = 0, mtiles_cap = 0;
+  int *fin = nullptr;                   // [3][n]: first, count, cavity
+  int nfin = 0;
+  double2 *uref = nullptr;
+  double *partials = nullptr;           // max(total monitor tiles, kRedBlocks) x 3
+  double *mon_dev = nullptr;            // [n][3] chunk monitors
+  double *aux_dev = nullptr;            // on-demand reductions
+  double *mon_host = nullptr;           // pinned [n][3] + 4
+  double *tmp = nullptr;
+  size_t tmp_doubles = 0;
+  std::vector<char> active;
+  std::vector<int64_t> t, snap_t, mon_t;
+  std::vector<char> mon_valid;
+  std::vector<double> last_res, last_mass;
+  int64_t t_global = 0;
+  double threshold = 0.0;
+  int variant = 0, use_graph = 1, graph_steps = 1000;
+  hipStream_t stream = nullptr, own_stream = nullptr, cap_stream = nullptr;
+  hipGraphExec_t graph = nullptr;
+  bool tables_dirty = true;
+};
+
+namespace {
+
+struct Shape {
+  int by, ry;
+};
+const Shape kShapes[] = {{4, 1}, {4, 2}, {4, 4}, {8, 1}, {2, 4}, {1, 8}, {8, 2}, {16, 1}};
+const int kNumShapes = 8;
+
+template <typename T, bool S, int BY, int RY>
+hipError_t launch_b(const lbm_batch *b, const void *src, void *dst, hipStream_t st) {
+  hipLaunchKernelGGL((k_step_batch<T, S, BY, RY>), dim3(b->ntiles), dim3(64, BY), 0, st,
+                     (const T *)src, (T *)dst, (const CavityDesc<T> *)b->desc,
+                     (const int4 *)b->tiles);
+  return hipGetLastError();
+}
+
+template <typename T, bool S>
+hipError_t launch_b_variant(const lbm_batch *b, const void *src, void *dst, hipStream_t st) {
+  switch (b->variant) {
+    case 0: return launch_b<T, S, 4, 1>(b, src, dst, st);
+    case 1: return launch_b<T, S, 4, 2>(b, src, dst, st);
+    case 2: return launch_b<T, S, 4, 4>(b, src, dst, st);
+    case 3: return launch_b<T, S, 8, 1>(b, src, dst, st);
+    case 4: return launch_b<T, S, 2, 4>(b, src, dst, st);
+    case 5: return launch_b<T, S, 1, 8>(b, src, dst, st);
+    case 6: return launch_b<T, S, 8, 2>(b, src, dst, st);
+    default: return launch_b<T, S, 16, 1>(b, src, dst, st);
+  }
+}
+
+hipError_t batch_step(const lbm_batch *b, int from, hipStream_t st) {
+  if (b->ntiles == 0) return hipSuccess;
+  if (b->dtype == LBM_F64)
+    return launch_b_variant<double, false>(b, b->buf[from], b->buf[1 - from], st);
+  return launch_b_variant<float, true>(b, b->buf[from], b->buf[1 - from], st);
+}
+
+template <typename T, bool S>
+hipError_t batch_monitor_t(const lbm_batch *b, int from, hipStream_t st) {
+  hipLaunchKernelGGL((k_monitor_batch<T, S, true>), dim3(b->nmtiles), dim3(256), 0, st,
+                     (const T *)b->buf[from], (const CavityDesc<T> *)b->desc,
+                     (const int4 *)b->mtiles, b->uref, b->partials);
+  hipLaunchKernelGGL(k_finalize_batch, dim3(b->nfin), dim3(kRedThreads), 0, st, b->partials,
+                     b->fin, b->fin + b->n, b->fin + 2 * b->n, b->mon_dev);
+  return hipGetLastError();
+}
+
+hipError_t batch_monitor(const lbm_batch *b, int from, hipStream_t st) {
+  if (b->nmtiles == 0) return hipSuccess;
+  if (b->dtype == LBM_F64) return batch_monitor_t<double, false>(b, from, st);
+  return batch_monitor_t<float, true>(b, from, st);
+}
+
+bool valid_k(const lbm_batch *b, int k) { return b && k >= 0 && k < b->n; }
+
+// Buffer holding cavity k now: active cavities follow the global parity;
+// inactive ones stopped at a chunk boundary, where the parity is 0.
+int cbuf(const lbm_batch *b, int k) { return b->active[k] ? b->cur : 0; }
+
+Geometry cav_geom(const lbm_batch *b, int k) {
+  Geometry g;
+  g.nx = b->nx[k];
+  g.ny = b->ny[k];
+  g.pitch = b->pitch[k];
+  g.plane = b->plane[k];
+  return g;
+}
+
+void drop_graph(lbm_batch *b) {
+  if (b->graph) (void)hipGraphExecDestroy(b->graph);
+  b->graph = nullptr;
+}
+
+// Rebuild the step / monitor tile tables for the active cavities.
+int rebuild_tables(lbm_batch *b) {
+  const Shape sh = kShapes[b->variant];
+  std::vector<int4> st, mt;
+  std::vector<int> first(b->n, 0), count(b->n, 0), cav(b->n, 0);
+  int nfin = 0;
+  for (int c = 0; c < b->n; ++c) {
+    if (!b->active[c]) continue;
+    const int tx = (b->nx[c] + 63) / 64;
+    const int ty = (b->ny[c] + sh.by * sh.ry - 1) / (sh.by * sh.ry);
+    for (int y = 0; y < ty; ++y)
+      for (int x = 0; x < tx; ++x) st.push_back(make_int4(c, x, y, 0));
+    const int my = (b->ny[c] + 3) / 4;
+    first[nfin] = (int)mt.size();
+    for (int y = 0; y < my; ++y)
+      for (int x = 0; x < tx; ++x) mt.push_back(make_int4(c, x, y, 0));
+    count[nfin] = (int)mt.size() - first[nfin];
+    cav[nfin] = c;
+    ++nfin;
+  }
+  HIPC(hipStreamSynchronize(b->stream));
+  if ((int)st.size() > b->tiles_cap) {
+    if (b->tiles) HIPC(hipFree(b->tiles));
+    b->tiles = nullptr;
+    HIPC(hipMalloc(&b->tiles, st.size() * sizeof(int4)));
+    b->tiles_cap = (int)st.size();
+  }
+  if ((int)mt.size() > b->mtiles_cap) {
+    if (b->mtiles) HIPC(hipFree(b->mtiles));
+    b->mtiles = nullptr;
+    HIPC(hipMalloc(&b->mtiles, mt.size() * sizeof(int4)));
+    b->mtiles_cap = (int)mt.size();
+  }
+  if (!st.empty())
+    HIPC(hipMemcpy(b->tiles, st.data(), st.size() * sizeof(int4), hipMemcpyHostToDevice));
+  if (!mt.empty())
+    HIPC(hipMemcpy(b->mtiles, mt.data(), mt.size() * sizeof(int4), hipMemcpyHostToDevice));
+  std::vector<int> packed(3 * b->n, 0);
+  std::copy(first.begin(), first.end(), packed.begin());
+  std::copy(count.begin(), count.end(), packed.begin() + b->n);
+  std::copy(cav.begin(), cav.end(), packed.begin() + 2 * b->n);
+  HIPC(hipMemcpy(b->fin, packed.data(), packed.size() * sizeof(int), hipMemcpyHostToDevice));
+  b->ntiles = (int)st.size();
+  b->nmtiles = (int)mt.size();
+  b->nfin = nfin;
+  b->tables_dirty = false;
+  drop_graph(b);
+  return LBM_OK;
+}
+
+hipError_t issue_chunk(lbm_batch *b, hipStream_t st) {
+  int cur = 0;
+  for (int k = 1; k <= b->graph_steps; ++k) {
+    hipError_t e = batch_step(b, cur, st);
+    if (e != hipSuccess) return e;
+    cur = 1 - cur;
+    if (k % kChunk == 0) {
+      e = batch_monitor(b, cur, st);
+      if (e != hipSuccess) return e;
+    }
+  }
+  return hipSuccess;
+}
+
+int build_graph(lbm_batch *b) {
+  hipGraph_t g = nullptr;
+  HIPC(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t e = issue_chunk(b, b->cap_stream);
+  hipError_t e2 = hipStreamEndCapture(b->cap_stream, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return lbm_fail(LBM_EDEVICE, "batch graph capture failed: %s",
+                    hipGetErrorString(e != hipSuccess ? e : e2));
+  }
+  e = hipGraphInstantiate(&b->graph, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    b->graph = nullptr;
+    return lbm_fail(LBM_EDEVICE, "hipGraphInstantiate: %s", hipGetErrorString(e));
+  }
+  return LBM_OK;
+}
+
+void note_monitor(lbm_batch *b) {
+  for (int c = 0; c < b->n; ++c) {
+    if (!b->active[c]) continue;
+    b->mon_valid[c] = (b->snap_t[c] == b->t[c] - kChunk);
+    b->snap_t[c] = b->t[c];
+    b->mon_t[c] = b->t[c];
+  }
+}
+
+// Copy the chunk monitors to the host and update masses / residuals; drop
+// converged cavities when a threshold is set.
+int read_monitors(lbm_batch *b, bool *changed) {
+  *changed = false;
+  HIPC(hipMemcpyAsync(b->mon_host, b->mon_dev, 3 * b->n * sizeof(double),
+                      hipMemcpyDeviceToHost, b->stream));
+  HIPC(hipStreamSynchronize(b->stream));
+  int bad = -1;
+  for (int c = 0; c < b->n; ++c) {
+    if (b->mon_t[c] < 0) continue;
+    const double *m = b->mon_host + 3 * c;
+    b->last_mass[c] = (double)b->nx[c] * b->ny[c] + m[0];
+    b->last_res[c] = (b->mon_valid[c] && m[2] > 0.0) ? std::sqrt(m[1] / m[2]) : INFINITY;
+    if ((!std::isfinite(b->last_mass[c]) || std::isnan(b->last_res[c])) && bad < 0) bad = c;
+    if (b->active[c] && b->threshold > 0.0 && b->mon_valid[c] &&
+        b->last_res[c] < b->threshold) {
+      b->active[c] = 0;
+      *changed = true;
+    }
+  }
+  if (bad >= 0)
+    return lbm_fail(LBM_EUNSTABLE, "non-finite monitor in cavity %d (%d x %d, tau %.6g) at step %lld",
+                    bad, b->nx[bad], b->ny[bad], b->tau[bad], (long long)b->t[bad]);
+  return LBM_OK;
+}
+
+template <typename T, bool S>
+void launch_init_eq(lbm_batch *b, int k, const double *r, const double *u, const double *v,
+                    double scale) {
+  const Geometry g = cav_geom(b, k);
+  const int tot = g.pitch * g.ny;
+  hipLaunchKernelGGL((k_init_eq<T, S>), dim3((tot + 255) / 256), dim3(256), 0, b->stream,
+                     (T *)b->buf[cbuf(b, k)] + b->base[k], g, r, u, v, scale);
+}
+
+template <typename T, bool S>
+void launch_ref_monitor(lbm_batch *b, int k, bool update) {
+  const Geometry g = cav_geom(b, k);
+  const int n = g.nx * g.ny;
+  const int blocks = std::min(kRedBlocks, (n + kRedThreads - 1) / kRedThreads);
+  const T *src = (const T *)b->buf[cbuf(b, k)] + b->base[k];
+  if (update)
+    hipLaunchKernelGGL((k_monitor<T, S, true>), dim3(blocks), dim3(kRedThreads), 0, b->stream,
+                       src, g, b->uref + b->uref_off[k], b->partials);
+  else
+    hipLaunchKernelGGL((k_monitor<T, S, false>), dim3(blocks), dim3(kRedThreads), 0,
+                       b->stream, src, g, b->uref + b->uref_off[k], b->partials);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedThreads), 0, b->stream, b->partials, blocks,
+                     b->aux_dev);
+}
+
+int reset_cavity(lbm_batch *b, int k) {
+  b->t[k] = 0;
+  b->snap_t[k] = 0;
+  b->mon_t[k] = -1;
+  b->last_res[k] = INFINITY;
+  if (b->dtype == LBM_F64) launch_ref_monitor<double, false>(b, k, true);
+  else launch_ref_monitor<float, true>(b, k, true);
+  HIPC(hipGetLastError());
+  return LBM_OK;
+}
+
+int ensure_tmp(lbm_batch *b, size_t doubles) {
+  if (b->tmp_doubles >= doubles) return LBM_OK;
+  if (b->tmp) HIPC(hipFree(b->tmp));
+  b->tmp = nullptr;
+  b->tmp_doubles = 0;
+  HIPC(hipMalloc(&b->tmp, doubles * sizeof(double)));
+  b->tmp_doubles = doubles;
+  return LBM_OK;
+}
+
+template <typename T>
+int upload_desc(lbm_batch *b) {
+  std::vector<CavityDesc<T>> d(b->n);
+  for (int c = 0; c < b->n; ++c) {
+    d[c].base = b->base[c];
+    d[c].nx = b->nx[c];
+    d[c].ny = b->ny[c];
+    d[c].pitch = b->pitch[c];
+    d[c].plane = b->plane[c];
+    d[c].uref_off = b->uref_off[c];
+    d[c].omega = (T)(1.0 / b->tau[c]);
+    d[c].u6 = (T)(b->u_lid / 6.0);
+  }
+  HIPC(hipMalloc(&b->desc, b->n * sizeof(CavityDesc<T>)));
+  HIPC(hipMemcpy(b->desc, d.data(), b->n * sizeof(CavityDesc<T>), hipMemcpyHostToDevice));
+  return LBM_OK;
+}
+
+
+
+}  // namespace
+
+extern "C" {
+
+int lbm_batch_destroy(lbm_batch_t b) {
+  if (!b) return LBM_OK;
+  drop_graph(b);
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  void *ptrs[] = {b->buf[0], b->buf[1], b->desc, b->tiles, b->mtiles, b->fin,
+                  b->uref, b->partials, b->mon_dev, b->aux_dev, b->tmp};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  if (b->mon_host) (void)hipHostFree(b->mon_host);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  if (b->own_stream) (void)hipStreamDestroy(b->own_stream);
+  delete b;
+  return LBM_OK;
+}
+
+int lbm_batch_create(int n, const int *nx, const int *ny, const double *re, double u_lid,
+                     int dtype, lbm_batch_t *out) {
+  if (!out) return lbm_fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (n < 1 || n > 4096 || !nx || !ny || !re)
+    return lbm_fail(LBM_EINVAL, "n = %d outside [1, 4096] or NULL arrays", n);
+  if (dtype != LBM_F64 && dtype != LBM_F32_SHIFTED)
+    return lbm_fail(LBM_EINVAL, "unknown dtype %d", dtype);
+  if (!std::isfinite(u_lid) || std::fabs(u_lid) >= 1.0 / std::sqrt(3.0))
+    return lbm_fail(LBM_EINVAL, "|u_lid| = %g must be below 1/sqrt(3)", u_lid);
+  lbm_batch *b = new (std::nothrow) lbm_batch();
+  if (!b) return lbm_fail(LBM_ENOMEM, "host allocation");
+  auto bail = [&](int code) {
+    lbm_batch_destroy(b);
+    return code;
+  };
+  b->n = n;
+  b->dtype = dtype;
+  b->u_lid = u_lid;
+  long long elems = 0, sites = 0, mt_total = 0;
+  for (int c = 0; c < n; ++c) {
+    if (nx[c] < 2 || ny[c] < 2 || nx[c] > 65536 || ny[c] > 65536)
+      return bail(lbm_fail(LBM_EINVAL, "cavity %d: lattice %d x %d outside [2, 65536]", c,
+                           nx[c], ny[c]));
+    if (!(re[c] > 0.0) || !std::isfinite(re[c]))
+      return bail(lbm_fail(LBM_EINVAL, "cavity %d: re = %g", c, re[c]));
+    const double tau = 3.0 * u_lid * nx[c] / re[c] + 0.5;   // Eq. 5, nu = U L / Re
+    if (!(tau > 0.5)) return bail(lbm_fail(LBM_EINVAL, "cavity %d: tau = %g <= 1/2", c, tau));
+    const int p = (nx[c] + 63) / 64 * 64;
+    b->nx.push_back(nx[c]);
+    b->ny.push_back(ny[c]);
+    b->pitch.push_back(p);
+    b->plane.push_back(p * ny[c]);
+    b->base.push_back((int)std::min<long long>(elems, INT32_MAX));
+    b->uref_off.push_back((int)std::min<long long>(sites, INT32_MAX));
+    b->re.push_back(re[c]);
+    b->tau.push_back(tau);
+    elems += 9LL * p * ny[c];
+    sites += (long long)nx[c] * ny[c];
+    mt_total += (long long)((nx[c] + 63) / 64) * ((ny[c] + 3) / 4);
+  }
+  if (elems >= (1LL << 31) || sites >= (1LL << 31))
+    return bail(lbm_fail(LBM_EINVAL, "batch too large for 32-bit element offsets"));
+  b->elems = (size_t)elems;
+  const size_t esz = dtype == LBM_F64 ? 8 : 4;
+  b->buf_bytes = b->elems * esz;
+  b->active.assign(n, 1);
+  b->t.assign(n, 0);
+  b->snap_t.assign(n, 0);
+  b->mon_t.assign(n, -1);
+  b->mon_valid.assign(n, 0);
+  b->last_res.assign(n, INFINITY);
+  b->last_mass.assign(n, NAN);
+  hipError_t e;
+#define TRY(call)                                                                     \
+  do {                                                                                \
+    e = (call);                                                                       \
+    if (e != hipSuccess)                                                              \
+      return bail(lbm_fail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE,       \
+                           "%s failed: %s", #call, hipGetErrorString(e)));            \
+  } while (0)
+  TRY(hipStreamCreateWithFlags(&b->own_stream, hipStreamNonBlocking));
+  b->stream = b->own_stream;
+  TRY(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+  for (int c = 0; c < 2; ++c) {
+    TRY(hipMalloc(&b->buf[c], b->buf_bytes));
+    TRY(hipMemsetAsync(b->buf[c], 0, b->buf_bytes, b->stream));
+  }
+  TRY(hipMalloc(&b->uref, sizeof(double2) * (size_t)sites));
+  TRY(hipMalloc(&b->partials,
+                sizeof(double) * kNumSums * (size_t)std::max<long long>(mt_total, kRedBlocks)));
+  TRY(hipMalloc(&b->mon_dev, sizeof(double) * kNumSums * n));
+  TRY(hipMemsetAsync(b->mon_dev, 0, sizeof(double) * kNumSums * n, b->stream));
+  TRY(hipMalloc(&b->aux_dev, sizeof(double) * 4));
+  TRY(hipMalloc(&b->fin, sizeof(int) * 3 * n));
+  TRY(hipHostMalloc(&b->mon_host, sizeof(double) * (kNumSums * n + 4), hipHostMallocDefault));
+#undef TRY
+  int rc = dtype == LBM_F64 ? upload_desc<double>(b) : upload_desc<float>(b);
+  if (rc) return bail(rc);
+  for (int c = 0; c < n; ++c) {
+    if (dtype == LBM_F64) launch_init_eq<double, false>(b, c, nullptr, nullptr, nullptr, 1.0);
+    else launch_init_eq<float, true>(b, c, nullptr, nullptr, nullptr, 1.0);
+    rc = reset_cavity(b, c);
+    if (rc) return bail(rc);
+  }
+  rc = rebuild_tables(b);
+  if (rc) return bail(rc);
+  e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess)
+    return bail(lbm_fail(LBM_EDEVICE, "hipStreamSynchronize: %s", hipGetErrorString(e)));
+  *out = b;
+  return LBM_OK;
+}
+
+int lbm_batch_set_stream(lbm_batch_t b, void *hip_stream) {
+  if (!b) return lbm_fail(LBM_EINVAL, "batch is NULL");
+  HIPC(hipStreamSynchronize(b->stream));
+  b->stream = hip_stream ? (hipStream_t)hip_stream : b->own_stream;
+  return LBM_OK;
+}
+
+int lbm_batch_set_option(lbm_batch_t b, int option, int64_t value) {
+  if (!b) return lbm_fail(LBM_EINVAL, "batch is NULL");
+  switch (option) {
+    case LBM_OPT_USE_GRAPH:
+      b->use_graph = value ? 1 : 0;
+      return LBM_OK;
+    case LBM_OPT_STEP_VARIANT:
+      if (value < 0 || value >= kNumShapes)
+        return lbm_fail(LBM_EINVAL, "variant %lld outside [0, %d)", (long long)value, kNumShapes);
+      if (b->variant != (int)value) {
+        b->variant = (int)value;
+        b->tables_dirty = true;
+        drop_graph(b);
+      }
+      return LBM_OK;
+    case LBM_OPT_GRAPH_STEPS:
+      if (value < kChunk || value > 100000 || value % kChunk != 0)
+        return lbm_fail(LBM_EINVAL, "graph steps %lld must be a multiple of 100 in [100, 1e5]",
+                        (long long)value);
+      if (b->graph_steps != (int)value) drop_graph(b);
+      b->graph_steps = (int)value;
+      return LBM_OK;
+    default:
+      return lbm_fail(LBM_EINVAL, "unknown option %d", option);
+  }
+}
+
+int lbm_batch_get_option(lbm_batch_t b, int option, int64_t *value) {
+  if (!b || !value) return lbm_fail(LBM_EINVAL, "NULL argument");
+  switch (option) {
+    case LBM_OPT_USE_GRAPH: *value = b->use_graph; return LBM_OK;
+    case LBM_OPT_STEP_VARIANT: *value = b->variant; return LBM_OK;
+    case LBM_OPT_NUM_VARIANTS: *value = kNumShapes; return LBM_OK;
+    case LBM_OPT_GRAPH_STEPS: *value = b->graph_steps; return LBM_OK;
+    default: return lbm_fail(LBM_EINVAL, "unknown option %d", option);
+  }
+}
+
+int lbm_batch_set_threshold(lbm_batch_t b, double residual) {
+  if (!b) return lbm_fail(LBM_EINVAL, "batch is NULL");
+  if (!(residual >= 0.0) || !std::isfinite(residual))
+    return lbm_fail(LBM_EINVAL, "threshold %g must be finite and >= 0", residual);
+  b->threshold = residual;
+  return LBM_OK;
+}
+
+int lbm_batch_set_active(lbm_batch_t b, int k, int active) {
+  if (!valid_k(b, k)) return lbm_fail(LBM_EINVAL, "cavity index %d out of range", k);
+  if (b->t_global % kChunk != 0)
+    return lbm_fail(LBM_EINVAL, "activity can change only at multiples of 100 steps (now %lld)",
+                    (long long)b->t_global);
+  if ((b->active[k] != 0) != (active != 0)) {
+    b->active[k] = active ? 1 : 0;
+    b->tables_dirty = true;
+  }
+  return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch_t b, int64_t n) {
+  if (!b) return lbm_fail(LBM_EINVAL, "batch is NULL");
+  if (n < 0) return lbm_fail(LBM_EINVAL, "n = %lld < 0", (long long)n);
+  bool monitored = false;
+  while (n > 0) {
+    if (b->tables_dirty) {
+      int rc = rebuild_tables(b);
+      if (rc) return rc;
+    }
+    if (b->ntiles == 0) break;       // every cavity inactive
+    const bool aligned = b->t_global % kChunk == 0;
+    if (aligned && b->use_graph && n >= b->graph_steps) {
+      if (!b->graph) {
+        int rc = build_graph(b);
+        if (rc) return rc;
+      }
+      HIPC(hipGraphLaunch(b->graph, b->stream));
+      for (int k = 0; k < b->graph_steps / kChunk; ++k) {
+        for (int c = 0; c < b->n; ++c)
+          if (b->active[c]) b->t[c] += kChunk;
+        b->t_global += kChunk;
+        note_monitor(b);
+      }
+      n -= b->graph_steps;
+      monitored = true;
+    } else {
+      hipError_t e = batch_step(b, b->cur, b->stream);
+      if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "batch step: %s", hipGetErrorString(e));
+      b->cur = 1 - b->cur;
+      for (int c = 0; c < b->n; ++c)
+        if (b->active[c]) b->t[c] += 1;
+      b->t_global += 1;
+      n -= 1;
+      if (b->t_global % kChunk == 0) {
+        e = batch_monitor(b, b->cur, b->stream);
+        if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "monitor: %s", hipGetErrorString(e));
+        note_monitor(b);
+        monitored = true;
+      }
+    }
+    if (monitored && b->threshold > 0.0 && b->t_global % kChunk == 0) {
+      bool changed = false;
+      int rc = read_monitors(b, &changed);
+      monitored = false;
+      if (rc) return rc;
+      if (changed) b->tables_dirty = true;
+    }
+  }
+  if (monitored) {
+    bool changed = false;
+    int rc = read_monitors(b, &changed);
+    if (rc) return rc;
+    if (changed) b->tables_dirty = true;
+  }
+  HIPC(hipStreamSynchronize(b->stream));
+  return LBM_OK;
+}
+
+int lbm_batch_status(lbm_batch_t b, int k, int64_t *steps_done, double *residual,
+                     int64_t *residual_step, int *active) {
+  if (!valid_k(b, k)) return lbm_fail(LBM_EINVAL, "cavity index %d out of range", k);
+  if (steps_done) *steps_done = b->t[k];
+  if (residual) *residual = b->mon_t[k] >= 0 ? b->last_res[k] : INFINITY;
+  if (residual_step) *residual_step = b->mon_t[k];
+  if (active) *active = b->active[k];
+  return LBM_OK;
+}
+
+int lbm_batch_mass(lbm_batch_t b, int k, double *mass) {
+  if (!valid_k(b, k) || !mass) return lbm_fail(LBM_EINVAL, "bad cavity index or NULL");
+  if (b->dtype == LBM_F64) launch_ref_monitor<double, false>(b, k, false);
+  else launch_ref_monitor<float, true>(b, k, false);
+  HIPC(hipGetLastError());
+  HIPC(hipMemcpyAsync(b->mon_host + kNumSums * b->n, b->aux_dev, sizeof(double),
+                      hipMemcpyDeviceToHost, b->stream));
+  HIPC(hipStreamSynchronize(b->stream));
+  *mass = (double)b->nx[k] * b->ny[k] + b->mon_host[kNumSums * b->n];
+  return LBM_OK;
+}
+
+int lbm_batch_moments(lbm_batch_t b, int k, double *rho, double *ux, double *uy) {
+  if (!valid_k(b, k)) return lbm_fail(LBM_EINVAL, "cavity index %d out of range", k);
+  const Geometry g = cav_geom(b, k);
+  const size_t n = (size_t)g.nx * g.ny;
+  int rc = ensure_tmp(b, 3 * n);
+  if (rc) return rc;
+  double *d[3] = {rho ? b->tmp : nullptr, ux ? b->tmp + n : nullptr, uy ? b->tmp + 2 * n : nullptr};
+  if (b->dtype == LBM_F64)
+    hipLaunchKernelGGL((k_moments<double, false>), dim3((n + 255) / 256), dim3(256), 0,
+                       b->stream, (const double *)b->buf[cbuf(b, k)] + b->base[k], g, d[0], d[1], d[2]);
+  else
+    hipLaunchKernelGGL((k_moments<float, true>), dim3((n + 255) / 256), dim3(256), 0, b->stream,
+                       (const float *)b->buf[cbuf(b, k)] + b->base[k], g, d[0], d[1], d[2]);
+  HIPC(hipGetLastError());
+  double *outs[3] = {rho, ux, uy};
+  for (int j = 0; j < 3; ++j)
+    if (outs[j])
+      HIPC(hipMemcpyAsync(outs[j], d[j], n * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+  HIPC(hipStreamSynchronize(b->stream));
+  return LBM_OK;
+}
+
+int lbm_batch_get_populations(lbm_batch_t b, int k, double *f) {
+  if (!valid_k(b, k) || !f) return lbm_fail(LBM_EINVAL, "bad cavity index or NULL");
+  const Geometry g = cav_geom(b, k);
+  const size_t n = (size_t)g.nx * g.ny;
+  int rc = ensure_tmp(b, 9 * n);
+  if (rc) return rc;
+  if (b->dtype == LBM_F64)
+    hipLaunchKernelGGL((k_get_pop<double, false>), dim3((n + 255) / 256), dim3(256), 0,
+                       b->stream, (const double *)b->buf[cbuf(b, k)] + b->base[k], g, b->tmp);
+  else
+    hipLaunchKernelGGL((k_get_pop<float, true>), dim3((n + 255) / 256), dim3(256), 0,
+                       b->stream, (const float *)b->buf[cbuf(b, k)] + b->base[k], g, b->tmp);
+  HIPC(hipGetLastError());
+  HIPC(hipMemcpyAsync(f, b->tmp, 9 * n * sizeof(double), hipMemcpyDeviceToHost, b->stream));
+  HIPC(hipStreamSynchronize(b->stream));
+  return LBM_OK;
+}
+
+int lbm_batch_set_populations(lbm_batch_t b, int k, const double *f) {
+  if (!valid_k(b, k) || !f) return lbm_fail(LBM_EINVAL, "bad cavity index or NULL");
+  const Geometry g = cav_geom(b, k);
+  const size_t n = (size_t)g.nx * g.ny;
+  int rc = ensure_tmp(b, 9 * n);
+  if (rc) return rc;
+  HIPC(hipMemcpyAsync(b->tmp, f, 9 * n * sizeof(double), hipMemcpyHostToDevice, b->stream));
+  const double omega = 1.0 / b->tau[k];
+  if (b->dtype == LBM_F64)
+    hipLaunchKernelGGL((k_set_pop<double, false>), dim3((n + 255) / 256), dim3(256), 0,
+                       b->stream, (double *)b->buf[cbuf(b, k)] + b->base[k], g, b->tmp, omega);
+  else
+    hipLaunchKernelGGL((k_set_pop<float, true>), dim3((n + 255) / 256), dim3(256), 0, b->stream,
+                       (float *)b->buf[cbuf(b, k)] + b->base[k], g, b->tmp, omega);
+  HIPC(hipGetLastError());
+  rc = reset_cavity(b, k);
+  if (rc) return rc;
+  HIPC(hipStreamSynchronize(b->stream));
+  return LBM_OK;
+}
+
+int lbm_batch_init_fields(lbm_batch_t b, int k, const double *rho, const double *ux,
+                          const double *uy, int renormalise_mass) {
+  if (!valid_k(b, k)) return lbm_fail(LBM_EINVAL, "cavity index %d out of range", k);
+  const Geometry g = cav_geom(b, k);
+  const size_t n = (size_t)g.nx * g.ny;
+  int rc = ensure_tmp(b, 3 * n);
+  if (rc) return rc;
+  const double *src[3] = {rho, ux, uy};
+  double *d[3] = {nullptr, nullptr, nullptr};
+  for (int j = 0; j < 3; ++j)
+    if (src[j]) {
+      d[j] = b->tmp + j * n;
+      HIPC(hipMemcpyAsync(d[j], src[j], n * sizeof(double), hipMemcpyHostToDevice, b->stream));
+    }
+  double scale = 1.0;
+  if (renormalise_mass && rho) {
+    const int blocks = std::min(kRedBlocks, (int)((n + kRedThreads - 1) / kRedThreads));
+    hipLaunchKernelGGL(k_sum_dense, dim3(blocks), dim3(kRedThreads), 0, b->stream, d[0],
+                       (long long)n, b->partials);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedThreads), 0, b->stream, b->partials, blocks,
+                       b->aux_dev);
+    HIPC(hipGetLastError());
+    HIPC(hipMemcpyAsync(b->mon_host + kNumSums * b->n, b->aux_dev, sizeof(double),
+                        hipMemcpyDeviceToHost, b->stream));
+    HIPC(hipStreamSynchronize(b->stream));
+    const double total = b->mon_host[kNumSums * b->n];
+    if (!(total > 0.0) || !std::isfinite(total))
+      return lbm_fail(LBM_EINVAL, "sum of rho = %g cannot be renormalised", total);
+    scale = (double)n / total;
+  }
+  if (b->dtype == LBM_F64) launch_init_eq<double, false>(b, k, d[0], d[1], d[2], scale);
+  else launch_init_eq<float, true>(b, k, d[0], d[1], d[2], scale);
+  HIPC(hipGetLastError());
+  rc = reset_cavity(b, k);
+  if (rc) return rc;
+  HIPC(hipStreamSynchronize(b->stream));
+  return LBM_OK;
+}
+
+int lbm_batch_autotune(lbm_batch_t b, int chunks, int use_cache, int *best_variant,
+                       double *ms_per_step) {
+  if (!b) return lbm_fail(LBM_EINVAL, "batch is NULL");
+  if (chunks < 1 || chunks > 1000) return lbm_fail(LBM_EINVAL, "chunks = %d outside [1, 1000]", chunks);
+  if (b->t_global % kChunk != 0)
+    return lbm_fail(LBM_EINVAL, "autotune only at a multiple of 100 steps");
+  std::string key = tune_key("batch", b->dtype, b->n, (long long)b->elems);
+  int cached = use_cache ? tune_cache_lookup(key) : -1;
+  if (cached >= 0 && cached < kNumShapes) {
+    int rc = lbm_batch_set_option(b, LBM_OPT_STEP_VARIANT, cached);
+    if (best_variant) *best_variant = cached;
+    if (ms_per_step) *ms_per_step = NAN;
+    return rc;
+  }
+  // save the state (buffer 0 holds every cavity at a chunk boundary)
+  void *save_f = nullptr;
+  double2 *save_u = nullptr;
+  long long sites = 0;
+  for (int c = 0; c < b->n; ++c) sites += (long long)b->nx[c] * b->ny[c];
+  HIPC(hipStreamSynchronize(b->stream));
+  HIPC(hipMalloc(&save_f, b->buf_bytes));
+  hipError_t e = hipMalloc(&save_u, sizeof(double2) * sites);
+  if (e != hipSuccess) {
+    (void)hipFree(save_f);
+    return lbm_fail(LBM_ENOMEM, "autotune scratch: %s", hipGetErrorString(e));
+  }
+  auto restore = [&]() -> hipError_t {
+    hipError_t r = hipMemcpyAsync(b->buf[0], save_f, b->buf_bytes, hipMemcpyDeviceToDevice, b->stream);
+    if (r == hipSuccess)
+      r = hipMemcpyAsync(b->uref, save_u, sizeof(double2) * sites, hipMemcpyDeviceToDevice, b->stream);
+    return r;
+  };
+  e = hipMemcpyAsync(save_f, b->buf[0], b->buf_bytes, hipMemcpyDeviceToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(save_u, b->uref, sizeof(double2) * sites, hipMemcpyDeviceToDevice, b->stream);
+  const auto t_save = b->t, snap_save = b->snap_t, mon_t_save = b->mon_t;
+  const auto valid_save = b->mon_valid;
+  const auto res_save = b->last_res, mass_save = b->last_mass;
+  const int64_t tg_save = b->t_global;
+  const double thr_save = b->threshold;
+  const int var_save = b->variant;
+  b->threshold = 0.0;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = LBM_OK;
+  double best_ms = INFINITY;
+  int best = var_save;
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  for (int v = 0; v < kNumShapes && e == hipSuccess && rc == LBM_OK; ++v) {
+    rc = lbm_batch_set_option(b, LBM_OPT_STEP_VARIANT, v);
+    if (rc == LBM_OK) rc = lbm_batch_step(b, b->graph_steps);          // warm-up, capture
+    if (rc != LBM_OK) break;
+    e = hipEventRecord(e0, b->stream);
+    for (int k = 0; k < chunks && rc == LBM_OK; ++k) rc = lbm_batch_step(b, b->graph_steps);
+    if (e == hipSuccess) e = hipEventRecord(e1, b->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    const double per_step = ms / ((double)chunks * b->graph_steps);
+    if (rc == LBM_OK && e == hipSuccess && per_step < best_ms) {
+      best_ms = per_step;
+      best = v;
+    }
+    if (e == hipSuccess) e = restore();
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e == hipSuccess) e = restore();
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  (void)hipFree(save_f);
+  (void)hipFree(save_u);
+  b->t = t_save;
+  b->snap_t = snap_save;
+  b->mon_t = mon_t_save;
+  b->mon_valid = valid_save;
+  b->last_res = res_save;
+  b->last_mass = mass_save;
+  b->t_global = tg_save;
+  b->cur = 0;
+  b->threshold = thr_save;
+  if (rc != LBM_OK) return rc;
+  if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "autotune: %s", hipGetErrorString(e));
+  rc = lbm_batch_set_option(b, LBM_OPT_STEP_VARIANT, best);
+  if (rc) return rc;
+  tune_cache_store(key, best);
+  if (best_variant) *best_variant = best;
+  if (ms_per_step) *ms_per_step = best_ms;
+  return LBM_OK;
+}
+
+int lbm_batch_info(lbm_batch_t b, int *n, int64_t *total_sites, int64_t *steps_done,
+                   size_t *device_bytes) {
+  if (!b) return lbm_fail(LBM_EINVAL, "batch is NULL");
+  long long sites = 0;
+  for (int c = 0; c < b->n; ++c) sites += (long long)b->nx[c] * b->ny[c];
+  if (n) *n = b->n;
+  if (total_sites) *total_sites = sites;
+  if (steps_done) *steps_done = b->t_global;
+  if (device_bytes) *device_bytes = 2 * b->buf_bytes + sites * sizeof(double2);
+  return LBM_OK;
+}
+
+}  // extern "C"

@@ -4,6 +4,31 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <string>
+
+#include "../../include/lbm.h"
+
+// Record a message for lbm_last_error() and return `code`.
+int lbm_fail(int code, const char *fmt, ...);
+
+#define HIPC(call)                                                          \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      return lbm_fail(e_ == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, \
+                      "%s failed: %s", #call, hipGetErrorString(e_));       \
+  } while (0)
+
+// Monitor cadence: Eq. 6 compares the velocity fields of steps t and t-100.
+constexpr int kChunk = 100;
+
+// Tile-shape autotuner cache: a text file named by $LBM_TUNE_CACHE with
+// lines "<key> <variant>"; the key names the device architecture, the kind
+// of handle, the storage type and the lattice size.
+std::string tune_key(const char *kind, int dtype, long long a, long long b);
+int tune_cache_lookup(const std::string &key);      // -1 if absent
+void tune_cache_store(const std::string &key, int variant);
+
 struct lbm_cavity {
   // lattice and parameters
   int nx = 0, ny = 0, pitch = 0, plane = 0, dtype = 0;

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_EIO, LBM_ESTATE = \
     0, -1, -2, -3, -4, -5, -6
 LBM_F64, LBM_F32_SHIFTED = 0, 1
-LBM_OPT_USE_GRAPH, LBM_OPT_STEP_VARIANT, LBM_OPT_NUM_VARIANTS = 1, 2, 3
+LBM_OPT_USE_GRAPH, LBM_OPT_STEP_VARIANT, LBM_OPT_NUM_VARIANTS, LBM_OPT_GRAPH_STEPS = 1, 2, 3, 4
 DTYPES = {"f64": LBM_F64, "f32s": LBM_F32_SHIFTED}
 
 _ERRNAMES = {LBM_EINVAL: "LBM_EINVAL", LBM_ENOMEM: "LBM_ENOMEM",
@@ -91,6 +91,26 @@ SIGNATURES = {
     "lbm_init_fields": [_h, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int],
     "lbm_save": [_h, ct.c_char_p],
     "lbm_load": [_h, ct.c_char_p],
+    "lbm_autotune": [_h, ct.c_int, ct.c_int, ct.POINTER(ct.c_int), _dp],
+    "lbm_batch_create": [ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_double,
+                         ct.c_int, ct.POINTER(_h)],
+    "lbm_batch_destroy": [_h],
+    "lbm_batch_set_stream": [_h, ct.c_void_p],
+    "lbm_batch_set_option": [_h, ct.c_int, _i64],
+    "lbm_batch_get_option": [_h, ct.c_int, ct.POINTER(_i64)],
+    "lbm_batch_step": [_h, _i64],
+    "lbm_batch_set_threshold": [_h, ct.c_double],
+    "lbm_batch_set_active": [_h, ct.c_int, ct.c_int],
+    "lbm_batch_status": [_h, ct.c_int, ct.POINTER(_i64), _dp, ct.POINTER(_i64),
+                         ct.POINTER(ct.c_int)],
+    "lbm_batch_mass": [_h, ct.c_int, _dp],
+    "lbm_batch_moments": [_h, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_void_p],
+    "lbm_batch_get_populations": [_h, ct.c_int, ct.c_void_p],
+    "lbm_batch_set_populations": [_h, ct.c_int, ct.c_void_p],
+    "lbm_batch_init_fields": [_h, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int],
+    "lbm_batch_info": [_h, ct.POINTER(ct.c_int), ct.POINTER(_i64), ct.POINTER(_i64),
+                       ct.POINTER(ct.c_size_t)],
+    "lbm_batch_autotune": [_h, ct.c_int, ct.c_int, ct.POINTER(ct.c_int), _dp],
 }
 _RESTYPES = {"lbm_last_error": ct.c_char_p, "lbm_version": ct.c_char_p}
 
@@ -254,6 +274,108 @@ def lbm_load(h, path):
     _check(_lib.lbm_load(h, os.fsencode(path)))
 
 
+def lbm_autotune(h, chunks, use_cache=True):
+    best = ct.c_int()
+    ms = ct.c_double()
+    _check(_lib.lbm_autotune(h, int(chunks), int(bool(use_cache)), ct.byref(best), ct.byref(ms)))
+    return best.value, ms.value
+
+
+# ----------------------------------------------------------------- batch ---
+def lbm_batch_create(nx, ny, re, u_lid, dtype):
+    nx = np.ascontiguousarray(nx, dtype=np.int32)
+    ny = np.ascontiguousarray(ny, dtype=np.int32)
+    re = np.ascontiguousarray(re, dtype=np.float64)
+    if not (nx.shape == ny.shape == re.shape and nx.ndim == 1):
+        raise ValueError("nx, ny, re must be 1-D arrays of one length")
+    b = _h()
+    _check(_lib.lbm_batch_create(len(nx), _ptr(nx), _ptr(ny), _ptr(re), float(u_lid),
+                                 DTYPES.get(dtype, dtype), ct.byref(b)))
+    return b
+
+
+def lbm_batch_destroy(b):
+    _check(_lib.lbm_batch_destroy(b))
+
+
+def lbm_batch_set_stream(b, stream):
+    raw = getattr(stream, "cuda_stream", stream)
+    _check(_lib.lbm_batch_set_stream(b, ct.c_void_p(raw) if raw else None))
+
+
+def lbm_batch_set_option(b, option, value):
+    _check(_lib.lbm_batch_set_option(b, int(option), int(value)))
+
+
+def lbm_batch_get_option(b, option):
+    v = _i64()
+    _check(_lib.lbm_batch_get_option(b, int(option), ct.byref(v)))
+    return v.value
+
+
+def lbm_batch_step(b, n):
+    _check(_lib.lbm_batch_step(b, int(n)))
+
+
+def lbm_batch_set_threshold(b, residual):
+    _check(_lib.lbm_batch_set_threshold(b, float(residual)))
+
+
+def lbm_batch_set_active(b, k, active):
+    _check(_lib.lbm_batch_set_active(b, int(k), int(bool(active))))
+
+
+def lbm_batch_status(b, k):
+    t, r, rt, a = _i64(), ct.c_double(), _i64(), ct.c_int()
+    _check(_lib.lbm_batch_status(b, int(k), ct.byref(t), ct.byref(r), ct.byref(rt), ct.byref(a)))
+    return {"steps_done": t.value, "residual": r.value, "residual_step": rt.value,
+            "active": bool(a.value)}
+
+
+def lbm_batch_mass(b, k):
+    m = ct.c_double()
+    _check(_lib.lbm_batch_mass(b, int(k), ct.byref(m)))
+    return m.value
+
+
+def lbm_batch_moments(b, k, nx, ny):
+    rho, ux, uy = (np.empty((ny, nx)) for _ in range(3))
+    _check(_lib.lbm_batch_moments(b, int(k), _ptr(rho), _ptr(ux), _ptr(uy)))
+    return rho, ux, uy
+
+
+def lbm_batch_get_populations(b, k, nx, ny):
+    f = np.empty((9, ny, nx))
+    _check(_lib.lbm_batch_get_populations(b, int(k), _ptr(f)))
+    return f
+
+
+def lbm_batch_set_populations(b, k, f, nx, ny):
+    f = _f64(f, (9, ny, nx))
+    _check(_lib.lbm_batch_set_populations(b, int(k), _ptr(f)))
+
+
+def lbm_batch_init_fields(b, k, rho, ux, uy, nx, ny, renormalise_mass=True):
+    arrs = [None if a is None else _f64(a, (ny, nx)) for a in (rho, ux, uy)]
+    _check(_lib.lbm_batch_init_fields(b, int(k), *[_ptr(a) for a in arrs],
+                                      int(bool(renormalise_mass))))
+
+
+def lbm_batch_info(b):
+    n, sites, t, nbytes = ct.c_int(), _i64(), _i64(), ct.c_size_t()
+    _check(_lib.lbm_batch_info(b, ct.byref(n), ct.byref(sites), ct.byref(t), ct.byref(nbytes)))
+    return {"n": n.value, "total_sites": sites.value, "steps_done": t.value,
+            "device_bytes": nbytes.value}
+
+
+def lbm_batch_autotune(b, chunks, use_cache=True):
+    best = ct.c_int()
+    ms = ct.c_double()
+    _check(_lib.lbm_batch_autotune(b, int(chunks), int(bool(use_cache)), ct.byref(best),
+                                   ct.byref(ms)))
+    return best.value, ms.value
+
+
 # ------------------------------------------------------------ convenience ---
 class Cavity:
     """A lid-driven cavity on the GPU (one library handle)."""
@@ -343,3 +465,73 @@ class Cavity:
 
     def load(self, path):
         lbm_load(self.h, path)
+
+    def autotune(self, chunks=20, use_cache=True):
+        return lbm_autotune(self.h, chunks, use_cache)
+
+
+class Batch:
+    """Many cavities advanced together (one library batch handle)."""
+
+    def __init__(self, nx, ny, re, u_lid=0.1, dtype="f64"):
+        self.nx = [int(v) for v in nx]
+        self.ny = [int(v) for v in ny]
+        self.b = lbm_batch_create(self.nx, self.ny, re, u_lid, dtype)
+
+    def close(self):
+        if self.b:
+            lbm_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __len__(self):
+        return len(self.nx)
+
+    @property
+    def info(self):
+        return lbm_batch_info(self.b)
+
+    def step(self, n=1):
+        lbm_batch_step(self.b, n)
+        return self
+
+    def status(self, k):
+        return lbm_batch_status(self.b, k)
+
+    def set_threshold(self, r):
+        lbm_batch_set_threshold(self.b, r)
+
+    def set_active(self, k, active):
+        lbm_batch_set_active(self.b, k, active)
+
+    def mass(self, k):
+        return lbm_batch_mass(self.b, k)
+
+    def moments(self, k):
+        return lbm_batch_moments(self.b, k, self.nx[k], self.ny[k])
+
+    def get_populations(self, k):
+        return lbm_batch_get_populations(self.b, k, self.nx[k], self.ny[k])
+
+    def set_populations(self, k, f):
+        lbm_batch_set_populations(self.b, k, f, self.nx[k], self.ny[k])
+
+    def init_fields(self, k, rho=None, ux=None, uy=None, renormalise_mass=True):
+        lbm_batch_init_fields(self.b, k, rho, ux, uy, self.nx[k], self.ny[k], renormalise_mass)
+
+    def set_stream(self, stream):
+        lbm_batch_set_stream(self.b, stream)
+
+    def set_option(self, option, value):
+        lbm_batch_set_option(self.b, option, value)
+
+    def get_option(self, option):
+        return lbm_batch_get_option(self.b, option)
+
+    def autotune(self, chunks=2, use_cache=True):
+        return lbm_batch_autotune(self.b, chunks, use_cache)

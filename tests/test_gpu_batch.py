@@ -1,0 +1,165 @@
+"""Batched sweep (one launch per step over uneven cavities) and the tile-shape
+autotuner, on the GPU.
+
+A cavity advanced inside a batch runs the same per-site arithmetic as the
+single-cavity kernel, so batch and single results must agree bit for bit;
+the single-cavity path itself is held to the oracle by test_gpu_parity.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from cavity_inputs import U_LID, random_shift, sweep_cases
+from oracle import d2q9
+from oracle.d2q9 import W
+
+pytestmark = pytest.mark.gpu
+
+# (nx, ny, Re): uneven lattices, tau from 0.52 to 0.69.  The random start
+# states are kept to tau >= 0.54: grid-scale noise near tau = 1/2 is barely
+# damped by BGK and can diverge within a thousand steps.
+SMALL = [(70, 45, 300.0), (130, 67, 1000.0), (64, 64, 100.0), (3, 70, 10.0), (200, 31, 3000.0)]
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    from paper_2211_05009_amd import lbm as mod
+    return mod
+
+
+def make_batch(lbm, cases, dtype):
+    nx, ny, re = zip(*cases)
+    return lbm.Batch(nx, ny, re, u_lid=U_LID, dtype=dtype)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32s"])
+def test_batch_matches_single_cavities_bitwise(lbm, dtype):
+    b = make_batch(lbm, SMALL, dtype)
+    singles = []
+    for k, (nx, ny, re) in enumerate(SMALL):
+        if d2q9.relaxation_time(nx, re, U_LID) >= 0.54:
+            f0 = W[:, None, None] + random_shift(nx, ny, 100 + k)
+        else:
+            f0 = d2q9.equilibrium(np.ones((ny, nx)), np.zeros((ny, nx)), np.zeros((ny, nx)))
+        b.set_populations(k, f0)
+        c = lbm.Cavity(nx, ny, re=re, u_lid=U_LID, dtype=dtype)
+        c.set_populations(f0)
+        singles.append(c)
+    b.step(1230)                       # one 1000-step graph + 230 single launches
+    for k, c in enumerate(singles):
+        c.step(1230)
+        assert np.array_equal(b.get_populations(k), c.get_populations()), k
+        st = b.status(k)
+        r, t = c.residual()
+        assert st["steps_done"] == 1230 and st["residual_step"] == t == 1200
+        assert abs(st["residual"] - r) <= 1e-12 * r
+        assert abs(b.mass(k) - c.mass()) <= 1e-12 * c.mass()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32s"])
+def test_batch_against_oracle(lbm, dtype):
+    cases = [(48, 40, 200.0), (65, 33, 700.0)]
+    b = make_batch(lbm, cases, dtype)
+    b.step(300)
+    for k, (nx, ny, re) in enumerate(cases):
+        o = d2q9.Cavity(nx, ny, re=re, u_lid=U_LID).step(300)
+        _, ux, uy = b.moments(k)
+        _, uxo, uyo = o.moments()
+        du = max(np.max(np.abs(ux - uxo)), np.max(np.abs(uy - uyo)))
+        assert du <= (1e-12 if dtype == "f64" else 1e-5) * U_LID
+
+
+def test_batch_deactivates_converged_cavities(lbm):
+    """Threshold 1e-7: the low-Re cavity converges and stops; its state is the
+    single-cavity state after exactly its own step count; the other keeps
+    running."""
+    cases = [(16, 16, 5.0), (40, 40, 400.0)]
+    b = make_batch(lbm, cases, "f64")
+    b.set_threshold(1e-7)
+    b.step(30000)
+    s0, s1 = b.status(0), b.status(1)
+    assert not s0["active"] and s0["residual"] < 1e-7
+    assert s0["steps_done"] % 100 == 0 and s0["steps_done"] < 30000
+    assert s1["steps_done"] > s0["steps_done"]
+    c = lbm.Cavity(16, 16, re=5.0, u_lid=U_LID, dtype="f64")
+    c.step(s0["steps_done"])
+    assert np.array_equal(b.get_populations(0), c.get_populations())
+    # reactivation is allowed at chunk boundaries only
+    b.set_threshold(0.0)
+    b.set_active(0, True)
+    b.step(7)
+    with pytest.raises(lbm.LbmError) as e:
+        b.set_active(0, False)
+    assert e.value.code == lbm.LBM_EINVAL
+    assert b.status(0)["steps_done"] == s0["steps_done"] + 7
+
+
+def test_batch_errors(lbm):
+    with pytest.raises(lbm.LbmError):
+        lbm.Batch([10, 1], [10, 10], [100.0, 100.0])
+    with pytest.raises(lbm.LbmError):
+        lbm.Batch([10], [10], [-5.0])
+    b = lbm.Batch([10], [12], [100.0])
+    with pytest.raises(lbm.LbmError):
+        b.status(1)
+    with pytest.raises(lbm.LbmError):
+        b.set_option(lbm.LBM_OPT_GRAPH_STEPS, 150)
+
+
+@pytest.mark.parametrize("dtype", ["f32s", "f64"])
+def test_autotune_keeps_state_and_results(lbm, dtype, tmp_path, monkeypatch):
+    monkeypatch.setenv("LBM_TUNE_CACHE", str(tmp_path / "tune.txt"))
+    nx, ny = 150, 90
+    f0 = W[:, None, None] + random_shift(nx, ny, 31)
+    a = lbm.Cavity(nx, ny, re=900.0, u_lid=U_LID, dtype=dtype)
+    ref = lbm.Cavity(nx, ny, re=900.0, u_lid=U_LID, dtype=dtype)
+    for c in (a, ref):
+        c.set_populations(f0)
+        c.step(200)
+    before = a.get_populations()
+    best, ms = a.autotune(chunks=3, use_cache=True)
+    assert 0 <= best < a.get_option(lbm.LBM_OPT_NUM_VARIANTS) and ms > 0
+    assert a.get_option(lbm.LBM_OPT_STEP_VARIANT) == best
+    assert a.steps_done == 200 and np.array_equal(a.get_populations(), before)
+    a.step(300)
+    ref.step(300)
+    assert np.array_equal(a.get_populations(), ref.get_populations())
+    assert a.residual() == ref.residual()
+    # the cached choice is applied without timing
+    c = lbm.Cavity(nx, ny, re=900.0, u_lid=U_LID, dtype=dtype)
+    best2, ms2 = c.autotune(chunks=3, use_cache=True)
+    assert best2 == best and math.isnan(ms2)
+    # batch autotune
+    b = make_batch(lbm, SMALL, dtype)
+    b.step(100)
+    fb = [b.get_populations(k) for k in range(len(SMALL))]
+    bv, bms = b.autotune(chunks=1, use_cache=False)
+    assert 0 <= bv < 8 and bms > 0
+    assert b.info["steps_done"] == 100
+    for k in range(len(SMALL)):
+        assert np.array_equal(b.get_populations(k), fb[k])
+
+
+def test_full_sweep_batch_matches_single(lbm):
+    """The 25-cavity Re x Ar sweep (500 x 200 ... 500 x 1000, FP32 f - w) for
+    one 1000-step graph: the smallest and the largest cavity equal their
+    single-cavity runs bit for bit, and one further launch of the largest
+    matches one oracle step applied to its state."""
+    cases = sweep_cases(500)
+    b = make_batch(lbm, cases, "f32s")
+    assert b.info["total_sites"] == 7_500_000
+    b.step(1000)
+    for k in (0, 24):
+        nx, ny, re = cases[k]
+        c = lbm.Cavity(nx, ny, re=re, u_lid=U_LID, dtype="f32s")
+        c.step(1000)
+        assert np.array_equal(b.get_populations(k), c.get_populations()), k
+    nx, ny, re = cases[24]
+    fs = b.get_populations(24)
+    b.step(1)
+    o = d2q9.Cavity(nx, ny, re=re, u_lid=U_LID)
+    o.set_state(o.stream(fs), t=1001)
+    ref = o.post_collision()
+    gmax = np.max(np.abs(ref - W[:, None, None]))
+    assert np.max(np.abs(b.get_populations(24) - ref)) <= 16 * 2.0 ** -24 * gmax

@@ -172,7 +172,7 @@ def test_mass_conservation_long_run(lbm):
     for dtype, tol in (("f64", 5e-12), ("f32s", 1e-7)):
         c = lbm.Cavity(64, 64, re=100.0, u_lid=U_LID, dtype=dtype)
         m0 = c.mass()
-        assert m0 == 64 * 64
+        assert abs(m0 - 64 * 64) <= 1e-12 * 64 * 64     # sum of the nine rounded w
         c.step(20000)
         drift = abs(c.mass() - m0) / m0
         print(f"{dtype}: relative mass drift after 20000 steps {drift:.3e}")
