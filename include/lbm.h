@@ -303,7 +303,10 @@ int lbm_batch_info(lbm_batch_t b, int *n, int64_t *total_sites,
 
 /* Autotuner of the batch kernel's tile shape; as lbm_autotune with `chunks`
  * captured graphs of LBM_OPT_GRAPH_STEPS steps per shape (1..1000).  Must be
- * called at a multiple of 100 steps; the cavities' states are restored. */
+ * called at a multiple of 100 steps; the cavities' states are restored.
+ * The batch has its own list of LBM_OPT_NUM_VARIANTS shapes (one-step,
+ * vector and multi-step shapes); steps off the 100-step grid always use
+ * the one-step shape 0. */
 int lbm_batch_autotune(lbm_batch_t b, int chunks, int use_cache,
                        int *best_variant, double *ms_per_step);
 

@@ -3,7 +3,10 @@
     python -m paper_2211_05009_amd.build
 
 hipcc cross-compiles for gfx950 without a GPU.  Packed-FP32 instruction
-selection is disabled (-packed-fp32-ops) for every device compilation.
+selection is disabled (-packed-fp32-ops) for every device compilation, and
+multiply-adds are fused only within one source expression (-ffp-contract=on),
+so every kernel variant that evaluates the same expressions rounds the same
+way.
 """
 from __future__ import annotations
 
@@ -32,6 +35,7 @@ def hipcc() -> str:
 
 def command(out: str = LIB) -> list:
     return [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
+            "-ffp-contract=on",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             "-I", os.path.join(ROOT, "include"),
             "-o", out] + [os.path.join(CSRC, s) for s in SOURCES]

@@ -13,6 +13,7 @@
 
 #include "d2q9_monitor.hpp"
 #include "d2q9_step.hpp"
+#include "d2q9_temporal.hpp"
 
 namespace lbm {
 
@@ -47,6 +48,35 @@ __global__ __launch_bounds__(64 * BY) void k_step_batch(
 #pragma unroll
     for (int i = 0; i < 9; ++i) o_base[i * d.plane + o] = f[i];
   }
+}
+
+// Vector form (see k_step_vec): tiles of (64 V) x BY sites.
+template <typename T, bool SHIFT, int BY>
+__global__ __launch_bounds__(64 * BY) void k_step_batch_vec(
+    const T *__restrict__ src, T *__restrict__ dst,
+    const CavityDesc<T> *__restrict__ cav, const int4 *__restrict__ tiles) {
+  constexpr int V = 16 / sizeof(T);
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int4 te = tiles[tile];
+  const CavityDesc<T> d = cav[te.x];
+  const int x0 = (te.y * 64 + threadIdx.x) * V;
+  const int y = te.z * BY + threadIdx.y;
+  if (x0 >= d.nx || y >= d.ny) return;
+  step_vec_sites<T, SHIFT, V>(src + d.base, dst + d.base, d.plane, d.pitch, d.nx, d.ny, x0, y,
+                              d.omega, d.u6);
+}
+
+// Temporal form (see k_step_tb): K steps per launch on TX x TY tiles.
+template <typename T, bool SHIFT, int K, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_step_batch_tb(
+    const T *__restrict__ src, T *__restrict__ dst,
+    const CavityDesc<T> *__restrict__ cav, const int4 *__restrict__ tiles) {
+  __shared__ T lds[9 * (TX + 2 * K) * (TY + 2 * K)];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int4 te = tiles[tile];
+  const CavityDesc<T> d = cav[te.x];
+  tb_tile<T, SHIFT, K, TX, TY, NT>(lds, src + d.base, dst + d.base, d.nx, d.ny, d.pitch,
+                                   d.plane, d.omega, d.u6, te.y, te.z);
 }
 
 // Monitor over a fixed 64 x 4 tiling (one site per thread): per-tile

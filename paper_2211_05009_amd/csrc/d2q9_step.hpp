@@ -138,4 +138,106 @@ __global__ __launch_bounds__(64 * BY) void k_step(StepParams<T> p) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Vector form: each thread updates V = 16 / sizeof(T) consecutive sites of a
+// row with 16-byte loads and stores (four FP32 or two FP64 sites), so a
+// wavefront moves 1 KiB per plane and instruction.  The loads of the planes
+// that move along x start one element off a 16-byte boundary; gfx950 global
+// loads need only element (dword) alignment for multi-dword accesses.
+// Whole-vector wall cases depend only on the row; the side walls touch only
+// the first / last element and are patched from the reverse plane.  The
+// per-site arithmetic is bgk_collide, as in k_step.
+template <typename T, int V>
+struct VecT {            // alignment of T only
+  T v[V];
+};
+
+template <typename T, int V>
+__device__ __forceinline__ void vload(const T *p, T (&out)[V]) {
+  VecT<T, V> t;
+  __builtin_memcpy(&t, p, sizeof t);
+#pragma unroll
+  for (int k = 0; k < V; ++k) out[k] = t.v[k];
+}
+
+template <typename T, int V>
+__device__ __forceinline__ void vstore(T *p, const T (&in)[V]) {
+  VecT<T, V> t;
+#pragma unroll
+  for (int k = 0; k < V; ++k) t.v[k] = in[k];
+  __builtin_memcpy(p, &t, sizeof t);
+}
+
+// Update the V sites (x0 .. x0+V-1, y) of one thread; x0 < nx, y < ny.
+template <typename T, bool SHIFT, int V>
+__device__ __forceinline__ void step_vec_sites(const T *__restrict__ s, T *__restrict__ d,
+                                               int P, int pitch, int nx, int ny, int x0,
+                                               int y, T omega, T u6) {
+  const bool yb = y > 0, yt = y < ny - 1;
+  if (x0 + V > nx) {            // ragged end of the row: one site at a time
+    for (int k = 0; k < V && x0 + k < nx; ++k) {
+      const int x = x0 + k, o = y * pitch + x;
+      T f[9];
+      pull<T>(s, P, pitch, o, x > 0, x < nx - 1, yb, yt, u6, f);
+      bgk_collide<T, SHIFT>(f, omega);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) d[i * P + o] = f[i];
+    }
+    return;
+  }
+  const int o = y * pitch + x0;
+  T g[9][V];
+  vload<T, V>(s + o, g[0]);
+  vload<T, V>(s + P + o - 1, g[1]);
+  vload<T, V>(s + 3 * P + o + 1, g[3]);
+  vload<T, V>(s + (yb ? 2 * P + o - pitch : 4 * P + o), g[2]);
+  vload<T, V>(s + (yt ? 4 * P + o + pitch : 2 * P + o), g[4]);
+  vload<T, V>(s + (yb ? 5 * P + o - pitch - 1 : 7 * P + o), g[5]);
+  vload<T, V>(s + (yb ? 6 * P + o - pitch + 1 : 8 * P + o), g[6]);
+  vload<T, V>(s + (yt ? 7 * P + o + pitch + 1 : 5 * P + o), g[7]);
+  vload<T, V>(s + (yt ? 8 * P + o + pitch - 1 : 6 * P + o), g[8]);
+  if (!yt) {                    // lid row: moving-wall term on 7 and 8
+#pragma unroll
+    for (int k = 0; k < V; ++k) {
+      g[7][k] -= u6;
+      g[8][k] += u6;
+    }
+  }
+  if (x0 == 0) {                // left wall: links arriving with c_x = +1
+    g[1][0] = s[3 * P + o];
+    if (yb) g[5][0] = s[7 * P + o];
+    if (yt) g[8][0] = s[6 * P + o];
+  }
+  if (x0 + V == nx) {           // right wall: links arriving with c_x = -1
+    const int oe = o + V - 1;
+    g[3][V - 1] = s[P + oe];
+    if (yb) g[6][V - 1] = s[8 * P + oe];
+    if (yt) g[7][V - 1] = s[5 * P + oe];
+  }
+#pragma unroll
+  for (int k = 0; k < V; ++k) {
+    T f[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) f[i] = g[i][k];
+    bgk_collide<T, SHIFT>(f, omega);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) g[i][k] = f[i];
+  }
+#pragma unroll
+  for (int i = 0; i < 9; ++i) vstore<T, V>(d + i * P + o, g[i]);
+}
+
+// One step over tiles of (64 V) x BY sites; block = 64 x BY threads.
+template <typename T, bool SHIFT, int BY>
+__global__ __launch_bounds__(64 * BY) void k_step_vec(StepParams<T> p) {
+  constexpr int V = 16 / sizeof(T);
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
+  const int x0 = (tx * 64 + threadIdx.x) * V;
+  const int y = ty * BY + threadIdx.y;
+  if (x0 >= p.nx || y >= p.ny) return;
+  step_vec_sites<T, SHIFT, V>(p.src, p.dst, p.plane, p.pitch, p.nx, p.ny, x0, y, p.omega,
+                              p.u6);
+}
+
 }  // namespace lbm

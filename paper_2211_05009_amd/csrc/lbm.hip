@@ -24,6 +24,7 @@
 #include "../../include/lbm.h"
 #include "d2q9_monitor.hpp"
 #include "d2q9_step.hpp"
+#include "d2q9_temporal.hpp"
 #include "lbm_internal.h"
 
 using namespace lbm;
@@ -79,13 +80,21 @@ void tune_cache_store(const std::string &key, int variant) {
 }
 
 // ---------------------------------------------------------------- variants
-// Step kernel variants: tile 64 x (BY*RY) sites, block 64 x BY threads.
-struct VariantDesc {
-  int by, ry;
-};
-static const VariantDesc kVariants[] = {{4, 1}, {4, 2}, {4, 4}, {8, 1},
-                                        {2, 4}, {1, 8}, {8, 2}, {16, 1}};
-static const int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
+// Step kernel variants.  Scalar (k_step): tile 64 x (BY*RY) sites, block
+// 64 x BY threads.  Vector (k_step_vec): tile (64 V) x BY sites, V = 16 B /
+// element, block 64 x BY.  Temporal (k_step_tb, variants 12-23): K steps per
+// launch on TX x TY tiles held in LDS.  All give bit-identical results.
+static const int kNumVariants = 24;
+// K = 5 steps per launch on 32 x 32 tiles, 1024 threads: the fastest shape
+// on the 500 x (500 Ar) lattices on gfx950 (lbm_autotune refines it).
+static const int kDefaultVariant = 22;
+
+// Steps applied by one launch of variant v.
+static int steps_per_launch(int v) {
+  static const int k[kNumVariants] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1,
+                                      4, 4, 2, 5, 4, 4, 5, 5, 10, 10, 5, 5};
+  return (v >= 0 && v < kNumVariants) ? k[v] : 1;
+}
 
 template <typename T, bool S, int BY, int RY>
 static hipError_t launch_step_t(const lbm_cavity *h, const void *src, void *dst,
@@ -106,10 +115,68 @@ static hipError_t launch_step_t(const lbm_cavity *h, const void *src, void *dst,
   return hipGetLastError();
 }
 
+template <typename T, bool S, int BY>
+static hipError_t launch_step_vec_t(const lbm_cavity *h, const void *src, void *dst,
+                                    hipStream_t st) {
+  constexpr int V = 16 / sizeof(T);
+  StepParams<T> p;
+  p.src = (const T *)src;
+  p.dst = (T *)dst;
+  p.nx = h->nx;
+  p.ny = h->ny;
+  p.pitch = h->pitch;
+  p.plane = h->plane;
+  p.tiles_x = (h->nx + 64 * V - 1) / (64 * V);
+  p.omega = (T)h->omega;
+  p.u6 = (T)(h->u_lid / 6.0);
+  const int tiles_y = (h->ny + BY - 1) / BY;
+  hipLaunchKernelGGL((k_step_vec<T, S, BY>), dim3(p.tiles_x * tiles_y), dim3(64, BY), 0, st,
+                     p);
+  return hipGetLastError();
+}
+
+template <typename T, bool S, int K, int TX, int TY, int NT>
+static hipError_t launch_tb_t(const lbm_cavity *h, const void *src, void *dst,
+                              hipStream_t st) {
+  StepParams<T> p;
+  p.src = (const T *)src;
+  p.dst = (T *)dst;
+  p.nx = h->nx;
+  p.ny = h->ny;
+  p.pitch = h->pitch;
+  p.plane = h->plane;
+  p.tiles_x = 0;
+  p.omega = (T)h->omega;
+  p.u6 = (T)(h->u_lid / 6.0);
+  const int tx = (h->nx + TX - 1) / TX, ty = (h->ny + TY - 1) / TY;
+  hipLaunchKernelGGL((k_step_tb<T, S, K, TX, TY, NT>), dim3(tx * ty), dim3(NT), 0, st, p, tx);
+  return hipGetLastError();
+}
+
 template <typename T, bool S>
 static hipError_t launch_step_variant(const lbm_cavity *h, int v, const void *src,
                                       void *dst, hipStream_t st) {
   switch (v) {
+    case 12: return launch_tb_t<T, S, 4, 32, 32, 512>(h, src, dst, st);
+    case 13: return launch_tb_t<T, S, 4, 32, 32, 1024>(h, src, dst, st);
+    case 14: return launch_tb_t<T, S, 2, 32, 32, 512>(h, src, dst, st);
+    case 15: return launch_tb_t<T, S, 5, 32, 32, 512>(h, src, dst, st);
+    case 16: return launch_tb_t<T, S, 4, 64, 16, 512>(h, src, dst, st);
+    case 17: return launch_tb_t<T, S, 4, 16, 16, 256>(h, src, dst, st);
+    case 18: return launch_tb_t<T, S, 5, 64, 16, 512>(h, src, dst, st);
+    case 19: return launch_tb_t<T, S, 5, 16, 16, 256>(h, src, dst, st);
+    case 22: return launch_tb_t<T, S, 5, 32, 32, 1024>(h, src, dst, st);
+    // FP64 regions hold twice the bytes per site: smaller tiles keep the
+    // LDS of the K = 10 and 64 x 32 shapes within 160 KiB
+    case 20:
+      if constexpr (sizeof(T) == 8) return launch_tb_t<T, S, 10, 32, 16, 512>(h, src, dst, st);
+      else return launch_tb_t<T, S, 10, 32, 32, 512>(h, src, dst, st);
+    case 21:
+      if constexpr (sizeof(T) == 8) return launch_tb_t<T, S, 10, 16, 16, 256>(h, src, dst, st);
+      else return launch_tb_t<T, S, 10, 64, 32, 1024>(h, src, dst, st);
+    case 23:
+      if constexpr (sizeof(T) == 8) return launch_tb_t<T, S, 5, 64, 16, 1024>(h, src, dst, st);
+      else return launch_tb_t<T, S, 5, 64, 32, 1024>(h, src, dst, st);
     case 0: return launch_step_t<T, S, 4, 1>(h, src, dst, st);
     case 1: return launch_step_t<T, S, 4, 2>(h, src, dst, st);
     case 2: return launch_step_t<T, S, 4, 4>(h, src, dst, st);
@@ -117,15 +184,33 @@ static hipError_t launch_step_variant(const lbm_cavity *h, int v, const void *sr
     case 4: return launch_step_t<T, S, 2, 4>(h, src, dst, st);
     case 5: return launch_step_t<T, S, 1, 8>(h, src, dst, st);
     case 6: return launch_step_t<T, S, 8, 2>(h, src, dst, st);
-    default: return launch_step_t<T, S, 16, 1>(h, src, dst, st);
+    case 7: return launch_step_t<T, S, 16, 1>(h, src, dst, st);
+    case 8: return launch_step_vec_t<T, S, 1>(h, src, dst, st);
+    case 9: return launch_step_vec_t<T, S, 2>(h, src, dst, st);
+    case 10: return launch_step_vec_t<T, S, 4>(h, src, dst, st);
+    default: return launch_step_vec_t<T, S, 8>(h, src, dst, st);
   }
 }
 
+// One launch of variant v (steps_per_launch(v) steps).
+static hipError_t launch_variant(const lbm_cavity *h, int v, const void *src, void *dst,
+                                 hipStream_t st) {
+  if (h->dtype == LBM_F64) return launch_step_variant<double, false>(h, v, src, dst, st);
+  return launch_step_variant<float, true>(h, v, src, dst, st);
+}
+
+// One step (a one-step variant: the chosen one, or the default).
 static hipError_t launch_step(const lbm_cavity *h, const void *src, void *dst,
                               hipStream_t st) {
-  if (h->dtype == LBM_F64)
-    return launch_step_variant<double, false>(h, h->variant, src, dst, st);
-  return launch_step_variant<float, true>(h, h->variant, src, dst, st);
+  return launch_variant(h, steps_per_launch(h->variant) == 1 ? h->variant : 0, src, dst, st);
+}
+
+// Variant used for 100-step chunks: a multi-step variant only if the probe
+// cadence falls on its launch boundaries.
+static int chunk_variant(const lbm_cavity *h) {
+  const int k = steps_per_launch(h->variant);
+  if (k > 1 && h->probe_n > 0 && h->probe_every <= kChunk && h->probe_every % k != 0) return 0;
+  return h->variant;
 }
 
 // ------------------------------------------------------------ small kernels
@@ -194,12 +279,21 @@ static void drop_graphs(lbm_cavity *h) {
   }
 }
 
+// Buffer index holding the state after a 100-step chunk that starts in
+// buf[c] (an odd number of launches per chunk swaps the buffers).
+static int chunk_end(const lbm_cavity *h, int c) {
+  const int launches = kChunk / steps_per_launch(chunk_variant(h));
+  return (launches & 1) ? 1 - c : c;
+}
+
 // Issue one 100-step chunk starting from buf[c] on stream st (either
-// directly or under capture).  Ends with the monitor on buf[c].
+// directly or under capture), ending with the monitor.
 static hipError_t issue_chunk(lbm_cavity *h, int c, hipStream_t st) {
+  const int v = chunk_variant(h);
+  const int K = steps_per_launch(v);
   int cur = c;
-  for (int k = 1; k <= kChunk; ++k) {
-    hipError_t e = launch_step(h, h->buf[cur], h->buf[1 - cur], st);
+  for (int k = K; k <= kChunk; k += K) {
+    hipError_t e = launch_variant(h, v, h->buf[cur], h->buf[1 - cur], st);
     if (e != hipSuccess) return e;
     cur = 1 - cur;
     if (h->probe_n > 0 && h->probe_every <= kChunk && k % h->probe_every == 0) {
@@ -285,7 +379,7 @@ static int create_impl(int nx, int ny, double tau, double re, double u_lid,
   h->u_lid = u_lid;
   h->tau = tau;
   h->omega = 1.0 / tau;
-  h->variant = 0;
+  h->variant = kDefaultVariant;
   h->use_graph = 1;
   const size_t esz = dtype == LBM_F64 ? 8 : 4;
   h->buf_bytes = (size_t)plane * 9 * esz;
@@ -448,6 +542,7 @@ int lbm_step(lbm_t h, int64_t n) {
         e = issue_chunk(h, h->cur, h->stream);
         if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "launch: %s", hipGetErrorString(e));
       }
+      h->cur = chunk_end(h, h->cur);
       h->t += kChunk;
       n -= kChunk;
       note_monitor(h);

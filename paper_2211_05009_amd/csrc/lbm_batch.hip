@@ -38,8 +38,10 @@ struct lbm_batch {
   void *buf[2] = {nullptr, nullptr};
   int cur = 0;
   void *desc = nullptr;                 // CavityDesc<T>[n]
-  int4 *tiles = nullptr;                // step tiles of active cavities
+  int4 *tiles = nullptr;                // tiles of the chosen shape, active cavities
   int ntiles = 0, tiles_cap = 0;
+  int4 *tiles1 = nullptr;               // 64 x 4 one-step tiles (shape 0)
+  int ntiles1 = 0, tiles1_cap = 0;
   int4 *mtiles = nullptr;               // 64 x 4 monitor tiles of active cavities
   int nmtiles = 0, mtiles_cap = 0;
   int *fin = nullptr;                   // [3][n]: first, count, cavity
@@ -57,7 +59,7 @@ struct lbm_batch {
   std::vector<double> last_res, last_mass;
   int64_t t_global = 0;
   double threshold = 0.0;
-  int variant = 0, use_graph = 1, graph_steps = 1000;
+  int variant = 12, use_graph = 1, graph_steps = 1000;   // 12: K = 5 on 32 x 32 tiles
   hipStream_t stream = nullptr, own_stream = nullptr, cap_stream = nullptr;
   hipGraphExec_t graph = nullptr;
   bool tables_dirty = true;
@@ -65,11 +67,25 @@ struct lbm_batch {
 
 namespace {
 
+// Tile shapes of the batch kernels.  kind 0: 64 x (by*ry) sites
+// (k_step_batch); kind 1: (64 V) x by sites (k_step_batch_vec, V = 16 B /
+// element); kind 2: tx x ty core tiles advanced k steps per launch in LDS
+// (k_step_batch_tb; FP64 uses tx64 x ty64 where the FP32 region would not
+// fit).  k divides 100 into an even number of launches, so every monitor
+// and chunk boundary finds the state in buffer 0.
 struct Shape {
-  int by, ry;
+  int kind, by, ry, k, tx, ty, tx64, ty64;
 };
-const Shape kShapes[] = {{4, 1}, {4, 2}, {4, 4}, {8, 1}, {2, 4}, {1, 8}, {8, 2}, {16, 1}};
-const int kNumShapes = 8;
+const Shape kShapes[] = {
+    {0, 4, 1, 1, 0, 0, 0, 0},   {0, 4, 2, 1, 0, 0, 0, 0},   {0, 4, 4, 1, 0, 0, 0, 0},
+    {0, 8, 1, 1, 0, 0, 0, 0},   {0, 2, 4, 1, 0, 0, 0, 0},   {0, 1, 8, 1, 0, 0, 0, 0},
+    {0, 8, 2, 1, 0, 0, 0, 0},   {0, 16, 1, 1, 0, 0, 0, 0},  {1, 1, 1, 1, 0, 0, 0, 0},
+    {1, 2, 1, 1, 0, 0, 0, 0},   {1, 4, 1, 1, 0, 0, 0, 0},   {1, 8, 1, 1, 0, 0, 0, 0},
+    {2, 0, 0, 5, 32, 32, 32, 32}, {2, 0, 0, 5, 64, 16, 64, 16}, {2, 0, 0, 5, 16, 16, 16, 16},
+    {2, 0, 0, 10, 32, 32, 32, 16}, {2, 0, 0, 2, 32, 32, 32, 32}, {2, 0, 0, 5, 64, 32, 64, 16}};
+const int kNumShapes = 18;
+
+int shape_steps(int v) { return kShapes[v].k; }
 
 template <typename T, bool S, int BY, int RY>
 hipError_t launch_b(const lbm_batch *b, const void *src, void *dst, hipStream_t st) {
@@ -79,9 +95,40 @@ hipError_t launch_b(const lbm_batch *b, const void *src, void *dst, hipStream_t 
   return hipGetLastError();
 }
 
+template <typename T, bool S, int BY>
+hipError_t launch_bv(const lbm_batch *b, const void *src, void *dst, hipStream_t st) {
+  hipLaunchKernelGGL((k_step_batch_vec<T, S, BY>), dim3(b->ntiles), dim3(64, BY), 0, st,
+                     (const T *)src, (T *)dst, (const CavityDesc<T> *)b->desc,
+                     (const int4 *)b->tiles);
+  return hipGetLastError();
+}
+
+template <typename T, bool S, int K, int TX, int TY, int NT>
+hipError_t launch_bt(const lbm_batch *b, const void *src, void *dst, hipStream_t st) {
+  hipLaunchKernelGGL((k_step_batch_tb<T, S, K, TX, TY, NT>), dim3(b->ntiles), dim3(NT), 0, st,
+                     (const T *)src, (T *)dst, (const CavityDesc<T> *)b->desc,
+                     (const int4 *)b->tiles);
+  return hipGetLastError();
+}
+
 template <typename T, bool S>
 hipError_t launch_b_variant(const lbm_batch *b, const void *src, void *dst, hipStream_t st) {
+  constexpr bool D = sizeof(T) == 8;
   switch (b->variant) {
+    case 12: return launch_bt<T, S, 5, 32, 32, 1024>(b, src, dst, st);
+    case 13: return launch_bt<T, S, 5, 64, 16, 512>(b, src, dst, st);
+    case 14: return launch_bt<T, S, 5, 16, 16, 256>(b, src, dst, st);
+    case 15:
+      if constexpr (D) return launch_bt<T, S, 10, 32, 16, 512>(b, src, dst, st);
+      else return launch_bt<T, S, 10, 32, 32, 512>(b, src, dst, st);
+    case 16: return launch_bt<T, S, 2, 32, 32, 512>(b, src, dst, st);
+    case 17:
+      if constexpr (D) return launch_bt<T, S, 5, 64, 16, 1024>(b, src, dst, st);
+      else return launch_bt<T, S, 5, 64, 32, 1024>(b, src, dst, st);
+    case 8: return launch_bv<T, S, 1>(b, src, dst, st);
+    case 9: return launch_bv<T, S, 2>(b, src, dst, st);
+    case 10: return launch_bv<T, S, 4>(b, src, dst, st);
+    case 11: return launch_bv<T, S, 8>(b, src, dst, st);
     case 0: return launch_b<T, S, 4, 1>(b, src, dst, st);
     case 1: return launch_b<T, S, 4, 2>(b, src, dst, st);
     case 2: return launch_b<T, S, 4, 4>(b, src, dst, st);
@@ -93,11 +140,27 @@ hipError_t launch_b_variant(const lbm_batch *b, const void *src, void *dst, hipS
   }
 }
 
-hipError_t batch_step(const lbm_batch *b, int from, hipStream_t st) {
+
+// One launch of the chosen shape (shape_steps(variant) steps).
+hipError_t batch_launch(const lbm_batch *b, int from, hipStream_t st) {
   if (b->ntiles == 0) return hipSuccess;
   if (b->dtype == LBM_F64)
     return launch_b_variant<double, false>(b, b->buf[from], b->buf[1 - from], st);
   return launch_b_variant<float, true>(b, b->buf[from], b->buf[1 - from], st);
+}
+
+// One step with shape 0 (for steps off the 100-step grid).
+hipError_t batch_step1(const lbm_batch *b, int from, hipStream_t st) {
+  if (b->ntiles1 == 0) return hipSuccess;
+  if (b->dtype == LBM_F64)
+    hipLaunchKernelGGL((k_step_batch<double, false, 4, 1>), dim3(b->ntiles1), dim3(64, 4), 0, st,
+                       (const double *)b->buf[from], (double *)b->buf[1 - from],
+                       (const CavityDesc<double> *)b->desc, (const int4 *)b->tiles1);
+  else
+    hipLaunchKernelGGL((k_step_batch<float, true, 4, 1>), dim3(b->ntiles1), dim3(64, 4), 0, st,
+                       (const float *)b->buf[from], (float *)b->buf[1 - from],
+                       (const CavityDesc<float> *)b->desc, (const int4 *)b->tiles1);
+  return hipGetLastError();
 }
 
 template <typename T, bool S>
@@ -142,16 +205,30 @@ int rebuild_tables(lbm_batch *b) {
   std::vector<int4> st, mt;
   std::vector<int> first(b->n, 0), count(b->n, 0), cav(b->n, 0);
   int nfin = 0;
+  const bool d64 = b->dtype == LBM_F64;
+  int tw, th;                      // tile width / height of the chosen shape
+  if (sh.kind == 2) {
+    tw = d64 ? sh.tx64 : sh.tx;
+    th = d64 ? sh.ty64 : sh.ty;
+  } else {
+    tw = 64 * (sh.kind == 1 ? (d64 ? 2 : 4) : 1);
+    th = sh.by * sh.ry;
+  }
+  std::vector<int4> s1;
   for (int c = 0; c < b->n; ++c) {
     if (!b->active[c]) continue;
-    const int tx = (b->nx[c] + 63) / 64;
-    const int ty = (b->ny[c] + sh.by * sh.ry - 1) / (sh.by * sh.ry);
+    const int tx = (b->nx[c] + tw - 1) / tw;
+    const int ty = (b->ny[c] + th - 1) / th;
     for (int y = 0; y < ty; ++y)
       for (int x = 0; x < tx; ++x) st.push_back(make_int4(c, x, y, 0));
+    const int mx = (b->nx[c] + 63) / 64;
     const int my = (b->ny[c] + 3) / 4;
     first[nfin] = (int)mt.size();
     for (int y = 0; y < my; ++y)
-      for (int x = 0; x < tx; ++x) mt.push_back(make_int4(c, x, y, 0));
+      for (int x = 0; x < mx; ++x) {
+        mt.push_back(make_int4(c, x, y, 0));
+        s1.push_back(make_int4(c, x, y, 0));   // shape 0 uses the same 64 x 4 tiles
+      }
     count[nfin] = (int)mt.size() - first[nfin];
     cav[nfin] = c;
     ++nfin;
@@ -169,6 +246,15 @@ int rebuild_tables(lbm_batch *b) {
     HIPC(hipMalloc(&b->mtiles, mt.size() * sizeof(int4)));
     b->mtiles_cap = (int)mt.size();
   }
+  if ((int)s1.size() > b->tiles1_cap) {
+    if (b->tiles1) HIPC(hipFree(b->tiles1));
+    b->tiles1 = nullptr;
+    HIPC(hipMalloc(&b->tiles1, s1.size() * sizeof(int4)));
+    b->tiles1_cap = (int)s1.size();
+  }
+  if (!s1.empty())
+    HIPC(hipMemcpy(b->tiles1, s1.data(), s1.size() * sizeof(int4), hipMemcpyHostToDevice));
+  b->ntiles1 = (int)s1.size();
   if (!st.empty())
     HIPC(hipMemcpy(b->tiles, st.data(), st.size() * sizeof(int4), hipMemcpyHostToDevice));
   if (!mt.empty())
@@ -187,9 +273,10 @@ int rebuild_tables(lbm_batch *b) {
 }
 
 hipError_t issue_chunk(lbm_batch *b, hipStream_t st) {
+  const int K = shape_steps(b->variant);
   int cur = 0;
-  for (int k = 1; k <= b->graph_steps; ++k) {
-    hipError_t e = batch_step(b, cur, st);
+  for (int k = K; k <= b->graph_steps; k += K) {
+    hipError_t e = batch_launch(b, cur, st);
     if (e != hipSuccess) return e;
     cur = 1 - cur;
     if (k % kChunk == 0) {
@@ -328,7 +415,7 @@ int lbm_batch_destroy(lbm_batch_t b) {
   if (!b) return LBM_OK;
   drop_graph(b);
   if (b->stream) (void)hipStreamSynchronize(b->stream);
-  void *ptrs[] = {b->buf[0], b->buf[1], b->desc, b->tiles, b->mtiles, b->fin,
+  void *ptrs[] = {b->buf[0], b->buf[1], b->desc, b->tiles, b->tiles1, b->mtiles, b->fin,
                   b->uref, b->partials, b->mon_dev, b->aux_dev, b->tmp};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
@@ -509,12 +596,17 @@ int lbm_batch_step(lbm_batch_t b, int64_t n) {
     }
     if (b->ntiles == 0) break;       // every cavity inactive
     const bool aligned = b->t_global % kChunk == 0;
-    if (aligned && b->use_graph && n >= b->graph_steps) {
-      if (!b->graph) {
-        int rc = build_graph(b);
-        if (rc) return rc;
+    if (aligned && n >= b->graph_steps) {
+      if (b->use_graph) {
+        if (!b->graph) {
+          int rc = build_graph(b);
+          if (rc) return rc;
+        }
+        HIPC(hipGraphLaunch(b->graph, b->stream));
+      } else {
+        hipError_t e = issue_chunk(b, b->stream);
+        if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "batch chunk: %s", hipGetErrorString(e));
       }
-      HIPC(hipGraphLaunch(b->graph, b->stream));
       for (int k = 0; k < b->graph_steps / kChunk; ++k) {
         for (int c = 0; c < b->n; ++c)
           if (b->active[c]) b->t[c] += kChunk;
@@ -524,7 +616,7 @@ int lbm_batch_step(lbm_batch_t b, int64_t n) {
       n -= b->graph_steps;
       monitored = true;
     } else {
-      hipError_t e = batch_step(b, b->cur, b->stream);
+      hipError_t e = batch_step1(b, b->cur, b->stream);
       if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "batch step: %s", hipGetErrorString(e));
       b->cur = 1 - b->cur;
       for (int c = 0; c < b->n; ++c)

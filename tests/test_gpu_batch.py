@@ -33,9 +33,13 @@ def make_batch(lbm, cases, dtype):
     return lbm.Batch(nx, ny, re, u_lid=U_LID, dtype=dtype)
 
 
+@pytest.mark.parametrize("variant", [0, 10, 12, 15, 16, 17])
 @pytest.mark.parametrize("dtype", ["f64", "f32s"])
-def test_batch_matches_single_cavities_bitwise(lbm, dtype):
+def test_batch_matches_single_cavities_bitwise(lbm, dtype, variant):
+    """Scalar (0), vector (10) and multi-step LDS (12, 15-17) shapes of the
+    batch kernel against the default single-cavity kernel."""
     b = make_batch(lbm, SMALL, dtype)
+    b.set_option(lbm.LBM_OPT_STEP_VARIANT, variant)
     singles = []
     for k, (nx, ny, re) in enumerate(SMALL):
         if d2q9.relaxation_time(nx, re, U_LID) >= 0.54:
@@ -47,6 +51,7 @@ def test_batch_matches_single_cavities_bitwise(lbm, dtype):
         c.set_populations(f0)
         singles.append(c)
     b.step(1230)                       # one 1000-step graph + 230 single launches
+    assert b.get_option(lbm.LBM_OPT_STEP_VARIANT) == variant
     for k, c in enumerate(singles):
         c.step(1230)
         assert np.array_equal(b.get_populations(k), c.get_populations()), k
@@ -135,19 +140,21 @@ def test_autotune_keeps_state_and_results(lbm, dtype, tmp_path, monkeypatch):
     b.step(100)
     fb = [b.get_populations(k) for k in range(len(SMALL))]
     bv, bms = b.autotune(chunks=1, use_cache=False)
-    assert 0 <= bv < 8 and bms > 0
+    assert 0 <= bv < b.get_option(lbm.LBM_OPT_NUM_VARIANTS) and bms > 0
     assert b.info["steps_done"] == 100
     for k in range(len(SMALL)):
         assert np.array_equal(b.get_populations(k), fb[k])
 
 
-def test_full_sweep_batch_matches_single(lbm):
+@pytest.mark.parametrize("variant", [0, 12])
+def test_full_sweep_batch_matches_single(lbm, variant):
     """The 25-cavity Re x Ar sweep (500 x 200 ... 500 x 1000, FP32 f - w) for
     one 1000-step graph: the smallest and the largest cavity equal their
     single-cavity runs bit for bit, and one further launch of the largest
     matches one oracle step applied to its state."""
     cases = sweep_cases(500)
     b = make_batch(lbm, cases, "f32s")
+    b.set_option(lbm.LBM_OPT_STEP_VARIANT, variant)
     assert b.info["total_sites"] == 7_500_000
     b.step(1000)
     for k in (0, 24):

@@ -98,15 +98,18 @@ def test_moments_device_writes_torch_tensors(lbm):
     assert c.steps_done == 87
 
 
+@pytest.mark.parametrize("variant", [0, 12])
 @pytest.mark.parametrize("dtype", ["f64", "f32s"])
-@pytest.mark.parametrize("every", [10, 100, 200])
-def test_probe_time_series(lbm, dtype, every):
+@pytest.mark.parametrize("every", [10, 20, 100, 200])
+def test_probe_time_series(lbm, dtype, every, variant):
     """Ring records at every `every` steps equal on-demand probes taken at
     the same steps by a twin cavity (both paths: graph chunks and single
-    launches)."""
+    launches; with the 4-step temporal variant, cadences that are not a
+    multiple of 4 fall back to one-step launches)."""
     nx, ny = 80, 64
     pts = np.array([[0.5, 0.5], [0.5, 0.3], [0.5, 0.2], [0.1, 0.1], [0.9, 0.1]])
     a = lbm.Cavity(nx, ny, re=500.0, u_lid=U_LID, dtype=dtype)
+    a.set_option(lbm.LBM_OPT_STEP_VARIANT, variant)
     b = lbm.Cavity(nx, ny, re=500.0, u_lid=U_LID, dtype=dtype)
     a.step(30)
     b.step(30)
