@@ -1,23 +1,30 @@
-"""Throughput of the fused D2Q9 BGK step on one MI355X.
+"""Throughput of the fused D2Q9 BGK update on one MI355X.
 
     python bench.py [--steps K] [--warmup W] [--ar 1.0] [--re 8000] [--dtype f32s]
 
 Workload: lid-driven cavity of 500 x (500 Ar) sites (the production lattice
 of arXiv 2211.05009, Sec. 3.2-3.3), lid speed 0.1, Re = 8000, populations
 stored as f - w in FP32, started from rest.  A "step" is one application of
-Eq. 1 to every site (one fused stream + bounce-back + collide launch) with the
-FP64 mass / Eq. 6 monitors every 100 steps, exactly as lbm_step runs them.
-The lattice is resident in device memory before timing starts.
+Eq. 1 to every site (pull streaming, half-way / moving-wall bounce-back, BGK
+collision) with the FP64 mass and Eq. 6 monitors every 100 steps, exactly as
+lbm_step runs them.  The kernel tile shape is picked by the library's
+autotuner before timing.  The lattice is resident in device memory before
+timing starts.
 
-Prints one JSON line: MLUPS (million lattice-site updates per second), the
-HBM roofline of the step kernel (72 B per site update in FP32, 144 B in FP64:
-nine populations read and nine written), per-case figures for the other
-aspect ratios and FP64 storage, and the CPU oracle timed on a bounded sample.
+One JSON line: MLUPS (million lattice-site updates per second); the HBM
+roofline of the step kernel (72 B per site update in FP32, 144 B in FP64:
+nine populations read and nine written; a multi-step launch counts K
+updates); per-case figures for the other aspect ratios and FP64 storage; the
+25-cavity Re x Ar sweep advanced as one batch against the same 25 cavities
+run one after another; a plain device copy's bandwidth on the same GPU; and
+the CPU oracle timed on a bounded sample.
 
 ``--copy-probe BYTES`` instead runs a plain device copy of BYTES bytes ten
 times (used to calibrate the rocprofv3 FETCH_SIZE / WRITE_SIZE counters).
 """
 import argparse
+import glob
+import hashlib
 import json
 import os
 import sys
@@ -29,68 +36,137 @@ sys.path.insert(0, ROOT)
 METRIC = "D2Q9 MLUPS & % HBM roofline at 500×500·Ar; sweep time-to-steady vs plain"
 HBM_PEAK_GBS = 8000.0                     # MI355X HBM3E, published
 BYTES_PER_SITE = {"f32s": 72, "f64": 144}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50000)
+    ap.add_argument("--steps", type=int, default=200000)
     ap.add_argument("--warmup", type=int, default=2000)
     ap.add_argument("--nx", type=int, default=500)
     ap.add_argument("--ar", type=float, default=1.0)
     ap.add_argument("--re", type=float, default=8000.0)
     ap.add_argument("--dtype", default="f32s", choices=["f32s", "f64"])
+    ap.add_argument("--variant", type=int, default=-1,
+                    help="step kernel shape (-1: autotune)")
     ap.add_argument("--cases", type=int, default=1,
                     help="also time Ar 0.4/1.0/2.0 in both storage types (0: skip)")
+    ap.add_argument("--sweep", type=int, default=1,
+                    help="also time the 25-cavity batch against sequential runs (0: skip)")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-steps", type=int, default=200)
-    ap.add_argument("--variant", type=int, default=-1, help="step tile shape (-1: default)")
     ap.add_argument("--copy-probe", type=int, default=0)
     return ap.parse_args()
 
 
-def time_case(lbm, torch, nx, ny, re, dtype, steps, warmup, variant=-1):
-    """Returns (seconds for `steps` steps, launches) with HIP events recorded on
-    the stream the library launches on."""
+def source_hash():
+    """Fingerprint of the HIP sources (decides whether stored counters apply)."""
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2211_05009_amd", "csrc", "*"))):
+        with open(p, "rb") as fh:
+            h.update(os.path.basename(p).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def time_single(lbm, torch, nx, ny, re, dtype, steps, warmup, variant=-1):
+    """Seconds for `steps` steps (HIP events on the library's stream), the
+    shape used and its steps per launch."""
     stream = torch.cuda.Stream()
     c = lbm.Cavity(nx, ny, re=re, u_lid=0.1, dtype=dtype)
     c.set_stream(stream)
+    c.step(warmup - warmup % 100)
     if variant >= 0:
         c.set_option(lbm.LBM_OPT_STEP_VARIANT, variant)
-    c.step(warmup)
+    else:
+        c.autotune(chunks=4, use_cache=False)
+    v = c.get_option(lbm.LBM_OPT_STEP_VARIANT)
+    k = c.get_option(lbm.LBM_OPT_STEPS_PER_LAUNCH)
+    c.step(1000)
     t_start = c.steps_done
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    e0, e1 = events(torch)
     torch.cuda.synchronize()
-    with torch.cuda.stream(stream):
-        ev0.record(stream)
-        c.step(steps)
-        ev1.record(stream)
+    e0.record(stream)
+    c.step(steps)
+    e1.record(stream)
     torch.cuda.synchronize()
-    sec = ev0.elapsed_time(ev1) / 1e3
+    sec = e0.elapsed_time(e1) / 1e3
     assert c.steps_done == t_start + steps
     mass = c.mass()
     c.close()
-    return sec, mass
+    return sec, (v, k), mass
+
+
+def kernel_of(variant, k):
+    """Kernel name of a single-cavity shape."""
+    if k > 1:
+        return "lbm::k_step_tb (K steps per launch, tile in LDS)"
+    if variant >= 8:
+        return "lbm::k_step_vec (16-byte loads)"
+    return "lbm::k_step"
+
+
+def time_sweep(lbm, torch, re_cases, dtype, steps):
+    """25-cavity sweep: one batch vs the same cavities one after another."""
+    nx, ny, re = zip(*re_cases)
+    sites = sum(a * b for a, b in zip(nx, ny))
+    stream = torch.cuda.Stream()
+    b = lbm.Batch(nx, ny, re, u_lid=0.1, dtype=dtype)
+    b.set_stream(stream)
+    b.step(1000)
+    bv, _ = b.autotune(chunks=2, use_cache=False)
+    b.step(1000)
+    e0, e1 = events(torch)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    b.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_batch = e0.elapsed_time(e1) / 1e3
+    b.close()
+    t_seq = 0.0
+    for (x, y, r) in re_cases:
+        s, _, _ = time_single(lbm, torch, x, y, r, dtype, steps, 1000)
+        t_seq += s
+    return {"cavities": len(re_cases), "sites": sites, "steps": steps, "storage": dtype,
+            "batch_variant": bv,
+            "batch_MLUPS": round(sites * steps / t_batch / 1e6, 1),
+            "sequential_MLUPS": round(sites * steps / t_seq / 1e6, 1),
+            "speedup": round(t_seq / t_batch, 3),
+            "batch_GBs_effective": round(sites * steps * BYTES_PER_SITE[dtype] / t_batch / 1e9, 1)}
+
+
+def copy_bandwidth(torch, nbytes=1 << 30):
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = events(torch)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    return round(2 * nbytes * 10 / sec / 1e9, 1)
 
 
 def cpu_baseline(nx, ny, re, steps):
     """The CPU oracle, untouched, on a bounded sample of the same workload."""
-    try:
-        from threadpoolctl import threadpool_limits
-    except ImportError:            # pragma: no cover
-        threadpool_limits = None
+    from threadpoolctl import threadpool_limits
     from oracle import d2q9
-    ctx = threadpool_limits(limits=1) if threadpool_limits else None
-    try:
+    with threadpool_limits(limits=1):
         o = d2q9.Cavity(nx, ny, re=re, u_lid=0.1)
         o.step(10)
         t0 = time.perf_counter()
         o.step(steps)
         dt = time.perf_counter() - t0
-    finally:
-        if ctx is not None:
-            ctx.__exit__(None, None, None)
     return {"value": round(nx * ny * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": 1,
             "kind": "oracle",
             "sample": f"{steps} steps of the {nx}x{ny} Re={re:g} cavity after 10 warm-up "
@@ -107,6 +183,20 @@ def copy_probe(nbytes):
     print(json.dumps({"copy_probe_bytes": nbytes, "launches": 10}), flush=True)
 
 
+def stored_traffic(kernel_variant, nx, ny, dtype):
+    """Per-launch HBM traffic measured by rocprofv3 for exactly this kernel
+    source, shape and lattice, else None."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if (t.get("source_hash") != source_hash() or t.get("variant") != kernel_variant
+            or t.get("nx") != nx or t.get("ny") != ny or t.get("storage") != dtype):
+        return None
+    return t.get("bytes_per_launch")
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -121,20 +211,24 @@ def main():
         copy_probe(args.copy_probe)
         return
     from paper_2211_05009_amd import lbm
+    from cavity_inputs import sweep_cases
     nx = args.nx
     ny = int(round(nx * args.ar))
     sites = nx * ny
 
-    sec, mass = time_case(lbm, torch, nx, ny, args.re, args.dtype, args.steps,
-                          args.warmup, args.variant)
+    sec, (variant, k), mass = time_single(lbm, torch, nx, ny, args.re, args.dtype, args.steps,
+                                          args.warmup, args.variant)
     mlups = sites * args.steps / sec / 1e6
-    per_launch = sec / args.steps
-    bpl = BYTES_PER_SITE[args.dtype] * sites            # algorithmic bytes per launch
+    per_step = sec / args.steps
+    kname = kernel_of(variant, k)
+    bpl = BYTES_PER_SITE[args.dtype] * sites * k          # algorithmic bytes per launch
+    per_launch = per_step * k
     achieved = bpl / per_launch / 1e9
+    traffic = stored_traffic(variant, nx, ny, args.dtype)
     out = {
         "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(per_launch * 1e3, 6), "higher_is_better": True,
+        "ms_per_step": round(per_step * 1e3, 6), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
         "dtype": "f32" if args.dtype == "f32s" else "f64", "data": "synthetic",
         "config": {"workload": f"lid-driven cavity {nx}x{ny} (Ar={args.ar:g}), Re={args.re:g}, "
@@ -144,26 +238,32 @@ def main():
                    "storage": args.dtype, "monitors_every": 100},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None,
-                     "kernel": "lbm::k_step (fused pull stream + bounce-back + BGK)",
-                     "bytes_per_launch": bpl,
-                     "note": "per-launch time = HIP-event time of the timed region / steps "
-                             "(includes the monitor kernels every 100 steps and launch gaps)"},
+                     "traffic": traffic, "kernel": kname, "variant": variant,
+                     "steps_per_launch": k, "bytes_per_launch": bpl,
+                     "launch_us": round(per_launch * 1e6, 3),
+                     "note": "launch time = HIP-event time of the timed region / launches "
+                             "(includes the monitor kernels every 100 steps and launch gaps); "
+                             "algorithmic bytes count 72 B (FP32) / 144 B (FP64) per site "
+                             "update, so a K-step launch can exceed the HBM peak"},
         "final_mass": mass,
+        "source_hash": source_hash(),
     }
     if args.cases:
         cases = []
         for ar in (0.4, 1.0, 2.0):
             for dt in ("f32s", "f64"):
                 nyc = int(round(nx * ar))
-                k = max(2000, args.steps // 5)
-                s, _ = time_case(lbm, torch, nx, nyc, args.re, dt, k, 1000)
-                ml = nx * nyc * k / s / 1e6
+                kk = max(10000, args.steps // 10)
+                s, (v, _), _ = time_single(lbm, torch, nx, nyc, args.re, dt, kk, 1000)
+                ml = nx * nyc * kk / s / 1e6
                 gbs = ml * BYTES_PER_SITE[dt] / 1e3
-                cases.append({"nx": nx, "ny": nyc, "storage": dt, "steps": k,
+                cases.append({"nx": nx, "ny": nyc, "storage": dt, "steps": kk, "variant": v,
                               "MLUPS": round(ml, 1), "GB/s": round(gbs, 1),
                               "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
         out["cases"] = cases
+    if args.sweep:
+        out["sweep"] = time_sweep(lbm, torch, sweep_cases(nx), "f32s", 5000)
+    out["copy_GBs"] = copy_bandwidth(torch)
     if args.cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(nx, ny, args.re, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -118,14 +118,18 @@ int lbm_info(lbm_t h, lbm_info_t *info);
  *   LBM_OPT_STEP_VARIANT  index of the step kernel's tile shape, in
  *                         [0, LBM_OPT_NUM_VARIANTS); picked by lbm_autotune.
  *   LBM_OPT_NUM_VARIANTS  read-only: number of tile shapes.
+ *   LBM_OPT_STEPS_PER_LAUNCH  read-only: steps of Eq. 1 one launch of the
+ *                         current shape applies (1, or K for the shapes that
+ *                         keep a tile in LDS for K steps).
  * LBM_EINVAL for an unknown option or an out-of-range value.
  */
 enum {
   LBM_OPT_USE_GRAPH = 1,
   LBM_OPT_STEP_VARIANT = 2,
   LBM_OPT_NUM_VARIANTS = 3,
-  LBM_OPT_GRAPH_STEPS = 4  /* batches only: steps per captured graph, a
+  LBM_OPT_GRAPH_STEPS = 4, /* batches only: steps per captured graph, a
                               multiple of 100 in [100, 100000] (default 1000) */
+  LBM_OPT_STEPS_PER_LAUNCH = 5
 };
 int lbm_set_option(lbm_t h, int option, int64_t value);
 int lbm_get_option(lbm_t h, int option, int64_t *value);

@@ -511,6 +511,7 @@ int lbm_get_option(lbm_t h, int option, int64_t *value) {
     case LBM_OPT_USE_GRAPH: *value = h->use_graph; return LBM_OK;
     case LBM_OPT_STEP_VARIANT: *value = h->variant; return LBM_OK;
     case LBM_OPT_NUM_VARIANTS: *value = kNumVariants; return LBM_OK;
+    case LBM_OPT_STEPS_PER_LAUNCH: *value = steps_per_launch(h->variant); return LBM_OK;
     default: return lbm_fail(LBM_EINVAL, "unknown option %d", option);
   }
 }

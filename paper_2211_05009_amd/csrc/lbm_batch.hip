@@ -561,6 +561,7 @@ int lbm_batch_get_option(lbm_batch_t b, int option, int64_t *value) {
     case LBM_OPT_STEP_VARIANT: *value = b->variant; return LBM_OK;
     case LBM_OPT_NUM_VARIANTS: *value = kNumShapes; return LBM_OK;
     case LBM_OPT_GRAPH_STEPS: *value = b->graph_steps; return LBM_OK;
+    case LBM_OPT_STEPS_PER_LAUNCH: *value = shape_steps(b->variant); return LBM_OK;
     default: return lbm_fail(LBM_EINVAL, "unknown option %d", option);
   }
 }

@@ -24,6 +24,7 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_EIO, LBM_ESTATE 
     0, -1, -2, -3, -4, -5, -6
 LBM_F64, LBM_F32_SHIFTED = 0, 1
 LBM_OPT_USE_GRAPH, LBM_OPT_STEP_VARIANT, LBM_OPT_NUM_VARIANTS, LBM_OPT_GRAPH_STEPS = 1, 2, 3, 4
+LBM_OPT_STEPS_PER_LAUNCH = 5
 DTYPES = {"f64": LBM_F64, "f32s": LBM_F32_SHIFTED}
 
 _ERRNAMES = {LBM_EINVAL: "LBM_EINVAL", LBM_ENOMEM: "LBM_ENOMEM",
