@@ -239,6 +239,10 @@ int lbm_get_populations(lbm_t h, double *fstar_host);
 int lbm_init_fields(lbm_t h, const double *rho_host, const double *ux_host,
                     const double *uy_host, int renormalise_mass);
 
+/* As lbm_init_fields with caller-owned *device* arrays (e.g. torch tensors). */
+int lbm_init_fields_device(lbm_t h, const double *rho_dev, const double *ux_dev,
+                           const double *uy_dev, int renormalise_mass);
+
 /*
  * Checkpoint: write / read a header (magic, version, nx, ny, dtype, steps,
  * tau, u_lid) followed by the raw stored populations.  Restoring gives a
@@ -301,6 +305,15 @@ int lbm_batch_init_fields(lbm_batch_t b, int k, const double *rho_host,
                           const double *ux_host, const double *uy_host,
                           int renormalise_mass);
 
+/* As lbm_batch_init_fields with caller-owned device arrays. */
+int lbm_batch_init_fields_device(lbm_batch_t b, int k, const double *rho_dev,
+                                 const double *ux_dev, const double *uy_dev,
+                                 int renormalise_mass);
+
+/* Lattice, Reynolds number and lid speed of cavity k (NULL outputs skipped). */
+int lbm_batch_cavity(lbm_batch_t b, int k, int *nx, int *ny, double *re,
+                     double *u_lid);
+
 /* Number of cavities, total sites, batch steps applied, device bytes held. */
 int lbm_batch_info(lbm_batch_t b, int *n, int64_t *total_sites,
                    int64_t *steps_done, size_t *device_bytes);
@@ -313,6 +326,95 @@ int lbm_batch_info(lbm_batch_t b, int *n, int64_t *total_sites,
  * the one-step shape 0. */
 int lbm_batch_autotune(lbm_batch_t b, int chunks, int use_cache,
                        int *best_variant, double *ms_per_step);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start (spec pattern 4; no counterpart in the paper).
+ *
+ * A convolutional surrogate maps (Re, Ar) to the steady field of the cavity
+ * so the lattice can start near its steady state instead of at rest
+ * (Sec. 2.2 (i)); the solver then converges by Eq. 1 as usual and the
+ * converged state does not depend on the start.
+ *
+ * Network: 4-level U-Net on a 256 (y) x 128 (x) canvas, NHWC bfloat16
+ * activations, FP32 master weights, FP32 accumulation on the BF16 matrix
+ * cores.  Input channels: cavity mask (rows y < round(128 Ar)),
+ * (x + 1/2)/128, (y + 1/2)/128, Re/3000, Ar/2.  Output channels:
+ * 100 (rho - 1), u_x / u_lid, u_y / u_lid on the 128 x round(128 Ar) cavity
+ * pixels (pixel centres at ((x + 1/2)/128, (y + 1/2)/128) in units of L).
+ * Convolutions 3 x 3, zero padding, ReLU; 2 x 2 average pooling; nearest 2x
+ * upsampling; skip concatenation.  Channel widths 32, 64, 128, 256;
+ * 1,964,448 parameters (padding included) stored as, for each of the 15
+ * convolutions in order, weights [9][ci][co] (tap = 3 dy + dx) then bias
+ * [co], with ci of the first and co of the last layer padded to 32 (padding
+ * entries must be zero).
+ * ------------------------------------------------------------------------ */
+typedef struct lbm_surrogate *lbm_sur_t;
+
+/* A surrogate for batches of up to max_batch (1..256) samples; parameters
+ * start at zero (load them with lbm_sur_set_params). */
+int lbm_sur_create(int max_batch, lbm_sur_t *out);
+int lbm_sur_destroy(lbm_sur_t s);
+int lbm_sur_set_stream(lbm_sur_t s, void *hip_stream);
+int lbm_sur_num_params(lbm_sur_t s, int64_t *n);
+
+/* Load n FP32 parameters (host, layout above); resets the optimiser. */
+int lbm_sur_set_params(lbm_sur_t s, const float *params_host, int64_t n);
+
+/* Copy the FP32 parameters and / or the gradients of the last training step
+ * to host arrays of lbm_sur_num_params floats (either may be NULL). */
+int lbm_sur_get_params(lbm_sur_t s, float *params_host, float *grads_host);
+
+/* Forward pass for n samples (Re, Ar host arrays; 0 < Ar <= 2): out_dev
+ * receives FP32 [n][256][128][3] (device). */
+int lbm_sur_forward(lbm_sur_t s, int n, const double *re, const double *ar,
+                    float *out_dev);
+
+/* One training step on n samples: masked mean-squared error against
+ * target_dev (FP32 [n][256][128][3], device) with mask_dev (FP32
+ * [n][256][128], 1 on cavity pixels), loss = sum over masked pixels and the
+ * three channels / number of masked pixels; backward pass; if apply_update,
+ * one Adam step (beta 0.9, 0.999, eps 1e-8) with learning rate lr.  *loss
+ * receives the loss before the update.  LBM_EUNSTABLE on a non-finite
+ * loss. */
+int lbm_sur_train_step(lbm_sur_t s, int n, const double *re, const double *ar,
+                       const float *target_dev, const float *mask_dev,
+                       double lr, int apply_update, double *loss);
+
+/* Warm start: predict the field for the handle's (Re, Ar = ny/nx), map it
+ * bilinearly onto the lattice (site centres in units of L, clamped to the
+ * cavity pixels), renormalise the mass to nx ny and set f = f^eq
+ * (lbm_init_fields_device).  The step counter restarts at 0. */
+int lbm_sur_warm_start(lbm_sur_t s, lbm_t h);
+int lbm_sur_warm_start_batch(lbm_sur_t s, lbm_batch_t b, int k);
+
+/* Single layer kernels (device pointers, bf16 stored as 16-bit words;
+ * tensors NHWC with a channel stride and offset so slices of a
+ * concatenation can be read or written; channel counts multiples of 32):
+ *   mode 0 forward:  out[p, oo+o] = relu?(sum_{t,c} x[p+d_t, xo+c] w[t][c][o]
+ *                                   + bias[o])
+ *   mode 1 dgrad:    out[p, oo+c] (+)= sum_{t,o} x[p-d_t, xo+o] w[t][c][o]
+ *                    (x is the output gradient, accumulate adds)
+ *   mode 2 wgrad:    out[t][c][o] += sum_p x[p+d_t, xo+c] g[p, go+o]
+ *                    (out FP32 [9][ci][co], accumulated with atomics)
+ * d_t = (dy - 1, dx - 1) for tap t = 3 dy + dx, zero outside the image. */
+int lbm_nn_conv3x3(int mode, int n, int h, int w, int ci, int co,
+                   const void *x, int xs, int xo, const void *g, int gs, int go,
+                   const void *wt, const float *bias, int relu, void *out,
+                   int os, int oo, int accumulate, void *stream);
+/* gb[o] += sum_p g[p, go+o] over npix pixels (FP32 atomics), co <= 256. */
+int lbm_nn_bias_grad(int npix, int co, const void *g, int gs, int go,
+                     float *gb, void *stream);
+/* 2 x 2 average pooling of an h x w (even) image: forward reads a slice
+ * (is, io) and writes dense [n][h/2][w/2][c]; backward reads the dense
+ * gradient and writes (or adds into, accumulate) the slice (os, oo). */
+int lbm_nn_pool2(int backward, int n, int h, int w, int c, const void *in,
+                 int is, int io, void *out, int os, int oo, int accumulate,
+                 void *stream);
+/* Nearest 2x upsampling of an h x w image: forward reads dense [n][h][w][c]
+ * and writes the slice (os, oo) of [n][2h][2w]; backward sums the gradient
+ * slice (is, io) of [n][2h][2w] into dense [n][h][w][c]. */
+int lbm_nn_up2(int backward, int n, int h, int w, int c, const void *in,
+               int is, int io, void *out, int os, int oo, void *stream);
 
 #ifdef __cplusplus
 }

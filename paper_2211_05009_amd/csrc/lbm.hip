@@ -860,20 +860,24 @@ int lbm_get_populations(lbm_t h, double *f) {
   return LBM_OK;
 }
 
-int lbm_init_fields(lbm_t h, const double *rho, const double *ux, const double *uy,
-                    int renormalise_mass) {
+static int init_fields_impl(lbm_t h, const double *rho, const double *ux, const double *uy,
+                            int renormalise_mass, bool on_device) {
   if (!h) return lbm_fail(LBM_EINVAL, "handle is NULL");
   const size_t n = (size_t)h->nx * h->ny;
-  int rc = ensure_tmp(h, 3 * n);
-  if (rc) return rc;
-  const double *src[3] = {rho, ux, uy};
-  double *d[3] = {nullptr, nullptr, nullptr};
-  for (int k = 0; k < 3; ++k)
-    if (src[k]) {
-      d[k] = h->tmp + k * n;
-      HIPC(hipMemcpyAsync(d[k], src[k], n * sizeof(double), hipMemcpyHostToDevice,
-                          h->stream));
+  const double *d[3] = {rho, ux, uy};
+  if (!on_device) {
+    int rc = ensure_tmp(h, 3 * n);
+    if (rc) return rc;
+    const double *src[3] = {rho, ux, uy};
+    for (int k = 0; k < 3; ++k) {
+      d[k] = nullptr;
+      if (src[k]) {
+        d[k] = h->tmp + k * n;
+        HIPC(hipMemcpyAsync(h->tmp + k * n, src[k], n * sizeof(double), hipMemcpyHostToDevice,
+                            h->stream));
+      }
     }
+  }
   double scale = 1.0;
   if (renormalise_mass && rho) {
     // FP64 sum of rho on the device (same fixed-order reduction as the
@@ -895,17 +899,25 @@ int lbm_init_fields(lbm_t h, const double *rho, const double *ux, const double *
   const int tot = h->pitch * h->ny;
   if (h->dtype == LBM_F64)
     hipLaunchKernelGGL((k_init_eq<double, false>), dim3((tot + 255) / 256), dim3(256), 0,
-                       h->stream, (double *)h->buf[h->cur], geom(h), d[0], d[1], d[2],
-                       scale);
+                       h->stream, (double *)h->buf[h->cur], geom(h), d[0], d[1], d[2], scale);
   else
     hipLaunchKernelGGL((k_init_eq<float, true>), dim3((tot + 255) / 256), dim3(256), 0,
-                       h->stream, (float *)h->buf[h->cur], geom(h), d[0], d[1], d[2],
-                       scale);
+                       h->stream, (float *)h->buf[h->cur], geom(h), d[0], d[1], d[2], scale);
   HIPC(hipGetLastError());
-  rc = reset_counters(h);
+  int rc = reset_counters(h);
   if (rc) return rc;
   HIPC(hipStreamSynchronize(h->stream));
   return LBM_OK;
+}
+
+int lbm_init_fields(lbm_t h, const double *rho, const double *ux, const double *uy,
+                    int renormalise_mass) {
+  return init_fields_impl(h, rho, ux, uy, renormalise_mass, false);
+}
+
+int lbm_init_fields_device(lbm_t h, const double *rho, const double *ux, const double *uy,
+                           int renormalise_mass) {
+  return init_fields_impl(h, rho, ux, uy, renormalise_mass, true);
 }
 
 // Checkpoint file: header, stored populations of buf[cur], Eq. 6 reference.

@@ -732,20 +732,25 @@ int lbm_batch_set_populations(lbm_batch_t b, int k, const double *f) {
   return LBM_OK;
 }
 
-int lbm_batch_init_fields(lbm_batch_t b, int k, const double *rho, const double *ux,
-                          const double *uy, int renormalise_mass) {
+static int batch_init_impl(lbm_batch_t b, int k, const double *rho, const double *ux,
+                           const double *uy, int renormalise_mass, bool on_device) {
   if (!valid_k(b, k)) return lbm_fail(LBM_EINVAL, "cavity index %d out of range", k);
   const Geometry g = cav_geom(b, k);
   const size_t n = (size_t)g.nx * g.ny;
-  int rc = ensure_tmp(b, 3 * n);
-  if (rc) return rc;
-  const double *src[3] = {rho, ux, uy};
-  double *d[3] = {nullptr, nullptr, nullptr};
-  for (int j = 0; j < 3; ++j)
-    if (src[j]) {
-      d[j] = b->tmp + j * n;
-      HIPC(hipMemcpyAsync(d[j], src[j], n * sizeof(double), hipMemcpyHostToDevice, b->stream));
+  const double *d[3] = {rho, ux, uy};
+  if (!on_device) {
+    int rc = ensure_tmp(b, 3 * n);
+    if (rc) return rc;
+    const double *src[3] = {rho, ux, uy};
+    for (int j = 0; j < 3; ++j) {
+      d[j] = nullptr;
+      if (src[j]) {
+        d[j] = b->tmp + j * n;
+        HIPC(hipMemcpyAsync(b->tmp + j * n, src[j], n * sizeof(double), hipMemcpyHostToDevice,
+                            b->stream));
+      }
     }
+  }
   double scale = 1.0;
   if (renormalise_mass && rho) {
     const int blocks = std::min(kRedBlocks, (int)((n + kRedThreads - 1) / kRedThreads));
@@ -765,9 +770,28 @@ int lbm_batch_init_fields(lbm_batch_t b, int k, const double *rho, const double 
   if (b->dtype == LBM_F64) launch_init_eq<double, false>(b, k, d[0], d[1], d[2], scale);
   else launch_init_eq<float, true>(b, k, d[0], d[1], d[2], scale);
   HIPC(hipGetLastError());
-  rc = reset_cavity(b, k);
+  int rc = reset_cavity(b, k);
   if (rc) return rc;
   HIPC(hipStreamSynchronize(b->stream));
+  return LBM_OK;
+}
+
+int lbm_batch_init_fields(lbm_batch_t b, int k, const double *rho, const double *ux,
+                          const double *uy, int renormalise_mass) {
+  return batch_init_impl(b, k, rho, ux, uy, renormalise_mass, false);
+}
+
+int lbm_batch_init_fields_device(lbm_batch_t b, int k, const double *rho, const double *ux,
+                                 const double *uy, int renormalise_mass) {
+  return batch_init_impl(b, k, rho, ux, uy, renormalise_mass, true);
+}
+
+int lbm_batch_cavity(lbm_batch_t b, int k, int *nx, int *ny, double *re, double *u_lid) {
+  if (!valid_k(b, k)) return lbm_fail(LBM_EINVAL, "cavity index %d out of range", k);
+  if (nx) *nx = b->nx[k];
+  if (ny) *ny = b->ny[k];
+  if (re) *re = b->re[k];
+  if (u_lid) *u_lid = b->u_lid;
   return LBM_OK;
 }
 

@@ -1,0 +1,623 @@
+// lbm_nn.hip -- the warm-start surrogate: BF16 MFMA layer kernels behind a
+// C ABI, and a native driver of the whole network (forward, backward, Adam)
+// (contracts in include/lbm.h, section "Learned warm start").
+//
+// Network (a 4-level U-Net on a 256 x 128 canvas, NHWC bf16, channel counts
+// padded to multiples of 32):
+//   level 0 (256 x 128): conv 5(32)->32, conv 32->32 = skip0
+//   level 1 (128 x 64):  avgpool, conv 32->64, conv 64->64 = skip1
+//   level 2 (64 x 32):   avgpool, conv 64->128, conv 128->128 = skip2
+//   level 3 (32 x 16):   avgpool, conv 128->256, conv 256->256
+//   decoder: nearest 2x up, concat skip, conv (256+128)->128, 128->128;
+//            up, concat, (128+64)->64, 64->64; up, concat, (64+32)->32,
+//            32->32; head conv 32->3 (stored as 32 output channels)
+// All convolutions are 3 x 3 with zero padding, bias, ReLU except the head.
+// Skip tensors live directly in their concatenation buffer's channel slice.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_internal.h"
+#include "nn_kernels.hpp"
+
+using namespace lbm::nn;
+
+namespace {
+
+inline unsigned blocks_for(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t conv_launch(int mode, const ConvArgs &a, hipStream_t st) {
+  const int HW = a.h * a.w;
+  if (mode == FWD) {
+    dim3 grid((a.n * HW + 63) / 64, (a.co + 63) / 64);
+    hipLaunchKernelGGL(k_conv3x3<FWD>, grid, dim3(256), 0, st, a);
+  } else if (mode == DGRAD) {
+    dim3 grid((a.n * HW + 63) / 64, (a.ci + 63) / 64);
+    hipLaunchKernelGGL(k_conv3x3<DGRAD>, grid, dim3(256), 0, st, a);
+  } else {
+    const int npix = a.n * HW;
+    dim3 grid((9 * a.ci + 63) / 64, (a.co + 63) / 64, (npix + a.kchunk - 1) / a.kchunk);
+    hipLaunchKernelGGL(k_conv3x3<WGRAD>, grid, dim3(256), 0, st, a);
+  }
+  return hipGetLastError();
+}
+
+bool chan_ok(int c) { return c >= 32 && c <= 1024 && c % 32 == 0; }
+
+// ------------------------------------------------------------------ network
+constexpr int kH = 256, kW = 128;   // canvas rows (y) x columns (x)
+constexpr int kInCh = 5, kOutCh = 3;
+
+struct View {
+  int buf;      // index into the activation arena list
+  int cs, co;   // channel stride, channel offset
+};
+
+enum OpType { OP_CONV, OP_POOL, OP_UP };
+
+struct Op {
+  OpType type;
+  int level;            // spatial level of the input
+  int ci, co, relu;     // conv: channels in/out; pool/up: channels = ci
+  View in, out;
+  size_t woff, boff;    // conv parameter offsets (floats)
+};
+
+struct Buf {
+  int level, ch;
+};
+
+}  // namespace
+
+struct lbm_surrogate {
+  int nmax = 0;
+  std::vector<Buf> bufs;
+  std::vector<Op> ops;
+  size_t nparams = 0;
+  std::vector<size_t> act_off;   // element offsets of each buffer (per batch of nmax)
+  size_t act_elems = 0;
+  uint16_t *act = nullptr, *gact = nullptr;     // activations and their gradients
+  float *w = nullptr, *m = nullptr, *v = nullptr, *gw = nullptr;   // FP32 params
+  uint16_t *wb = nullptr;                        // bf16 copy of the params
+  float *target = nullptr, *mask = nullptr, *out3 = nullptr;
+  float *loss_dev = nullptr, *loss_host = nullptr;
+  double *rearr = nullptr;                       // [2 nmax] (Re, Ar)
+  double *field = nullptr;                       // warm-start fields
+  size_t field_doubles = 0;
+  int64_t adam_t = 0;
+  hipStream_t stream = nullptr, own_stream = nullptr;
+};
+
+namespace {
+
+int level_h(int l) { return kH >> l; }
+int level_w(int l) { return kW >> l; }
+
+int add_buf(lbm_surrogate *s, int level, int ch) {
+  s->bufs.push_back({level, ch});
+  return (int)s->bufs.size() - 1;
+}
+
+void add_conv(lbm_surrogate *s, int level, int ci, int co, int relu, View in, View out) {
+  Op o;
+  o.type = OP_CONV;
+  o.level = level;
+  o.ci = ci;
+  o.co = co;
+  o.relu = relu;
+  o.in = in;
+  o.out = out;
+  o.woff = s->nparams;
+  s->nparams += (size_t)9 * ci * co;
+  o.boff = s->nparams;
+  s->nparams += co;
+  s->ops.push_back(o);
+}
+
+void add_pool(lbm_surrogate *s, int level, int c, View in, View out) {
+  Op o{};
+  o.type = OP_POOL;
+  o.level = level;
+  o.ci = o.co = c;
+  o.in = in;
+  o.out = out;
+  s->ops.push_back(o);
+}
+
+void add_up(lbm_surrogate *s, int level, int c, View in, View out) {
+  Op o{};
+  o.type = OP_UP;
+  o.level = level;   // level of the (low-resolution) input
+  o.ci = o.co = c;
+  o.in = in;
+  o.out = out;
+  s->ops.push_back(o);
+}
+
+void build_net(lbm_surrogate *s) {
+  const int X0 = add_buf(s, 0, 32), A0 = add_buf(s, 0, 32), C0 = add_buf(s, 0, 96);
+  const int P0 = add_buf(s, 1, 32), A1 = add_buf(s, 1, 64), C1 = add_buf(s, 1, 192);
+  const int P1 = add_buf(s, 2, 64), A2 = add_buf(s, 2, 128), C2 = add_buf(s, 2, 384);
+  const int P2 = add_buf(s, 3, 128), B0 = add_buf(s, 3, 256), B1 = add_buf(s, 3, 256);
+  const int D2a = add_buf(s, 2, 128), D2b = add_buf(s, 2, 128);
+  const int D1a = add_buf(s, 1, 64), D1b = add_buf(s, 1, 64);
+  const int D0a = add_buf(s, 0, 32), D0b = add_buf(s, 0, 32), Y = add_buf(s, 0, 32);
+  auto full = [&](int b) { return View{b, s->bufs[b].ch, 0}; };
+  add_conv(s, 0, 32, 32, 1, full(X0), full(A0));
+  add_conv(s, 0, 32, 32, 1, full(A0), View{C0, 96, 64});
+  add_pool(s, 0, 32, View{C0, 96, 64}, full(P0));
+  add_conv(s, 1, 32, 64, 1, full(P0), full(A1));
+  add_conv(s, 1, 64, 64, 1, full(A1), View{C1, 192, 128});
+  add_pool(s, 1, 64, View{C1, 192, 128}, full(P1));
+  add_conv(s, 2, 64, 128, 1, full(P1), full(A2));
+  add_conv(s, 2, 128, 128, 1, full(A2), View{C2, 384, 256});
+  add_pool(s, 2, 128, View{C2, 384, 256}, full(P2));
+  add_conv(s, 3, 128, 256, 1, full(P2), full(B0));
+  add_conv(s, 3, 256, 256, 1, full(B0), full(B1));
+  add_up(s, 3, 256, full(B1), View{C2, 384, 0});
+  add_conv(s, 2, 384, 128, 1, full(C2), full(D2a));
+  add_conv(s, 2, 128, 128, 1, full(D2a), full(D2b));
+  add_up(s, 2, 128, full(D2b), View{C1, 192, 0});
+  add_conv(s, 1, 192, 64, 1, full(C1), full(D1a));
+  add_conv(s, 1, 64, 64, 1, full(D1a), full(D1b));
+  add_up(s, 1, 64, full(D1b), View{C0, 96, 0});
+  add_conv(s, 0, 96, 32, 1, full(C0), full(D0a));
+  add_conv(s, 0, 32, 32, 1, full(D0a), full(D0b));
+  add_conv(s, 0, 32, 32, 0, full(D0b), full(Y));
+}
+
+uint16_t *bptr(lbm_surrogate *s, uint16_t *base, const View &v) {
+  return base + s->act_off[v.buf];
+}
+
+// Encode (Re, Ar) pairs into the input canvas: channel 0 = cavity mask
+// (rows y < round(128 Ar)), 1 = (x + 1/2)/128, 2 = (y + 1/2)/128,
+// 3 = Re / 3000, 4 = Ar / 2, channels 5-31 zero.
+__global__ void k_encode(const double *ra, int n, uint16_t *x) {
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= (long long)n * kH * kW) return;
+  const int b = i / (kH * kW), r = i % (kH * kW), y = r / kW, xx = r % kW;
+  const double re = ra[2 * b], ar = ra[2 * b + 1];
+  const int ny = (int)rint(128.0 * ar);
+  float ch[kInCh] = {y < ny ? 1.f : 0.f, (xx + 0.5f) / 128.f, (y + 0.5f) / 128.f,
+                     (float)(re / 3000.0), (float)(ar / 2.0)};
+  uint16_t *o = x + i * 32;
+  for (int c = 0; c < 32; ++c) o[c] = c < kInCh ? f2bf(ch[c]) : (uint16_t)0;
+}
+
+// Head output channels 0..2 -> FP32 [n][H][W][3].
+__global__ void k_extract(const uint16_t *y, long long npix, float *out) {
+  const long long i = blockIdx.x * 256LL + threadIdx.x;
+  if (i >= npix * kOutCh) return;
+  out[i] = bf2f(y[(i / kOutCh) * 32 + i % kOutCh]);
+}
+
+// Bilinear map of sample 0's prediction (rows < ny_c of the canvas) onto an
+// nx x ny lattice: site (i, j) at ((i + 1/2)/nx, (j + 1/2)/nx) in units of L
+// reads canvas position ((i + 1/2) 128/nx - 1/2, (j + 1/2) 128/nx - 1/2),
+// clamped to the cavity's pixel centres.  Output rho = 1 + c0 / 100,
+// u = u_lid c1, v = u_lid c2 (FP64 [ny][nx] each).
+__global__ void k_to_lattice(const float *p3, int ny_c, int nx, int ny, double u_lid,
+                             double *rho, double *ux, double *uy) {
+  const long long k = blockIdx.x * 256LL + threadIdx.x;
+  if (k >= (long long)nx * ny) return;
+  const int j = k / nx, i = k % nx;
+  double X = (i + 0.5) * 128.0 / nx - 0.5, Y = (j + 0.5) * 128.0 / nx - 0.5;
+  X = fmin(fmax(X, 0.0), 127.0);
+  Y = fmin(fmax(Y, 0.0), (double)(ny_c - 1));
+  int x0 = (int)floor(X), y0 = (int)floor(Y);
+  if (x0 > 126) x0 = 126;
+  if (y0 > ny_c - 2) y0 = max(ny_c - 2, 0);
+  const int x1 = x0 + 1, y1 = min(y0 + 1, ny_c - 1);
+  const double tx = X - x0, ty = Y - y0;
+  double v[3];
+  for (int c = 0; c < 3; ++c) {
+    auto at = [&](int yy, int xx) { return (double)p3[((size_t)yy * kW + xx) * 3 + c]; };
+    v[c] = (1 - tx) * (1 - ty) * at(y0, x0) + tx * (1 - ty) * at(y0, x1) +
+           (1 - tx) * ty * at(y1, x0) + tx * ty * at(y1, x1);
+  }
+  rho[k] = 1.0 + v[0] / 100.0;
+  ux[k] = u_lid * v[1];
+  uy[k] = u_lid * v[2];
+}
+
+int forward(lbm_surrogate *s, int n) {
+  hipStream_t st = s->stream;
+  for (const Op &o : s->ops) {
+    const int h = level_h(o.level), w = level_w(o.level);
+    if (o.type == OP_CONV) {
+      ConvArgs a{};
+      a.n = n;
+      a.h = h;
+      a.w = w;
+      a.ci = o.ci;
+      a.co = o.co;
+      a.x = bptr(s, s->act, o.in);
+      a.xs = o.in.cs;
+      a.xo = o.in.co;
+      a.wt = s->wb + o.woff;
+      a.bias = s->w + o.boff;
+      a.relu = o.relu;
+      a.out = bptr(s, s->act, o.out);
+      a.os = o.out.cs;
+      a.oo = o.out.co;
+      HIPC(conv_launch(FWD, a, st));
+    } else if (o.type == OP_POOL) {
+      hipLaunchKernelGGL(k_pool_fwd, dim3(blocks_for((long long)n * h * w * o.ci / 4)), dim3(256),
+                         0, st, bptr(s, s->act, o.in), o.in.cs, o.in.co, n, h, w, o.ci,
+                         bptr(s, s->act, o.out));
+      HIPC(hipGetLastError());
+    } else {
+      hipLaunchKernelGGL(k_up_fwd, dim3(blocks_for((long long)n * 4 * h * w * o.ci)), dim3(256), 0,
+                         st, bptr(s, s->act, o.in), n, h, w, o.ci, bptr(s, s->act, o.out),
+                         o.out.cs, o.out.co);
+      HIPC(hipGetLastError());
+    }
+  }
+  return LBM_OK;
+}
+
+int backward(lbm_surrogate *s, int n) {
+  hipStream_t st = s->stream;
+  HIPC(hipMemsetAsync(s->gw, 0, s->nparams * sizeof(float), st));
+  for (int k = (int)s->ops.size() - 1; k >= 0; --k) {
+    const Op &o = s->ops[k];
+    const int h = level_h(o.level), w = level_w(o.level);
+    if (o.type == OP_CONV) {
+      const long long npix = (long long)n * h * w;
+      uint16_t *gy = bptr(s, s->gact, o.out);
+      if (o.relu) {
+        hipLaunchKernelGGL(k_relu_bwd, dim3(blocks_for(npix * o.co)), dim3(256), 0, st,
+                           bptr(s, s->act, o.out), o.out.cs, o.out.co, gy, o.out.cs, o.out.co,
+                           npix, o.co);
+        HIPC(hipGetLastError());
+      }
+      ConvArgs a{};
+      a.n = n;
+      a.h = h;
+      a.w = w;
+      a.ci = o.ci;
+      a.co = o.co;
+      a.x = bptr(s, s->act, o.in);
+      a.xs = o.in.cs;
+      a.xo = o.in.co;
+      a.g = gy;
+      a.gs = o.out.cs;
+      a.go = o.out.co;
+      a.out = s->gw + o.woff;
+      a.kchunk = 2048;
+      HIPC(conv_launch(WGRAD, a, st));
+      const int chunk = 256;
+      hipLaunchKernelGGL(k_bias_grad, dim3(blocks_for(npix, chunk)), dim3(256), 0, st, gy,
+                         o.out.cs, o.out.co, (int)npix, o.co, chunk, s->gw + o.boff);
+      HIPC(hipGetLastError());
+      if (k > 0) {   // the network input needs no gradient
+        ConvArgs d{};
+        d.n = n;
+        d.h = h;
+        d.w = w;
+        d.ci = o.ci;
+        d.co = o.co;
+        d.x = gy;
+        d.xs = o.out.cs;
+        d.xo = o.out.co;
+        d.wt = s->wb + o.woff;
+        d.out = bptr(s, s->gact, o.in);
+        d.os = o.in.cs;
+        d.oo = o.in.co;
+        d.accumulate = 0;
+        HIPC(conv_launch(DGRAD, d, st));
+      }
+    } else if (o.type == OP_POOL) {
+      // skip slice: add to the gradient the decoder already wrote there
+      hipLaunchKernelGGL(k_pool_bwd, dim3(blocks_for((long long)n * h * w * o.ci)), dim3(256), 0,
+                         st, bptr(s, s->gact, o.out), n, h, w, o.ci, bptr(s, s->gact, o.in),
+                         o.in.cs, o.in.co, 1);
+      HIPC(hipGetLastError());
+    } else {
+      hipLaunchKernelGGL(k_up_bwd, dim3(blocks_for((long long)n * h * w * o.ci)), dim3(256), 0, st,
+                         bptr(s, s->gact, o.out), o.out.cs, o.out.co, n, h, w, o.ci,
+                         bptr(s, s->gact, o.in));
+      HIPC(hipGetLastError());
+    }
+  }
+  return LBM_OK;
+}
+
+const View &head_view(lbm_surrogate *s) { return s->ops.back().out; }
+
+int encode(lbm_surrogate *s, int n, const double *re, const double *ar) {
+  std::vector<double> ra(2 * n);
+  for (int b = 0; b < n; ++b) {
+    if (!(re[b] > 0.0) || !(ar[b] > 0.0) || !std::isfinite(re[b]) || 128.0 * ar[b] > kH + 0.5)
+      return lbm_fail(LBM_EINVAL, "sample %d: Re = %g, Ar = %g outside (0, inf) x (0, 2]", b,
+                      re[b], ar[b]);
+    ra[2 * b] = re[b];
+    ra[2 * b + 1] = ar[b];
+  }
+  HIPC(hipMemcpyAsync(s->rearr, ra.data(), 2 * n * sizeof(double), hipMemcpyHostToDevice,
+                      s->stream));
+  const View x0{0, 32, 0};
+  hipLaunchKernelGGL(k_encode, dim3(blocks_for((long long)n * kH * kW)), dim3(256), 0, s->stream,
+                     s->rearr, n, bptr(s, s->act, x0));
+  HIPC(hipGetLastError());
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+// ------------------------------------------------------------ layer kernels
+int lbm_nn_conv3x3(int mode, int n, int h, int w, int ci, int co, const void *x, int xs, int xo,
+                   const void *g, int gs, int go, const void *wt, const float *bias, int relu,
+                   void *out, int os, int oo, int accumulate, void *stream) {
+  if (mode < 0 || mode > 2) return lbm_fail(LBM_EINVAL, "mode %d", mode);
+  if (n < 1 || h < 1 || w < 1 || !chan_ok(ci) || !chan_ok(co))
+    return lbm_fail(LBM_EINVAL, "bad shape n %d h %d w %d ci %d co %d", n, h, w, ci, co);
+  if (!x || !out || (mode != WGRAD && !wt) || (mode == WGRAD && !g))
+    return lbm_fail(LBM_EINVAL, "NULL tensor");
+  ConvArgs a{};
+  a.n = n;
+  a.h = h;
+  a.w = w;
+  a.ci = ci;
+  a.co = co;
+  a.x = (const uint16_t *)x;
+  a.xs = xs;
+  a.xo = xo;
+  a.g = (const uint16_t *)g;
+  a.gs = gs;
+  a.go = go;
+  a.wt = (const uint16_t *)wt;
+  a.bias = bias;
+  a.relu = relu;
+  a.out = out;
+  a.os = os;
+  a.oo = oo;
+  a.accumulate = accumulate;
+  a.kchunk = 2048;
+  const int cin = mode == DGRAD ? co : ci, cout = mode == DGRAD ? ci : co;
+  if (mode != WGRAD && (xs < cin || xo < 0 || xo + cin > xs || xs % 8 || xo % 8 || os < cout ||
+                        oo < 0 || oo + cout > os))
+    return lbm_fail(LBM_EINVAL, "bad channel stride / offset");
+  HIPC(conv_launch(mode, a, (hipStream_t)stream));
+  return LBM_OK;
+}
+
+int lbm_nn_bias_grad(int npix, int co, const void *g, int gs, int go, float *gb, void *stream) {
+  if (npix < 1 || co < 1 || co > 256 || !g || !gb) return lbm_fail(LBM_EINVAL, "bad arguments");
+  hipLaunchKernelGGL(k_bias_grad, dim3(blocks_for(npix, 256)), dim3(256), 0, (hipStream_t)stream,
+                     (const uint16_t *)g, gs, go, npix, co, 256, gb);
+  HIPC(hipGetLastError());
+  return LBM_OK;
+}
+
+int lbm_nn_pool2(int backward, int n, int h, int w, int c, const void *in, int is, int io,
+                 void *out, int os, int oo, int accumulate, void *stream) {
+  if (n < 1 || h < 2 || w < 2 || h % 2 || w % 2 || c < 1 || !in || !out)
+    return lbm_fail(LBM_EINVAL, "bad pool arguments");
+  hipStream_t st = (hipStream_t)stream;
+  if (!backward) {   // in: [n][h][w] slice (is, io); out dense [n][h/2][w/2][c]
+    hipLaunchKernelGGL(k_pool_fwd, dim3(blocks_for((long long)n * h * w * c / 4)), dim3(256), 0,
+                       st, (const uint16_t *)in, is, io, n, h, w, c, (uint16_t *)out);
+  } else {           // in: dense gradient [n][h/2][w/2][c]; out: slice (os, oo)
+    hipLaunchKernelGGL(k_pool_bwd, dim3(blocks_for((long long)n * h * w * c)), dim3(256), 0, st,
+                       (const uint16_t *)in, n, h, w, c, (uint16_t *)out, os, oo, accumulate);
+  }
+  HIPC(hipGetLastError());
+  return LBM_OK;
+}
+
+int lbm_nn_up2(int backward, int n, int h, int w, int c, const void *in, int is, int io,
+               void *out, int os, int oo, void *stream) {
+  if (n < 1 || h < 1 || w < 1 || c < 1 || !in || !out)
+    return lbm_fail(LBM_EINVAL, "bad upsample arguments");
+  hipStream_t st = (hipStream_t)stream;
+  if (!backward)   // in dense [n][h][w][c] -> out slice of [n][2h][2w]
+    hipLaunchKernelGGL(k_up_fwd, dim3(blocks_for((long long)n * 4 * h * w * c)), dim3(256), 0, st,
+                       (const uint16_t *)in, n, h, w, c, (uint16_t *)out, os, oo);
+  else             // in: gradient slice of [n][2h][2w] -> out dense [n][h][w][c]
+    hipLaunchKernelGGL(k_up_bwd, dim3(blocks_for((long long)n * h * w * c)), dim3(256), 0, st,
+                       (const uint16_t *)in, is, io, n, h, w, c, (uint16_t *)out);
+  HIPC(hipGetLastError());
+  return LBM_OK;
+}
+
+// ------------------------------------------------------------------ driver
+int lbm_sur_destroy(lbm_sur_t s) {
+  if (!s) return LBM_OK;
+  if (s->stream) (void)hipStreamSynchronize(s->stream);
+  void *ptrs[] = {s->act, s->gact, s->w, s->m, s->v, s->gw, s->wb, s->target, s->mask, s->out3,
+                  s->loss_dev, s->rearr, s->field};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  if (s->loss_host) (void)hipHostFree(s->loss_host);
+  if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
+  delete s;
+  return LBM_OK;
+}
+
+int lbm_sur_create(int max_batch, lbm_sur_t *out) {
+  if (!out) return lbm_fail(LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (max_batch < 1 || max_batch > 256)
+    return lbm_fail(LBM_EINVAL, "max_batch %d outside [1, 256]", max_batch);
+  lbm_surrogate *s = new (std::nothrow) lbm_surrogate();
+  if (!s) return lbm_fail(LBM_ENOMEM, "host allocation");
+  s->nmax = max_batch;
+  build_net(s);
+  for (const Buf &b : s->bufs) {
+    s->act_off.push_back(s->act_elems);
+    s->act_elems += (size_t)max_batch * level_h(b.level) * level_w(b.level) * b.ch;
+  }
+  const size_t npix = (size_t)max_batch * kH * kW;
+  auto bail = [&](int rc) {
+    lbm_sur_destroy(s);
+    return rc;
+  };
+  hipError_t e = hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking);
+  s->stream = s->own_stream;
+  void **allocs[] = {(void **)&s->act,    (void **)&s->gact,  (void **)&s->w,
+                     (void **)&s->m,      (void **)&s->v,     (void **)&s->gw,
+                     (void **)&s->wb,     (void **)&s->target, (void **)&s->mask,
+                     (void **)&s->out3,   (void **)&s->loss_dev, (void **)&s->rearr};
+  const size_t sizes[] = {s->act_elems * 2, s->act_elems * 2, s->nparams * 4, s->nparams * 4,
+                          s->nparams * 4,   s->nparams * 4,   s->nparams * 2, npix * 3 * 4,
+                          npix * 4,         npix * 3 * 4,     16,             (size_t)max_batch * 16};
+  for (int i = 0; i < 12 && e == hipSuccess; ++i) e = hipMalloc(allocs[i], sizes[i]);
+  if (e == hipSuccess) e = hipMemsetAsync(s->act, 0, s->act_elems * 2, s->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(s->gact, 0, s->act_elems * 2, s->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(s->w, 0, s->nparams * 4, s->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(s->m, 0, s->nparams * 4, s->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(s->v, 0, s->nparams * 4, s->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(s->wb, 0, s->nparams * 2, s->stream);
+  if (e == hipSuccess) e = hipHostMalloc(&s->loss_host, 16, hipHostMallocDefault);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess)
+    return bail(lbm_fail(e == hipErrorOutOfMemory ? LBM_ENOMEM : LBM_EDEVICE, "surrogate setup: %s",
+                         hipGetErrorString(e)));
+  *out = s;
+  return LBM_OK;
+}
+
+int lbm_sur_num_params(lbm_sur_t s, int64_t *n) {
+  if (!s || !n) return lbm_fail(LBM_EINVAL, "NULL argument");
+  *n = (int64_t)s->nparams;
+  return LBM_OK;
+}
+
+int lbm_sur_set_stream(lbm_sur_t s, void *hip_stream) {
+  if (!s) return lbm_fail(LBM_EINVAL, "surrogate is NULL");
+  HIPC(hipStreamSynchronize(s->stream));
+  s->stream = hip_stream ? (hipStream_t)hip_stream : s->own_stream;
+  return LBM_OK;
+}
+
+int lbm_sur_set_params(lbm_sur_t s, const float *params_host, int64_t n) {
+  if (!s || !params_host) return lbm_fail(LBM_EINVAL, "NULL argument");
+  if (n != (int64_t)s->nparams)
+    return lbm_fail(LBM_EINVAL, "expected %zu parameters, got %lld", s->nparams, (long long)n);
+  HIPC(hipMemcpyAsync(s->w, params_host, s->nparams * 4, hipMemcpyHostToDevice, s->stream));
+  HIPC(hipMemsetAsync(s->m, 0, s->nparams * 4, s->stream));
+  HIPC(hipMemsetAsync(s->v, 0, s->nparams * 4, s->stream));
+  hipLaunchKernelGGL(k_to_bf16, dim3(blocks_for((long long)s->nparams)), dim3(256), 0, s->stream,
+                     s->w, s->wb, (long long)s->nparams);
+  HIPC(hipGetLastError());
+  s->adam_t = 0;
+  HIPC(hipStreamSynchronize(s->stream));
+  return LBM_OK;
+}
+
+int lbm_sur_get_params(lbm_sur_t s, float *params_host, float *grads_host) {
+  if (!s) return lbm_fail(LBM_EINVAL, "NULL argument");
+  HIPC(hipStreamSynchronize(s->stream));
+  if (params_host) HIPC(hipMemcpy(params_host, s->w, s->nparams * 4, hipMemcpyDeviceToHost));
+  if (grads_host) HIPC(hipMemcpy(grads_host, s->gw, s->nparams * 4, hipMemcpyDeviceToHost));
+  return LBM_OK;
+}
+
+int lbm_sur_forward(lbm_sur_t s, int n, const double *re, const double *ar, float *out_dev) {
+  if (!s || !re || !ar || !out_dev) return lbm_fail(LBM_EINVAL, "NULL argument");
+  if (n < 1 || n > s->nmax) return lbm_fail(LBM_EINVAL, "n = %d outside [1, %d]", n, s->nmax);
+  int rc = encode(s, n, re, ar);
+  if (rc) return rc;
+  rc = forward(s, n);
+  if (rc) return rc;
+  const long long npix = (long long)n * kH * kW;
+  hipLaunchKernelGGL(k_extract, dim3(blocks_for(npix * kOutCh)), dim3(256), 0, s->stream,
+                     bptr(s, s->act, head_view(s)), npix, out_dev);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(s->stream));
+  return LBM_OK;
+}
+
+int lbm_sur_train_step(lbm_sur_t s, int n, const double *re, const double *ar,
+                       const float *target_dev, const float *mask_dev, double lr,
+                       int apply_update, double *loss) {
+  if (!s || !re || !ar || !target_dev || !mask_dev) return lbm_fail(LBM_EINVAL, "NULL argument");
+  if (n < 1 || n > s->nmax) return lbm_fail(LBM_EINVAL, "n = %d outside [1, %d]", n, s->nmax);
+  if (!(lr >= 0.0) || !std::isfinite(lr)) return lbm_fail(LBM_EINVAL, "lr = %g", lr);
+  double count = 0.0;
+  for (int b = 0; b < n; ++b) count += 128.0 * std::rint(128.0 * ar[b]);
+  int rc = encode(s, n, re, ar);
+  if (rc) return rc;
+  rc = forward(s, n);
+  if (rc) return rc;
+  const long long npix = (long long)n * kH * kW;
+  HIPC(hipMemsetAsync(s->loss_dev, 0, sizeof(float), s->stream));
+  const View &hv = head_view(s);
+  hipLaunchKernelGGL(k_mse, dim3(blocks_for(npix)), dim3(256), 0, s->stream,
+                     bptr(s, s->act, hv), hv.cs, target_dev, mask_dev, npix, kOutCh,
+                     (float)(1.0 / count), bptr(s, s->gact, hv), hv.cs, s->loss_dev);
+  HIPC(hipGetLastError());
+  rc = backward(s, n);
+  if (rc) return rc;
+  if (apply_update) {
+    s->adam_t += 1;
+    const double b1 = 0.9, b2 = 0.999;
+    const double c1 = 1.0 / (1.0 - std::pow(b1, (double)s->adam_t));
+    const double c2 = 1.0 / (1.0 - std::pow(b2, (double)s->adam_t));
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for((long long)s->nparams)), dim3(256), 0, s->stream,
+                       s->w, s->m, s->v, s->gw, s->wb, (long long)s->nparams, (float)lr, (float)b1,
+                       (float)b2, 1e-8f, (float)c1, (float)c2);
+    HIPC(hipGetLastError());
+  }
+  HIPC(hipMemcpyAsync(s->loss_host, s->loss_dev, sizeof(float), hipMemcpyDeviceToHost, s->stream));
+  HIPC(hipStreamSynchronize(s->stream));
+  if (loss) *loss = (double)s->loss_host[0];
+  if (!std::isfinite(s->loss_host[0])) return lbm_fail(LBM_EUNSTABLE, "non-finite loss");
+  return LBM_OK;
+}
+
+// Predict the steady field of an nx x ny cavity at Reynolds number re and map
+// it onto the lattice: s->field = (rho, ux, uy), each [ny][nx].
+static int predict_lattice(lbm_sur_t s, int nx, int ny, double re, double u_lid) {
+  const double ar = (double)ny / nx;
+  int rc = lbm_sur_forward(s, 1, &re, &ar, s->out3);
+  if (rc) return rc;
+  const size_t n = (size_t)nx * ny;
+  if (s->field_doubles < 3 * n) {
+    if (s->field) HIPC(hipFree(s->field));
+    s->field = nullptr;
+    s->field_doubles = 0;
+    HIPC(hipMalloc(&s->field, 3 * n * sizeof(double)));
+    s->field_doubles = 3 * n;
+  }
+  const int ny_c = (int)std::rint(128.0 * ar);
+  hipLaunchKernelGGL(k_to_lattice, dim3(blocks_for((long long)n)), dim3(256), 0, s->stream,
+                     s->out3, std::max(ny_c, 2), nx, ny, u_lid, s->field, s->field + n,
+                     s->field + 2 * n);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(s->stream));
+  return LBM_OK;
+}
+
+int lbm_sur_warm_start(lbm_sur_t s, lbm_t h) {
+  if (!s || !h) return lbm_fail(LBM_EINVAL, "NULL argument");
+  lbm_info_t info;
+  int rc = lbm_info(h, &info);
+  if (rc) return rc;
+  rc = predict_lattice(s, info.nx, info.ny, info.re, info.u_lid);
+  if (rc) return rc;
+  const size_t n = (size_t)info.nx * info.ny;
+  return lbm_init_fields_device(h, s->field, s->field + n, s->field + 2 * n, 1);
+}
+
+int lbm_sur_warm_start_batch(lbm_sur_t s, lbm_batch_t b, int k) {
+  if (!s || !b) return lbm_fail(LBM_EINVAL, "NULL argument");
+  int nx = 0, ny = 0;
+  double re = 0, u = 0;
+  int rc = lbm_batch_cavity(b, k, &nx, &ny, &re, &u);
+  if (rc) return rc;
+  rc = predict_lattice(s, nx, ny, re, u);
+  if (rc) return rc;
+  const size_t n = (size_t)nx * ny;
+  return lbm_batch_init_fields_device(b, k, s->field, s->field + n, s->field + 2 * n, 1);
+}
+
+}  // extern "C"

@@ -112,6 +112,31 @@ SIGNATURES = {
     "lbm_batch_info": [_h, ct.POINTER(ct.c_int), ct.POINTER(_i64), ct.POINTER(_i64),
                        ct.POINTER(ct.c_size_t)],
     "lbm_batch_autotune": [_h, ct.c_int, ct.c_int, ct.POINTER(ct.c_int), _dp],
+    "lbm_init_fields_device": [_h, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int],
+    "lbm_batch_init_fields_device": [_h, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                                     ct.c_int],
+    "lbm_batch_cavity": [_h, ct.c_int, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int), _dp, _dp],
+    "lbm_sur_create": [ct.c_int, ct.POINTER(_h)],
+    "lbm_sur_destroy": [_h],
+    "lbm_sur_set_stream": [_h, ct.c_void_p],
+    "lbm_sur_num_params": [_h, ct.POINTER(_i64)],
+    "lbm_sur_set_params": [_h, ct.c_void_p, _i64],
+    "lbm_sur_get_params": [_h, ct.c_void_p, ct.c_void_p],
+    "lbm_sur_forward": [_h, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_void_p],
+    "lbm_sur_train_step": [_h, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
+                           ct.c_double, ct.c_int, _dp],
+    "lbm_sur_warm_start": [_h, _h],
+    "lbm_sur_warm_start_batch": [_h, _h, ct.c_int],
+    "lbm_nn_conv3x3": [ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int,
+                       ct.c_void_p, ct.c_int, ct.c_int, ct.c_void_p, ct.c_int, ct.c_int,
+                       ct.c_void_p, ct.c_void_p, ct.c_int, ct.c_void_p, ct.c_int, ct.c_int,
+                       ct.c_int, ct.c_void_p],
+    "lbm_nn_bias_grad": [ct.c_int, ct.c_int, ct.c_void_p, ct.c_int, ct.c_int, ct.c_void_p,
+                         ct.c_void_p],
+    "lbm_nn_pool2": [ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_void_p, ct.c_int,
+                     ct.c_int, ct.c_void_p, ct.c_int, ct.c_int, ct.c_int, ct.c_void_p],
+    "lbm_nn_up2": [ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_int, ct.c_void_p, ct.c_int,
+                   ct.c_int, ct.c_void_p, ct.c_int, ct.c_int, ct.c_void_p],
 }
 _RESTYPES = {"lbm_last_error": ct.c_char_p, "lbm_version": ct.c_char_p}
 
@@ -377,6 +402,113 @@ def lbm_batch_autotune(b, chunks, use_cache=True):
     return best.value, ms.value
 
 
+def _dptr(t):
+    """Device pointer of a torch tensor (or an int / None)."""
+    if t is None:
+        return None
+    return ct.c_void_p(t.data_ptr() if hasattr(t, "data_ptr") else int(t))
+
+
+def _sptr(stream):
+    raw = getattr(stream, "cuda_stream", stream)
+    return ct.c_void_p(raw) if raw else None
+
+
+def lbm_init_fields_device(h, rho, ux, uy, renormalise_mass=True):
+    _check(_lib.lbm_init_fields_device(h, _dptr(rho), _dptr(ux), _dptr(uy),
+                                       int(bool(renormalise_mass))))
+
+
+def lbm_batch_init_fields_device(b, k, rho, ux, uy, renormalise_mass=True):
+    _check(_lib.lbm_batch_init_fields_device(b, int(k), _dptr(rho), _dptr(ux), _dptr(uy),
+                                             int(bool(renormalise_mass))))
+
+
+def lbm_batch_cavity(b, k):
+    nx, ny, re, u = ct.c_int(), ct.c_int(), ct.c_double(), ct.c_double()
+    _check(_lib.lbm_batch_cavity(b, int(k), ct.byref(nx), ct.byref(ny), ct.byref(re),
+                                 ct.byref(u)))
+    return nx.value, ny.value, re.value, u.value
+
+
+# -------------------------------------------------------------- surrogate ---
+def lbm_sur_create(max_batch):
+    s = _h()
+    _check(_lib.lbm_sur_create(int(max_batch), ct.byref(s)))
+    return s
+
+
+def lbm_sur_destroy(s):
+    _check(_lib.lbm_sur_destroy(s))
+
+
+def lbm_sur_set_stream(s, stream):
+    _check(_lib.lbm_sur_set_stream(s, _sptr(stream)))
+
+
+def lbm_sur_num_params(s):
+    n = _i64()
+    _check(_lib.lbm_sur_num_params(s, ct.byref(n)))
+    return n.value
+
+
+def lbm_sur_set_params(s, params):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _check(_lib.lbm_sur_set_params(s, _ptr(p), p.size))
+
+
+def lbm_sur_get_params(s, with_grads=False):
+    n = lbm_sur_num_params(s)
+    p = np.empty(n, dtype=np.float32)
+    g = np.empty(n, dtype=np.float32) if with_grads else None
+    _check(_lib.lbm_sur_get_params(s, _ptr(p), _ptr(g)))
+    return (p, g) if with_grads else p
+
+
+def lbm_sur_forward(s, re, ar, out):
+    re = np.ascontiguousarray(re, dtype=np.float64)
+    ar = np.ascontiguousarray(ar, dtype=np.float64)
+    _check(_lib.lbm_sur_forward(s, len(re), _ptr(re), _ptr(ar), _dptr(out)))
+
+
+def lbm_sur_train_step(s, re, ar, target, mask, lr, apply_update=True):
+    re = np.ascontiguousarray(re, dtype=np.float64)
+    ar = np.ascontiguousarray(ar, dtype=np.float64)
+    loss = ct.c_double()
+    _check(_lib.lbm_sur_train_step(s, len(re), _ptr(re), _ptr(ar), _dptr(target), _dptr(mask),
+                                   float(lr), int(bool(apply_update)), ct.byref(loss)))
+    return loss.value
+
+
+def lbm_sur_warm_start(s, h):
+    _check(_lib.lbm_sur_warm_start(s, h))
+
+
+def lbm_sur_warm_start_batch(s, b, k):
+    _check(_lib.lbm_sur_warm_start_batch(s, b, int(k)))
+
+
+def lbm_nn_conv3x3(mode, n, h, w, ci, co, x, xs, xo, g, gs, go, wt, bias, relu, out, os_, oo,
+                   accumulate=False, stream=None):
+    _check(_lib.lbm_nn_conv3x3(int(mode), n, h, w, ci, co, _dptr(x), xs, xo, _dptr(g), gs, go,
+                               _dptr(wt), _dptr(bias), int(relu), _dptr(out), os_, oo,
+                               int(bool(accumulate)), _sptr(stream)))
+
+
+def lbm_nn_bias_grad(npix, co, g, gs, go, gb, stream=None):
+    _check(_lib.lbm_nn_bias_grad(npix, co, _dptr(g), gs, go, _dptr(gb), _sptr(stream)))
+
+
+def lbm_nn_pool2(backward, n, h, w, c, x, xs, xo, out, os_, oo, accumulate=False, stream=None):
+    _check(_lib.lbm_nn_pool2(int(bool(backward)), n, h, w, c, _dptr(x), xs, xo, _dptr(out), os_,
+                             oo, int(bool(accumulate)), _sptr(stream)))
+
+
+def lbm_nn_up2(backward, n, h, w, c, x, xs, xo, out, os_, oo, stream=None):
+    _check(_lib.lbm_nn_up2(int(bool(backward)), n, h, w, c, _dptr(x), xs, xo, _dptr(out), os_,
+                           oo, _sptr(stream)))
+
+
 # ------------------------------------------------------------ convenience ---
 class Cavity:
     """A lid-driven cavity on the GPU (one library handle)."""
@@ -470,6 +602,9 @@ class Cavity:
     def autotune(self, chunks=20, use_cache=True):
         return lbm_autotune(self.h, chunks, use_cache)
 
+    def init_fields_device(self, rho, ux, uy, renormalise_mass=True):
+        lbm_init_fields_device(self.h, rho, ux, uy, renormalise_mass)
+
 
 class Batch:
     """Many cavities advanced together (one library batch handle)."""
@@ -536,3 +671,50 @@ class Batch:
 
     def autotune(self, chunks=2, use_cache=True):
         return lbm_batch_autotune(self.b, chunks, use_cache)
+
+    def cavity(self, k):
+        return lbm_batch_cavity(self.b, k)
+
+
+class Surrogate:
+    """The warm-start network (one library surrogate handle)."""
+
+    def __init__(self, max_batch=16):
+        self.s = lbm_sur_create(max_batch)
+        self.max_batch = max_batch
+
+    def close(self):
+        if self.s:
+            lbm_sur_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_params(self):
+        return lbm_sur_num_params(self.s)
+
+    def set_params(self, p):
+        lbm_sur_set_params(self.s, p)
+
+    def get_params(self, with_grads=False):
+        return lbm_sur_get_params(self.s, with_grads)
+
+    def set_stream(self, stream):
+        lbm_sur_set_stream(self.s, stream)
+
+    def forward(self, re, ar, out):
+        lbm_sur_forward(self.s, re, ar, out)
+
+    def train_step(self, re, ar, target, mask, lr, apply_update=True):
+        return lbm_sur_train_step(self.s, re, ar, target, mask, lr, apply_update)
+
+    def warm_start(self, cavity):
+        lbm_sur_warm_start(self.s, cavity.h)
+
+    def warm_start_batch(self, batch, k):
+        lbm_sur_warm_start_batch(self.s, batch.b, k)
