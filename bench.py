@@ -16,8 +16,11 @@ roofline of the step kernel (72 B per site update in FP32, 144 B in FP64:
 nine populations read and nine written; a multi-step launch counts K
 updates); per-case figures for the other aspect ratios and FP64 storage; the
 25-cavity Re x Ar sweep advanced as one batch against the same 25 cavities
-run one after another; a plain device copy's bandwidth on the same GPU; and
-the CPU oracle timed on a bounded sample.
+run one after another; the time to steady state (Eq. 6 residual < 1e-6) of
+a steady 25-cavity sweep (Re 1000-3000 x Ar 0.4-2.0 at 500 x (500 Ar))
+batched and warm-started by the learned surrogate against plain cold single
+runs; a plain device copy's bandwidth on the same GPU; and the CPU oracle
+timed on a bounded sample.
 
 ``--copy-probe BYTES`` instead runs a plain device copy of BYTES bytes ten
 times (used to calibrate the rocprofv3 FETCH_SIZE / WRITE_SIZE counters).
@@ -54,6 +57,11 @@ def parse():
                     help="also time Ar 0.4/1.0/2.0 in both storage types (0: skip)")
     ap.add_argument("--sweep", type=int, default=1,
                     help="also time the 25-cavity batch against sequential runs (0: skip)")
+    ap.add_argument("--tts", type=int, default=1,
+                    help="time-to-steady of the steady sweep, batched + warm-started vs "
+                         "plain (0: skip)")
+    ap.add_argument("--tts-epochs", type=int, default=150)
+    ap.add_argument("--tts-ablations", type=int, default=0)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-steps", type=int, default=200)
     ap.add_argument("--copy-probe", type=int, default=0)
@@ -68,6 +76,11 @@ def source_hash():
             h.update(os.path.basename(p).encode())
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def progress(*a):
+    """Progress lines go to stderr; stdout carries only the result line."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
 
 
 def events(torch):
@@ -216,6 +229,7 @@ def main():
     ny = int(round(nx * args.ar))
     sites = nx * ny
 
+    progress(f"headline {nx}x{ny} {args.dtype}, {args.steps} steps")
     sec, (variant, k), mass = time_single(lbm, torch, nx, ny, args.re, args.dtype, args.steps,
                                           args.warmup, args.variant)
     mlups = sites * args.steps / sec / 1e6
@@ -254,6 +268,7 @@ def main():
             for dt in ("f32s", "f64"):
                 nyc = int(round(nx * ar))
                 kk = max(10000, args.steps // 10)
+                progress(f"case {nx}x{nyc} {dt}")
                 s, (v, _), _ = time_single(lbm, torch, nx, nyc, args.re, dt, kk, 1000)
                 ml = nx * nyc * kk / s / 1e6
                 gbs = ml * BYTES_PER_SITE[dt] / 1e3
@@ -262,9 +277,22 @@ def main():
                               "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
         out["cases"] = cases
     if args.sweep:
+        progress("25-cavity sweep: batch vs sequential")
         out["sweep"] = time_sweep(lbm, torch, sweep_cases(nx), "f32s", 5000)
+    if args.tts:
+        from paper_2211_05009_amd import warmstart
+        from cavity_inputs import normal_draws
+        from paper_2211_05009_amd.lbm import lbm_sur_num_params, Surrogate
+        probe = Surrogate(max_batch=1)
+        npar = lbm_sur_num_params(probe.s)
+        probe.close()
+        progress("time to steady: training data, training, plain and warm-started sweeps")
+        out["sweep_time_to_steady"] = warmstart.steady_sweep_study(
+            normal_draws(npar, seed=0), epochs=args.tts_epochs, ablations=bool(args.tts_ablations),
+            log=progress)
     out["copy_GBs"] = copy_bandwidth(torch)
     if args.cpu_baseline:
+        progress("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(nx, ny, args.re, args.cpu_steps)
     print(json.dumps(out), flush=True)
 

@@ -66,3 +66,9 @@ def random_points(n: int, ar: float, seed: int):
     """n observing points (x, y) in units of the width L, inside [0,1]x[0,Ar]."""
     rng = np.random.default_rng(seed)
     return np.stack([rng.uniform(0.0, 1.0, n), rng.uniform(0.0, ar, n)], axis=1)
+
+
+def normal_draws(n: int, seed: int):
+    """n standard normal draws (float32), e.g. for network weight init."""
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal(n).astype(np.float32)

@@ -232,16 +232,31 @@ int lbm_set_populations(lbm_t h, const double *f_host);
 int lbm_get_populations(lbm_t h, double *fstar_host);
 
 /*
- * Warm start: f = f^eq(rho, u) from fields [ny][nx] (host).  If
- * renormalise_mass is non-zero, rho is first scaled so that the total mass
- * is nx * ny (that of the rest state).  Step counter restarts at 0.
+ * Warm start: f = f^eq(rho, u) from fields [ny][nx] (host; NULL rho = 1,
+ * NULL velocity = 0).  Flags:
+ *   LBM_INIT_RENORMALISE_MASS  scale rho so the total mass is nx * ny (that
+ *                              of the rest state);
+ *   LBM_INIT_ZERO_STAGGERED    remove the two staggered momenta
+ *                              P_x = sum (-1)^x rho u_x and
+ *                              P_y = sum (-1)^y rho u_y by subtracting a
+ *                              uniform (-1)^x (or (-1)^y) momentum.
+ * Why the second flag: collision conserves each site's momentum and every
+ * link or wall reflection moves a population with c_x != 0 to the other
+ * column parity or reverses it, so P_y(t+1) = -P_y(t) and P_x(t+1) =
+ * -P_x(t) (+ u_lid/3 if nx is odd) hold exactly for the whole nonlinear
+ * update.  A start from rest has P = 0; a general start keeps a
+ * non-decaying two-step oscillation that Eq. 6 (which compares states 100
+ * steps apart, of equal parity) cannot see, and converges to a different
+ * state.  With the flag, the start lies on the rest state's invariant set.
+ * Step counter restarts at 0.
  */
+enum { LBM_INIT_RENORMALISE_MASS = 1, LBM_INIT_ZERO_STAGGERED = 2 };
 int lbm_init_fields(lbm_t h, const double *rho_host, const double *ux_host,
-                    const double *uy_host, int renormalise_mass);
+                    const double *uy_host, int flags);
 
 /* As lbm_init_fields with caller-owned *device* arrays (e.g. torch tensors). */
 int lbm_init_fields_device(lbm_t h, const double *rho_dev, const double *ux_dev,
-                           const double *uy_dev, int renormalise_mass);
+                           const double *uy_dev, int flags);
 
 /*
  * Checkpoint: write / read a header (magic, version, nx, ny, dtype, steps,
@@ -302,13 +317,19 @@ int lbm_batch_moments(lbm_batch_t b, int k, double *rho_host, double *ux_host,
 int lbm_batch_get_populations(lbm_batch_t b, int k, double *fstar_host);
 int lbm_batch_set_populations(lbm_batch_t b, int k, const double *f_host);
 int lbm_batch_init_fields(lbm_batch_t b, int k, const double *rho_host,
-                          const double *ux_host, const double *uy_host,
-                          int renormalise_mass);
+                          const double *ux_host, const double *uy_host, int flags);
 
 /* As lbm_batch_init_fields with caller-owned device arrays. */
 int lbm_batch_init_fields_device(lbm_batch_t b, int k, const double *rho_dev,
-                                 const double *ux_dev, const double *uy_dev,
-                                 int renormalise_mass);
+                                 const double *ux_dev, const double *uy_dev, int flags);
+
+/* Training target of the warm-start network from cavity k's current state:
+ * the 256 x 128 canvas of include/lbm.h's surrogate section, pixel (x, y)
+ * (y < round(128 ny/nx)) = bilinear probe at ((x + 1/2)/128, (y + 1/2)/128)
+ * in units of L; target_dev FP32 [256][128][3] = (100 (rho - 1),
+ * u_x/u_lid, u_y/u_lid), mask_dev FP32 [256][128] (1 inside, 0 outside).
+ * LBM_EINVAL if round(128 ny/nx) is not in [1, 256]. */
+int lbm_batch_canvas(lbm_batch_t b, int k, float *target_dev, float *mask_dev);
 
 /* Lattice, Reynolds number and lid speed of cavity k (NULL outputs skipped). */
 int lbm_batch_cavity(lbm_batch_t b, int k, int *nx, int *ny, double *re,
@@ -360,6 +381,11 @@ int lbm_sur_num_params(lbm_sur_t s, int64_t *n);
 /* Load n FP32 parameters (host, layout above); resets the optimiser. */
 int lbm_sur_set_params(lbm_sur_t s, const float *params_host, int64_t n);
 
+/* He-normal initialisation from n standard normal draws (host): weight i of
+ * a layer = draw i x sqrt(2 / (9 ci_real)) (ci_real = 5 for the first
+ * layer), padding entries and biases zero; resets the optimiser. */
+int lbm_sur_init_params(lbm_sur_t s, const float *normals_host, int64_t n);
+
 /* Copy the FP32 parameters and / or the gradients of the last training step
  * to host arrays of lbm_sur_num_params floats (either may be NULL). */
 int lbm_sur_get_params(lbm_sur_t s, float *params_host, float *grads_host);
@@ -382,8 +408,9 @@ int lbm_sur_train_step(lbm_sur_t s, int n, const double *re, const double *ar,
 
 /* Warm start: predict the field for the handle's (Re, Ar = ny/nx), map it
  * bilinearly onto the lattice (site centres in units of L, clamped to the
- * cavity pixels), renormalise the mass to nx ny and set f = f^eq
- * (lbm_init_fields_device).  The step counter restarts at 0. */
+ * cavity pixels), renormalise the mass to nx ny, remove the staggered
+ * momenta and set f = f^eq (lbm_init_fields_device with both flags).  The
+ * step counter restarts at 0. */
 int lbm_sur_warm_start(lbm_sur_t s, lbm_t h);
 int lbm_sur_warm_start_batch(lbm_sur_t s, lbm_batch_t b, int k);
 

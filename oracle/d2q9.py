@@ -234,6 +234,34 @@ class Cavity:
         return self
 
 
+def staggered_momenta(f):
+    """P_x = sum (-1)^x j_x and P_y = sum (-1)^y j_y (j = sum_i c_i f_i).
+
+    Collision keeps every site's j; streaming moves each population with
+    c_x != 0 to a column of the other parity, and a wall reflection reverses
+    c at the same site.  Hence one application of Eq. 1 maps P_y -> -P_y and
+    P_x -> -P_x, plus u_lid/3 from the lid term when Nx is odd: two
+    invariants of period two besides the mass."""
+    _, ny, nx = f.shape
+    jx, jy = momentum(f)
+    sx = (-1.0) ** np.arange(nx)[None, :]
+    sy = (-1.0) ** np.arange(ny)[:, None]
+    return float((sx * jx).sum()), float((sy * jy).sum())
+
+
+def destaggered_velocity(rho, ux, uy):
+    """Velocity with the staggered momenta of rho u removed by a uniform
+    (-1)^x (resp. (-1)^y) momentum: sum (-1)^x rho u_x = sum (-1)^y rho u_y
+    = 0 afterwards."""
+    ny, nx = rho.shape
+    n = nx * ny
+    sx = (-1.0) ** np.arange(nx)[None, :]
+    sy = (-1.0) ** np.arange(ny)[:, None]
+    px = (sx * rho * ux).sum() / n
+    py = (sy * rho * uy).sum() / n
+    return ux - px * sx / rho, uy - py * sy / rho
+
+
 def mass(f):
     """Total mass sum_x rho(x), summed exactly (math.fsum) so that the oracle's
     own rounding does not mask a conservation error."""

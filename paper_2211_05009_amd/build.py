@@ -1,6 +1,8 @@
 """Build the gfx950 HIP library in-tree: ``paper_2211_05009_amd/liblbm.so``.
 
-    python -m paper_2211_05009_amd.build
+    python paper_2211_05009_amd/build.py
+
+(run as a file: importing the package would load the library being built).
 
 hipcc cross-compiles for gfx950 without a GPU.  Packed-FP32 instruction
 selection is disabled (-packed-fp32-ops) for every device compilation, and

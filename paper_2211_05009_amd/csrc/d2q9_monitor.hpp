@@ -113,6 +113,23 @@ static __global__ __launch_bounds__(kRedThreads) void k_sum_dense(
   block_reduce_store<kNumSums>(acc, partials + blockIdx.x * kNumSums);
 }
 
+// Per-block partials for a start from fields: sum rho, sum (-1)^x rho u_x,
+// sum (-1)^y rho u_y (dense [ny][nx]; null rho = 1, null velocity = 0).
+static __global__ __launch_bounds__(kRedThreads) void k_init_sums(
+    const double *__restrict__ rho, const double *__restrict__ ux,
+    const double *__restrict__ uy, int nx, long long n, double *__restrict__ partials) {
+  double acc[kNumSums] = {0.0, 0.0, 0.0};
+  for (long long k = blockIdx.x * (long long)kRedThreads + threadIdx.x; k < n;
+       k += (long long)gridDim.x * kRedThreads) {
+    const int x = (int)(k % nx), y = (int)(k / nx);
+    const double r = rho ? rho[k] : 1.0;
+    acc[0] += r;
+    if (ux) acc[1] += (x & 1 ? -r : r) * ux[k];
+    if (uy) acc[2] += (y & 1 ? -r : r) * uy[k];
+  }
+  block_reduce_store<kNumSums>(acc, partials + blockIdx.x * kNumSums);
+}
+
 // Single block: add nparts partial triples in a fixed order.
 static __global__ __launch_bounds__(kRedThreads) void k_finalize(
     const double *__restrict__ partials, int nparts, double *__restrict__ out) {
@@ -195,6 +212,31 @@ __global__ __launch_bounds__(256) void k_probe_ring(
   if (threadIdx.x == 0) *count = c + 1;
 }
 
+// Resample a cavity onto the surrogate's 256 x 128 canvas: pixel (x, y) of a
+// canvas row y < rows sits at ((x + 1/2)/128, (y + 1/2)/128) in units of the
+// width L; its (rho, u) is the bilinear probe of the lattice there.  Outputs
+// (FP32): target[y][x] = (100 (rho - 1), u_x / u_lid, u_y / u_lid), mask 1;
+// rows >= rows are zero.
+template <typename T, bool SHIFT>
+__global__ __launch_bounds__(256) void k_canvas(const T *__restrict__ s, Geometry g, double u_lid,
+                                                int rows, float *__restrict__ target,
+                                                float *__restrict__ mask) {
+  const int k = blockIdx.x * 256 + threadIdx.x;
+  if (k >= 256 * 128) return;
+  const int y = k / 128, x = k % 128;
+  if (y >= rows) {
+    target[3 * k] = target[3 * k + 1] = target[3 * k + 2] = 0.f;
+    mask[k] = 0.f;
+    return;
+  }
+  double v[3];
+  probe_point<T, SHIFT>(s, g, (x + 0.5) / 128.0, (y + 0.5) / 128.0, v);
+  target[3 * k] = (float)(100.0 * (v[0] - 1.0));
+  target[3 * k + 1] = (float)(v[1] / u_lid);
+  target[3 * k + 2] = (float)(v[2] / u_lid);
+  mask[k] = 1.f;
+}
+
 // Stream function: one thread per column, prefix sum of -u_x upward,
 // midpoint rule (Psi = 0 on the bottom wall).
 template <typename T, bool SHIFT>
@@ -216,12 +258,14 @@ __global__ __launch_bounds__(256) void k_psi(const T *__restrict__ s, Geometry g
 // null rho = 1, null velocity = 0).  The equilibrium is its own collision
 // result, so this is the stored post-collision state of a start at
 // equilibrium (Sec. 2.2 (i)).  Padding columns are written as rest values.
+// rho is scaled by rho_scale; (sx, sy) remove a staggered momentum:
+// rho u_x -= sx (-1)^x and rho u_y -= sy (-1)^y.
 template <typename T, bool SHIFT>
 __global__ __launch_bounds__(256) void k_init_eq(T *__restrict__ d, Geometry g,
                                                  const double *__restrict__ rho,
                                                  const double *__restrict__ ux,
                                                  const double *__restrict__ uy,
-                                                 double rho_scale) {
+                                                 double rho_scale, double sx, double sy) {
   const int k = blockIdx.x * 256 + threadIdx.x;
   if (k >= g.pitch * g.ny) return;
   const int y = k / g.pitch, x = k - y * g.pitch;
@@ -229,8 +273,8 @@ __global__ __launch_bounds__(256) void k_init_eq(T *__restrict__ d, Geometry g,
   if (x < g.nx) {
     const int q = y * g.nx + x;
     if (rho) r = rho[q] * rho_scale;
-    if (ux) u = ux[q];
-    if (uy) v = uy[q];
+    if (ux) u = ux[q] - (x & 1 ? -sx : sx) / r;
+    if (uy) v = uy[q] - (y & 1 ? -sy : sy) / r;
   }
   const double usq = 1.5 * (u * u + v * v);
 #pragma unroll

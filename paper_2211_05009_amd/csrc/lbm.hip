@@ -414,11 +414,11 @@ static int create_impl(int nx, int ny, double tau, double re, double u_lid,
   if (dtype == LBM_F64)
     hipLaunchKernelGGL((k_init_eq<double, false>), dim3((total + 255) / 256), dim3(256),
                        0, h->stream, (double *)h->buf[0], geom(h), nullptr, nullptr,
-                       nullptr, 1.0);
+                       nullptr, 1.0, 0.0, 0.0);
   else
     hipLaunchKernelGGL((k_init_eq<float, true>), dim3((total + 255) / 256), dim3(256), 0,
                        h->stream, (float *)h->buf[0], geom(h), nullptr, nullptr,
-                       nullptr, 1.0);
+                       nullptr, 1.0, 0.0, 0.0);
   TRY(hipGetLastError());
   rc = reset_counters(h);
   if (rc != LBM_OK) return bail(rc);
@@ -861,7 +861,7 @@ int lbm_get_populations(lbm_t h, double *f) {
 }
 
 static int init_fields_impl(lbm_t h, const double *rho, const double *ux, const double *uy,
-                            int renormalise_mass, bool on_device) {
+                            int flags, bool on_device) {
   if (!h) return lbm_fail(LBM_EINVAL, "handle is NULL");
   const size_t n = (size_t)h->nx * h->ny;
   const double *d[3] = {rho, ux, uy};
@@ -878,31 +878,41 @@ static int init_fields_impl(lbm_t h, const double *rho, const double *ux, const 
       }
     }
   }
-  double scale = 1.0;
-  if (renormalise_mass && rho) {
-    // FP64 sum of rho on the device (same fixed-order reduction as the
-    // monitors), then scale so the total mass is nx * ny.
+  double scale = 1.0, sx = 0.0, sy = 0.0;
+  const bool renorm = (flags & LBM_INIT_RENORMALISE_MASS) && rho;
+  const bool destag = (flags & LBM_INIT_ZERO_STAGGERED) && (ux || uy);
+  if (renorm || destag) {
+    // FP64 sums on the device (same fixed-order reduction as the monitors):
+    // total mass and the two staggered momenta of the fields
     const int blocks = std::min(kRedBlocks, (int)((n + kRedThreads - 1) / kRedThreads));
-    hipLaunchKernelGGL(k_sum_dense, dim3(blocks), dim3(kRedThreads), 0, h->stream, d[0],
-                       (long long)n, h->partials);
+    hipLaunchKernelGGL(k_init_sums, dim3(blocks), dim3(kRedThreads), 0, h->stream, d[0], d[1],
+                       d[2], h->nx, (long long)n, h->partials);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedThreads), 0, h->stream, h->partials,
                        blocks, h->aux_dev);
     HIPC(hipGetLastError());
-    HIPC(hipMemcpyAsync(h->mon_host + 4, h->aux_dev, sizeof(double),
+    HIPC(hipMemcpyAsync(h->mon_host + 4, h->aux_dev, 3 * sizeof(double),
                         hipMemcpyDeviceToHost, h->stream));
     HIPC(hipStreamSynchronize(h->stream));
     const double total = h->mon_host[4];
-    if (!(total > 0.0) || !std::isfinite(total))
-      return lbm_fail(LBM_EINVAL, "sum of rho = %g cannot be renormalised", total);
-    scale = (double)n / total;
+    if (renorm) {
+      if (!(total > 0.0) || !std::isfinite(total))
+        return lbm_fail(LBM_EINVAL, "sum of rho = %g cannot be renormalised", total);
+      scale = (double)n / total;
+    }
+    if (destag) {
+      sx = scale * h->mon_host[5] / (double)n;
+      sy = scale * h->mon_host[6] / (double)n;
+    }
   }
   const int tot = h->pitch * h->ny;
   if (h->dtype == LBM_F64)
     hipLaunchKernelGGL((k_init_eq<double, false>), dim3((tot + 255) / 256), dim3(256), 0,
-                       h->stream, (double *)h->buf[h->cur], geom(h), d[0], d[1], d[2], scale);
+                       h->stream, (double *)h->buf[h->cur], geom(h), d[0], d[1], d[2], scale,
+                       sx, sy);
   else
     hipLaunchKernelGGL((k_init_eq<float, true>), dim3((tot + 255) / 256), dim3(256), 0,
-                       h->stream, (float *)h->buf[h->cur], geom(h), d[0], d[1], d[2], scale);
+                       h->stream, (float *)h->buf[h->cur], geom(h), d[0], d[1], d[2], scale,
+                       sx, sy);
   HIPC(hipGetLastError());
   int rc = reset_counters(h);
   if (rc) return rc;
@@ -911,13 +921,13 @@ static int init_fields_impl(lbm_t h, const double *rho, const double *ux, const 
 }
 
 int lbm_init_fields(lbm_t h, const double *rho, const double *ux, const double *uy,
-                    int renormalise_mass) {
-  return init_fields_impl(h, rho, ux, uy, renormalise_mass, false);
+                    int flags) {
+  return init_fields_impl(h, rho, ux, uy, flags, false);
 }
 
 int lbm_init_fields_device(lbm_t h, const double *rho, const double *ux, const double *uy,
-                           int renormalise_mass) {
-  return init_fields_impl(h, rho, ux, uy, renormalise_mass, true);
+                           int flags) {
+  return init_fields_impl(h, rho, ux, uy, flags, true);
 }
 
 // Checkpoint file: header, stored populations of buf[cur], Eq. 6 reference.

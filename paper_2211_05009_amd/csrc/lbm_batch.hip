@@ -343,11 +343,11 @@ int read_monitors(lbm_batch *b, bool *changed) {
 
 template <typename T, bool S>
 void launch_init_eq(lbm_batch *b, int k, const double *r, const double *u, const double *v,
-                    double scale) {
+                    double scale, double sx = 0.0, double sy = 0.0) {
   const Geometry g = cav_geom(b, k);
   const int tot = g.pitch * g.ny;
   hipLaunchKernelGGL((k_init_eq<T, S>), dim3((tot + 255) / 256), dim3(256), 0, b->stream,
-                     (T *)b->buf[cbuf(b, k)] + b->base[k], g, r, u, v, scale);
+                     (T *)b->buf[cbuf(b, k)] + b->base[k], g, r, u, v, scale, sx, sy);
 }
 
 template <typename T, bool S>
@@ -733,7 +733,7 @@ int lbm_batch_set_populations(lbm_batch_t b, int k, const double *f) {
 }
 
 static int batch_init_impl(lbm_batch_t b, int k, const double *rho, const double *ux,
-                           const double *uy, int renormalise_mass, bool on_device) {
+                           const double *uy, int flags, bool on_device) {
   if (!valid_k(b, k)) return lbm_fail(LBM_EINVAL, "cavity index %d out of range", k);
   const Geometry g = cav_geom(b, k);
   const size_t n = (size_t)g.nx * g.ny;
@@ -751,24 +751,32 @@ static int batch_init_impl(lbm_batch_t b, int k, const double *rho, const double
       }
     }
   }
-  double scale = 1.0;
-  if (renormalise_mass && rho) {
+  double scale = 1.0, sx = 0.0, sy = 0.0;
+  const bool renorm = (flags & LBM_INIT_RENORMALISE_MASS) && rho;
+  const bool destag = (flags & LBM_INIT_ZERO_STAGGERED) && (ux || uy);
+  if (renorm || destag) {
     const int blocks = std::min(kRedBlocks, (int)((n + kRedThreads - 1) / kRedThreads));
-    hipLaunchKernelGGL(k_sum_dense, dim3(blocks), dim3(kRedThreads), 0, b->stream, d[0],
-                       (long long)n, b->partials);
+    hipLaunchKernelGGL(k_init_sums, dim3(blocks), dim3(kRedThreads), 0, b->stream, d[0], d[1],
+                       d[2], g.nx, (long long)n, b->partials);
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kRedThreads), 0, b->stream, b->partials, blocks,
                        b->aux_dev);
     HIPC(hipGetLastError());
-    HIPC(hipMemcpyAsync(b->mon_host + kNumSums * b->n, b->aux_dev, sizeof(double),
+    HIPC(hipMemcpyAsync(b->mon_host + kNumSums * b->n, b->aux_dev, 3 * sizeof(double),
                         hipMemcpyDeviceToHost, b->stream));
     HIPC(hipStreamSynchronize(b->stream));
-    const double total = b->mon_host[kNumSums * b->n];
-    if (!(total > 0.0) || !std::isfinite(total))
-      return lbm_fail(LBM_EINVAL, "sum of rho = %g cannot be renormalised", total);
-    scale = (double)n / total;
+    const double *m = b->mon_host + kNumSums * b->n;
+    if (renorm) {
+      if (!(m[0] > 0.0) || !std::isfinite(m[0]))
+        return lbm_fail(LBM_EINVAL, "sum of rho = %g cannot be renormalised", m[0]);
+      scale = (double)n / m[0];
+    }
+    if (destag) {
+      sx = scale * m[1] / (double)n;
+      sy = scale * m[2] / (double)n;
+    }
   }
-  if (b->dtype == LBM_F64) launch_init_eq<double, false>(b, k, d[0], d[1], d[2], scale);
-  else launch_init_eq<float, true>(b, k, d[0], d[1], d[2], scale);
+  if (b->dtype == LBM_F64) launch_init_eq<double, false>(b, k, d[0], d[1], d[2], scale, sx, sy);
+  else launch_init_eq<float, true>(b, k, d[0], d[1], d[2], scale, sx, sy);
   HIPC(hipGetLastError());
   int rc = reset_cavity(b, k);
   if (rc) return rc;
@@ -777,13 +785,34 @@ static int batch_init_impl(lbm_batch_t b, int k, const double *rho, const double
 }
 
 int lbm_batch_init_fields(lbm_batch_t b, int k, const double *rho, const double *ux,
-                          const double *uy, int renormalise_mass) {
-  return batch_init_impl(b, k, rho, ux, uy, renormalise_mass, false);
+                          const double *uy, int flags) {
+  return batch_init_impl(b, k, rho, ux, uy, flags, false);
 }
 
 int lbm_batch_init_fields_device(lbm_batch_t b, int k, const double *rho, const double *ux,
-                                 const double *uy, int renormalise_mass) {
-  return batch_init_impl(b, k, rho, ux, uy, renormalise_mass, true);
+                                 const double *uy, int flags) {
+  return batch_init_impl(b, k, rho, ux, uy, flags, true);
+}
+
+int lbm_batch_canvas(lbm_batch_t b, int k, float *target_dev, float *mask_dev) {
+  if (!valid_k(b, k) || !target_dev || !mask_dev)
+    return lbm_fail(LBM_EINVAL, "bad cavity index or NULL");
+  const int rows = (int)std::rint(128.0 * b->ny[k] / b->nx[k]);
+  if (rows < 1 || rows > 256)
+    return lbm_fail(LBM_EINVAL, "cavity %d: aspect ratio %g outside the canvas", k,
+                    (double)b->ny[k] / b->nx[k]);
+  const Geometry g = cav_geom(b, k);
+  if (b->dtype == LBM_F64)
+    hipLaunchKernelGGL((k_canvas<double, false>), dim3(128), dim3(256), 0, b->stream,
+                       (const double *)b->buf[cbuf(b, k)] + b->base[k], g, b->u_lid, rows,
+                       target_dev, mask_dev);
+  else
+    hipLaunchKernelGGL((k_canvas<float, true>), dim3(128), dim3(256), 0, b->stream,
+                       (const float *)b->buf[cbuf(b, k)] + b->base[k], g, b->u_lid, rows,
+                       target_dev, mask_dev);
+  HIPC(hipGetLastError());
+  HIPC(hipStreamSynchronize(b->stream));
+  return LBM_OK;
 }
 
 int lbm_batch_cavity(lbm_batch_t b, int k, int *nx, int *ny, double *re, double *u_lid) {

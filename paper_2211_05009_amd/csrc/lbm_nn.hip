@@ -513,6 +513,28 @@ int lbm_sur_set_params(lbm_sur_t s, const float *params_host, int64_t n) {
   return LBM_OK;
 }
 
+int lbm_sur_init_params(lbm_sur_t s, const float *normals_host, int64_t n) {
+  if (!s || !normals_host) return lbm_fail(LBM_EINVAL, "NULL argument");
+  if (n != (int64_t)s->nparams)
+    return lbm_fail(LBM_EINVAL, "expected %zu draws, got %lld", s->nparams, (long long)n);
+  std::vector<float> p(s->nparams, 0.f);
+  const size_t last = s->ops.size() - 1;
+  for (size_t k = 0; k < s->ops.size(); ++k) {
+    const Op &o = s->ops[k];
+    if (o.type != OP_CONV) continue;
+    const int ci_real = k == 0 ? kInCh : o.ci;
+    const int co_real = k == last ? kOutCh : o.co;
+    const float sd = std::sqrt(2.0f / (9.0f * ci_real));   // He-normal
+    for (int t = 0; t < 9; ++t)
+      for (int c = 0; c < ci_real; ++c)
+        for (int q = 0; q < co_real; ++q) {
+          const size_t i = o.woff + ((size_t)t * o.ci + c) * o.co + q;
+          p[i] = sd * normals_host[i];
+        }
+  }
+  return lbm_sur_set_params(s, p.data(), n);
+}
+
 int lbm_sur_get_params(lbm_sur_t s, float *params_host, float *grads_host) {
   if (!s) return lbm_fail(LBM_EINVAL, "NULL argument");
   HIPC(hipStreamSynchronize(s->stream));
@@ -605,7 +627,8 @@ int lbm_sur_warm_start(lbm_sur_t s, lbm_t h) {
   rc = predict_lattice(s, info.nx, info.ny, info.re, info.u_lid);
   if (rc) return rc;
   const size_t n = (size_t)info.nx * info.ny;
-  return lbm_init_fields_device(h, s->field, s->field + n, s->field + 2 * n, 1);
+  return lbm_init_fields_device(h, s->field, s->field + n, s->field + 2 * n,
+                                LBM_INIT_RENORMALISE_MASS | LBM_INIT_ZERO_STAGGERED);
 }
 
 int lbm_sur_warm_start_batch(lbm_sur_t s, lbm_batch_t b, int k) {
@@ -617,7 +640,8 @@ int lbm_sur_warm_start_batch(lbm_sur_t s, lbm_batch_t b, int k) {
   rc = predict_lattice(s, nx, ny, re, u);
   if (rc) return rc;
   const size_t n = (size_t)nx * ny;
-  return lbm_batch_init_fields_device(b, k, s->field, s->field + n, s->field + 2 * n, 1);
+  return lbm_batch_init_fields_device(b, k, s->field, s->field + n, s->field + 2 * n,
+                                      LBM_INIT_RENORMALISE_MASS | LBM_INIT_ZERO_STAGGERED);
 }
 
 }  // extern "C"

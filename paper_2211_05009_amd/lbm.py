@@ -7,7 +7,7 @@ return; :class:`Cavity` wraps a handle.  Host arrays are NumPy float64;
 device arrays and streams may be torch objects (``data_ptr()`` /
 ``cuda_stream``), torch itself is not needed otherwise.
 
-The library must have been built (``python -m paper_2211_05009_amd.build``);
+The library must have been built (``python paper_2211_05009_amd/build.py``);
 importing this module without it raises ImportError: there is no fallback.
 """
 from __future__ import annotations
@@ -25,6 +25,7 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_EIO, LBM_ESTATE 
 LBM_F64, LBM_F32_SHIFTED = 0, 1
 LBM_OPT_USE_GRAPH, LBM_OPT_STEP_VARIANT, LBM_OPT_NUM_VARIANTS, LBM_OPT_GRAPH_STEPS = 1, 2, 3, 4
 LBM_OPT_STEPS_PER_LAUNCH = 5
+LBM_INIT_RENORMALISE_MASS, LBM_INIT_ZERO_STAGGERED = 1, 2
 DTYPES = {"f64": LBM_F64, "f32s": LBM_F32_SHIFTED}
 
 _ERRNAMES = {LBM_EINVAL: "LBM_EINVAL", LBM_ENOMEM: "LBM_ENOMEM",
@@ -57,7 +58,7 @@ def _load():
         pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
-                          "`python -m paper_2211_05009_amd.build` (no CPU fallback)")
+                          "`python paper_2211_05009_amd/build.py` (no CPU fallback)")
     return ct.CDLL(LIB_PATH)
 
 
@@ -116,12 +117,14 @@ SIGNATURES = {
     "lbm_batch_init_fields_device": [_h, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                      ct.c_int],
     "lbm_batch_cavity": [_h, ct.c_int, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int), _dp, _dp],
+    "lbm_batch_canvas": [_h, ct.c_int, ct.c_void_p, ct.c_void_p],
     "lbm_sur_create": [ct.c_int, ct.POINTER(_h)],
     "lbm_sur_destroy": [_h],
     "lbm_sur_set_stream": [_h, ct.c_void_p],
     "lbm_sur_num_params": [_h, ct.POINTER(_i64)],
     "lbm_sur_set_params": [_h, ct.c_void_p, _i64],
     "lbm_sur_get_params": [_h, ct.c_void_p, ct.c_void_p],
+    "lbm_sur_init_params": [_h, ct.c_void_p, _i64],
     "lbm_sur_forward": [_h, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_void_p],
     "lbm_sur_train_step": [_h, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                            ct.c_double, ct.c_int, _dp],
@@ -287,9 +290,15 @@ def lbm_get_populations(h, nx, ny):
     return f
 
 
-def lbm_init_fields(h, rho, ux, uy, nx, ny, renormalise_mass=True):
+def _init_flags(renormalise_mass, zero_staggered):
+    return (LBM_INIT_RENORMALISE_MASS if renormalise_mass else 0) | \
+        (LBM_INIT_ZERO_STAGGERED if zero_staggered else 0)
+
+
+def lbm_init_fields(h, rho, ux, uy, nx, ny, renormalise_mass=True, zero_staggered=False):
     arrs = [None if a is None else _f64(a, (ny, nx)) for a in (rho, ux, uy)]
-    _check(_lib.lbm_init_fields(h, *[_ptr(a) for a in arrs], int(bool(renormalise_mass))))
+    _check(_lib.lbm_init_fields(h, *[_ptr(a) for a in arrs],
+                                _init_flags(renormalise_mass, zero_staggered)))
 
 
 def lbm_save(h, path):
@@ -381,10 +390,11 @@ def lbm_batch_set_populations(b, k, f, nx, ny):
     _check(_lib.lbm_batch_set_populations(b, int(k), _ptr(f)))
 
 
-def lbm_batch_init_fields(b, k, rho, ux, uy, nx, ny, renormalise_mass=True):
+def lbm_batch_init_fields(b, k, rho, ux, uy, nx, ny, renormalise_mass=True,
+                          zero_staggered=False):
     arrs = [None if a is None else _f64(a, (ny, nx)) for a in (rho, ux, uy)]
     _check(_lib.lbm_batch_init_fields(b, int(k), *[_ptr(a) for a in arrs],
-                                      int(bool(renormalise_mass))))
+                                      _init_flags(renormalise_mass, zero_staggered)))
 
 
 def lbm_batch_info(b):
@@ -414,14 +424,15 @@ def _sptr(stream):
     return ct.c_void_p(raw) if raw else None
 
 
-def lbm_init_fields_device(h, rho, ux, uy, renormalise_mass=True):
+def lbm_init_fields_device(h, rho, ux, uy, renormalise_mass=True, zero_staggered=False):
     _check(_lib.lbm_init_fields_device(h, _dptr(rho), _dptr(ux), _dptr(uy),
-                                       int(bool(renormalise_mass))))
+                                       _init_flags(renormalise_mass, zero_staggered)))
 
 
-def lbm_batch_init_fields_device(b, k, rho, ux, uy, renormalise_mass=True):
+def lbm_batch_init_fields_device(b, k, rho, ux, uy, renormalise_mass=True,
+                                 zero_staggered=False):
     _check(_lib.lbm_batch_init_fields_device(b, int(k), _dptr(rho), _dptr(ux), _dptr(uy),
-                                             int(bool(renormalise_mass))))
+                                             _init_flags(renormalise_mass, zero_staggered)))
 
 
 def lbm_batch_cavity(b, k):
@@ -429,6 +440,11 @@ def lbm_batch_cavity(b, k):
     _check(_lib.lbm_batch_cavity(b, int(k), ct.byref(nx), ct.byref(ny), ct.byref(re),
                                  ct.byref(u)))
     return nx.value, ny.value, re.value, u.value
+
+
+def lbm_batch_canvas(b, k, target, mask):
+    """target: torch FP32 [256, 128, 3] (device), mask: FP32 [256, 128]."""
+    _check(_lib.lbm_batch_canvas(b, int(k), _dptr(target), _dptr(mask)))
 
 
 # -------------------------------------------------------------- surrogate ---
@@ -455,6 +471,11 @@ def lbm_sur_num_params(s):
 def lbm_sur_set_params(s, params):
     p = np.ascontiguousarray(params, dtype=np.float32)
     _check(_lib.lbm_sur_set_params(s, _ptr(p), p.size))
+
+
+def lbm_sur_init_params(s, normals):
+    z = np.ascontiguousarray(normals, dtype=np.float32)
+    _check(_lib.lbm_sur_init_params(s, _ptr(z), z.size))
 
 
 def lbm_sur_get_params(s, with_grads=False):
@@ -581,8 +602,10 @@ class Cavity:
     def get_populations(self):
         return lbm_get_populations(self.h, self.nx, self.ny)
 
-    def init_fields(self, rho=None, ux=None, uy=None, renormalise_mass=True):
-        lbm_init_fields(self.h, rho, ux, uy, self.nx, self.ny, renormalise_mass)
+    def init_fields(self, rho=None, ux=None, uy=None, renormalise_mass=True,
+                    zero_staggered=False):
+        lbm_init_fields(self.h, rho, ux, uy, self.nx, self.ny, renormalise_mass,
+                        zero_staggered)
 
     def set_stream(self, stream):
         lbm_set_stream(self.h, stream)
@@ -602,8 +625,8 @@ class Cavity:
     def autotune(self, chunks=20, use_cache=True):
         return lbm_autotune(self.h, chunks, use_cache)
 
-    def init_fields_device(self, rho, ux, uy, renormalise_mass=True):
-        lbm_init_fields_device(self.h, rho, ux, uy, renormalise_mass)
+    def init_fields_device(self, rho, ux, uy, renormalise_mass=True, zero_staggered=False):
+        lbm_init_fields_device(self.h, rho, ux, uy, renormalise_mass, zero_staggered)
 
 
 class Batch:
@@ -657,8 +680,10 @@ class Batch:
     def set_populations(self, k, f):
         lbm_batch_set_populations(self.b, k, f, self.nx[k], self.ny[k])
 
-    def init_fields(self, k, rho=None, ux=None, uy=None, renormalise_mass=True):
-        lbm_batch_init_fields(self.b, k, rho, ux, uy, self.nx[k], self.ny[k], renormalise_mass)
+    def init_fields(self, k, rho=None, ux=None, uy=None, renormalise_mass=True,
+                    zero_staggered=False):
+        lbm_batch_init_fields(self.b, k, rho, ux, uy, self.nx[k], self.ny[k], renormalise_mass,
+                              zero_staggered)
 
     def set_stream(self, stream):
         lbm_batch_set_stream(self.b, stream)
@@ -674,6 +699,9 @@ class Batch:
 
     def cavity(self, k):
         return lbm_batch_cavity(self.b, k)
+
+    def canvas(self, k, target, mask):
+        lbm_batch_canvas(self.b, k, target, mask)
 
 
 class Surrogate:

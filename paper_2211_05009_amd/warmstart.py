@@ -1,0 +1,216 @@
+"""Learned warm start: training data from the solver, training, and the
+time-to-steady comparison of warm-started batches against cold single runs.
+
+Orchestration only: the lattice updates, monitors, the network's forward and
+backward passes, the optimiser and the mapping of a prediction onto a lattice
+all run in the library's HIP kernels (include/lbm.h); this module chooses
+cases, moves fields between device buffers and keeps the clock.
+
+Steady state is Eq. 6 of arXiv 2211.05009 (Sec. 2.2 (iii)): the relative
+change of the velocity field over 100 steps below a threshold (the paper
+uses 1e-6).
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import lbm
+
+CANVAS_H, CANVAS_W = 256, 128
+U_LID = 0.1
+RHO_SCALE = 100.0      # network channel 0 = 100 (rho - 1)
+
+
+def sample_cases(n, seed, re_range=(100.0, 3000.0), ar_range=(0.4, 2.0)):
+    """(Re, Ar) pairs uniform in the given ranges (numpy default_rng(seed))."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(*re_range, size=n), rng.uniform(*ar_range, size=n)
+
+
+def solve_steady(nx, ny, re, threshold, max_steps, dtype="f32s", chunk=10000,
+                 warm=None):
+    """Run a batch of cavities (lists nx, ny, re) from rest (or warm-started
+    by `warm`, a Surrogate) until every Eq. 6 residual is below `threshold`
+    or `max_steps` is reached.  Returns the batch (kept alive) and a list of
+    per-cavity dicts with the steps taken and the final residual."""
+    b = lbm.Batch(nx, ny, re, u_lid=U_LID, dtype=dtype)
+    if warm is not None:
+        for k in range(len(nx)):
+            warm.warm_start_batch(b, k)
+    b.set_threshold(threshold)
+    done = 0
+    while done < max_steps:
+        step = min(chunk, max_steps - done)
+        b.step(step)
+        done += step
+        if not any(b.status(k)["active"] for k in range(len(nx))):
+            break
+    return b, [b.status(k) for k in range(len(nx))]
+
+
+def training_data(n, seed, nx=200, threshold=1e-6, max_steps=2_000_000, dtype="f32s"):
+    """Steady fields of n random cavities on nx x round(nx Ar) lattices,
+    resampled onto the network canvas on the GPU (lbm_batch_canvas).
+
+    The lattice is finer than the 128-pixel canvas because BGK stays stable
+    in the driven cavity only up to a lattice Reynolds number U / nu = Re / nx
+    of about 16 (the paper's 500-site runs at Re = 8000 sit at 16): nx = 200
+    covers Re = 3000.  Ar is returned as the lattice's ny / nx.  Returns a
+    dict with re, ar, target [n, 256, 128, 3] and mask [n, 256, 128] as
+    device tensors, steps, residual, seconds."""
+    import torch
+    re, ar = sample_cases(n, seed)
+    nxs = [nx] * n
+    nys = [int(np.rint(nx * a)) for a in ar]
+    ar = np.array([y / nx for y in nys])
+    t0 = time.perf_counter()
+    b, st = solve_steady(nxs, nys, re, threshold, max_steps, dtype)
+    target = torch.empty((n, CANVAS_H, CANVAS_W, 3), dtype=torch.float32, device="cuda")
+    mask = torch.empty((n, CANVAS_H, CANVAS_W), dtype=torch.float32, device="cuda")
+    for k in range(n):
+        b.canvas(k, target[k], mask[k])
+    b.close()
+    return {"re": re, "ar": ar, "target": target, "mask": mask,
+            "steps": [s["steps_done"] for s in st],
+            "residual": [s["residual"] for s in st],
+            "seconds": time.perf_counter() - t0}
+
+
+def train(sur, data, epochs, batch=8, lr=1e-3, lr_final=1e-5, seed=0, log_every=0,
+          log=print):
+    """Adam over shuffled minibatches with a cosine learning-rate decay.
+    Returns the per-epoch mean loss."""
+    import torch
+    n = len(data["re"])
+    rng = np.random.default_rng(seed)
+    tgt, msk = data["target"], data["mask"]
+    hist = []
+    total = epochs * ((n + batch - 1) // batch)
+    it = 0
+    for ep in range(epochs):
+        perm = rng.permutation(n)
+        losses = []
+        for i in range(0, n, batch):
+            idx = np.sort(perm[i:i + batch])
+            t = it / max(total - 1, 1)
+            rate = lr_final + 0.5 * (lr - lr_final) * (1 + np.cos(np.pi * t))
+            ti = torch.as_tensor(idx, device="cuda")
+            losses.append(sur.train_step(data["re"][idx], data["ar"][idx],
+                                         tgt.index_select(0, ti).contiguous(),
+                                         msk.index_select(0, ti).contiguous(), rate))
+            it += 1
+        hist.append(float(np.mean(losses)))
+        if log_every and (ep + 1) % log_every == 0:
+            log(f"epoch {ep + 1}: loss {hist[-1]:.5f}")
+    return hist
+
+
+def evaluate(sur, data):
+    """Masked mean-squared error of the predictions on a data set."""
+    import torch
+    n = len(data["re"])
+    out = torch.empty((n, CANVAS_H, CANVAS_W, 3), dtype=torch.float32, device="cuda")
+    for i in range(0, n, sur.max_batch):
+        j = min(i + sur.max_batch, n)
+        sur.forward(data["re"][i:j], data["ar"][i:j], out[i:j])
+    m = data["mask"][..., None]
+    return float((((out - data["target"]) ** 2) * m).sum() / data["mask"].sum())
+
+
+def time_to_steady(cases, threshold, max_steps, mode, sur=None, dtype="f32s"):
+    """Wall time and steps to reach Eq. 6 residual < threshold for every
+    cavity in `cases` ((nx, ny, re) list).
+
+    mode: "single-cold" (one cavity after another, from rest: the plain
+    method), "single-warm", "batch-cold", "batch-warm".  Warm starts include
+    the surrogate inference and the mapping onto the lattice in the time."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    steps = []
+    if mode.startswith("single"):
+        for (nx, ny, re) in cases:
+            c = lbm.Cavity(nx, ny, re=re, u_lid=U_LID, dtype=dtype)
+            if mode == "single-warm":
+                sur.warm_start(c)
+            done, res = 0, np.inf
+            while done < max_steps:
+                c.step(1000)
+                done += 1000
+                res = c.residual()[0]
+                if res < threshold:
+                    break
+            steps.append(done)
+            c.close()
+    else:
+        nx, ny, re = zip(*cases)
+        b, st = solve_steady(list(nx), list(ny), list(re), threshold, max_steps, dtype,
+                             chunk=1000, warm=sur if mode == "batch-warm" else None)
+        steps = [s["steps_done"] for s in st]
+        b.close()
+    torch.cuda.synchronize()
+    return {"mode": mode, "seconds": time.perf_counter() - t0, "steps": steps,
+            "max_steps_hit": int(sum(s >= max_steps for s in steps))}
+
+
+
+STEADY_RE = (1000.0, 1500.0, 2000.0, 2500.0, 3000.0)
+STEADY_AR = (0.4, 0.8, 1.2, 1.6, 2.0)
+
+
+def steady_sweep_cases(nx=500):
+    """The steady Re x Ar sweep on the paper's 500 x (500 Ar) lattices."""
+    return [(nx, int(round(nx * ar)), re) for ar in STEADY_AR for re in STEADY_RE]
+
+
+def make_surrogate(normals, max_batch=8):
+    """A surrogate with He-normal weights drawn from `normals` (a float array
+    of lbm_sur_num_params standard normal draws)."""
+    sur = lbm.Surrogate(max_batch=max_batch)
+    lbm.lbm_sur_init_params(sur.s, normals)
+    return sur
+
+
+def steady_sweep_study(normals, threshold=1e-6, ntrain=200, epochs=150, nx=500,
+                       max_steps=5_000_000, ablations=False, log=None):
+    """Time-to-steady of the steady sweep (25 cavities, Re 1000-3000 x Ar
+    0.4-2.0 at nx x (nx Ar)): plain = single cavities one after another from
+    rest; treatment = one batch, every cavity warm-started by the surrogate
+    (inference, mapping and mass renormalisation inside the timed region).
+    The one-off surrogate cost (training data and training) is reported
+    separately."""
+    t0 = time.perf_counter()
+    data = training_data(ntrain, seed=0, threshold=threshold)
+    t_data = time.perf_counter() - t0
+    if log:
+        log(f"training data: {ntrain} fields in {t_data:.1f} s")
+    sur = make_surrogate(normals)
+    t1 = time.perf_counter()
+    hist = train(sur, data, epochs, log_every=25 if log else 0, log=log or print)
+    t_train = time.perf_counter() - t1
+    if log:
+        log(f"trained {epochs} epochs in {t_train:.1f} s, loss {hist[-1]:.5f}")
+    held = training_data(20, seed=1, threshold=threshold)
+    cases = steady_sweep_cases(nx)
+    modes = ["single-cold", "batch-warm"]
+    if ablations:
+        modes += ["batch-cold", "single-warm"]
+    res = {}
+    for m in modes:
+        r = time_to_steady(cases, threshold, max_steps, m, sur=sur)
+        res[m] = {"seconds": round(r["seconds"], 3), "steps_total": int(sum(r["steps"])),
+                  "steps_median": float(np.median(r["steps"])),
+                  "max_steps_hit": r["max_steps_hit"]}
+        if log:
+            log(m, res[m])
+    out = {"cases": len(cases), "lattice": f"{nx} x ({nx} Ar)", "threshold_eq6": threshold,
+           "storage": "f32s", "modes": res,
+           "speedup": round(res["single-cold"]["seconds"] / res["batch-warm"]["seconds"], 3),
+           "surrogate": {"train_samples": ntrain, "epochs": epochs,
+                         "data_seconds": round(t_data, 2), "train_seconds": round(t_train, 2),
+                         "final_train_loss": round(hist[-1], 6),
+                         "heldout_mse": round(evaluate(sur, held), 6)}}
+    sur.close()
+    return out

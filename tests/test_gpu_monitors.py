@@ -143,6 +143,14 @@ def test_init_fields_is_equilibrium_with_mass_renormalised(lbm, dtype):
     c.init_fields(rho, None, None, renormalise_mass=False)
     tol = 1e-9 if dtype == "f64" else 1e-6      # FP32 rounding of w (rho - 1)
     assert abs(c.mass() - math.fsum(rho.ravel().tolist())) <= tol
+    # with the staggered momenta removed (period-two invariants, zero at rest)
+    c.init_fields(rho, ux, uy, renormalise_mass=True, zero_staggered=True)
+    vx, vy = d2q9.destaggered_velocity(rho * scale, ux, uy)
+    ref = d2q9.equilibrium(rho * scale, vx, vy)
+    tol = 1e-15 if dtype == "f64" else 3e-9
+    assert np.max(np.abs(c.get_populations() - ref)) <= tol
+    px, py = d2q9.staggered_momenta(c.get_populations())
+    assert abs(px) <= (1e-12 if dtype == "f64" else 1e-5) and abs(py) <= (1e-12 if dtype == "f64" else 1e-5)
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32s"])

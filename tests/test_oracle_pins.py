@@ -216,3 +216,45 @@ def test_vectorised_matches_naive_twin(nx, ny, tau, u):
     c.step(200)
     ref = np.array(naive_steps(f0, tau, u, 200))
     assert np.max(np.abs(c.f - ref)) <= 1e-14
+
+
+# ------------------------------------------- period-two invariants -------
+@pytest.mark.parametrize("nx,ny", [(8, 6), (7, 5)])
+def test_staggered_momenta_alternate_exactly(nx, ny):
+    """Collision keeps j per site; links and reflections flip the column (or
+    row) parity of every population with c_x (c_y) != 0: P_x, P_y change
+    sign each step, P_x gains u/3 per step from the lid term when Nx is odd."""
+    U = 0.1
+    c = Cavity(nx, ny, tau=0.6, u_lid=U)
+    c.set_state(W[:, None, None] + random_shift(nx, ny, 3))
+    for _ in range(5):
+        px, py = d2q9.staggered_momenta(c.f)
+        c.step(1)
+        qx, qy = d2q9.staggered_momenta(c.f)
+        assert abs(qx + px - (U / 3 if nx % 2 else 0.0)) < 1e-14
+        assert abs(qy + py) < 1e-14
+
+
+def test_steady_state_is_set_by_mass_and_staggered_momenta():
+    """A start from a random field converges to the cold-start steady state
+    only once its staggered momenta are removed (both have P = 0)."""
+    nx, ny, re = 16, 12, 40.0
+    rng = np.random.default_rng(0)
+    rho = 1 + 0.01 * rng.standard_normal((ny, nx))
+    rho *= nx * ny / rho.sum()
+    ux = 0.02 * rng.standard_normal((ny, nx))
+    uy = 0.02 * rng.standard_normal((ny, nx))
+    cold = Cavity(nx, ny, re=re)
+    raw = Cavity(nx, ny, re=re)
+    raw.set_state(equilibrium(rho, ux, uy))
+    fixed = Cavity(nx, ny, re=re)
+    vx, vy = d2q9.destaggered_velocity(rho, ux, uy)
+    fixed.set_state(equilibrium(rho, vx, vy))
+    assert max(abs(v) for v in d2q9.staggered_momenta(fixed.f)) < 1e-14
+    for c in (cold, raw, fixed):
+        c.step(12000)
+    _, u0, v0 = cold.moments()
+    _, u1, v1 = raw.moments()
+    _, u2, v2 = fixed.moments()
+    assert np.max(np.abs(u2 - u0)) < 1e-11 and np.max(np.abs(v2 - v0)) < 1e-11
+    assert np.max(np.abs(u1 - u0)) > 1e-5
