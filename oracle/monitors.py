@@ -17,6 +17,10 @@
 * ``vortex_extrema``  -- the primary vortex (max Psi) and the two bottom
                          corner vortices (min Psi in each bottom quadrant), with
                          centre positions in units of L, as in Tables 1-2.
+* ``vortex_centres``  -- every vortex centre: an interior site where Psi is a
+                         strict extremum of its 3 x 3 neighbourhood.
+* ``bottom_vortex_count`` -- the vortex centres below the primary vortex
+                         (the count of Table 2's last column).
 """
 from __future__ import annotations
 
@@ -113,3 +117,37 @@ def vortex_extrema(psi, nx):
         ii += xs.start
         res[name] = (float(psi[jj, ii]), (ii + 0.5) / nx, (jj + 0.5) / nx)
     return res
+
+
+def vortex_centres(psi, min_abs=0.0):
+    """Sites (iy, ix) with 1 <= ix <= Nx-2 and 1 <= iy <= Ny-2 where Psi is
+    strictly greater (kind +1) or strictly smaller (kind -1) than at all
+    eight neighbours, and |Psi| >= min_abs.  Returns (iy, ix, kind, psi)
+    tuples in row-major order."""
+    psi = np.asarray(psi, dtype=np.float64)
+    ny, nx = psi.shape
+    if nx < 3 or ny < 3:
+        return []
+    c = psi[1:-1, 1:-1]
+    is_max = np.ones(c.shape, dtype=bool)
+    is_min = np.ones(c.shape, dtype=bool)
+    for dy in (-1, 0, 1):
+        for dx in (-1, 0, 1):
+            if dy == 0 and dx == 0:
+                continue
+            nb = psi[1 + dy:ny - 1 + dy, 1 + dx:nx - 1 + dx]
+            is_max &= c > nb
+            is_min &= c < nb
+    keep = np.abs(c) >= min_abs
+    out = []
+    for j, i in zip(*np.nonzero((is_max | is_min) & keep)):
+        out.append((int(j) + 1, int(i) + 1, 1 if is_max[j, i] else -1, float(c[j, i])))
+    return out
+
+
+def bottom_vortex_count(psi, min_abs=0.0):
+    """Number of vortex centres strictly below the primary vortex's centre
+    (the first site of maximal Psi in row-major order)."""
+    psi = np.asarray(psi, dtype=np.float64)
+    jp, _ = np.unravel_index(int(np.argmax(psi)), psi.shape)
+    return sum(1 for (j, _, _, _) in vortex_centres(psi, min_abs) if j < jp)

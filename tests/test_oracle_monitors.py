@@ -72,3 +72,56 @@ def test_centreline_even_and_odd():
     u, v = monitors.centreline(ux, uy)
     assert np.array_equal(u, 0.5 * (ux[:, 1] + ux[:, 2]))
     assert np.array_equal(v, uy[1])
+
+
+def _cells(P=7, Q=9, a=3, b=2, ramp=0.1):
+    """Psi = sin(pi (x + 1/2) / P) sin(pi (y + 1/2) / Q) (1 + ramp y / Ny) on
+    a P x Q-cell checkerboard: odd P and Q put each cell's extremum exactly
+    on a site, with both neighbours in each direction strictly lower."""
+    nx, ny = a * P, b * Q
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    psi = np.sin(np.pi * (x + 0.5) / P) * np.sin(np.pi * (y + 0.5) / Q) * (1 + ramp * y / ny)
+    return psi, P, Q, a, b
+
+
+def test_vortex_centres_of_a_checkerboard():
+    psi, P, Q, a, b = _cells()
+    got = monitors.vortex_centres(psi)
+    want = []
+    for cb in range(b):
+        for ca in range(a):
+            j, i = cb * Q + (Q - 1) // 2, ca * P + (P - 1) // 2
+            want.append((j, i, 1 if (ca + cb) % 2 == 0 else -1, psi[j, i]))
+    assert got == want
+    # the threshold drops the weaker bottom row: |Psi| = 1 + ramp * 4/18 there
+    thr = 0.5 * (abs(psi[4, 3]) + abs(psi[13, 3]))
+    assert [c[:2] for c in monitors.vortex_centres(psi, thr)] == [(13, 3), (13, 10), (13, 17)]
+    assert monitors.vortex_centres(psi, 10.0) == []
+
+
+def test_vortex_centres_need_a_strict_extremum():
+    y, x = np.mgrid[0:21, 0:21].astype(np.float64)
+    assert monitors.vortex_centres((x - 10) ** 2 - (y - 10) ** 2) == []      # saddle
+    assert monitors.vortex_centres(np.full((9, 9), 0.25)) == []             # plateau
+    assert monitors.vortex_centres(monitors.stream_function(0.01 * y)) == []  # shear flow
+    bump = -((x - 10) ** 2 + (y - 10) ** 2)
+    assert monitors.vortex_centres(bump) == [(10, 10, 1, 0.0)]
+    bump[10, 11] = 0.0                        # a tie with a neighbour: not strict
+    assert monitors.vortex_centres(bump) == []
+    # above its four axis neighbours but below a diagonal one: not a centre
+    assert monitors.vortex_centres((x + y) - 3 * (x - y) ** 2) == []
+    # the outer ring is never a candidate
+    edge = np.zeros((5, 5))
+    edge[0, 2] = edge[2, 0] = 1.0
+    assert monitors.vortex_centres(edge) == []
+    assert monitors.vortex_centres(np.zeros((2, 7))) == []
+
+
+def test_bottom_vortex_count():
+    psi, *_ = _cells()
+    # the ramp makes the top row of cells stronger: the primary is the top
+    # row's first maximum, and the three centres of the bottom row lie below it
+    assert monitors.bottom_vortex_count(psi) == 3
+    assert monitors.bottom_vortex_count(psi[::-1].copy()) == 0
+    psi3, *_ = _cells(b=3)
+    assert monitors.bottom_vortex_count(psi3) == 6
