@@ -19,6 +19,12 @@
                          centre positions in units of L, as in Tables 1-2.
 * ``vortex_centres``  -- every vortex centre: an interior site where Psi is a
                          strict extremum of its 3 x 3 neighbourhood.
+* ``stream_function_nodes`` -- Psi on a lattice whose walls lie on the
+                         outermost nodes (the paper's own wall scheme): Psi = 0
+                         on the bottom row, trapezoid rule up each column.
+
+``probe`` and ``vortex_extrema`` take ``on_node=True`` for such lattices: node
+i then sits at i / (Nx - 1) in units of L.
 * ``bottom_vortex_count`` -- the vortex centres below the primary vortex
                          (the count of Table 2's last column).
 """
@@ -53,6 +59,15 @@ def stream_function(ux):
     return -(below + 0.5 * ux)
 
 
+def stream_function_nodes(ux):
+    """Psi[0, x] = 0, Psi[y, x] = Psi[y-1, x] - (u_x[y-1, x] + u_x[y, x]) / 2."""
+    ux = np.asarray(ux, dtype=np.float64)
+    psi = np.zeros_like(ux)
+    for y in range(1, ux.shape[0]):
+        psi[y] = psi[y - 1] - 0.5 * (ux[y - 1] + ux[y])
+    return psi
+
+
 def _bilinear(field, X, Y):
     ny, nx = field.shape
     X = min(max(X, 0.0), nx - 1.0)
@@ -67,15 +82,20 @@ def _bilinear(field, X, Y):
             + (1 - tx) * ty * field[j1, i0] + tx * ty * field[j1, i1])
 
 
-def probe(rho, ux, uy, points):
+def probe(rho, ux, uy, points, on_node=False):
     """(rho, u_x, u_y) at each point (x, y), coordinates in units of L = Nx.
 
-    Site (i, j) has its centre at ((i + 1/2)/Nx, (j + 1/2)/Nx)."""
+    Site (i, j) has its centre at ((i + 1/2)/Nx, (j + 1/2)/Nx); with
+    on_node, node (i, j) sits at (i, j)/(Nx - 1) and L = Nx - 1."""
     nx = np.asarray(rho).shape[1]
     out = []
     for (px, py) in points:
-        X = px * nx - 0.5
-        Y = py * nx - 0.5
+        if on_node:
+            X = px * (nx - 1)
+            Y = py * (nx - 1)
+        else:
+            X = px * nx - 0.5
+            Y = py * nx - 0.5
         out.append([_bilinear(np.asarray(rho), X, Y),
                     _bilinear(np.asarray(ux), X, Y),
                     _bilinear(np.asarray(uy), X, Y)])
@@ -99,23 +119,28 @@ def centreline(ux, uy):
     return u_vert, v_horz
 
 
-def vortex_extrema(psi, nx):
+def vortex_extrema(psi, nx, on_node=False):
     """Primary vortex = global max of Psi; lower-left / lower-right vortices =
     min of Psi over the bottom-left / bottom-right quarter (x < W/2 or
-    x >= W/2, y < W/2).  Positions are site centres in units of L = Nx.
-    Returns a dict of (value, x, y)."""
+    x >= W/2, y < W/2, W = Nx sites or nodes).  Positions are site centres in
+    units of L = Nx (on_node: node positions i / (Nx - 1)).  Returns a dict of
+    (value, x, y)."""
     psi = np.asarray(psi)
     ny = psi.shape[0]
+
+    def pos(i):
+        return i / (nx - 1) if on_node else (i + 0.5) / nx
+
     res = {}
     j, i = np.unravel_index(int(np.argmax(psi)), psi.shape)
-    res["primary"] = (float(psi[j, i]), (i + 0.5) / nx, (j + 0.5) / nx)
+    res["primary"] = (float(psi[j, i]), pos(i), pos(j))
     hy = min(ny, nx // 2)
     for name, xs in (("lower_left", slice(0, nx // 2)),
                      ("lower_right", slice(nx // 2, nx))):
         sub = psi[:hy, xs]
         jj, ii = np.unravel_index(int(np.argmin(sub)), sub.shape)
         ii += xs.start
-        res[name] = (float(psi[jj, ii]), (ii + 0.5) / nx, (jj + 0.5) / nx)
+        res[name] = (float(psi[jj, ii]), pos(ii), pos(jj))
     return res
 
 

@@ -82,3 +82,53 @@ def naive_steps(f, tau, u_lid, nsteps, num=float):
                     nxt[r][y][x] = post[i] - 6 * wgt[i] * one * (cx * wall_u)
         cur = nxt
     return cur
+
+
+def naive_steps_nee(f, tau, u_lid, nsteps, num=float):
+    """Push-form twin of ``oracle.nee``: walls on the outermost nodes, rebuilt
+    after every step from the nearest fluid node by non-equilibrium
+    extrapolation (Sec. 2.2 (ii)); the top row, corners included, moves
+    with (u_lid, 0).  ``f`` is [9][ny][nx] with ny, nx >= 3."""
+    ny = len(f[0])
+    nx = len(f[0][0])
+    one = num(1)
+    wgt = [num(a) / num(b) for a, b in zip(_WGT_NUM, _WGT_DEN)]
+    tau = num(tau)
+    u_lid = num(u_lid)
+    cur = [[[num(f[i][y][x]) for x in range(nx)] for y in range(ny)]
+           for i in range(9)]
+
+    def moments(pops):
+        rho = sum(pops, num(0))
+        jx = sum((_VEL[i][0] * pops[i] for i in range(9)), num(0))
+        jy = sum((_VEL[i][1] * pops[i] for i in range(9)), num(0))
+        return rho, jx / rho, jy / rho
+
+    def fluid(x, y):
+        return 0 < x < nx - 1 and 0 < y < ny - 1
+
+    for _ in range(nsteps):
+        nxt = [[[None] * nx for _ in range(ny)] for _ in range(9)]
+        for y in range(ny):
+            for x in range(nx):
+                pops = [cur[i][y][x] for i in range(9)]
+                rho, ux, uy = moments(pops)
+                eq = _feq_site(rho, ux, uy, wgt, one)
+                for i in range(9):
+                    tx, ty = x + _VEL[i][0], y + _VEL[i][1]
+                    if fluid(tx, ty):
+                        nxt[i][ty][tx] = pops[i] - (pops[i] - eq[i]) / tau
+        for y in range(ny):
+            for x in range(nx):
+                if fluid(x, y):
+                    continue
+                xr = min(max(x, 1), nx - 2)
+                yr = min(max(y, 1), ny - 2)
+                ref = [nxt[i][yr][xr] for i in range(9)]
+                rho, ux, uy = moments(ref)
+                eq_ref = _feq_site(rho, ux, uy, wgt, one)
+                eq_wall = _feq_site(rho, u_lid if y == ny - 1 else num(0), num(0), wgt, one)
+                for i in range(9):
+                    nxt[i][y][x] = eq_wall[i] + ref[i] - eq_ref[i]
+        cur = nxt
+    return cur

@@ -125,3 +125,32 @@ def test_bottom_vortex_count():
     assert monitors.bottom_vortex_count(psi[::-1].copy()) == 0
     psi3, *_ = _cells(b=3)
     assert monitors.bottom_vortex_count(psi3) == 6
+
+
+def test_node_stream_function_closed_forms():
+    """Trapezoid rule from the bottom wall row: exact for uniform and linear
+    (Couette) profiles on nodes y = 0 ... Ny - 1."""
+    ny, nx, U = 9, 4, 0.1
+    y = np.arange(ny, dtype=np.float64)[:, None] * np.ones((1, nx))
+    assert np.allclose(monitors.stream_function_nodes(np.full((ny, nx), 0.03)), -0.03 * y,
+                       rtol=0, atol=1e-16)
+    psi = monitors.stream_function_nodes(U * y / (ny - 1))
+    assert np.allclose(psi, -U * y ** 2 / (2 * (ny - 1)), rtol=0, atol=1e-16)
+    assert np.all(psi[0] == 0)
+
+
+def test_on_node_positions():
+    nx = 11
+    psi = np.zeros((8, nx))
+    psi[5, 3] = 2.0
+    psi[1, 2] = -1.0
+    psi[2, 8] = -0.5
+    ext = monitors.vortex_extrema(psi, nx, on_node=True)
+    assert ext["primary"] == (2.0, 0.3, 0.5)
+    assert ext["lower_left"] == (-1.0, 0.2, 0.1)
+    assert ext["lower_right"] == (-0.5, 0.8, 0.2)
+    # probe at nodes and between them (node i at i / (nx - 1))
+    yy, xx = np.mgrid[0:8, 0:nx].astype(np.float64)
+    f = 3.0 + 0.5 * xx - 0.25 * yy
+    got = monitors.probe(f, f, f, [(0.3, 0.5), (0.35, 0.05)], on_node=True)
+    assert np.allclose(got[:, 0], [3.0 + 1.5 - 1.25, 3.0 + 1.75 - 0.125], rtol=0, atol=1e-15)
