@@ -16,17 +16,18 @@ roofline of the step kernel (72 B per site update in FP32, 144 B in FP64:
 nine populations read and nine written; a multi-step launch counts K
 updates); per-case figures for the other aspect ratios and FP64 storage; the
 25-cavity Re x Ar sweep advanced as one batch against the same 25 cavities
-run one after another; the time to steady state (Eq. 6 residual < 1e-6) of
-a steady 25-cavity sweep (Re 1000-3000 x Ar 0.4-2.0 at 500 x (500 Ar))
-batched and warm-started by the learned surrogate against plain cold single
-runs; a plain device copy's bandwidth on the same GPU; and the CPU oracle
-timed on a bounded sample.
+run one after another; the time to steady state (Eq. 6 residual below
+--tts-threshold, 1e-6 by default) of a steady 25-cavity sweep (Re 1000-3000
+x Ar 0.4-2.0 at 500 x (500 Ar)) batched and warm-started by the learned
+surrogate against plain cold single runs, with the batched-cold and
+single-warm ablations and the surrogate's MFMA throughput; a plain device
+copy's bandwidth on the same GPU; and the CPU oracle timed on a bounded
+sample.
 
 ``--copy-probe BYTES`` instead runs a plain device copy of BYTES bytes ten
 times (used to calibrate the rocprofv3 FETCH_SIZE / WRITE_SIZE counters).
 """
 import argparse
-import glob
 import hashlib
 import json
 import os
@@ -61,17 +62,29 @@ def parse():
                     help="time-to-steady of the steady sweep, batched + warm-started vs "
                          "plain (0: skip)")
     ap.add_argument("--tts-epochs", type=int, default=150)
-    ap.add_argument("--tts-ablations", type=int, default=0)
+    ap.add_argument("--tts-modes", default="single-cold,batch-warm,batch-cold,single-warm",
+                    help="time-to-steady arms: plain (single-cold), treatment (batch-warm) "
+                         "and the two ablations")
+    ap.add_argument("--tts-dtype", default="f32s", choices=["f32s", "f64"],
+                    help="storage of the time-to-steady runs")
+    ap.add_argument("--tts-threshold", type=float, default=1e-6,
+                    help="Eq. 6 residual that counts as steady")
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-steps", type=int, default=200)
+    ap.add_argument("--cpu-steps", type=int, default=700)
     ap.add_argument("--copy-probe", type=int, default=0)
     return ap.parse_args()
 
 
+# Sources that define the single-cavity step kernels and their launch.
+STEP_SOURCES = ("d2q9_step.hpp", "d2q9_temporal.hpp", "lbm_internal.h", "lbm.hip")
+
+
 def source_hash():
-    """Fingerprint of the HIP sources (decides whether stored counters apply)."""
+    """Fingerprint of the step kernels' sources (decides whether stored
+    counters still apply)."""
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_2211_05009_amd", "csrc", "*"))):
+    for name in STEP_SOURCES:
+        p = os.path.join(ROOT, "paper_2211_05009_amd", "csrc", name)
         with open(p, "rb") as fh:
             h.update(os.path.basename(p).encode())
             h.update(fh.read())
@@ -288,8 +301,8 @@ def main():
         probe.close()
         progress("time to steady: training data, training, plain and warm-started sweeps")
         out["sweep_time_to_steady"] = warmstart.steady_sweep_study(
-            normal_draws(npar, seed=0), epochs=args.tts_epochs, ablations=bool(args.tts_ablations),
-            log=progress)
+            normal_draws(npar, seed=0), threshold=args.tts_threshold, epochs=args.tts_epochs,
+            modes=tuple(args.tts_modes.split(",")), dtype=args.tts_dtype, log=progress)
     out["copy_GBs"] = copy_bandwidth(torch)
     if args.cpu_baseline:
         progress("CPU oracle baseline")

@@ -14,11 +14,11 @@
  *   - Sec. 2.2 (i): start from rest, rho = 1, f = f^eq;
  *   - Sec. 2.2 (iii) Eq. 6: relative L2 change of u over 100 steps;
  *   - Sec. 3.3: velocity at observing points, positions in units of L.
- * Walls: half-way bounce-back on the three resting walls and the
- * moving-wall bounce-back term -6 w rho_w (c . u_w), rho_w = 1, on the lid
- * (the paper's own non-equilibrium-extrapolation scheme, Sec. 2.2 (ii), is
- * not this library's boundary).  Links through the two top corners belong
- * to the lid.
+ * Walls (default): half-way bounce-back on the three resting walls and the
+ * moving-wall bounce-back term -6 w rho_w (c . u_w), rho_w = 1, on the lid.
+ * Links through the two top corners belong to the lid.  The paper's own
+ * scheme, non-equilibrium extrapolation on on-node walls (Sec. 2.2 (ii)),
+ * is selected with lbm_create_wall.
  *
  * Lattice: Nx sites along the lid, Ny sites up; site (x, y), y = 0 at the
  * bottom.  Host arrays exchanged through this ABI are row-major [ny][nx]
@@ -65,6 +65,12 @@ enum {
                            mass, residual, probes, Psi reduced in FP64 */
 };
 
+/* Wall schemes. */
+enum {
+  LBM_WALL_BOUNCE_BACK = 0,  /* half-way bounce-back; walls half a link outside the sites */
+  LBM_WALL_NEE = 1           /* non-equilibrium extrapolation on on-node walls */
+};
+
 typedef struct lbm_cavity *lbm_t;
 
 typedef struct {
@@ -75,6 +81,7 @@ typedef struct {
   double tau, omega;    /* relaxation time (Eq. 5) and 1/tau */
   int64_t steps_done;   /* applications of Eq. 1 since the last (re)start */
   size_t device_bytes;  /* device memory held by the handle */
+  int wall;             /* LBM_WALL_BOUNCE_BACK or LBM_WALL_NEE */
 } lbm_info_t;
 
 /* Message of the last failed call on this thread ("" if none). */
@@ -98,6 +105,26 @@ int lbm_create(int nx, int ny, double re, double u_lid, int dtype, lbm_t *out);
  * 3 u_lid nx / (tau - 1/2) (infinite if u_lid = 0). */
 int lbm_create_tau(int nx, int ny, double tau, double u_lid, int dtype,
                    lbm_t *out);
+
+/*
+ * Create a cavity with a chosen wall scheme.  LBM_WALL_BOUNCE_BACK is
+ * lbm_create.  LBM_WALL_NEE is the paper's scheme (Sec. 2.2 (ii)): nx x ny
+ * nodes whose outermost rows and columns are the walls, so L = nx - 1 and
+ * tau = 3 u_lid (nx - 1) / re + 1/2.  Each step, wall node (x, y) stores
+ *   f*_b = f^eq(rho_r, u_w) + (1 - 1/tau) (f_r - f^eq(rho_r, u_r)),
+ * f_r being the streamed populations of its reference node
+ * r = (clamp(x, 1, nx-2), clamp(y, 1, ny-2)); u_w = (u_lid, 0) on the top
+ * row, corners included, and 0 on the other wall nodes.  Initial state
+ * (Sec. 2.2 (i)): f = f^eq(1, u0), u0 = (u_lid, 0) on the top row, 0
+ * elsewhere.  Mass, Eq. 6 and moments cover all nodes; probes, Psi and
+ * vortex positions use node positions x / (nx - 1) in units of L, and Psi
+ * is the trapezoid rule up each column from Psi = 0 on the bottom row.  NEE
+ * handles run one-step kernels (LBM_OPT_NUM_VARIANTS = 4 tile shapes).
+ * Errors: as lbm_create; LBM_EINVAL for an unknown wall, or NEE with nx or
+ * ny < 3.
+ */
+int lbm_create_wall(int nx, int ny, double re, double u_lid, int dtype, int wall,
+                    lbm_t *out);
 
 /* Free the handle and its device memory.  NULL is a no-op. */
 int lbm_destroy(lbm_t h);
@@ -215,6 +242,52 @@ int lbm_residual(lbm_t h, double *residual, int64_t *at_step);
  * u_lid * nx for the normalisation of Table 1.
  */
 int lbm_stream_function(lbm_t h, double *psi_host);
+
+/*
+ * A vortex of the stream function Psi above (Tables 1-2: the primary vortex,
+ * its maximum of Psi and centre; the corner vortices; the bottom vortices).
+ */
+typedef struct {
+  double psi;   /* Psi at the centre site, lattice units (as lbm_stream_function) */
+  double x, y;  /* the site's centre in units of the width L: ((ix + 1/2)/nx, (iy + 1/2)/nx) */
+  int ix, iy;   /* site indices, y = 0 at the bottom */
+  int kind;     /* +1: local maximum of Psi, -1: local minimum */
+  int reserved;
+} lbm_vortex_t;
+
+/*
+ * Primary and bottom corner vortices of the current state (Table 1's three
+ * column groups), computed on the device in FP64:
+ *   out[0] = the site of maximal Psi over the lattice (the primary vortex),
+ *   out[1] = the site of minimal Psi with x < nx/2, y < min(ny, nx/2)
+ *            (lower-left vortex),
+ *   out[2] = likewise with x >= nx/2 (lower-right vortex).
+ * Ties go to the smaller linear index y nx + x.  out[1] and out[2] are
+ * the minima of those regions even where no corner vortex exists (then
+ * their Psi is >= 0).  out is a caller-owned host array of 3 records.
+ * Errors: LBM_EINVAL for NULL arguments or nx < 2 (no lower-right region).
+ */
+int lbm_vortex_extrema(lbm_t h, lbm_vortex_t *out);
+
+/*
+ * Vortex centres of the current state: every site with
+ * 1 <= ix <= nx-2 and 1 <= iy <= ny-2 where Psi is strictly greater (kind
+ * +1) or strictly smaller (kind -1) than at all eight neighbouring sites,
+ * with |Psi| >= min_abs_psi (lattice units; 0 keeps all).  *count receives
+ * the number of centres; the first min(count, cap) of them in row-major
+ * order (by iy, then ix) are written to out (caller-owned host array of cap
+ * records; may be NULL when cap = 0).
+ * Errors: LBM_EINVAL for cap < 0, a NULL count, or out NULL with cap > 0.
+ */
+int lbm_vortex_centres(lbm_t h, double min_abs_psi, int cap, lbm_vortex_t *out,
+                       int *count);
+
+/*
+ * Number of bottom vortices (Table 2's last column): the vortex centres of
+ * lbm_vortex_centres (same min_abs_psi) that lie strictly below the primary
+ * vortex's row (iy < out[0].iy of lbm_vortex_extrema).
+ */
+int lbm_bottom_vortex_count(lbm_t h, double min_abs_psi, int *count);
 
 /*
  * Replace the state by the populations f(t) [9][ny][nx] (host, the

@@ -24,8 +24,6 @@ LIB = os.path.join(PKG, "liblbm.so")
 ARCH = "gfx950"
 
 SOURCES = ["lbm.hip", "lbm_batch.hip", "lbm_nn.hip"]
-DEPS = ["lbm.hip", "lbm_batch.hip", "lbm_internal.h", "d2q9_step.hpp",
-        "d2q9_monitor.hpp", "d2q9_batch.hpp"]
 
 
 def hipcc() -> str:

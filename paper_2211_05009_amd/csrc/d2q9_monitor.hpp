@@ -18,8 +18,12 @@ constexpr int kRedThreads = 256;   // threads per reduction block
 constexpr int kRedBlocks = 1024;   // fixed grid of the reduction kernels
 constexpr int kNumSums = 3;        // sums carried by the monitor reduction
 
+// on_node = 1: walls on the outermost nodes (non-equilibrium extrapolation),
+// node i at i / (nx - 1) in units of L; 0: half-way walls, site i's centre
+// at (i + 1/2) / nx.
 struct Geometry {
   int nx, ny, pitch, plane;
+  int on_node = 0;
 };
 
 // Weights of the nine directions, velocity order of d2q9_step.hpp.
@@ -156,12 +160,20 @@ __global__ __launch_bounds__(256) void k_moments(const T *__restrict__ s,
   if (uy) uy[k] = jy / r;
 }
 
-// Bilinear interpolation of (rho, ux, uy) between site centres at points
-// given in units of the width L (site i's centre is (i + 1/2)/nx).
+// Bilinear interpolation of (rho, ux, uy) between site centres (or nodes)
+// at points given in units of the width L (site i's centre is (i + 1/2)/nx;
+// node i sits at i / (nx - 1)).
 template <typename T, bool SHIFT>
 __device__ void probe_point(const T *__restrict__ s, Geometry g, double px,
                             double py, double *out3) {
-  double X = px * g.nx - 0.5, Y = py * g.nx - 0.5;
+  double X, Y;
+  if (g.on_node) {
+    X = px * (g.nx - 1);
+    Y = py * (g.nx - 1);
+  } else {
+    X = px * g.nx - 0.5;
+    Y = py * g.nx - 0.5;
+  }
   X = fmin(fmax(X, 0.0), (double)(g.nx - 1));
   Y = fmin(fmax(Y, 0.0), (double)(g.ny - 1));
   int i0 = (int)floor(X), j0 = (int)floor(Y);

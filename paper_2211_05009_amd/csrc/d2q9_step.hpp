@@ -47,6 +47,7 @@ struct StepParams {
   int tiles_x;      // tiles along x (64 sites each)
   T omega;          // 1 / tau
   T u6;             // u_lid / 6: the moving-wall term for links 7 and 8
+  T ulid = T(0);    // lid speed (non-equilibrium extrapolation walls)
 };
 
 // Collide one site.  f[0..8] in: populations after streaming (or their

@@ -23,8 +23,10 @@
 
 #include "../../include/lbm.h"
 #include "d2q9_monitor.hpp"
+#include "d2q9_nee.hpp"
 #include "d2q9_step.hpp"
 #include "d2q9_temporal.hpp"
+#include "d2q9_vortex.hpp"
 #include "lbm_internal.h"
 
 using namespace lbm;
@@ -94,6 +96,48 @@ static int steps_per_launch(int v) {
   static const int k[kNumVariants] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1,
                                       4, 4, 2, 5, 4, 4, 5, 5, 10, 10, 5, 5};
   return (v >= 0 && v < kNumVariants) ? k[v] : 1;
+}
+
+// Non-equilibrium extrapolation handles have their own one-step shapes.
+static const int kNumNeeVariants = 4;
+
+static int num_variants(const lbm_cavity *h) {
+  return h->wall == LBM_WALL_NEE ? kNumNeeVariants : kNumVariants;
+}
+
+static int launch_steps(const lbm_cavity *h, int v) {
+  return h->wall == LBM_WALL_NEE ? 1 : steps_per_launch(v);
+}
+
+template <typename T, bool S, int BY, int RY>
+static hipError_t launch_nee_t(const lbm_cavity *h, const void *src, void *dst,
+                               hipStream_t st) {
+  StepParams<T> p;
+  p.src = (const T *)src;
+  p.dst = (T *)dst;
+  p.nx = h->nx;
+  p.ny = h->ny;
+  p.pitch = h->pitch;
+  p.plane = h->plane;
+  p.tiles_x = (h->nx + 63) / 64;
+  p.omega = (T)h->omega;
+  p.u6 = (T)(h->u_lid / 6.0);
+  p.ulid = (T)h->u_lid;
+  const int tiles_y = (h->ny + BY * RY - 1) / (BY * RY);
+  hipLaunchKernelGGL((k_step_nee<T, S, BY, RY>), dim3(p.tiles_x * tiles_y), dim3(64, BY), 0,
+                     st, p);
+  return hipGetLastError();
+}
+
+template <typename T, bool S>
+static hipError_t launch_nee_variant(const lbm_cavity *h, int v, const void *src, void *dst,
+                                     hipStream_t st) {
+  switch (v) {
+    case 1: return launch_nee_t<T, S, 4, 2>(h, src, dst, st);
+    case 2: return launch_nee_t<T, S, 8, 1>(h, src, dst, st);
+    case 3: return launch_nee_t<T, S, 2, 4>(h, src, dst, st);
+    default: return launch_nee_t<T, S, 4, 1>(h, src, dst, st);
+  }
 }
 
 template <typename T, bool S, int BY, int RY>
@@ -195,6 +239,10 @@ static hipError_t launch_step_variant(const lbm_cavity *h, int v, const void *sr
 // One launch of variant v (steps_per_launch(v) steps).
 static hipError_t launch_variant(const lbm_cavity *h, int v, const void *src, void *dst,
                                  hipStream_t st) {
+  if (h->wall == LBM_WALL_NEE) {
+    if (h->dtype == LBM_F64) return launch_nee_variant<double, false>(h, v, src, dst, st);
+    return launch_nee_variant<float, true>(h, v, src, dst, st);
+  }
   if (h->dtype == LBM_F64) return launch_step_variant<double, false>(h, v, src, dst, st);
   return launch_step_variant<float, true>(h, v, src, dst, st);
 }
@@ -202,13 +250,13 @@ static hipError_t launch_variant(const lbm_cavity *h, int v, const void *src, vo
 // One step (a one-step variant: the chosen one, or the default).
 static hipError_t launch_step(const lbm_cavity *h, const void *src, void *dst,
                               hipStream_t st) {
-  return launch_variant(h, steps_per_launch(h->variant) == 1 ? h->variant : 0, src, dst, st);
+  return launch_variant(h, launch_steps(h, h->variant) == 1 ? h->variant : 0, src, dst, st);
 }
 
 // Variant used for 100-step chunks: a multi-step variant only if the probe
 // cadence falls on its launch boundaries.
 static int chunk_variant(const lbm_cavity *h) {
-  const int k = steps_per_launch(h->variant);
+  const int k = launch_steps(h, h->variant);
   if (k > 1 && h->probe_n > 0 && h->probe_every <= kChunk && h->probe_every % k != 0) return 0;
   return h->variant;
 }
@@ -220,6 +268,7 @@ static Geometry geom(const lbm_cavity *h) {
   g.ny = h->ny;
   g.pitch = h->pitch;
   g.plane = h->plane;
+  g.on_node = h->wall == LBM_WALL_NEE;
   return g;
 }
 
@@ -282,7 +331,7 @@ static void drop_graphs(lbm_cavity *h) {
 // Buffer index holding the state after a 100-step chunk that starts in
 // buf[c] (an odd number of launches per chunk swaps the buffers).
 static int chunk_end(const lbm_cavity *h, int c) {
-  const int launches = kChunk / steps_per_launch(chunk_variant(h));
+  const int launches = kChunk / launch_steps(h, chunk_variant(h));
   return (launches & 1) ? 1 - c : c;
 }
 
@@ -290,7 +339,7 @@ static int chunk_end(const lbm_cavity *h, int c) {
 // directly or under capture), ending with the monitor.
 static hipError_t issue_chunk(lbm_cavity *h, int c, hipStream_t st) {
   const int v = chunk_variant(h);
-  const int K = steps_per_launch(v);
+  const int K = launch_steps(h, v);
   int cur = c;
   for (int k = K; k <= kChunk; k += K) {
     hipError_t e = launch_variant(h, v, h->buf[cur], h->buf[1 - cur], st);
@@ -352,11 +401,16 @@ const char *lbm_last_error(void) { return g_lbm_err.c_str(); }
 const char *lbm_version(void) { return "mi355x-lbm 0.1 (gfx950)"; }
 
 static int create_impl(int nx, int ny, double tau, double re, double u_lid,
-                       int dtype, lbm_t *out) {
+                       int dtype, int wall, lbm_t *out) {
   if (!out) return lbm_fail(LBM_EINVAL, "out is NULL");
   *out = nullptr;
   if (nx < 2 || ny < 2 || nx > 65536 || ny > 65536)
     return lbm_fail(LBM_EINVAL, "lattice %d x %d outside [2, 65536]", nx, ny);
+  if (wall != LBM_WALL_BOUNCE_BACK && wall != LBM_WALL_NEE)
+    return lbm_fail(LBM_EINVAL, "unknown wall scheme %d", wall);
+  if (wall == LBM_WALL_NEE && (nx < 3 || ny < 3))
+    return lbm_fail(LBM_EINVAL, "on-node walls need at least 3 x 3 nodes, got %d x %d", nx,
+                    ny);
   if (dtype != LBM_F64 && dtype != LBM_F32_SHIFTED)
     return lbm_fail(LBM_EINVAL, "unknown dtype %d", dtype);
   if (!std::isfinite(u_lid) || std::fabs(u_lid) >= 1.0 / std::sqrt(3.0))
@@ -375,11 +429,12 @@ static int create_impl(int nx, int ny, double tau, double re, double u_lid,
   h->pitch = pitch;
   h->plane = (int)plane;
   h->dtype = dtype;
+  h->wall = wall;
   h->re = re;
   h->u_lid = u_lid;
   h->tau = tau;
   h->omega = 1.0 / tau;
-  h->variant = kDefaultVariant;
+  h->variant = wall == LBM_WALL_NEE ? 0 : kDefaultVariant;
   h->use_graph = 1;
   const size_t esz = dtype == LBM_F64 ? 8 : 4;
   h->buf_bytes = (size_t)plane * 9 * esz;
@@ -420,6 +475,15 @@ static int create_impl(int nx, int ny, double tau, double re, double u_lid,
                        h->stream, (float *)h->buf[0], geom(h), nullptr, nullptr,
                        nullptr, 1.0, 0.0, 0.0);
   TRY(hipGetLastError());
+  if (wall == LBM_WALL_NEE) {   // the lid's nodes start with the lid's velocity
+    if (dtype == LBM_F64)
+      hipLaunchKernelGGL((k_init_lid_row<double, false>), dim3((nx + 255) / 256), dim3(256), 0,
+                         h->stream, (double *)h->buf[0], geom(h), u_lid);
+    else
+      hipLaunchKernelGGL((k_init_lid_row<float, true>), dim3((nx + 255) / 256), dim3(256), 0,
+                         h->stream, (float *)h->buf[0], geom(h), u_lid);
+    TRY(hipGetLastError());
+  }
   rc = reset_counters(h);
   if (rc != LBM_OK) return bail(rc);
   TRY(hipStreamSynchronize(h->stream));
@@ -434,13 +498,31 @@ int lbm_create(int nx, int ny, double re, double u_lid, int dtype, lbm_t *out) {
   const double tau = 3.0 * u_lid * nx / re + 0.5;   // Eq. 5, nu = U L / Re
   if (!(tau > 0.5))
     return lbm_fail(LBM_EINVAL, "tau = 3 u nx / re + 1/2 = %.17g must exceed 1/2", tau);
-  return create_impl(nx, ny, tau, re, u_lid, dtype, out);
+  return create_impl(nx, ny, tau, re, u_lid, dtype, LBM_WALL_BOUNCE_BACK, out);
 }
 
 int lbm_create_tau(int nx, int ny, double tau, double u_lid, int dtype, lbm_t *out) {
   const double re = (tau > 0.5 && u_lid != 0.0) ? 3.0 * u_lid * nx / (tau - 0.5)
                                                  : INFINITY;
-  return create_impl(nx, ny, tau, re, u_lid, dtype, out);
+  return create_impl(nx, ny, tau, re, u_lid, dtype, LBM_WALL_BOUNCE_BACK, out);
+}
+
+int lbm_create_wall(int nx, int ny, double re, double u_lid, int dtype, int wall,
+                    lbm_t *out) {
+  if (wall != LBM_WALL_NEE) {
+    if (wall != LBM_WALL_BOUNCE_BACK) {
+      if (out) *out = nullptr;
+      return lbm_fail(LBM_EINVAL, "unknown wall scheme %d", wall);
+    }
+    return lbm_create(nx, ny, re, u_lid, dtype, out);
+  }
+  if (!(re > 0.0) || !std::isfinite(re))
+    return lbm_fail(LBM_EINVAL, "re = %g must be positive and finite", re);
+  // Eq. 5 with L = nx - 1: the on-node walls are nx - 1 spacings apart
+  const double tau = 3.0 * u_lid * (nx - 1) / re + 0.5;
+  if (!(tau > 0.5))
+    return lbm_fail(LBM_EINVAL, "tau = 3 u (nx - 1) / re + 1/2 = %.17g must exceed 1/2", tau);
+  return create_impl(nx, ny, tau, re, u_lid, dtype, LBM_WALL_NEE, out);
 }
 
 int lbm_destroy(lbm_t h) {
@@ -484,6 +566,7 @@ int lbm_info(lbm_t h, lbm_info_t *info) {
   info->steps_done = h->t;
   info->device_bytes = 2 * h->buf_bytes + sizeof(double2) * (size_t)h->nx * h->ny +
                        h->tmp_doubles * sizeof(double);
+  info->wall = h->wall;
   return LBM_OK;
 }
 
@@ -494,9 +577,9 @@ int lbm_set_option(lbm_t h, int option, int64_t value) {
       h->use_graph = value ? 1 : 0;
       return LBM_OK;
     case LBM_OPT_STEP_VARIANT:
-      if (value < 0 || value >= kNumVariants)
+      if (value < 0 || value >= num_variants(h))
         return lbm_fail(LBM_EINVAL, "variant %lld outside [0, %d)", (long long)value,
-                    kNumVariants);
+                        num_variants(h));
       if (h->variant != (int)value) drop_graphs(h);
       h->variant = (int)value;
       return LBM_OK;
@@ -510,8 +593,8 @@ int lbm_get_option(lbm_t h, int option, int64_t *value) {
   switch (option) {
     case LBM_OPT_USE_GRAPH: *value = h->use_graph; return LBM_OK;
     case LBM_OPT_STEP_VARIANT: *value = h->variant; return LBM_OK;
-    case LBM_OPT_NUM_VARIANTS: *value = kNumVariants; return LBM_OK;
-    case LBM_OPT_STEPS_PER_LAUNCH: *value = steps_per_launch(h->variant); return LBM_OK;
+    case LBM_OPT_NUM_VARIANTS: *value = num_variants(h); return LBM_OK;
+    case LBM_OPT_STEPS_PER_LAUNCH: *value = launch_steps(h, h->variant); return LBM_OK;
     default: return lbm_fail(LBM_EINVAL, "unknown option %d", option);
   }
 }
@@ -592,9 +675,10 @@ int lbm_autotune(lbm_t h, int chunks, int use_cache, int *best_variant, double *
   if (chunks < 1 || chunks > 10000)
     return lbm_fail(LBM_EINVAL, "chunks = %d outside [1, 10000]", chunks);
   if (h->t % kChunk != 0) return lbm_fail(LBM_EINVAL, "autotune only at a multiple of 100 steps");
-  const std::string key = tune_key("single", h->dtype, h->nx, h->ny);
+  const std::string key =
+      tune_key(h->wall == LBM_WALL_NEE ? "single-nee" : "single", h->dtype, h->nx, h->ny);
   const int cached = use_cache ? tune_cache_lookup(key) : -1;
-  if (cached >= 0 && cached < kNumVariants) {
+  if (cached >= 0 && cached < num_variants(h)) {
     if (best_variant) *best_variant = cached;
     if (ms_per_step) *ms_per_step = NAN;
     return lbm_set_option(h, LBM_OPT_STEP_VARIANT, cached);
@@ -631,7 +715,7 @@ int lbm_autotune(lbm_t h, int chunks, int use_cache, int *best_variant, double *
   int best = h->variant;
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
-  for (int v = 0; v < kNumVariants && e == hipSuccess && rc == LBM_OK; ++v) {
+  for (int v = 0; v < num_variants(h) && e == hipSuccess && rc == LBM_OK; ++v) {
     rc = lbm_set_option(h, LBM_OPT_STEP_VARIANT, v);
     if (rc == LBM_OK) rc = lbm_step(h, kChunk);           // warm-up and capture
     if (rc != LBM_OK) break;
@@ -807,20 +891,187 @@ int lbm_residual(lbm_t h, double *residual, int64_t *at_step) {
   return LBM_OK;
 }
 
+// Psi of the current state into the device array psi ([ny][nx] FP64).
+static int launch_psi(lbm_cavity *h, double *psi) {
+  if (h->wall == LBM_WALL_NEE) {
+    if (h->dtype == LBM_F64)
+      hipLaunchKernelGGL((k_psi_nodes<double, false>), dim3((h->nx + 255) / 256), dim3(256), 0,
+                         h->stream, (const double *)h->buf[h->cur], geom(h), psi);
+    else
+      hipLaunchKernelGGL((k_psi_nodes<float, true>), dim3((h->nx + 255) / 256), dim3(256), 0,
+                         h->stream, (const float *)h->buf[h->cur], geom(h), psi);
+    HIPC(hipGetLastError());
+    return LBM_OK;
+  }
+  if (h->dtype == LBM_F64)
+    hipLaunchKernelGGL((k_psi<double, false>), dim3((h->nx + 255) / 256), dim3(256), 0,
+                       h->stream, (const double *)h->buf[h->cur], geom(h), psi);
+  else
+    hipLaunchKernelGGL((k_psi<float, true>), dim3((h->nx + 255) / 256), dim3(256), 0,
+                       h->stream, (const float *)h->buf[h->cur], geom(h), psi);
+  HIPC(hipGetLastError());
+  return LBM_OK;
+}
+
 int lbm_stream_function(lbm_t h, double *psi) {
   if (!h || !psi) return lbm_fail(LBM_EINVAL, "NULL argument");
   const size_t n = (size_t)h->nx * h->ny;
   int rc = ensure_tmp(h, n);
   if (rc) return rc;
-  if (h->dtype == LBM_F64)
-    hipLaunchKernelGGL((k_psi<double, false>), dim3((h->nx + 255) / 256), dim3(256), 0,
-                       h->stream, (const double *)h->buf[h->cur], geom(h), h->tmp);
-  else
-    hipLaunchKernelGGL((k_psi<float, true>), dim3((h->nx + 255) / 256), dim3(256), 0,
-                       h->stream, (const float *)h->buf[h->cur], geom(h), h->tmp);
-  HIPC(hipGetLastError());
+  rc = launch_psi(h, h->tmp);
+  if (rc) return rc;
   HIPC(hipMemcpyAsync(psi, h->tmp, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
   HIPC(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+// ---------------------------------------------------------------- vortices
+namespace {
+// Views into h->tmp for the vortex routines: Psi, the per-block partials of
+// the three regions, the three results, the centre counter and up to `cap`
+// centres (value; site index and kind as an int pair).
+struct VortexScratch {
+  double *psi, *pv, *ov, *ev;
+  int *pk, *ok, *ek;
+  unsigned int *cnt;
+  int nb;
+};
+}  // namespace
+
+static int vortex_scratch(lbm_cavity *h, size_t cap, VortexScratch &s) {
+  const size_t n = (size_t)h->nx * h->ny;
+  s.nb = (int)std::min<size_t>(1024, (n + kVortexThreads - 1) / kVortexThreads);
+  const size_t pk_doubles = (3 * (size_t)s.nb + 1) / 2;
+  int rc = ensure_tmp(h, n + 3 * s.nb + pk_doubles + 3 + 2 + 1 + 2 * cap);
+  if (rc) return rc;
+  double *p = h->tmp;
+  s.psi = p;
+  p += n;
+  s.pv = p;
+  p += 3 * s.nb;
+  s.pk = reinterpret_cast<int *>(p);
+  p += pk_doubles;
+  s.ov = p;
+  p += 3;
+  s.ok = reinterpret_cast<int *>(p);
+  p += 2;
+  s.cnt = reinterpret_cast<unsigned int *>(p);
+  p += 1;
+  s.ev = p;
+  p += cap;
+  s.ek = reinterpret_cast<int *>(p);
+  return LBM_OK;
+}
+
+static lbm_vortex_t vortex_record(const lbm_cavity *h, double psi, int k, int kind) {
+  lbm_vortex_t v{};
+  v.psi = psi;
+  v.iy = k / h->nx;
+  v.ix = k - v.iy * h->nx;
+  if (h->wall == LBM_WALL_NEE) {   // node positions, L = nx - 1
+    v.x = (double)v.ix / (h->nx - 1);
+    v.y = (double)v.iy / (h->nx - 1);
+  } else {                         // site centres, L = nx
+    v.x = (v.ix + 0.5) / h->nx;
+    v.y = (v.iy + 0.5) / h->nx;
+  }
+  v.kind = kind;
+  return v;
+}
+
+int lbm_vortex_extrema(lbm_t h, lbm_vortex_t *out) {
+  if (!h || !out) return lbm_fail(LBM_EINVAL, "NULL argument");
+  if (h->nx < 2) return lbm_fail(LBM_EINVAL, "nx = %d < 2", h->nx);
+  VortexScratch s;
+  int rc = vortex_scratch(h, 0, s);
+  if (rc) return rc;
+  rc = launch_psi(h, s.psi);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_vortex_partial, dim3(s.nb), dim3(kVortexThreads), 0, h->stream, s.psi,
+                     h->nx, h->ny, s.pv, s.pk);
+  HIPC(hipGetLastError());
+  hipLaunchKernelGGL(k_vortex_final, dim3(1), dim3(kVortexThreads), 0, h->stream, s.pv, s.pk,
+                     s.nb, s.ov, s.ok);
+  HIPC(hipGetLastError());
+  double v[3];
+  int k[3];
+  HIPC(hipMemcpyAsync(v, s.ov, sizeof(v), hipMemcpyDeviceToHost, h->stream));
+  HIPC(hipMemcpyAsync(k, s.ok, sizeof(k), hipMemcpyDeviceToHost, h->stream));
+  HIPC(hipStreamSynchronize(h->stream));
+  for (int r = 0; r < 3; ++r) {
+    if (k[r] < 0) return lbm_fail(LBM_EDEVICE, "vortex region %d came back empty", r);
+    out[r] = vortex_record(h, v[r], k[r], r == 0 ? 1 : -1);
+  }
+  return LBM_OK;
+}
+
+// All vortex centres with |Psi| >= min_abs, sorted by site index.
+static int find_centres(lbm_cavity *h, double min_abs, std::vector<lbm_vortex_t> &all) {
+  const size_t n = (size_t)h->nx * h->ny;
+  size_t cap = 4096;
+  for (int pass = 0; pass < 2; ++pass) {
+    VortexScratch s;
+    int rc = vortex_scratch(h, cap, s);
+    if (rc) return rc;
+    rc = launch_psi(h, s.psi);
+    if (rc) return rc;
+    HIPC(hipMemsetAsync(s.cnt, 0, sizeof(unsigned int), h->stream));
+    hipLaunchKernelGGL(k_vortex_centres, dim3((unsigned)((n + kVortexThreads - 1) / kVortexThreads)),
+                       dim3(kVortexThreads), 0, h->stream, s.psi, h->nx, h->ny, min_abs,
+                       (int)cap, s.cnt, s.ev, s.ek);
+    HIPC(hipGetLastError());
+    unsigned int cnt = 0;
+    HIPC(hipMemcpyAsync(&cnt, s.cnt, sizeof(cnt), hipMemcpyDeviceToHost, h->stream));
+    HIPC(hipStreamSynchronize(h->stream));
+    if (cnt > cap) {   // more centres than slots: run again with room for all
+      cap = cnt;
+      continue;
+    }
+    std::vector<double> ev(cnt);
+    std::vector<int> ek(2 * (size_t)cnt);
+    if (cnt) {
+      HIPC(hipMemcpyAsync(ev.data(), s.ev, cnt * sizeof(double), hipMemcpyDeviceToHost,
+                          h->stream));
+      HIPC(hipMemcpyAsync(ek.data(), s.ek, 2 * (size_t)cnt * sizeof(int),
+                          hipMemcpyDeviceToHost, h->stream));
+      HIPC(hipStreamSynchronize(h->stream));
+    }
+    all.clear();
+    for (unsigned int i = 0; i < cnt; ++i)
+      all.push_back(vortex_record(h, ev[i], ek[2 * i], ek[2 * i + 1]));
+    std::sort(all.begin(), all.end(), [](const lbm_vortex_t &a, const lbm_vortex_t &b) {
+      return a.iy != b.iy ? a.iy < b.iy : a.ix < b.ix;
+    });
+    return LBM_OK;
+  }
+  return lbm_fail(LBM_EDEVICE, "vortex centre count changed between two scans");
+}
+
+int lbm_vortex_centres(lbm_t h, double min_abs_psi, int cap, lbm_vortex_t *out, int *count) {
+  if (!h || !count) return lbm_fail(LBM_EINVAL, "NULL argument");
+  if (cap < 0 || (cap > 0 && !out))
+    return lbm_fail(LBM_EINVAL, "cap = %d with out = %p", cap, (void *)out);
+  if (!(min_abs_psi >= 0.0)) return lbm_fail(LBM_EINVAL, "min_abs_psi = %g", min_abs_psi);
+  std::vector<lbm_vortex_t> all;
+  int rc = find_centres(h, min_abs_psi, all);
+  if (rc) return rc;
+  *count = (int)all.size();
+  for (int i = 0; i < cap && i < (int)all.size(); ++i) out[i] = all[i];
+  return LBM_OK;
+}
+
+int lbm_bottom_vortex_count(lbm_t h, double min_abs_psi, int *count) {
+  if (!h || !count) return lbm_fail(LBM_EINVAL, "NULL argument");
+  if (!(min_abs_psi >= 0.0)) return lbm_fail(LBM_EINVAL, "min_abs_psi = %g", min_abs_psi);
+  lbm_vortex_t ext[3];
+  int rc = lbm_vortex_extrema(h, ext);
+  if (rc) return rc;
+  std::vector<lbm_vortex_t> all;
+  rc = find_centres(h, min_abs_psi, all);
+  if (rc) return rc;
+  int c = 0;
+  for (const lbm_vortex_t &v : all) c += v.iy < ext[0].iy;
+  *count = c;
   return LBM_OK;
 }
 
@@ -933,7 +1184,7 @@ int lbm_init_fields_device(lbm_t h, const double *rho, const double *ux, const d
 // Checkpoint file: header, stored populations of buf[cur], Eq. 6 reference.
 struct CkptHeader {
   char magic[8];
-  int32_t version, nx, ny, pitch, dtype, pad;
+  int32_t version, nx, ny, pitch, dtype, wall;
   int64_t t, snap_t, mon_t;
   double tau, u_lid, last_res, last_mass;
   uint64_t buf_bytes, uref_bytes;
@@ -949,6 +1200,7 @@ int lbm_save(lbm_t h, const char *path) {
   hd.ny = h->ny;
   hd.pitch = h->pitch;
   hd.dtype = h->dtype;
+  hd.wall = h->wall;
   hd.t = h->t;
   hd.snap_t = h->snap_t;
   hd.mon_t = h->mon_t;
@@ -983,11 +1235,12 @@ int lbm_load(lbm_t h, const char *path) {
     return lbm_fail(LBM_EIO, "%s is not a checkpoint of this library", path);
   }
   if (hd.nx != h->nx || hd.ny != h->ny || hd.pitch != h->pitch || hd.dtype != h->dtype ||
-      hd.buf_bytes != h->buf_bytes ||
+      hd.wall != h->wall || hd.buf_bytes != h->buf_bytes ||
       hd.uref_bytes != sizeof(double2) * (size_t)h->nx * h->ny) {
     std::fclose(fp);
-    return lbm_fail(LBM_ESTATE, "checkpoint lattice %dx%d dtype %d does not match the handle",
-                hd.nx, hd.ny, hd.dtype);
+    return lbm_fail(LBM_ESTATE,
+                    "checkpoint lattice %dx%d dtype %d wall %d does not match the handle",
+                    hd.nx, hd.ny, hd.dtype, hd.wall);
   }
   std::vector<char> a(hd.buf_bytes), b(hd.uref_bytes);
   const bool ok = std::fread(a.data(), 1, a.size(), fp) == a.size() &&

@@ -32,6 +32,7 @@ void tune_cache_store(const std::string &key, int variant);
 struct lbm_cavity {
   // lattice and parameters
   int nx = 0, ny = 0, pitch = 0, plane = 0, dtype = 0;
+  int wall = LBM_WALL_BOUNCE_BACK;
   double re = 0, u_lid = 0, tau = 0, omega = 0;
   int device = 0;
   // population buffers (A/B); buf[cur] holds the post-collision state

@@ -26,6 +26,8 @@ LBM_F64, LBM_F32_SHIFTED = 0, 1
 LBM_OPT_USE_GRAPH, LBM_OPT_STEP_VARIANT, LBM_OPT_NUM_VARIANTS, LBM_OPT_GRAPH_STEPS = 1, 2, 3, 4
 LBM_OPT_STEPS_PER_LAUNCH = 5
 LBM_INIT_RENORMALISE_MASS, LBM_INIT_ZERO_STAGGERED = 1, 2
+LBM_WALL_BOUNCE_BACK, LBM_WALL_NEE = 0, 1
+WALLS = {"bounce-back": LBM_WALL_BOUNCE_BACK, "nee": LBM_WALL_NEE}
 DTYPES = {"f64": LBM_F64, "f32s": LBM_F32_SHIFTED}
 
 _ERRNAMES = {LBM_EINVAL: "LBM_EINVAL", LBM_ENOMEM: "LBM_ENOMEM",
@@ -43,7 +45,8 @@ class lbm_info_t(ct.Structure):
     _fields_ = [("nx", ct.c_int), ("ny", ct.c_int), ("pitch", ct.c_int),
                 ("dtype", ct.c_int), ("re", ct.c_double), ("u_lid", ct.c_double),
                 ("tau", ct.c_double), ("omega", ct.c_double),
-                ("steps_done", ct.c_int64), ("device_bytes", ct.c_size_t)]
+                ("steps_done", ct.c_int64), ("device_bytes", ct.c_size_t),
+                ("wall", ct.c_int)]
 
 
 def _load():
@@ -73,6 +76,8 @@ SIGNATURES = {
     "lbm_version": [],
     "lbm_create": [ct.c_int, ct.c_int, ct.c_double, ct.c_double, ct.c_int, ct.POINTER(_h)],
     "lbm_create_tau": [ct.c_int, ct.c_int, ct.c_double, ct.c_double, ct.c_int, ct.POINTER(_h)],
+    "lbm_create_wall": [ct.c_int, ct.c_int, ct.c_double, ct.c_double, ct.c_int, ct.c_int,
+                        ct.POINTER(_h)],
     "lbm_destroy": [_h],
     "lbm_set_stream": [_h, ct.c_void_p],
     "lbm_info": [_h, ct.POINTER(lbm_info_t)],
@@ -88,6 +93,9 @@ SIGNATURES = {
     "lbm_mass": [_h, _dp],
     "lbm_residual": [_h, _dp, ct.POINTER(_i64)],
     "lbm_stream_function": [_h, ct.c_void_p],
+    "lbm_vortex_extrema": [_h, ct.c_void_p],
+    "lbm_vortex_centres": [_h, ct.c_double, ct.c_int, ct.c_void_p, ct.POINTER(ct.c_int)],
+    "lbm_bottom_vortex_count": [_h, ct.c_double, ct.POINTER(ct.c_int)],
     "lbm_set_populations": [_h, ct.c_void_p],
     "lbm_get_populations": [_h, ct.c_void_p],
     "lbm_init_fields": [_h, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_int],
@@ -189,6 +197,13 @@ def lbm_create_tau(nx, ny, tau, u_lid, dtype):
     return h
 
 
+def lbm_create_wall(nx, ny, re, u_lid, dtype, wall):
+    h = _h()
+    _check(_lib.lbm_create_wall(int(nx), int(ny), float(re), float(u_lid),
+                                DTYPES.get(dtype, dtype), WALLS.get(wall, wall), ct.byref(h)))
+    return h
+
+
 def lbm_destroy(h):
     _check(_lib.lbm_destroy(h))
 
@@ -277,6 +292,39 @@ def lbm_stream_function(h, nx, ny):
     psi = np.empty((ny, nx))
     _check(_lib.lbm_stream_function(h, _ptr(psi)))
     return psi
+
+
+class Vortex(ct.Structure):
+    """lbm_vortex_t: Psi (lattice units), centre (x, y) in units of the
+    width, site indices and kind (+1 maximum of Psi, -1 minimum)."""
+    _fields_ = [("psi", ct.c_double), ("x", ct.c_double), ("y", ct.c_double),
+                ("ix", ct.c_int), ("iy", ct.c_int), ("kind", ct.c_int), ("reserved", ct.c_int)]
+
+    def as_tuple(self):
+        return (self.iy, self.ix, self.kind, self.psi)
+
+
+def lbm_vortex_extrema(h):
+    """[primary, lower_left, lower_right] as Vortex records."""
+    out = (Vortex * 3)()
+    _check(_lib.lbm_vortex_extrema(h, out))
+    return list(out)
+
+
+def lbm_vortex_centres(h, min_abs_psi=0.0, cap=4096):
+    """(list of the first min(count, cap) Vortex records in row-major order,
+    total count)."""
+    out = (Vortex * max(int(cap), 1))()
+    n = ct.c_int()
+    _check(_lib.lbm_vortex_centres(h, float(min_abs_psi), int(cap), out if cap > 0 else None,
+                                   ct.byref(n)))
+    return list(out[:min(n.value, int(cap))]), n.value
+
+
+def lbm_bottom_vortex_count(h, min_abs_psi=0.0):
+    n = ct.c_int()
+    _check(_lib.lbm_bottom_vortex_count(h, float(min_abs_psi), ct.byref(n)))
+    return n.value
 
 
 def lbm_set_populations(h, f, nx, ny):
@@ -532,12 +580,21 @@ def lbm_nn_up2(backward, n, h, w, c, x, xs, xo, out, os_, oo, stream=None):
 
 # ------------------------------------------------------------ convenience ---
 class Cavity:
-    """A lid-driven cavity on the GPU (one library handle)."""
+    """A lid-driven cavity on the GPU (one library handle).
 
-    def __init__(self, nx, ny, re=None, u_lid=0.1, dtype="f64", tau=None):
+    wall: "bounce-back" (half-way walls, nx x ny sites, L = nx) or "nee"
+    (non-equilibrium extrapolation on on-node walls, nx x ny nodes,
+    L = nx - 1)."""
+
+    def __init__(self, nx, ny, re=None, u_lid=0.1, dtype="f64", tau=None, wall="bounce-back"):
         self.nx, self.ny = int(nx), int(ny)
+        self.wall = wall
         if tau is not None:
+            if WALLS.get(wall, wall) != LBM_WALL_BOUNCE_BACK:
+                raise ValueError("tau= is for half-way walls; give re for wall='nee'")
             self.h = lbm_create_tau(nx, ny, tau, u_lid, dtype)
+        elif WALLS.get(wall, wall) != LBM_WALL_BOUNCE_BACK:
+            self.h = lbm_create_wall(nx, ny, re, u_lid, dtype, wall)
         else:
             self.h = lbm_create(nx, ny, re, u_lid, dtype)
         self.npts = 0
@@ -595,6 +652,15 @@ class Cavity:
 
     def stream_function(self):
         return lbm_stream_function(self.h, self.nx, self.ny)
+
+    def vortex_extrema(self):
+        return lbm_vortex_extrema(self.h)
+
+    def vortex_centres(self, min_abs_psi=0.0, cap=4096):
+        return lbm_vortex_centres(self.h, min_abs_psi, cap)
+
+    def bottom_vortex_count(self, min_abs_psi=0.0):
+        return lbm_bottom_vortex_count(self.h, min_abs_psi)
 
     def set_populations(self, f):
         lbm_set_populations(self.h, f, self.nx, self.ny)

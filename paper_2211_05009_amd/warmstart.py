@@ -23,6 +23,54 @@ U_LID = 0.1
 RHO_SCALE = 100.0      # network channel 0 = 100 (rho - 1)
 
 
+# (level, ci, co) of the network's 15 convolutions as the kernels run them
+# (padded channel counts); level l works on (256 >> l) x (128 >> l) pixels.
+CONV_SHAPES = ((0, 32, 32), (0, 32, 32), (1, 32, 64), (1, 64, 64), (2, 64, 128),
+               (2, 128, 128), (3, 128, 256), (3, 256, 256), (2, 384, 128), (2, 128, 128),
+               (1, 192, 64), (1, 64, 64), (0, 96, 32), (0, 32, 32), (0, 32, 32))
+
+
+def conv_flops(backward=False):
+    """Multiply-add work (2 flops each) of the 3 x 3 convolutions for one
+    sample: the forward pass, or the backward pass (weight gradients of every
+    layer, input gradients of every layer but the first)."""
+    fwd = [2 * 9 * ci * co * (CANVAS_H >> l) * (CANVAS_W >> l) for l, ci, co in CONV_SHAPES]
+    return sum(fwd) + sum(fwd[1:]) if backward else sum(fwd)
+
+
+def surrogate_throughput(sur, n=8, reps=20, seed=0):
+    """MFMA throughput of the surrogate: TFLOP/s of the forward pass and of a
+    whole training step (forward + backward + Adam) at batch n, timed over
+    `reps` repetitions after one warm-up."""
+    import torch
+    rng = np.random.default_rng(seed)
+    re, ar = rng.uniform(100.0, 3000.0, n), rng.uniform(0.4, 2.0, n)
+    out = torch.empty((n, CANVAS_H, CANVAS_W, 3), dtype=torch.float32, device="cuda")
+    mask = torch.ones((n, CANVAS_H, CANVAS_W), dtype=torch.float32, device="cuda")
+    sur.forward(re, ar, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sur.forward(re, ar, out)
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / reps
+    target = out.clone()
+    sur.train_step(re, ar, target, mask, 0.0, apply_update=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sur.train_step(re, ar, target, mask, 0.0, apply_update=False)
+    torch.cuda.synchronize()
+    t_train = (time.perf_counter() - t0) / reps
+    f_fwd, f_bwd = conv_flops(), conv_flops(backward=True)
+    return {"batch": n, "forward_ms": round(t_fwd * 1e3, 3),
+            "forward_TFLOPs": round(n * f_fwd / t_fwd / 1e12, 2),
+            "train_step_ms": round(t_train * 1e3, 3),
+            "train_step_TFLOPs": round(n * (f_fwd + f_bwd) / t_train / 1e12, 2),
+            "gflop_per_sample_fwd": round(f_fwd / 1e9, 3),
+            "gflop_per_sample_fwd_bwd": round((f_fwd + f_bwd) / 1e9, 3)}
+
+
 def sample_cases(n, seed, re_range=(100.0, 3000.0), ar_range=(0.4, 2.0)):
     """(Re, Ar) pairs uniform in the given ranges (numpy default_rng(seed))."""
     rng = np.random.default_rng(seed)
@@ -30,23 +78,29 @@ def sample_cases(n, seed, re_range=(100.0, 3000.0), ar_range=(0.4, 2.0)):
 
 
 def solve_steady(nx, ny, re, threshold, max_steps, dtype="f32s", chunk=10000,
-                 warm=None):
+                 warm=None, log=None, log_every=30.0):
     """Run a batch of cavities (lists nx, ny, re) from rest (or warm-started
     by `warm`, a Surrogate) until every Eq. 6 residual is below `threshold`
     or `max_steps` is reached.  Returns the batch (kept alive) and a list of
-    per-cavity dicts with the steps taken and the final residual."""
+    per-cavity dicts with the steps taken and the final residual.  With
+    `log`, reports the number of running cavities every `log_every` s."""
     b = lbm.Batch(nx, ny, re, u_lid=U_LID, dtype=dtype)
     if warm is not None:
         for k in range(len(nx)):
             warm.warm_start_batch(b, k)
     b.set_threshold(threshold)
     done = 0
+    t_log = time.perf_counter()
     while done < max_steps:
         step = min(chunk, max_steps - done)
         b.step(step)
         done += step
-        if not any(b.status(k)["active"] for k in range(len(nx))):
+        active = sum(b.status(k)["active"] for k in range(len(nx)))
+        if not active:
             break
+        if log and time.perf_counter() - t_log > log_every:
+            log(f"step {done}: {active} of {len(nx)} cavities running")
+            t_log = time.perf_counter()
     return b, [b.status(k) for k in range(len(nx))]
 
 
@@ -119,14 +173,18 @@ def evaluate(sur, data):
     return float((((out - data["target"]) ** 2) * m).sum() / data["mask"].sum())
 
 
-def time_to_steady(cases, threshold, max_steps, mode, sur=None, dtype="f32s"):
+def time_to_steady(cases, threshold, max_steps, mode, sur=None, dtype="f32s", log=None):
     """Wall time and steps to reach Eq. 6 residual < threshold for every
     cavity in `cases` ((nx, ny, re) list).
 
     mode: "single-cold" (one cavity after another, from rest: the plain
     method), "single-warm", "batch-cold", "batch-warm".  Warm starts include
-    the surrogate inference and the mapping onto the lattice in the time."""
+    the surrogate inference and the mapping onto the lattice in the time.
+    `log` receives a progress line per cavity (single modes) or every 30 s
+    (batch modes)."""
     import torch
+    if mode not in TTS_MODES:
+        raise ValueError(f"unknown mode {mode!r}: one of {TTS_MODES}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     steps = []
@@ -144,10 +202,13 @@ def time_to_steady(cases, threshold, max_steps, mode, sur=None, dtype="f32s"):
                     break
             steps.append(done)
             c.close()
+            if log:
+                log(f"{mode} {len(steps)}/{len(cases)}: {nx} x {ny}, Re {re:g}: {done} steps")
     else:
         nx, ny, re = zip(*cases)
         b, st = solve_steady(list(nx), list(ny), list(re), threshold, max_steps, dtype,
-                             chunk=1000, warm=sur if mode == "batch-warm" else None)
+                             chunk=1000, warm=sur if mode == "batch-warm" else None,
+                             log=log)
         steps = [s["steps_done"] for s in st]
         b.close()
     torch.cuda.synchronize()
@@ -173,16 +234,25 @@ def make_surrogate(normals, max_batch=8):
     return sur
 
 
+TTS_MODES = ("single-cold", "batch-warm", "batch-cold", "single-warm")
+
+
 def steady_sweep_study(normals, threshold=1e-6, ntrain=200, epochs=150, nx=500,
-                       max_steps=5_000_000, ablations=False, log=None):
+                       max_steps=5_000_000, modes=TTS_MODES, dtype="f32s",
+                       data_threshold=1e-6, log=None):
     """Time-to-steady of the steady sweep (25 cavities, Re 1000-3000 x Ar
     0.4-2.0 at nx x (nx Ar)): plain = single cavities one after another from
     rest; treatment = one batch, every cavity warm-started by the surrogate
-    (inference, mapping and mass renormalisation inside the timed region).
+    (inference, mapping and mass renormalisation inside the timed region);
+    batch-cold and single-warm are the two ablations.  Per-cavity step counts
+    do not depend on batching (a batched cavity evolves bit for bit as it
+    does alone, and both check Eq. 6 every 1000 steps).
     The one-off surrogate cost (training data and training) is reported
-    separately."""
+    separately.  `dtype` is the storage of the timed runs; the training data
+    are FP32 runs to `data_threshold` (or the FP32 residual floor) whatever
+    the timed storage."""
     t0 = time.perf_counter()
-    data = training_data(ntrain, seed=0, threshold=threshold)
+    data = training_data(ntrain, seed=0, threshold=data_threshold)
     t_data = time.perf_counter() - t0
     if log:
         log(f"training data: {ntrain} fields in {t_data:.1f} s")
@@ -192,25 +262,24 @@ def steady_sweep_study(normals, threshold=1e-6, ntrain=200, epochs=150, nx=500,
     t_train = time.perf_counter() - t1
     if log:
         log(f"trained {epochs} epochs in {t_train:.1f} s, loss {hist[-1]:.5f}")
-    held = training_data(20, seed=1, threshold=threshold)
+    held = training_data(20, seed=1, threshold=data_threshold)
+    perf = surrogate_throughput(sur)
     cases = steady_sweep_cases(nx)
-    modes = ["single-cold", "batch-warm"]
-    if ablations:
-        modes += ["batch-cold", "single-warm"]
     res = {}
     for m in modes:
-        r = time_to_steady(cases, threshold, max_steps, m, sur=sur)
+        r = time_to_steady(cases, threshold, max_steps, m, sur=sur, dtype=dtype, log=log)
         res[m] = {"seconds": round(r["seconds"], 3), "steps_total": int(sum(r["steps"])),
                   "steps_median": float(np.median(r["steps"])),
-                  "max_steps_hit": r["max_steps_hit"]}
+                  "max_steps_hit": r["max_steps_hit"], "steps": [int(v) for v in r["steps"]]}
         if log:
-            log(m, res[m])
+            log(m, {k: v for k, v in res[m].items() if k != "steps"})
     out = {"cases": len(cases), "lattice": f"{nx} x ({nx} Ar)", "threshold_eq6": threshold,
-           "storage": "f32s", "modes": res,
-           "speedup": round(res["single-cold"]["seconds"] / res["batch-warm"]["seconds"], 3),
+           "storage": dtype, "modes": res,
+           "speedup": (round(res["single-cold"]["seconds"] / res["batch-warm"]["seconds"], 3)
+                       if "single-cold" in res and "batch-warm" in res else None),
            "surrogate": {"train_samples": ntrain, "epochs": epochs,
                          "data_seconds": round(t_data, 2), "train_seconds": round(t_train, 2),
                          "final_train_loss": round(hist[-1], 6),
-                         "heldout_mse": round(evaluate(sur, held), 6)}}
+                         "heldout_mse": round(evaluate(sur, held), 6), **perf}}
     sur.close()
     return out

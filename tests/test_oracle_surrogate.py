@@ -95,3 +95,17 @@ def test_network_gradient_finite_differences():
             lm = S.loss_and_grad(p - e, re, ar, target, mask, H, W)[0]
             fd = (lp - lm) / (2 * h)
             assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])), (li, i, fd, g[i])
+
+
+def test_flop_table_matches_the_network():
+    """The throughput report counts the convolutions the library runs: its
+    shape table gives the same channel list and parameter count as the
+    reference network."""
+    from paper_2211_05009_amd import warmstart as W
+    assert [(ci, co) for _, ci, co in W.CONV_SHAPES] == [(ci, co) for ci, co, _ in S.CONVS]
+    assert sum(9 * ci * co + co for _, ci, co in W.CONV_SHAPES) == S.n_params()
+    # levels: 2 convs per encoder level, the bottleneck pair, 2 per decoder level + head
+    assert [l for l, _, _ in W.CONV_SHAPES] == [0, 0, 1, 1, 2, 2, 3, 3, 2, 2, 1, 1, 0, 0, 0]
+    fwd = W.conv_flops()
+    assert fwd == sum(2 * 9 * ci * co * (256 >> l) * (128 >> l) for l, ci, co in W.CONV_SHAPES)
+    assert W.conv_flops(backward=True) == 2 * fwd - 2 * 9 * 32 * 32 * 256 * 128
