@@ -224,6 +224,60 @@ int lbm_probe_config(lbm_t h, int npts, const double *xy_host, int every,
 int lbm_probe_read(lbm_t h, double *buf_host, int64_t max_records,
                    int64_t *n_records);
 
+/*
+ * Flow state of time series (Sec. 3.3: stable, periodic, or aperiodic and
+ * unstable, judged from the velocity at an observing point over a late
+ * window; Table 3: periods).  The paper judges from plots; this library's
+ * definition, computed on the device in FP64:
+ *   amplitude A = max - min over the window; LBM_FLOW_STEADY if
+ *   A <= steady_tol;
+ *   D(T) = mean_{k < n-T} (u[k+T] - u[k])^2 / sigma^2 (sigma: standard
+ *   deviation over the window) for lags T in [min_lag, max_lag]
+ *   (max_lag <= 0: n / 3; capped at n - 2);
+ *   a candidate is a lag with D(T-1) > D(T) <= D(T+1), min_lag < T <
+ *   max_lag, reached after D exceeded 1 at a smaller lag; the parabola
+ *   through D at T-1, T, T+1 gives the period (its vertex, in samples) and
+ *   the mismatch sqrt(max(vertex value, 0));
+ *   LBM_FLOW_PERIODIC at the first candidate with mismatch <= periodic_tol,
+ *   LBM_FLOW_APERIODIC otherwise (mismatch = the smallest over candidates,
+ *   +inf if none).
+ * A period should span a dozen or more samples; a shorter one can come out
+ * as a multiple of itself.
+ */
+enum { LBM_FLOW_STEADY = 0, LBM_FLOW_PERIODIC = 1, LBM_FLOW_APERIODIC = 2 };
+typedef struct {
+  int state;          /* LBM_FLOW_* */
+  int lag;            /* integer lag of the period (periodic only) */
+  double period;      /* refined period in samples; 0 unless periodic */
+  double amplitude;   /* max - min over the window */
+  double mean, std;   /* over the window */
+  double mismatch;    /* see above; 0 when steady */
+} lbm_flow_state_t;
+
+/*
+ * Classify nseries device series: sample k of series s at
+ * series_dev[s * ld + k] (caller-owned device memory, n >= 8 samples,
+ * ld >= n).  1 <= min_lag; the lag range must hold at least 3 lags.
+ * out_host: nseries records (caller-owned host).  Work runs on hip_stream
+ * (NULL: the default stream); the call allocates and frees its device
+ * scratch and returns after the work has finished.
+ * Errors: LBM_EINVAL for bad sizes, lags or NULL pointers.
+ */
+int lbm_classify_series(const double *series_dev, int nseries, int64_t n, int64_t ld,
+                        double steady_tol, double periodic_tol, int min_lag, int max_lag,
+                        lbm_flow_state_t *out_host, void *hip_stream);
+
+/*
+ * Classify the recorded probe series of h (lbm_probe_config) directly on
+ * the device: for each probe point, component c (0: rho, 1: u_x, 2: u_y)
+ * over the most recent `window` records, one record per `every` steps (so
+ * a period in steps is period * every).  window must not exceed the
+ * records held (min(recorded, capacity)).  out_host: npts records.
+ */
+int lbm_probe_classify(lbm_t h, int component, int64_t window, double steady_tol,
+                       double periodic_tol, int min_lag, int max_lag,
+                       lbm_flow_state_t *out_host);
+
 /* Total mass sum_x rho(x) now, accumulated in FP64. */
 int lbm_mass(lbm_t h, double *mass);
 

@@ -51,7 +51,7 @@ __device__ __forceinline__ void block_best(int r, double &v, int &k, double *sv,
 }
 
 // Per-block best site of each region; partials are [region][block].
-__global__ __launch_bounds__(kVortexThreads) void k_vortex_partial(
+static __global__ __launch_bounds__(kVortexThreads) void k_vortex_partial(
     const double *__restrict__ psi, int nx, int ny, double *__restrict__ pv,
     int *__restrict__ pk) {
   __shared__ double sv[kVortexThreads];
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(kVortexThreads) void k_vortex_partial(
 }
 
 // One block: best of the nb partials of each region -> out_v[3], out_k[3].
-__global__ __launch_bounds__(kVortexThreads) void k_vortex_final(
+static __global__ __launch_bounds__(kVortexThreads) void k_vortex_final(
     const double *__restrict__ pv, const int *__restrict__ pk, int nb,
     double *__restrict__ out_v, int *__restrict__ out_k) {
   __shared__ double sv[kVortexThreads];
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kVortexThreads) void k_vortex_final(
 // neighbours and |Psi| >= min_abs.  Each centre takes a slot from *count
 // (a global atomic) and, if the slot is below cap, stores (Psi, k, kind);
 // the slots come in no particular order.
-__global__ __launch_bounds__(kVortexThreads) void k_vortex_centres(
+static __global__ __launch_bounds__(kVortexThreads) void k_vortex_centres(
     const double *__restrict__ psi, int nx, int ny, double min_abs, int cap,
     unsigned int *__restrict__ count, double *__restrict__ ev, int *__restrict__ ek) {
   const int q = blockIdx.x * kVortexThreads + threadIdx.x;

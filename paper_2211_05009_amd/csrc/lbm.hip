@@ -24,6 +24,7 @@
 #include "../../include/lbm.h"
 #include "d2q9_monitor.hpp"
 #include "d2q9_nee.hpp"
+#include "d2q9_series.hpp"
 #include "d2q9_step.hpp"
 #include "d2q9_temporal.hpp"
 #include "d2q9_vortex.hpp"
@@ -846,6 +847,35 @@ int lbm_probe_config(lbm_t h, int npts, const double *xy, int every, int64_t cap
   // first recorded step: next multiple of `every` after now
   h->probe_t0 = (h->t / every + 1) * every;
   return LBM_OK;
+}
+
+int lbm_probe_classify(lbm_t h, int component, int64_t window, double steady_tol,
+                       double periodic_tol, int min_lag, int max_lag,
+                       lbm_flow_state_t *out) {
+  if (!h || !out) return lbm_fail(LBM_EINVAL, "NULL argument");
+  if (!h->probe_ring || h->probe_n == 0) return lbm_fail(LBM_EINVAL, "no probes configured");
+  if (component < 0 || component > 2)
+    return lbm_fail(LBM_EINVAL, "component %d outside {0, 1, 2}", component);
+  if (!(steady_tol >= 0.0) || !(periodic_tol >= 0.0))
+    return lbm_fail(LBM_EINVAL, "tolerances must be >= 0 (steady %g, periodic %g)", steady_tol,
+                    periodic_tol);
+  int rc = check_lags(window, min_lag, max_lag);
+  if (rc) return rc;
+  unsigned long long count = 0;
+  HIPC(hipStreamSynchronize(h->stream));
+  HIPC(hipMemcpy(&count, h->probe_count, sizeof count, hipMemcpyDeviceToHost));
+  const int64_t avail = std::min<int64_t>((int64_t)count, h->probe_cap);
+  if (window > avail)
+    return lbm_fail(LBM_EINVAL, "window %lld exceeds the %lld records held", (long long)window,
+                    (long long)avail);
+  const long long start = (long long)((count - (unsigned long long)window) %
+                                      (unsigned long long)h->probe_cap);
+  std::vector<SeriesDesc> d(h->probe_n);
+  for (int p = 0; p < h->probe_n; ++p)
+    d[p] = SeriesDesc{h->probe_ring + 3 * p + component, (long long)h->probe_cap, start,
+                      (long long)window, 3LL * h->probe_n};
+  return classify_series_descs(d.data(), h->probe_n, window, steady_tol, periodic_tol, min_lag,
+                               max_lag, h->stream, out);
 }
 
 int lbm_probe_read(lbm_t h, double *buf, int64_t max_records, int64_t *n_records) {

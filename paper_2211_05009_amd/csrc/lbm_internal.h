@@ -29,6 +29,18 @@ std::string tune_key(const char *kind, int dtype, long long a, long long b);
 int tune_cache_lookup(const std::string &key);      // -1 if absent
 void tune_cache_store(const std::string &key, int variant);
 
+namespace lbm {
+struct SeriesDesc;
+}
+// Classify nseries series described on the host (d2q9_series.hpp), longest
+// n_max samples, on stream st; allocates its own device scratch.
+int classify_series_descs(const lbm::SeriesDesc *descs_host, int nseries, long long n_max,
+                          double steady_tol, double periodic_tol, int min_lag, int max_lag,
+                          hipStream_t st, lbm_flow_state_t *out_host);
+
+// Validate a series length and lag range (LBM_EINVAL with a message).
+int check_lags(long long n, int min_lag, int max_lag);
+
 struct lbm_cavity {
   // lattice and parameters
   int nx = 0, ny = 0, pitch = 0, plane = 0, dtype = 0;

@@ -93,6 +93,10 @@ SIGNATURES = {
     "lbm_mass": [_h, _dp],
     "lbm_residual": [_h, _dp, ct.POINTER(_i64)],
     "lbm_stream_function": [_h, ct.c_void_p],
+    "lbm_classify_series": [ct.c_void_p, ct.c_int, _i64, _i64, ct.c_double, ct.c_double,
+                            ct.c_int, ct.c_int, ct.c_void_p, ct.c_void_p],
+    "lbm_probe_classify": [_h, ct.c_int, _i64, ct.c_double, ct.c_double, ct.c_int, ct.c_int,
+                           ct.c_void_p],
     "lbm_vortex_extrema": [_h, ct.c_void_p],
     "lbm_vortex_centres": [_h, ct.c_double, ct.c_int, ct.c_void_p, ct.POINTER(ct.c_int)],
     "lbm_bottom_vortex_count": [_h, ct.c_double, ct.POINTER(ct.c_int)],
@@ -208,10 +212,15 @@ def lbm_destroy(h):
     _check(_lib.lbm_destroy(h))
 
 
+def _stream_ptr(stream):
+    """A torch.cuda.Stream, a raw hipStream_t integer, or None -> c_void_p."""
+    raw = getattr(stream, "cuda_stream", stream)
+    return ct.c_void_p(raw) if raw else None
+
+
 def lbm_set_stream(h, stream):
     """``stream``: a torch.cuda.Stream, a raw hipStream_t integer, or None."""
-    raw = getattr(stream, "cuda_stream", stream)
-    _check(_lib.lbm_set_stream(h, ct.c_void_p(raw) if raw else None))
+    _check(_lib.lbm_set_stream(h, _stream_ptr(stream)))
 
 
 def lbm_info(h):
@@ -292,6 +301,45 @@ def lbm_stream_function(h, nx, ny):
     psi = np.empty((ny, nx))
     _check(_lib.lbm_stream_function(h, _ptr(psi)))
     return psi
+
+
+LBM_FLOW_STEADY, LBM_FLOW_PERIODIC, LBM_FLOW_APERIODIC = 0, 1, 2
+FLOW_STATES = {LBM_FLOW_STEADY: "steady", LBM_FLOW_PERIODIC: "periodic",
+               LBM_FLOW_APERIODIC: "aperiodic"}
+
+
+class FlowState(ct.Structure):
+    """lbm_flow_state_t."""
+    _fields_ = [("state", ct.c_int), ("lag", ct.c_int), ("period", ct.c_double),
+                ("amplitude", ct.c_double), ("mean", ct.c_double), ("std", ct.c_double),
+                ("mismatch", ct.c_double)]
+
+    def as_dict(self):
+        return {"state": FLOW_STATES[self.state], "lag": self.lag, "period": self.period,
+                "amplitude": self.amplitude, "mean": self.mean, "std": self.std,
+                "mismatch": self.mismatch}
+
+
+def lbm_classify_series(series_dev, steady_tol, periodic_tol, min_lag=1, max_lag=0,
+                        stream=None):
+    """series_dev: a 2-D FP64 device tensor [nseries, n] (rows contiguous)."""
+    ns, n = int(series_dev.shape[0]), int(series_dev.shape[1])
+    if series_dev.stride(1) != 1:
+        raise ValueError("rows must be contiguous")
+    out = (FlowState * ns)()
+    _check(_lib.lbm_classify_series(ct.c_void_p(series_dev.data_ptr()), ns, n,
+                                    int(series_dev.stride(0)), float(steady_tol),
+                                    float(periodic_tol), int(min_lag), int(max_lag), out,
+                                    _stream_ptr(stream)))
+    return [o.as_dict() for o in out]
+
+
+def lbm_probe_classify(h, npts, component, window, steady_tol, periodic_tol, min_lag=1,
+                       max_lag=0):
+    out = (FlowState * int(npts))()
+    _check(_lib.lbm_probe_classify(h, int(component), int(window), float(steady_tol),
+                                   float(periodic_tol), int(min_lag), int(max_lag), out))
+    return [o.as_dict() for o in out]
 
 
 class Vortex(ct.Structure):
@@ -652,6 +700,11 @@ class Cavity:
 
     def stream_function(self):
         return lbm_stream_function(self.h, self.nx, self.ny)
+
+    def probe_classify(self, component, window, steady_tol, periodic_tol, min_lag=1,
+                       max_lag=0):
+        return lbm_probe_classify(self.h, self.npts, component, window, steady_tol,
+                                  periodic_tol, min_lag, max_lag)
 
     def vortex_extrema(self):
         return lbm_vortex_extrema(self.h)

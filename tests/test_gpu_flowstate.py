@@ -1,0 +1,107 @@
+"""GPU flow-state classification (lbm_classify_series, lbm_probe_classify)
+against the oracle's definition (oracle/flowstate.py) on the same series."""
+import math
+
+import numpy as np
+import pytest
+
+from cavity_inputs import U_LID
+from oracle import flowstate as F
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2211_05009_amd import lbm
+    return torch, lbm
+
+
+def _signals(n=3000):
+    k = np.arange(n, dtype=np.float64)
+    x = np.empty(n)
+    x[0] = 0.3
+    for i in range(1, n):
+        x[i] = 3.9 * x[i - 1] * (1 - x[i - 1])
+    rng = np.random.default_rng(5)
+    phi = (1 + math.sqrt(5)) / 2
+    return [
+        0.01 + 1e-10 * np.sin(k),                                     # steady
+        0.02 * np.sin(2 * np.pi * k / 37.25 + 0.3) + 0.01,
+        3.0 * np.sin(2 * np.pi * k / 125.4 + 2.0) - 1.0,
+        np.sign(np.sin(2 * np.pi * (k + 0.5) / 40)) + 0.3 * np.sin(6 * np.pi * k / 40),
+        np.sin(2 * np.pi * k / 20) + 0.5 * np.sin(2 * np.pi * k / 40),
+        np.sin(2 * np.pi * k / 63.7) + 1e-3 * rng.normal(size=n),
+        x,                                                            # chaotic
+        rng.normal(size=n),
+        np.sin(2 * np.pi * k / 20) + np.sin(2 * np.pi * k * phi / 20),  # quasi-periodic
+        1e-3 * k,                                                     # drift
+    ]
+
+
+def _same(got, want):
+    assert got["state"] == want["state"]
+    assert got["lag"] == want["lag"]
+    for key in ("amplitude", "mean", "std"):
+        assert math.isclose(got[key], want[key], rel_tol=1e-12, abs_tol=1e-15), key
+    assert math.isclose(got["period"], want["period"], rel_tol=1e-9, abs_tol=0)
+    if math.isinf(want["mismatch"]):
+        assert math.isinf(got["mismatch"])
+    else:
+        assert abs(got["mismatch"] - want["mismatch"]) <= 1e-7
+
+
+@pytest.mark.parametrize("lags", [(1, 0), (3, 700)])
+def test_series_match_the_oracle(env, lags):
+    torch, lbm = env
+    sig = _signals()
+    dev = torch.tensor(np.stack(sig), dtype=torch.float64, device="cuda")
+    got = lbm.lbm_classify_series(dev, 1e-7, 0.02, *lags)
+    for g, u in zip(got, sig):
+        _same(g, F.classify(u, 1e-7, 0.02, min_lag=lags[0], max_lag=lags[1] or None))
+    states = [g["state"] for g in got]
+    assert states == ["steady"] + ["periodic"] * 5 + ["aperiodic"] * 4
+
+
+def test_strided_rows_and_errors(env):
+    torch, lbm = env
+    sig = _signals(500)
+    big = torch.zeros((len(sig), 640), dtype=torch.float64, device="cuda")
+    big[:, :500] = torch.tensor(np.stack(sig), dtype=torch.float64)
+    got = lbm.lbm_classify_series(big[:, :500], 1e-7, 0.02)
+    for g, u in zip(got, sig):
+        _same(g, F.classify(u, 1e-7, 0.02))
+    short = torch.zeros((1, 7), dtype=torch.float64, device="cuda")
+    for args in ((short, 1e-7, 0.02), (big[:, :500], 1e-7, 0.02, 0), (big[:, :500], 1e-7, 0.02, 150, 151),
+                 (big[:, :500], -1.0, 0.02)):
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm_classify_series(*args)
+        assert e.value.code == lbm.LBM_EINVAL
+
+
+@pytest.mark.parametrize("capacity", [5000, 700])
+def test_probe_series_on_the_device_match_the_read_back_series(env, capacity):
+    """lbm_probe_classify reads the ring in place; the same records read back
+    with lbm_probe_read and classified by the oracle must agree, also after
+    the ring has wrapped (capacity 700 < 1200 records)."""
+    torch, lbm = env
+    nx, ny = 200, 160
+    c = lbm.Cavity(nx, ny, re=3000.0, u_lid=U_LID, dtype="f32s")
+    pts = np.array([[0.5, 0.4], [0.2, 0.1], [0.8, 0.7]])
+    c.probe_config(pts, every=50, capacity=capacity)
+    c.step(60000)
+    recs = c.probe_read(capacity)
+    window = min(600, len(recs))
+    for comp in (0, 1, 2):
+        got = c.probe_classify(comp, window, 1e-9, 0.05)
+        for p in range(len(pts)):
+            u = recs[-window:, 1 + 3 * p + comp]
+            _same(got[p], F.classify(u, 1e-9, 0.05))
+    with pytest.raises(lbm.LbmError):
+        c.probe_classify(1, len(recs) + 1, 1e-9, 0.05)
+    with pytest.raises(lbm.LbmError):
+        c.probe_classify(3, 100, 1e-9, 0.05)
+    c.close()
