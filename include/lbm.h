@@ -244,7 +244,12 @@ int lbm_probe_read(lbm_t h, double *buf_host, int64_t max_records,
  * A period should span a dozen or more samples; a shorter one can come out
  * as a multiple of itself.
  */
-enum { LBM_FLOW_STEADY = 0, LBM_FLOW_PERIODIC = 1, LBM_FLOW_APERIODIC = 2 };
+enum {
+  LBM_FLOW_TOO_SHORT = -1,  /* batches: fewer records than the window */
+  LBM_FLOW_STEADY = 0,
+  LBM_FLOW_PERIODIC = 1,
+  LBM_FLOW_APERIODIC = 2
+};
 typedef struct {
   int state;          /* LBM_FLOW_* */
   int lag;            /* integer lag of the period (periodic only) */
@@ -457,6 +462,38 @@ int lbm_batch_init_fields_device(lbm_batch_t b, int k, const double *rho_dev,
  * u_x/u_lid, u_y/u_lid), mask_dev FP32 [256][128] (1 inside, 0 outside).
  * LBM_EINVAL if round(128 ny/nx) is not in [1, 256]. */
 int lbm_batch_canvas(lbm_batch_t b, int k, float *target_dev, float *mask_dev);
+
+/*
+ * Probe time series of a batch (the observing points of Sec. 3.3, one set
+ * per cavity): npts points per cavity, xy_host [n][npts][2] in units of L
+ * (bilinear over site centres as lbm_probe), recorded at every monitor of
+ * an active cavity -- every 100 of its steps -- into a ring of `capacity`
+ * records per cavity.  npts = 0 removes the probes.  Recording starts at
+ * the next monitor; reconfiguring drops earlier records.
+ * Errors: LBM_EINVAL for npts outside [0, 4096], capacity < 1, NULL xy, or
+ * rings above 64 GB; LBM_ENOMEM.
+ */
+int lbm_batch_probe_config(lbm_batch_t b, int npts, const double *xy_host, int64_t capacity);
+
+/*
+ * The most recent min(max_records, held) records of cavity k, oldest first,
+ * each 3 npts doubles (rho, u_x, u_y per point), into buf_host.
+ * *first_step receives the cavity's step count at the first returned record
+ * (records are 100 of its steps apart); -1 if none.
+ */
+int lbm_batch_probe_read(lbm_batch_t b, int k, double *buf_host, int64_t max_records,
+                         int64_t *n_records, int64_t *first_step);
+
+/*
+ * Flow state (lbm_classify_series' definition) of component c (0: rho,
+ * 1: u_x, 2: u_y) of every probe point of every cavity over its most recent
+ * `window` records (window <= capacity), on the device.  out_host: [n][npts]
+ * records; cavities with fewer records than the window get
+ * LBM_FLOW_TOO_SHORT.  Periods are in records (100 steps each).
+ */
+int lbm_batch_probe_classify(lbm_batch_t b, int component, int64_t window, double steady_tol,
+                             double periodic_tol, int min_lag, int max_lag,
+                             lbm_flow_state_t *out_host);
 
 /* Lattice, Reynolds number and lid speed of cavity k (NULL outputs skipped). */
 int lbm_batch_cavity(lbm_batch_t b, int k, int *nx, int *ny, double *re,

@@ -125,4 +125,30 @@ static __global__ __launch_bounds__(kRedThreads) void k_finalize_batch(
   block_reduce_store<kNumSums>(acc, out + cav_of[j] * kNumSums);
 }
 
+// Probe records of the batch: one block per active cavity (cav_of lists
+// them), its npts points (units of L, [n][npts][2]) interpolated as
+// probe_point does, written to record count[c] % cap of the cavity's ring
+// ([n][cap][npts][3]); then count[c] advances.
+template <typename T, bool SHIFT>
+__global__ __launch_bounds__(256) void k_probe_ring_batch(
+    const T *__restrict__ buf, const CavityDesc<T> *__restrict__ cav,
+    const int *__restrict__ cav_of, const double *__restrict__ xy, int npts,
+    double *__restrict__ ring, long long cap, unsigned long long *__restrict__ count) {
+  const int c = cav_of[blockIdx.x];
+  const CavityDesc<T> d = cav[c];
+  Geometry g;
+  g.nx = d.nx;
+  g.ny = d.ny;
+  g.pitch = d.pitch;
+  g.plane = d.plane;
+  const unsigned long long k = count[c];
+  double *rec = ring + ((long long)c * cap + (long long)(k % (unsigned long long)cap)) * 3 * npts;
+  for (int p = threadIdx.x; p < npts; p += 256) {
+    const long long q = ((long long)c * npts + p) * 2;
+    probe_point<T, SHIFT>(buf + d.base, g, xy[q], xy[q + 1], rec + 3 * p);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) count[c] = k + 1;
+}
+
 }  // namespace lbm

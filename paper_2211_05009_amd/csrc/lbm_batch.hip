@@ -23,6 +23,7 @@
 
 #include "../../include/lbm.h"
 #include "d2q9_batch.hpp"
+#include "d2q9_series.hpp"
 #include "d2q9_monitor.hpp"
 #include "d2q9_step.hpp"
 #include "lbm_internal.h"
@@ -63,6 +64,13 @@ struct lbm_batch {
   hipStream_t stream = nullptr, own_stream = nullptr, cap_stream = nullptr;
   hipGraphExec_t graph = nullptr;
   bool tables_dirty = true;
+  // probe time series, recorded at every monitor of an active cavity
+  double *probe_xy = nullptr;                 // [n][probe_n][2]
+  double *probe_ring = nullptr;               // [n][probe_cap][probe_n][3]
+  unsigned long long *probe_count = nullptr;  // [n] records written
+  int probe_n = 0;
+  int64_t probe_cap = 0;
+  std::vector<int64_t> probe_records, probe_last;   // host mirror: count, step of the latest
 };
 
 namespace {
@@ -173,10 +181,23 @@ hipError_t batch_monitor_t(const lbm_batch *b, int from, hipStream_t st) {
   return hipGetLastError();
 }
 
+template <typename T, bool S>
+hipError_t batch_probe_t(const lbm_batch *b, int from, hipStream_t st) {
+  hipLaunchKernelGGL((k_probe_ring_batch<T, S>), dim3(b->nfin), dim3(256), 0, st,
+                     (const T *)b->buf[from], (const CavityDesc<T> *)b->desc, b->fin + 2 * b->n,
+                     b->probe_xy, b->probe_n, b->probe_ring, (long long)b->probe_cap,
+                     b->probe_count);
+  return hipGetLastError();
+}
+
+// The monitor pair of every active cavity, then its probe record.
 hipError_t batch_monitor(const lbm_batch *b, int from, hipStream_t st) {
   if (b->nmtiles == 0) return hipSuccess;
-  if (b->dtype == LBM_F64) return batch_monitor_t<double, false>(b, from, st);
-  return batch_monitor_t<float, true>(b, from, st);
+  hipError_t e = b->dtype == LBM_F64 ? batch_monitor_t<double, false>(b, from, st)
+                                     : batch_monitor_t<float, true>(b, from, st);
+  if (e != hipSuccess || b->probe_n == 0 || b->nfin == 0) return e;
+  return b->dtype == LBM_F64 ? batch_probe_t<double, false>(b, from, st)
+                             : batch_probe_t<float, true>(b, from, st);
 }
 
 bool valid_k(const lbm_batch *b, int k) { return b && k >= 0 && k < b->n; }
@@ -312,6 +333,10 @@ void note_monitor(lbm_batch *b) {
     b->mon_valid[c] = (b->snap_t[c] == b->t[c] - kChunk);
     b->snap_t[c] = b->t[c];
     b->mon_t[c] = b->t[c];
+    if (b->probe_n > 0) {      // k_probe_ring_batch recorded this cavity
+      ++b->probe_records[c];
+      b->probe_last[c] = b->t[c];
+    }
   }
 }
 
@@ -416,7 +441,8 @@ int lbm_batch_destroy(lbm_batch_t b) {
   drop_graph(b);
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   void *ptrs[] = {b->buf[0], b->buf[1], b->desc, b->tiles, b->tiles1, b->mtiles, b->fin,
-                  b->uref, b->partials, b->mon_dev, b->aux_dev, b->tmp};
+                  b->uref, b->partials, b->mon_dev, b->aux_dev, b->tmp, b->probe_xy,
+                  b->probe_ring, b->probe_count};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (b->mon_host) (void)hipHostFree(b->mon_host);
@@ -927,3 +953,94 @@ int lbm_batch_info(lbm_batch_t b, int *n, int64_t *total_sites, int64_t *steps_d
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------------ probes
+int lbm_batch_probe_config(lbm_batch_t b, int npts, const double *xy, int64_t capacity) {
+  if (!b) return lbm_fail(LBM_EINVAL, "batch is NULL");
+  if (npts < 0 || npts > 4096) return lbm_fail(LBM_EINVAL, "npts = %d outside [0, 4096]", npts);
+  if (npts > 0 && (!xy || capacity < 1))
+    return lbm_fail(LBM_EINVAL, "npts = %d needs points and capacity >= 1", npts);
+  const double bytes = (double)b->n * (double)capacity * npts * 3 * sizeof(double);
+  if (npts > 0 && bytes > 64.0 * (1ull << 30))
+    return lbm_fail(LBM_EINVAL, "probe rings of %.3g GB exceed 64 GB", bytes / 1e9);
+  HIPC(hipStreamSynchronize(b->stream));
+  drop_graph(b);
+  for (void **p : {(void **)&b->probe_xy, (void **)&b->probe_ring, (void **)&b->probe_count}) {
+    if (*p) HIPC(hipFree(*p));
+    *p = nullptr;
+  }
+  b->probe_n = 0;
+  b->probe_cap = 0;
+  b->probe_records.assign(b->n, 0);
+  b->probe_last.assign(b->n, -1);
+  if (npts == 0) return LBM_OK;
+  const size_t nxy = (size_t)b->n * npts * 2;
+  HIPC(hipMalloc(&b->probe_xy, nxy * sizeof(double)));
+  HIPC(hipMalloc(&b->probe_ring, (size_t)b->n * capacity * npts * 3 * sizeof(double)));
+  HIPC(hipMalloc(&b->probe_count, (size_t)b->n * sizeof(unsigned long long)));
+  HIPC(hipMemcpy(b->probe_xy, xy, nxy * sizeof(double), hipMemcpyHostToDevice));
+  HIPC(hipMemset(b->probe_count, 0, (size_t)b->n * sizeof(unsigned long long)));
+  b->probe_n = npts;
+  b->probe_cap = capacity;
+  return LBM_OK;
+}
+
+int lbm_batch_probe_read(lbm_batch_t b, int k, double *buf, int64_t max_records,
+                         int64_t *n_records, int64_t *first_step) {
+  if (!valid_k(b, k) || !n_records) return lbm_fail(LBM_EINVAL, "bad cavity index or NULL");
+  *n_records = 0;
+  if (first_step) *first_step = -1;
+  if (b->probe_n == 0) return LBM_OK;
+  if (max_records > 0 && !buf) return lbm_fail(LBM_EINVAL, "buf is NULL");
+  HIPC(hipStreamSynchronize(b->stream));
+  const int64_t count = b->probe_records[k];
+  const int64_t take = std::min<int64_t>(std::min<int64_t>(count, b->probe_cap), max_records);
+  const int rec = 3 * b->probe_n;
+  for (int64_t i = 0; i < take; ++i) {
+    const int64_t idx = count - take + i;
+    const int64_t slot = idx % b->probe_cap;
+    HIPC(hipMemcpy(buf + i * rec, b->probe_ring + ((int64_t)k * b->probe_cap + slot) * rec,
+                   rec * sizeof(double), hipMemcpyDeviceToHost));
+  }
+  *n_records = take;
+  if (first_step && take > 0) *first_step = b->probe_last[k] - (int64_t)kChunk * (take - 1);
+  return LBM_OK;
+}
+
+int lbm_batch_probe_classify(lbm_batch_t b, int component, int64_t window, double steady_tol,
+                             double periodic_tol, int min_lag, int max_lag,
+                             lbm_flow_state_t *out) {
+  if (!b || !out) return lbm_fail(LBM_EINVAL, "NULL argument");
+  if (b->probe_n == 0) return lbm_fail(LBM_EINVAL, "no probes configured");
+  if (component < 0 || component > 2)
+    return lbm_fail(LBM_EINVAL, "component %d outside {0, 1, 2}", component);
+  if (!(steady_tol >= 0.0) || !(periodic_tol >= 0.0))
+    return lbm_fail(LBM_EINVAL, "tolerances must be >= 0");
+  int rc = check_lags(window, min_lag, max_lag);
+  if (rc) return rc;
+  if (window > b->probe_cap)
+    return lbm_fail(LBM_EINVAL, "window %lld exceeds the ring capacity %lld", (long long)window,
+                    (long long)b->probe_cap);
+  HIPC(hipStreamSynchronize(b->stream));
+  std::vector<SeriesDesc> d;
+  std::vector<int> slot_of;
+  const int rec = 3 * b->probe_n;
+  for (int c = 0; c < b->n; ++c)
+    for (int p = 0; p < b->probe_n; ++p) {
+      lbm_flow_state_t &o = out[(size_t)c * b->probe_n + p];
+      std::memset(&o, 0, sizeof o);
+      o.state = LBM_FLOW_TOO_SHORT;
+      if (b->probe_records[c] < window) continue;
+      const long long start = (long long)((b->probe_records[c] - window) % b->probe_cap);
+      d.push_back(SeriesDesc{b->probe_ring + (size_t)c * b->probe_cap * rec + 3 * p + component,
+                             (long long)b->probe_cap, start, (long long)window, (long long)rec});
+      slot_of.push_back(c * b->probe_n + p);
+    }
+  if (d.empty()) return LBM_OK;
+  std::vector<lbm_flow_state_t> res(d.size());
+  rc = classify_series_descs(d.data(), (int)d.size(), window, steady_tol, periodic_tol, min_lag,
+                             max_lag, b->stream, res.data());
+  if (rc) return rc;
+  for (size_t i = 0; i < d.size(); ++i) out[slot_of[i]] = res[i];
+  return LBM_OK;
+}

@@ -129,6 +129,11 @@ SIGNATURES = {
     "lbm_batch_init_fields_device": [_h, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                      ct.c_int],
     "lbm_batch_cavity": [_h, ct.c_int, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int), _dp, _dp],
+    "lbm_batch_probe_config": [_h, ct.c_int, ct.c_void_p, _i64],
+    "lbm_batch_probe_read": [_h, ct.c_int, ct.c_void_p, _i64, ct.POINTER(_i64),
+                             ct.POINTER(_i64)],
+    "lbm_batch_probe_classify": [_h, ct.c_int, _i64, ct.c_double, ct.c_double, ct.c_int,
+                                 ct.c_int, ct.c_void_p],
     "lbm_batch_canvas": [_h, ct.c_int, ct.c_void_p, ct.c_void_p],
     "lbm_sur_create": [ct.c_int, ct.POINTER(_h)],
     "lbm_sur_destroy": [_h],
@@ -303,9 +308,9 @@ def lbm_stream_function(h, nx, ny):
     return psi
 
 
-LBM_FLOW_STEADY, LBM_FLOW_PERIODIC, LBM_FLOW_APERIODIC = 0, 1, 2
-FLOW_STATES = {LBM_FLOW_STEADY: "steady", LBM_FLOW_PERIODIC: "periodic",
-               LBM_FLOW_APERIODIC: "aperiodic"}
+LBM_FLOW_TOO_SHORT, LBM_FLOW_STEADY, LBM_FLOW_PERIODIC, LBM_FLOW_APERIODIC = -1, 0, 1, 2
+FLOW_STATES = {LBM_FLOW_TOO_SHORT: "too short", LBM_FLOW_STEADY: "steady",
+               LBM_FLOW_PERIODIC: "periodic", LBM_FLOW_APERIODIC: "aperiodic"}
 
 
 class FlowState(ct.Structure):
@@ -529,6 +534,34 @@ def lbm_batch_init_fields_device(b, k, rho, ux, uy, renormalise_mass=True,
                                  zero_staggered=False):
     _check(_lib.lbm_batch_init_fields_device(b, int(k), _dptr(rho), _dptr(ux), _dptr(uy),
                                              _init_flags(renormalise_mass, zero_staggered)))
+
+
+def lbm_batch_probe_config(b, xy, capacity):
+    """xy: [n, npts, 2] points in units of L (npts = 0 removes the probes)."""
+    xy = np.ascontiguousarray(xy, dtype=np.float64)
+    npts = int(xy.shape[1]) if xy.ndim == 3 else 0
+    _check(_lib.lbm_batch_probe_config(b, npts, _ptr(xy) if npts else None, int(capacity)))
+    return npts
+
+
+def lbm_batch_probe_read(b, k, npts, max_records):
+    """(records [m, npts, 3], step of the first record)."""
+    buf = np.empty((max(int(max_records), 1), npts, 3))
+    n = _i64()
+    first = _i64()
+    _check(_lib.lbm_batch_probe_read(b, int(k), _ptr(buf), int(max_records), ct.byref(n),
+                                     ct.byref(first)))
+    return buf[:n.value], first.value
+
+
+def lbm_batch_probe_classify(b, n, npts, component, window, steady_tol, periodic_tol,
+                             min_lag=1, max_lag=0):
+    """[n][npts] dicts (state "too short" for cavities with too few records)."""
+    out = (FlowState * (int(n) * int(npts)))()
+    _check(_lib.lbm_batch_probe_classify(b, int(component), int(window), float(steady_tol),
+                                         float(periodic_tol), int(min_lag), int(max_lag), out))
+    res = [o.as_dict() for o in out]
+    return [res[c * npts:(c + 1) * npts] for c in range(int(n))]
 
 
 def lbm_batch_cavity(b, k):
@@ -815,6 +848,16 @@ class Batch:
 
     def autotune(self, chunks=2, use_cache=True):
         return lbm_batch_autotune(self.b, chunks, use_cache)
+
+    def probe_config(self, xy, capacity):
+        self.probe_npts = lbm_batch_probe_config(self.b, xy, capacity)
+
+    def probe_read(self, k, max_records):
+        return lbm_batch_probe_read(self.b, k, self.probe_npts, max_records)
+
+    def probe_classify(self, component, window, steady_tol, periodic_tol, min_lag=1, max_lag=0):
+        return lbm_batch_probe_classify(self.b, len(self.nx), self.probe_npts, component, window,
+                                        steady_tol, periodic_tol, min_lag, max_lag)
 
     def cavity(self, k):
         return lbm_batch_cavity(self.b, k)

@@ -170,3 +170,61 @@ def test_full_sweep_batch_matches_single(lbm, variant):
     ref = o.post_collision()
     gmax = np.max(np.abs(ref - W[:, None, None]))
     assert np.max(np.abs(b.get_populations(24) - ref)) <= 16 * 2.0 ** -24 * gmax
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32s"])
+def test_batch_probes_match_single_cavity_probes(lbm, dtype):
+    """Batch probe records (every monitor, i.e. every 100 steps) equal the
+    single-cavity records of the same points bit for bit, through graph
+    chunks and the one-step path, and survive ring wrap-around; the flow
+    states computed on the device equal the oracle's on the read-back
+    series."""
+    from oracle import flowstate
+    cases = [(120, 90, 1000.0), (100, 150, 800.0), (80, 40, 400.0)]   # Re / N <= 8
+    pts = np.array([[[0.5, 0.3], [0.2, 0.6]], [[0.5, 0.5], [0.9, 0.1]],
+                    [[0.5, 0.2], [0.1, 0.45]]])
+    b = make_batch(lbm, cases, dtype)
+    b.probe_config(pts, capacity=40)
+    b.step(2000)          # graph chunks
+    b.step(1037)          # one-step path across monitors
+    b.step(1963)          # back onto the grid, then chunks: 50 records in all
+    for k, (nx, ny, re) in enumerate(cases):
+        c = lbm.Cavity(nx, ny, re=re, u_lid=U_LID, dtype=dtype)
+        c.probe_config(pts[k], every=100, capacity=100)
+        c.step(5000)
+        single = c.probe_read(100)
+        assert len(single) == 50
+        recs, first = b.probe_read(k, 1000)
+        assert len(recs) == 40 and first == 1100     # the ring keeps the last 40
+        assert np.array_equal(single[-40:, 0], first + 100 * np.arange(40))
+        assert np.array_equal(recs.reshape(40, -1), single[-40:, 1:])
+        c.close()
+    states = b.probe_classify(1, 30, 1e-9, 0.05)
+    for k in range(len(cases)):
+        recs, _ = b.probe_read(k, 30)
+        for p in range(2):
+            want = flowstate.classify(recs[:, p, 1], 1e-9, 0.05)
+            assert states[k][p]["state"] == want["state"]
+            assert math.isclose(states[k][p]["std"], want["std"], rel_tol=1e-12)
+    with pytest.raises(lbm.LbmError):
+        b.probe_classify(1, 41, 1e-9, 0.05)            # window above the capacity
+    b.close()
+
+
+def test_batch_probes_stop_with_the_cavity(lbm):
+    """A cavity that converges leaves the batch and records no more; one
+    with fewer records than the window is reported as too short."""
+    cases = [(16, 16, 5.0), (40, 40, 400.0)]
+    b = make_batch(lbm, cases, "f64")
+    b.probe_config(np.array([[[0.5, 0.5]], [[0.5, 0.5]]]), capacity=1000)
+    b.set_threshold(1e-7)
+    b.step(30000)
+    s0 = b.status(0)
+    assert not s0["active"]
+    recs0, first0 = b.probe_read(0, 1000)
+    assert len(recs0) == s0["steps_done"] // 100 and first0 == 100
+    recs1, _ = b.probe_read(1, 1000)
+    assert len(recs1) > len(recs0)
+    st = b.probe_classify(1, len(recs0) + 1, 1e-12, 0.05)
+    assert st[0][0]["state"] == "too short" and st[1][0]["state"] != "too short"
+    b.close()
