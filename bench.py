@@ -69,6 +69,17 @@ def parse():
                     help="storage of the time-to-steady runs")
     ap.add_argument("--tts-threshold", type=float, default=1e-6,
                     help="Eq. 6 residual that counts as steady")
+    ap.add_argument("--long", type=int, default=1,
+                    help="also run the long unsteady cavity (500 x 750, Re 8000, 2 M steps, "
+                         "5 probes) and classify its probe series (0: skip)")
+    ap.add_argument("--flowmap", default="",
+                    help="run a flow-state map instead: 'fig17' (153 cavities) or "
+                         "'Re1,Re2,...:Ar1,Ar2,...'; prints one JSON line")
+    ap.add_argument("--flowmap-steps", type=int, default=3_000_000)
+    ap.add_argument("--aux", type=int, default=0,
+                    help="instead time the kernels off the metric (non-equilibrium-"
+                         "extrapolation step, vortex extraction, surrogate convolutions, "
+                         "series classifier); prints one JSON line")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-steps", type=int, default=700)
     ap.add_argument("--copy-probe", type=int, default=0)
@@ -231,6 +242,10 @@ def main():
               "MI355X; multi-GPU runs are not part of this build", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.flowmap:
+        return run_flowmap(args)
+    if args.aux:
+        return run_aux()
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
@@ -304,11 +319,77 @@ def main():
         out["sweep_time_to_steady"] = warmstart.steady_sweep_study(
             normal_draws(npar, seed=0), threshold=args.tts_threshold, epochs=args.tts_epochs,
             modes=tuple(args.tts_modes.split(",")), dtype=args.tts_dtype, log=progress)
+    if args.long:
+        from paper_2211_05009_amd import flowmap
+        progress("long unsteady cavity with probes")
+        out["long_unsteady"] = flowmap.long_unsteady(log=progress)
     out["copy_GBs"] = copy_bandwidth(torch)
     if args.cpu_baseline:
         progress("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(nx, ny, args.re, args.cpu_steps)
     print(json.dumps(out), flush=True)
+
+
+def run_aux():
+    """Timings of the kernels off the metric, for profiling (one JSON line)."""
+    import torch
+    import numpy as np
+    from paper_2211_05009_amd import lbm, warmstart
+    from cavity_inputs import normal_draws
+    out = {}
+    for dt in ("f64", "f32s"):           # the paper's walls, 256 x 256 validation lattice
+        c = lbm.Cavity(257, 257, re=1000.0, u_lid=0.1, dtype=dt, wall="nee")
+        c.autotune(chunks=5)
+        c.step(2000)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.step(20000)
+        sec = time.perf_counter() - t0
+        out[f"nee_257_{dt}"] = {"MLUPS": round(257 * 257 * 20000 / sec / 1e6, 1),
+                                "variant": c.get_option(lbm.LBM_OPT_STEP_VARIANT)}
+        c.close()
+    progress("vortex extraction")
+    c = lbm.Cavity(500, 600, re=6000.0, u_lid=0.1, dtype="f32s")
+    c.step(20000)
+    t0 = time.perf_counter()
+    for _ in range(10):
+        c.vortex_extrema()
+        n = c.vortex_centres(1e-9 * 50)[1]
+    out["vortex_500x600_ms"] = round((time.perf_counter() - t0) / 10 * 1e3, 3)
+    out["vortex_centres"] = n
+    c.close()
+    progress("surrogate throughput")
+    sur = warmstart.make_surrogate(normal_draws(lbm.Surrogate(1).num_params, seed=0))
+    out["surrogate"] = warmstart.surrogate_throughput(sur)
+    sur.close()
+    progress("series classifier")
+    k = np.arange(10000, dtype=np.float64)
+    rng = np.random.default_rng(0)
+    ser = np.stack([np.sin(2 * np.pi * k / (80 + i)) + 1e-3 * rng.normal(size=k.size)
+                    for i in range(153)])
+    dev = torch.tensor(ser, dtype=torch.float64, device="cuda")
+    lbm.lbm_classify_series(dev, 1e-6, 0.05)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = lbm.lbm_classify_series(dev, 1e-6, 0.05)
+    out["classify_153x10000_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+    out["classify_periodic"] = sum(r["state"] == "periodic" for r in res)
+    print(json.dumps({"aux": out}), flush=True)
+
+
+def run_flowmap(args):
+    """Flow-state map (Sec. 3.3, Fig. 17) as one batch; one JSON line."""
+    from paper_2211_05009_amd import flowmap
+    if args.flowmap == "fig17":
+        res, ars = flowmap.FIG17_RE, flowmap.FIG17_AR
+    else:
+        a, b = args.flowmap.split(":")
+        res = [float(v) for v in a.split(",")]
+        ars = [float(v) for v in b.split(",")]
+    cases = [(re, ar) for ar in ars for re in res]
+    progress(f"flow-state map: {len(cases)} cavities, {args.flowmap_steps} steps")
+    rows, run = flowmap.state_map(cases, steps=args.flowmap_steps, log=progress)
+    print(json.dumps({"flowmap": rows, "run": run, "cavities": len(cases)}), flush=True)
 
 
 if __name__ == "__main__":

@@ -238,9 +238,11 @@ int lbm_probe_read(lbm_t h, double *buf_host, int64_t max_records,
  *   max_lag, reached after D exceeded 1 at a smaller lag; the parabola
  *   through D at T-1, T, T+1 gives the period (its vertex, in samples) and
  *   the mismatch sqrt(max(vertex value, 0));
- *   LBM_FLOW_PERIODIC at the first candidate with mismatch <= periodic_tol,
- *   LBM_FLOW_APERIODIC otherwise (mismatch = the smallest over candidates,
- *   +inf if none).
+ *   LBM_FLOW_PERIODIC at the first candidate with mismatch <= periodic_tol;
+ *   LBM_FLOW_DRIFT if there is no candidate (the series never returns
+ *   towards an earlier value within the window: a monotone approach, e.g.
+ *   to a steady state, or a period longer than max_lag; mismatch = +inf);
+ *   LBM_FLOW_APERIODIC otherwise (mismatch = the smallest over candidates).
  * A period should span a dozen or more samples; a shorter one can come out
  * as a multiple of itself.
  */
@@ -248,7 +250,8 @@ enum {
   LBM_FLOW_TOO_SHORT = -1,  /* batches: fewer records than the window */
   LBM_FLOW_STEADY = 0,
   LBM_FLOW_PERIODIC = 1,
-  LBM_FLOW_APERIODIC = 2
+  LBM_FLOW_APERIODIC = 2,
+  LBM_FLOW_DRIFT = 3
 };
 typedef struct {
   int state;          /* LBM_FLOW_* */

@@ -16,12 +16,15 @@ definition used here (and by the library) is:
   this); the parabola through D at T - 1, T, T + 1 gives the refined period
   (its vertex) and the mismatch sqrt(max(vertex value, 0)); the series is
   periodic at the first candidate with mismatch <= periodic_tol;
-* aperiodic otherwise.
+* drift if there is no candidate at all: the series never returns towards
+  an earlier value within the window (a monotone approach, e.g. to a steady
+  state, or a period longer than max_lag);
+* aperiodic otherwise (returns, but none close enough).
 
-Returns a dict: state ("steady", "periodic", "aperiodic"), lag (the
+Returns a dict: state ("steady", "periodic", "drift", "aperiodic"), lag (the
 integer lag, periodic only), period (samples; 0 unless periodic), amplitude,
 mean, std, mismatch (at the chosen candidate; for an aperiodic series the
-smallest over all candidates, inf if there is none).
+smallest over all candidates; inf for a drift).
 
 The parabola models D near a period well when the period spans a dozen or
 more samples; a period of a few samples can come out as a multiple of itself.
@@ -73,5 +76,5 @@ def classify(u, steady_tol, periodic_tol, min_lag=1, max_lag=None):
         if mismatch <= periodic_tol:
             out.update(state="periodic", lag=lags[j], period=period, mismatch=mismatch)
             return out
-    out.update(state="aperiodic", mismatch=best)
+    out.update(state="drift" if best == math.inf else "aperiodic", mismatch=best)
     return out

@@ -72,7 +72,7 @@ __device__ __forceinline__ void nee_wall(T (&f)[9], T omega, T uw) {
   const T jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
   const T jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
   const T rho = SHIFT ? T(1) + s : s;
-  const T rinv = T(1) / rho;
+  const T rinv = recip<T>(rho);
   const T base = SHIFT ? s : rho;
   T er[9], ew[9];
   equilibrium9<T>(base, rho, jx * rinv, jy * rinv, er);

@@ -8,8 +8,8 @@
 //   [min_lag, max_lag]; candidates are interior local minima of D reached
 //   after D exceeded 1; the parabola through D at T-1, T, T+1 refines the
 //   period (vertex) and gives the mismatch sqrt(max(vertex value, 0));
-//   periodic at the first candidate with mismatch <= periodic_tol, else
-//   aperiodic.
+//   periodic at the first candidate with mismatch <= periodic_tol; a drift
+//   if there is no candidate; aperiodic otherwise.
 // Every sum runs in a fixed order (per-thread sequential sums, then a fixed
 // LDS tree), so the result does not depend on scheduling.
 #pragma once
@@ -137,6 +137,7 @@ static __global__ __launch_bounds__(kSeriesThreads) void k_classify_series(
     }
   }
   r.mismatch = best;
+  if (best == INFINITY) r.state = 3;   // no return within the window: a drift
   out[blockIdx.x] = r;
 }
 

@@ -308,9 +308,11 @@ def lbm_stream_function(h, nx, ny):
     return psi
 
 
-LBM_FLOW_TOO_SHORT, LBM_FLOW_STEADY, LBM_FLOW_PERIODIC, LBM_FLOW_APERIODIC = -1, 0, 1, 2
+LBM_FLOW_TOO_SHORT, LBM_FLOW_STEADY, LBM_FLOW_PERIODIC, LBM_FLOW_APERIODIC, LBM_FLOW_DRIFT = \
+    -1, 0, 1, 2, 3
 FLOW_STATES = {LBM_FLOW_TOO_SHORT: "too short", LBM_FLOW_STEADY: "steady",
-               LBM_FLOW_PERIODIC: "periodic", LBM_FLOW_APERIODIC: "aperiodic"}
+               LBM_FLOW_PERIODIC: "periodic", LBM_FLOW_APERIODIC: "aperiodic",
+               LBM_FLOW_DRIFT: "drift"}
 
 
 class FlowState(ct.Structure):

@@ -68,6 +68,12 @@ def test_aperiodic_signals():
     assert r["state"] == "aperiodic" and r["period"] == 0.0 and r["mismatch"] > 0.02
 
 
-def test_a_monotone_drift_is_not_periodic():
-    r = F.classify(1e-3 * K, 1e-7, 0.02)
-    assert r["state"] == "aperiodic" and r["mismatch"] == math.inf
+def test_monotone_approaches_are_drifts():
+    """A linear drift and an exponential approach to a steady value never
+    return within the window: drift, not an aperiodic oscillation."""
+    for u in (1e-3 * K, 0.3 + 1e-4 * np.exp(-K / 2000.0)):
+        r = F.classify(u, 1e-7, 0.02)
+        assert r["state"] == "drift" and r["mismatch"] == math.inf and r["period"] == 0.0
+    # a period longer than the lag range is a drift too
+    r = F.classify(np.sin(2 * np.pi * K / 5000.0), 1e-7, 0.02)
+    assert r["state"] == "drift"
