@@ -132,3 +132,48 @@ def naive_steps_nee(f, tau, u_lid, nsteps, num=float):
                     nxt[i][y][x] = eq_wall[i] + ref[i] - eq_ref[i]
         cur = nxt
     return cur
+
+
+# D3Q19 set and weights, written out again (no import from oracle.d3q19).
+_VEL3 = [(0, 0, 0)] + [v for a in range(3) for v in
+                       (tuple(1 if k == a else 0 for k in range(3)),
+                        tuple(-1 if k == a else 0 for k in range(3)))]
+_VEL3 += [(1, 1, 0), (-1, -1, 0), (1, -1, 0), (-1, 1, 0), (1, 0, 1), (-1, 0, -1), (1, 0, -1),
+          (-1, 0, 1), (0, 1, 1), (0, -1, -1), (0, 1, -1), (0, -1, 1)]
+
+
+def naive_steps_3d(f, tau, u_lid, nsteps, num=float):
+    """Push-form twin of ``oracle.d3q19`` for a closed box (all six faces
+    half-way bounce-back, lid above y = ny - 1 moving with (u_lid, 0, 0) and
+    owning every link through its plane).  ``f`` is [19][nz][ny][nx]."""
+    nz, ny, nx = len(f[0]), len(f[0][0]), len(f[0][0][0])
+    one = num(1)
+    wgt = [num(1) / num(3)] + [num(1) / num(18)] * 6 + [num(1) / num(36)] * 12
+    tau, u_lid = num(tau), num(u_lid)
+    cur = [[[[num(f[i][z][y][x]) for x in range(nx)] for y in range(ny)] for z in range(nz)]
+           for i in range(19)]
+    for _ in range(nsteps):
+        nxt = [[[[None] * nx for _ in range(ny)] for _ in range(nz)] for _ in range(19)]
+        for z in range(nz):
+            for y in range(ny):
+                for x in range(nx):
+                    pops = [cur[i][z][y][x] for i in range(19)]
+                    rho = sum(pops, num(0))
+                    u = [sum((_VEL3[i][a] * pops[i] for i in range(19)), num(0)) / rho
+                         for a in range(3)]
+                    uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2]
+                    for i in range(19):
+                        c = _VEL3[i]
+                        cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2]
+                        eq = wgt[i] * rho * (one + 3 * cu + (9 * one / 2) * cu * cu
+                                             - (3 * one / 2) * uu)
+                        post = pops[i] - (pops[i] - eq) / tau
+                        tx, ty, tz = x + c[0], y + c[1], z + c[2]
+                        if 0 <= tx < nx and 0 <= ty < ny and 0 <= tz < nz:
+                            nxt[i][tz][ty][tx] = post
+                        else:
+                            wall_u = u_lid if ty >= ny else num(0)
+                            r = _VEL3.index((-c[0], -c[1], -c[2]))
+                            nxt[r][z][y][x] = post - 6 * wgt[i] * one * (c[0] * wall_u)
+        cur = nxt
+    return cur
