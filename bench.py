@@ -26,6 +26,10 @@ sample.
 
 ``--copy-probe BYTES`` instead runs a plain device copy of BYTES bytes ten
 times (used to calibrate the rocprofv3 FETCH_SIZE / WRITE_SIZE counters).
+Other single-purpose modes, each printing one JSON line: ``--flowmap`` (the
+Fig. 17 flow-state map as one batch), ``--precision`` (FP32 f - w against
+FP64 on the nine 500 x (500 Ar) cavities), ``--aux`` (kernels off the
+metric: the paper's wall scheme, vortex extraction, surrogate, classifier).
 """
 import argparse
 import hashlib
@@ -58,6 +62,7 @@ def parse():
                     help="also time Ar 0.4/1.0/2.0 in both storage types (0: skip)")
     ap.add_argument("--sweep", type=int, default=1,
                     help="also time the 25-cavity batch against sequential runs (0: skip)")
+    ap.add_argument("--sweep-steps", type=int, default=50000)
     ap.add_argument("--tts", type=int, default=1,
                     help="time-to-steady of the steady sweep, batched + warm-started vs "
                          "plain (0: skip)")
@@ -76,10 +81,16 @@ def parse():
                     help="run a flow-state map instead: 'fig17' (153 cavities) or "
                          "'Re1,Re2,...:Ar1,Ar2,...'; prints one JSON line")
     ap.add_argument("--flowmap-steps", type=int, default=3_000_000)
+    ap.add_argument("--cube", type=int, default=1,
+                    help="also time the D3Q19 box: 256^3 FP32 and 192^3 FP64 (0: skip)")
     ap.add_argument("--aux", type=int, default=0,
                     help="instead time the kernels off the metric (non-equilibrium-"
                          "extrapolation step, vortex extraction, surrogate convolutions, "
                          "series classifier); prints one JSON line")
+    ap.add_argument("--precision", type=int, default=0,
+                    help="instead compare FP32 f - w storage with FP64 on the nine "
+                         "500 x (500 Ar) cavities (Ar 0.4/1.0/2.0 x Re 1000/4000/8000) after "
+                         "1000 and 200,000 steps; prints one JSON line")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-steps", type=int, default=700)
     ap.add_argument("--copy-probe", type=int, default=0)
@@ -179,6 +190,30 @@ def time_sweep(lbm, torch, re_cases, dtype, steps):
             "batch_GBs_effective": round(sites * steps * BYTES_PER_SITE[dtype] / t_batch / 1e9, 1)}
 
 
+def time_cube(lbm, torch, n, dtype, steps):
+    """D3Q19 lid-driven box of n^3 sites (Re 1000): MLUPS and the HBM
+    roofline at 19 populations read and written per site update (152 B in
+    FP32, 304 B in FP64), timed with HIP events on the handle's stream."""
+    c = lbm.Cube(n, n, n, re=1000.0, u_lid=0.1, dtype=dtype)
+    stream = torch.cuda.Stream()
+    lbm.lbm3d_set_stream(c.h, stream)
+    best, _ = c.autotune(2)
+    c.step(200)
+    e0, e1 = events(torch)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    c.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3
+    c.close()
+    mlups = n ** 3 * steps / sec / 1e6
+    bps = 152 if dtype == "f32s" else 304
+    return {"sites": f"{n}^3", "storage": dtype, "steps": steps, "variant": best,
+            "MLUPS": round(mlups, 1), "GB/s": round(mlups * bps / 1e3, 1),
+            "frac_hbm": round(mlups * bps / 1e3 / HBM_PEAK_GBS, 4)}
+
+
 def copy_bandwidth(torch, nbytes=1 << 30):
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
@@ -246,6 +281,8 @@ def main():
         return run_flowmap(args)
     if args.aux:
         return run_aux()
+    if args.precision:
+        return run_precision()
     if not torch.cuda.is_available():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(2)
@@ -307,7 +344,7 @@ def main():
         out["cases"] = cases
     if args.sweep:
         progress("25-cavity sweep: batch vs sequential")
-        out["sweep"] = time_sweep(lbm, torch, sweep_cases(nx), "f32s", 5000)
+        out["sweep"] = time_sweep(lbm, torch, sweep_cases(nx), "f32s", args.sweep_steps)
     if args.tts:
         from paper_2211_05009_amd import warmstart
         from cavity_inputs import normal_draws
@@ -319,6 +356,10 @@ def main():
         out["sweep_time_to_steady"] = warmstart.steady_sweep_study(
             normal_draws(npar, seed=0), threshold=args.tts_threshold, epochs=args.tts_epochs,
             modes=tuple(args.tts_modes.split(",")), dtype=args.tts_dtype, log=progress)
+    if args.cube:
+        progress("D3Q19 box")
+        out["cube"] = [time_cube(lbm, torch, n, dt, k) for n, dt, k in
+                       ((256, "f32s", 2000), (192, "f64", 1000))]
     if args.long:
         from paper_2211_05009_amd import flowmap
         progress("long unsteady cavity with probes")
@@ -328,6 +369,49 @@ def main():
         progress("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(nx, ny, args.re, args.cpu_steps)
     print(json.dumps(out), flush=True)
+
+
+def run_precision():
+    """Error of the FP32 f - w storage against FP64 for each reported result
+    (velocity field, mass, Eq. 6 residual, Psi maximum, the observing point's
+    velocity), on the nine 500 x (500 Ar) cavities.  The FP64 path matches
+    the CPU oracle to 1e-12 (the parity tests), so it stands in for it at
+    these sizes.  Beyond about a thousand steps the unsteady cavities
+    (Re >= 4500) amplify any rounding difference, so their 200 k-step figures
+    measure trajectory divergence, not accuracy."""
+    import numpy as np
+    from paper_2211_05009_amd import lbm
+    from paper_2211_05009_amd.flowmap import observing_point
+    rows = []
+    for ar in (0.4, 1.0, 2.0):
+        for re in (1000.0, 4000.0, 8000.0):
+            nx, ny = 500, int(round(500 * ar))
+            progress(f"precision {nx}x{ny} Re {re:g}")
+            h = {dt: lbm.Cavity(nx, ny, re=re, u_lid=0.1, dtype=dt) for dt in ("f64", "f32s")}
+            pt = np.array([observing_point(ar)])
+            done = 0
+            for horizon in (1000, 200000):
+                for c in h.values():
+                    c.step(horizon - done)
+                done = horizon
+                m = {dt: c.moments() for dt, c in h.items()}
+                du = max(np.abs(m["f32s"][1] - m["f64"][1]).max(),
+                         np.abs(m["f32s"][2] - m["f64"][2]).max())
+                psi = {dt: c.stream_function().max() for dt, c in h.items()}
+                pr = {dt: c.probe(pt)[0] for dt, c in h.items()}
+                res = {dt: c.residual()[0] for dt, c in h.items()}
+                rows.append({"nx": nx, "ny": ny, "re": re, "steps": horizon,
+                             "max_du_over_U": float(du / 0.1),
+                             "max_drho": float(np.abs(m["f32s"][0] - m["f64"][0]).max()),
+                             "mass_rel": float(abs(h["f32s"].mass() - h["f64"].mass())
+                                               / (nx * ny)),
+                             "residual": [float(res["f64"]), float(res["f32s"])],
+                             "psi_max_rel": float(abs(psi["f32s"] - psi["f64"]) / psi["f64"]),
+                             "probe_du_over_U": float(np.abs(pr["f32s"][1:] - pr["f64"][1:]).max()
+                                                      / 0.1)})
+            for c in h.values():
+                c.close()
+    print(json.dumps({"precision": rows}), flush=True)
 
 
 def run_aux():

@@ -438,6 +438,10 @@ int lbm_batch_set_threshold(lbm_batch_t b, double residual);
 /* Switch cavity k on or off; only at a multiple of 100 batch steps. */
 int lbm_batch_set_active(lbm_batch_t b, int k, int active);
 
+/* The last Eq. 6 residual of every cavity, residuals_host[n] (+inf where
+ * none or not valid); the values lbm_batch_status reports one by one. */
+int lbm_batch_residuals(lbm_batch_t b, double *residuals_host);
+
 /* Per-cavity state: steps applied to it, last Eq. 6 residual (+inf if none
  * or not valid), the step of that monitor (-1 if none), active flag.
  * NULL outputs are skipped. */
@@ -609,6 +613,53 @@ int lbm_nn_pool2(int backward, int n, int h, int w, int c, const void *in,
  * slice (is, io) of [n][2h][2w] into dense [n][h][w][c]. */
 int lbm_nn_up2(int backward, int n, int h, int w, int c, const void *in,
                int is, int io, void *out, int os, int oo, void *stream);
+
+/* ------------------------------------------------------------------------
+ * 3-D lid-driven box (D3Q19), the extension Sec. 4 names as future work.
+ *
+ * The same method on the D3Q19 set (weights 1/3, 1/18, 1/36; c_s^2 = 1/3):
+ * nx x ny x nz sites, half-way bounce-back on all six faces, the lid above
+ * the top row y = ny - 1 moving with (u_lid, 0, 0) and owning every link
+ * through its plane (links 8 = (-1,-1,0) and 9 = (1,-1,0) pick up -/+ u_lid/6),
+ * tau = 3 u_lid nx / re + 1/2.  Velocity order:
+ *   0 (0,0,0); 1 (1,0,0) 2 (-1,0,0) 3 (0,1,0) 4 (0,-1,0) 5 (0,0,1) 6 (0,0,-1)
+ *   7 (1,1,0) 8 (-1,-1,0) 9 (1,-1,0) 10 (-1,1,0) 11 (1,0,1) 12 (-1,0,-1)
+ *   13 (1,0,-1) 14 (-1,0,1) 15 (0,1,1) 16 (0,-1,-1) 17 (0,1,-1) 18 (0,-1,1).
+ * Host arrays are [nz][ny][nx] doubles (populations [19][nz][ny][nx]).
+ * Storage LBM_F64 or LBM_F32_SHIFTED as in two dimensions; monitors (mass,
+ * Eq. 6 over the three velocity components) every 100 steps in FP64; aligned
+ * 100-step chunks replayed from HIP graphs.  Options LBM_OPT_USE_GRAPH,
+ * LBM_OPT_STEP_VARIANT (3 tile shapes 64 x {1, 2, 4}), LBM_OPT_NUM_VARIANTS,
+ * LBM_OPT_STEPS_PER_LAUNCH (1).
+ * ------------------------------------------------------------------------ */
+typedef struct lbm_cube *lbm3d_t;
+
+/* Create a box at rest.  Errors: LBM_EINVAL for a side outside [2, 4096],
+ * re <= 0, tau <= 1/2, |u_lid| >= 1/sqrt(3), unknown dtype, or a box whose
+ * 19 planes exceed 2^31 elements; LBM_ENOMEM / LBM_EDEVICE. */
+int lbm3d_create(int nx, int ny, int nz, double re, double u_lid, int dtype, lbm3d_t *out);
+int lbm3d_destroy(lbm3d_t h);
+int lbm3d_set_stream(lbm3d_t h, void *hip_stream);
+int lbm3d_set_option(lbm3d_t h, int option, int64_t value);
+int lbm3d_get_option(lbm3d_t h, int option, int64_t *value);
+/* Advance n >= 0 steps; LBM_EUNSTABLE if a monitor goes non-finite. */
+int lbm3d_step(lbm3d_t h, int64_t n);
+int lbm3d_steps_done(lbm3d_t h, int64_t *steps);
+/* Eq. 6 from the last monitor (+inf if none or not 100 steps apart). */
+int lbm3d_residual(lbm3d_t h, double *residual, int64_t *at_step);
+/* sum rho over the box, FP64. */
+int lbm3d_mass(lbm3d_t h, double *mass);
+/* rho, u_x, u_y, u_z [nz][ny][nx] (host; NULL outputs skipped). */
+int lbm3d_moments(lbm3d_t h, double *rho_host, double *ux_host, double *uy_host,
+                  double *uz_host);
+/* Replace the state by f(t) [19][nz][ny][nx] (host, before the collision);
+ * the step counter restarts at 0. */
+int lbm3d_set_populations(lbm3d_t h, const double *f_host);
+/* Stored post-collision populations f*(t) [19][nz][ny][nx] (host). */
+int lbm3d_get_populations(lbm3d_t h, double *fstar_host);
+/* Time the tile shapes over `chunks` 100-step chunks (1..1000), keep the
+ * fastest; state, counters and the Eq. 6 reference are restored. */
+int lbm3d_autotune(lbm3d_t h, int chunks, int *best_variant, double *ms_per_step);
 
 #ifdef __cplusplus
 }

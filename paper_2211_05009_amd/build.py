@@ -23,7 +23,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbm.so")
 ARCH = "gfx950"
 
-SOURCES = ["lbm.hip", "lbm_batch.hip", "lbm_nn.hip", "lbm_series.hip"]
+SOURCES = ["lbm.hip", "lbm_batch.hip", "lbm_nn.hip", "lbm_series.hip", "lbm3d.hip"]
 
 
 def hipcc() -> str:

@@ -1,0 +1,226 @@
+// d3q19_step.hpp -- the fused D3Q19 lattice-BGK step of the lid-driven box
+// (the three-dimensional extension named as future work in Sec. 4 of arXiv
+// 2211.05009), and its FP64 monitors.
+//
+// Same method as the two-dimensional step (Eqs. 1-3, 5): pull streaming of
+// the post-collision populations, half-way bounce-back on all six faces, the
+// lid above the top row y = ny - 1 moving with (u_lid, 0, 0) and owning every
+// link through its plane, BGK collision towards the second-order equilibrium
+// with the D3Q19 weights 1/3, 1/18, 1/36.  Stored state: f*(t).
+//
+// Layout: 19 planes of nz x ny x pitch elements (pitch = nx rounded up to
+// 64), plane i at element offset i * plane; a 64-lane wavefront covers 64
+// consecutive x of one row.  SHIFT storage holds g = f - w in FP32.
+//
+// Velocity order (each odd index followed by its opposite):
+//   0 (0,0,0); 1 (1,0,0) 2 (-1,0,0) 3 (0,1,0) 4 (0,-1,0) 5 (0,0,1) 6 (0,0,-1)
+//   7 (1,1,0) 8 (-1,-1,0) 9 (1,-1,0) 10 (-1,1,0) 11 (1,0,1) 12 (-1,0,-1)
+//   13 (1,0,-1) 14 (-1,0,1) 15 (0,1,1) 16 (0,-1,-1) 17 (0,1,-1) 18 (0,-1,1)
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "d2q9_monitor.hpp"
+#include "d2q9_step.hpp"
+
+namespace lbm {
+
+__device__ __forceinline__ int cx19(int i) {
+  constexpr int v[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+  return v[i];
+}
+__device__ __forceinline__ int cy19(int i) {
+  constexpr int v[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+  return v[i];
+}
+__device__ __forceinline__ int cz19(int i) {
+  constexpr int v[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+  return v[i];
+}
+__device__ __forceinline__ int opp19(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+__device__ __forceinline__ double w19(int i) {
+  return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+template <typename T>
+struct Step3Params {
+  const T *__restrict__ src;
+  T *__restrict__ dst;
+  int nx, ny, nz, pitch;
+  int plane;        // elements per population plane
+  int tiles_x, tiles_y;
+  T omega, u6;      // 1/tau, u_lid / 6 (the lid term of links 8 and 9)
+};
+
+// Collide one site: f[19] in (after streaming; g = f - w for SHIFT), out the
+// post-collision values.
+template <typename T, bool SHIFT>
+__device__ __forceinline__ void bgk_collide19(T (&f)[19], T omega) {
+  T s = T(0), jx = T(0), jy = T(0), jz = T(0);
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    s += f[i];
+    jx += T(cx19(i)) * f[i];
+    jy += T(cy19(i)) * f[i];
+    jz += T(cz19(i)) * f[i];
+  }
+  const T rho = SHIFT ? T(1) + s : s;
+  const T rinv = recip<T>(rho);
+  const T ux = jx * rinv, uy = jy * rinv, uz = jz * rinv;
+  const T usq = T(1.5) * (ux * ux + uy * uy + uz * uz);
+  const T base = SHIFT ? s : rho;   // the "1" term times rho, less w in SHIFT form
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const T w = T(w19(i));
+    const T cu = T(cx19(i)) * ux + T(cy19(i)) * uy + T(cz19(i)) * uz;
+    const T feq = w * base + (w * rho) * (T(3) * cu + T(4.5) * cu * cu - usq);
+    f[i] += omega * (feq - f[i]);
+  }
+}
+
+// One step: block 64 x BY threads = one tile of 64 x BY sites of one z
+// plane; blocks are ordered tile-x fastest, then tile-y, then z, and handed
+// to XCDs in contiguous ranges.
+template <typename T, bool SHIFT, int BY>
+__global__ __launch_bounds__(64 * BY) void k_step3(Step3Params<T> p) {
+  const int b = xcd_tile(blockIdx.x, gridDim.x);
+  const int per_z = p.tiles_x * p.tiles_y;
+  const int z = b / per_z, r = b - z * per_z;
+  const int ty = r / p.tiles_x, tx = r - ty * p.tiles_x;
+  const int x = tx * 64 + threadIdx.x, y = ty * BY + threadIdx.y;
+  if (x >= p.nx || y >= p.ny || z >= p.nz) return;
+  const int rowp = p.pitch, slab = p.pitch * p.ny;
+  const int o = z * slab + y * rowp + x;
+  T f[19];
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const int xs = x - cx19(i), ys = y - cy19(i), zs = z - cz19(i);
+    if (xs >= 0 && xs < p.nx && ys >= 0 && ys < p.ny && zs >= 0 && zs < p.nz) {
+      f[i] = p.src[i * p.plane + o - cx19(i) - cy19(i) * rowp - cz19(i) * slab];
+    } else {
+      // reflected at the wall the link crosses: the reverse population of
+      // this site, plus the moving-wall term when the link crosses the lid
+      f[i] = p.src[opp19(i) * p.plane + o];
+      if (ys >= p.ny) {
+        if (i == 8) f[i] -= p.u6;        // -6 w_7 (c_7 . u_w) = -u/6
+        else if (i == 9) f[i] += p.u6;   // -6 w_10 (c_10 . u_w) = +u/6
+      }
+    }
+  }
+  bgk_collide19<T, SHIFT>(f, p.omega);
+#pragma unroll
+  for (int i = 0; i < 19; ++i) p.dst[i * p.plane + o] = f[i];
+}
+
+// FP64 moments of a stored site: drho = rho - 1, momentum j.
+template <typename T, bool SHIFT>
+__device__ __forceinline__ void site_moments19(const T *__restrict__ s, int plane, int o,
+                                               double &drho, double &jx, double &jy,
+                                               double &jz) {
+  double sum = 0.0, a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const double v = (double)s[i * plane + o];
+    sum += v;
+    a += cx19(i) * v;
+    b += cy19(i) * v;
+    c += cz19(i) * v;
+  }
+  drho = SHIFT ? sum : sum - 1.0;
+  jx = a;
+  jy = b;
+  jz = c;
+}
+
+// Monitor sums over the box (one site per thread, grid-stride): sum (rho - 1),
+// sum |u - u_ref|^2, sum |u_ref|^2; with UPDATE the reference field (dense
+// [3][n] FP64) becomes the current velocity.  Block partials [kNumSums] per
+// block, added in a fixed order by k_finalize.
+template <typename T, bool SHIFT, bool UPDATE>
+__global__ __launch_bounds__(kRedThreads) void k_monitor3(const T *__restrict__ s, int nx,
+                                                          int ny, int nz, int pitch, int plane,
+                                                          double *__restrict__ uref,
+                                                          double *__restrict__ partials) {
+  const long long n = (long long)nx * ny * nz;
+  double acc[kNumSums] = {0.0, 0.0, 0.0};
+  for (long long q = blockIdx.x * (long long)kRedThreads + threadIdx.x; q < n;
+       q += (long long)gridDim.x * kRedThreads) {
+    const int x = (int)(q % nx);
+    const long long yz = q / nx;
+    const int y = (int)(yz % ny), z = (int)(yz / ny);
+    double drho, jx, jy, jz;
+    site_moments19<T, SHIFT>(s, plane, (z * ny + y) * pitch + x, drho, jx, jy, jz);
+    const double rho = 1.0 + drho;
+    const double u[3] = {jx / rho, jy / rho, jz / rho};
+    acc[0] += drho;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double r = uref[a * n + q];
+      acc[1] += (u[a] - r) * (u[a] - r);
+      acc[2] += r * r;
+      if (UPDATE) uref[a * n + q] = u[a];
+    }
+  }
+  block_reduce_store<kNumSums>(acc, partials + blockIdx.x * kNumSums);
+}
+
+// Moments into dense [n] FP64 arrays (any may be null), n = nx ny nz,
+// index (z ny + y) nx + x.
+template <typename T, bool SHIFT>
+__global__ __launch_bounds__(256) void k_moments3(const T *__restrict__ s, int nx, int ny,
+                                                  int nz, int pitch, int plane,
+                                                  double *__restrict__ rho,
+                                                  double *__restrict__ ux,
+                                                  double *__restrict__ uy,
+                                                  double *__restrict__ uz) {
+  const long long n = (long long)nx * ny * nz;
+  const long long q = blockIdx.x * 256LL + threadIdx.x;
+  if (q >= n) return;
+  const int x = (int)(q % nx);
+  const long long yz = q / nx;
+  const int y = (int)(yz % ny), z = (int)(yz / ny);
+  double drho, jx, jy, jz;
+  site_moments19<T, SHIFT>(s, plane, (z * ny + y) * pitch + x, drho, jx, jy, jz);
+  const double r = 1.0 + drho;
+  if (rho) rho[q] = r;
+  if (ux) ux[q] = jx / r;
+  if (uy) uy[q] = jy / r;
+  if (uz) uz[q] = jz / r;
+}
+
+// Populations: set the stored state from f(t) (dense [19][n] FP64; collided
+// here so the stored state is f*(t)), or read the stored f*(t) back.
+template <typename T, bool SHIFT>
+__global__ __launch_bounds__(256) void k_set_pop3(T *__restrict__ d, int nx, int ny, int nz,
+                                                  int pitch, int plane,
+                                                  const double *__restrict__ f, double omega) {
+  const long long n = (long long)nx * ny * nz;
+  const long long q = blockIdx.x * 256LL + threadIdx.x;
+  if (q >= n) return;
+  const int x = (int)(q % nx);
+  const long long yz = q / nx;
+  const int y = (int)(yz % ny), z = (int)(yz / ny);
+  double g[19];
+#pragma unroll
+  for (int i = 0; i < 19; ++i) g[i] = f[i * n + q] - (SHIFT ? w19(i) : 0.0);
+  bgk_collide19<double, SHIFT>(g, omega);
+  const int o = (z * ny + y) * pitch + x;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) d[i * plane + o] = (T)g[i];
+}
+
+template <typename T, bool SHIFT>
+__global__ __launch_bounds__(256) void k_get_pop3(const T *__restrict__ s, int nx, int ny,
+                                                  int nz, int pitch, int plane,
+                                                  double *__restrict__ f) {
+  const long long n = (long long)nx * ny * nz;
+  const long long q = blockIdx.x * 256LL + threadIdx.x;
+  if (q >= n) return;
+  const int x = (int)(q % nx);
+  const long long yz = q / nx;
+  const int y = (int)(yz % ny), z = (int)(yz / ny);
+  const int o = (z * ny + y) * pitch + x;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) f[i * n + q] = (double)s[i * plane + o] + (SHIFT ? w19(i) : 0.0);
+}
+
+}  // namespace lbm

@@ -685,6 +685,13 @@ int lbm_batch_status(lbm_batch_t b, int k, int64_t *steps_done, double *residual
   return LBM_OK;
 }
 
+int lbm_batch_residuals(lbm_batch_t b, double *residuals) {
+  if (!b || !residuals) return lbm_fail(LBM_EINVAL, "NULL argument");
+  for (int k = 0; k < b->n; ++k)
+    residuals[k] = b->mon_t[k] >= 0 ? b->last_res[k] : INFINITY;
+  return LBM_OK;
+}
+
 int lbm_batch_mass(lbm_batch_t b, int k, double *mass) {
   if (!valid_k(b, k) || !mass) return lbm_fail(LBM_EINVAL, "bad cavity index or NULL");
   if (b->dtype == LBM_F64) launch_ref_monitor<double, false>(b, k, false);

@@ -98,6 +98,20 @@ SIGNATURES = {
     "lbm_probe_classify": [_h, ct.c_int, _i64, ct.c_double, ct.c_double, ct.c_int, ct.c_int,
                            ct.c_void_p],
     "lbm_vortex_extrema": [_h, ct.c_void_p],
+    "lbm3d_create": [ct.c_int, ct.c_int, ct.c_int, ct.c_double, ct.c_double, ct.c_int,
+                     ct.POINTER(_h)],
+    "lbm3d_destroy": [_h],
+    "lbm3d_set_stream": [_h, ct.c_void_p],
+    "lbm3d_set_option": [_h, ct.c_int, _i64],
+    "lbm3d_get_option": [_h, ct.c_int, ct.POINTER(_i64)],
+    "lbm3d_step": [_h, _i64],
+    "lbm3d_steps_done": [_h, ct.POINTER(_i64)],
+    "lbm3d_residual": [_h, ct.POINTER(ct.c_double), ct.POINTER(_i64)],
+    "lbm3d_mass": [_h, ct.POINTER(ct.c_double)],
+    "lbm3d_moments": [_h, ct.c_void_p, ct.c_void_p, ct.c_void_p, ct.c_void_p],
+    "lbm3d_set_populations": [_h, ct.c_void_p],
+    "lbm3d_get_populations": [_h, ct.c_void_p],
+    "lbm3d_autotune": [_h, ct.c_int, ct.POINTER(ct.c_int), ct.POINTER(ct.c_double)],
     "lbm_vortex_centres": [_h, ct.c_double, ct.c_int, ct.c_void_p, ct.POINTER(ct.c_int)],
     "lbm_bottom_vortex_count": [_h, ct.c_double, ct.POINTER(ct.c_int)],
     "lbm_set_populations": [_h, ct.c_void_p],
@@ -129,6 +143,7 @@ SIGNATURES = {
     "lbm_batch_init_fields_device": [_h, ct.c_int, ct.c_void_p, ct.c_void_p, ct.c_void_p,
                                      ct.c_int],
     "lbm_batch_cavity": [_h, ct.c_int, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int), _dp, _dp],
+    "lbm_batch_residuals": [_h, ct.c_void_p],
     "lbm_batch_probe_config": [_h, ct.c_int, ct.c_void_p, _i64],
     "lbm_batch_probe_read": [_h, ct.c_int, ct.c_void_p, _i64, ct.POINTER(_i64),
                              ct.POINTER(_i64)],
@@ -538,6 +553,12 @@ def lbm_batch_init_fields_device(b, k, rho, ux, uy, renormalise_mass=True,
                                              _init_flags(renormalise_mass, zero_staggered)))
 
 
+def lbm_batch_residuals(b, n):
+    r = np.empty(int(n))
+    _check(_lib.lbm_batch_residuals(b, _ptr(r)))
+    return r
+
+
 def lbm_batch_probe_config(b, xy, capacity):
     """xy: [n, npts, 2] points in units of L (npts = 0 removes the probes)."""
     xy = np.ascontiguousarray(xy, dtype=np.float64)
@@ -851,6 +872,9 @@ class Batch:
     def autotune(self, chunks=2, use_cache=True):
         return lbm_batch_autotune(self.b, chunks, use_cache)
 
+    def residuals(self):
+        return lbm_batch_residuals(self.b, len(self.nx))
+
     def probe_config(self, xy, capacity):
         self.probe_npts = lbm_batch_probe_config(self.b, xy, capacity)
 
@@ -910,3 +934,126 @@ class Surrogate:
 
     def warm_start_batch(self, batch, k):
         lbm_sur_warm_start_batch(self.s, batch.b, k)
+
+
+# ---------------------------------------------------------------- 3-D box
+def lbm3d_create(nx, ny, nz, re, u_lid, dtype):
+    h = _h()
+    _check(_lib.lbm3d_create(int(nx), int(ny), int(nz), float(re), float(u_lid),
+                             DTYPES.get(dtype, dtype), ct.byref(h)))
+    return h
+
+
+def lbm3d_destroy(h):
+    _check(_lib.lbm3d_destroy(h))
+
+
+def lbm3d_set_stream(h, stream):
+    _check(_lib.lbm3d_set_stream(h, _stream_ptr(stream)))
+
+
+def lbm3d_set_option(h, option, value):
+    _check(_lib.lbm3d_set_option(h, int(option), int(value)))
+
+
+def lbm3d_get_option(h, option):
+    v = _i64()
+    _check(_lib.lbm3d_get_option(h, int(option), ct.byref(v)))
+    return v.value
+
+
+def lbm3d_step(h, n):
+    _check(_lib.lbm3d_step(h, int(n)))
+
+
+def lbm3d_steps_done(h):
+    v = _i64()
+    _check(_lib.lbm3d_steps_done(h, ct.byref(v)))
+    return v.value
+
+
+def lbm3d_residual(h):
+    r, t = ct.c_double(), _i64()
+    _check(_lib.lbm3d_residual(h, ct.byref(r), ct.byref(t)))
+    return r.value, t.value
+
+
+def lbm3d_mass(h):
+    m = ct.c_double()
+    _check(_lib.lbm3d_mass(h, ct.byref(m)))
+    return m.value
+
+
+def lbm3d_moments(h, nx, ny, nz):
+    out = [np.empty((nz, ny, nx)) for _ in range(4)]
+    _check(_lib.lbm3d_moments(h, *[_ptr(a) for a in out]))
+    return tuple(out)
+
+
+def lbm3d_set_populations(h, f, nx, ny, nz):
+    f = np.ascontiguousarray(f, dtype=np.float64)
+    if f.shape != (19, nz, ny, nx):
+        raise ValueError(f"populations must be [19, {nz}, {ny}, {nx}]")
+    _check(_lib.lbm3d_set_populations(h, _ptr(f)))
+
+
+def lbm3d_get_populations(h, nx, ny, nz):
+    f = np.empty((19, nz, ny, nx))
+    _check(_lib.lbm3d_get_populations(h, _ptr(f)))
+    return f
+
+
+def lbm3d_autotune(h, chunks=5):
+    best, ms = ct.c_int(), ct.c_double()
+    _check(_lib.lbm3d_autotune(h, int(chunks), ct.byref(best), ct.byref(ms)))
+    return best.value, ms.value
+
+
+class Cube:
+    """A D3Q19 lid-driven box on the GPU (one library handle)."""
+
+    def __init__(self, nx, ny, nz, re, u_lid=0.1, dtype="f64"):
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.h = lbm3d_create(nx, ny, nz, re, u_lid, dtype)
+
+    def close(self):
+        if self.h:
+            lbm3d_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n):
+        lbm3d_step(self.h, n)
+        return self
+
+    def moments(self):
+        return lbm3d_moments(self.h, self.nx, self.ny, self.nz)
+
+    def mass(self):
+        return lbm3d_mass(self.h)
+
+    def residual(self):
+        return lbm3d_residual(self.h)
+
+    def steps_done(self):
+        return lbm3d_steps_done(self.h)
+
+    def set_populations(self, f):
+        lbm3d_set_populations(self.h, f, self.nx, self.ny, self.nz)
+
+    def get_populations(self):
+        return lbm3d_get_populations(self.h, self.nx, self.ny, self.nz)
+
+    def set_option(self, option, value):
+        lbm3d_set_option(self.h, option, value)
+
+    def get_option(self, option):
+        return lbm3d_get_option(self.h, option)
+
+    def autotune(self, chunks=5):
+        return lbm3d_autotune(self.h, chunks)

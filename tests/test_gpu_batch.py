@@ -85,6 +85,7 @@ def test_batch_deactivates_converged_cavities(lbm):
     b.step(30000)
     s0, s1 = b.status(0), b.status(1)
     assert not s0["active"] and s0["residual"] < 1e-7
+    assert list(b.residuals()) == [s0["residual"], s1["residual"]]
     assert s0["steps_done"] % 100 == 0 and s0["steps_done"] < 30000
     assert s1["steps_done"] > s0["steps_done"]
     c = lbm.Cavity(16, 16, re=5.0, u_lid=U_LID, dtype="f64")

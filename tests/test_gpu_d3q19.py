@@ -1,0 +1,119 @@
+"""GPU D3Q19 lid-driven box (lbm3d_*) against the D3Q19 oracle
+(oracle/d3q19.py): populations and moments after hundreds of steps, every
+tile shape bit-identical, monitors, symmetry."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import d3q19 as D
+
+pytestmark = pytest.mark.gpu
+U = 0.1
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("needs a GPU")
+    from paper_2211_05009_amd import lbm as m
+    return m
+
+
+def _pair(lbm, shape, re, dtype, seed):
+    nx, ny, nz = shape
+    ref = D.Cube(nx, ny, nz, re=re, u_lid=U)
+    c = lbm.Cube(nx, ny, nz, re=re, u_lid=U, dtype=dtype)
+    if seed is not None:
+        rng = np.random.default_rng(seed)
+        ref.set_state(ref.f + rng.uniform(-4e-3, 4e-3, ref.f.shape))
+        c.set_populations(ref.f)
+    return ref, c
+
+
+@pytest.mark.parametrize("shape,re,steps,seed", [((67, 9, 5), 60.0, 300, None),
+                                                 ((3, 3, 3), 5.0, 250, 1),
+                                                 ((20, 17, 11), 100.0, 200, 2),
+                                                 ((2, 66, 4), 20.0, 150, 3)])
+def test_fp64_parity_and_shapes(lbm, shape, re, steps, seed):
+    ref, c = _pair(lbm, shape, re, "f64", seed)
+    f0 = ref.f.copy()
+    ref.step(steps)
+    r0, u0, v0, w0 = ref.moments()
+    fs0 = ref.post_collision()
+    outs = []
+    for v in range(c.get_option(lbm.LBM_OPT_NUM_VARIANTS)):
+        c.set_option(lbm.LBM_OPT_STEP_VARIANT, v)
+        c.set_populations(f0)
+        c.step(steps)
+        r, u, vv, w = c.moments()
+        assert np.abs(r - r0).max() <= 1e-12
+        assert max(np.abs(u - u0).max(), np.abs(vv - v0).max(), np.abs(w - w0).max()) <= 1e-12 * U
+        outs.append(c.get_populations())
+        assert np.abs(outs[-1] - fs0).max() <= 1e-12
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    c.close()
+
+
+def test_fp32_parity(lbm):
+    ref, c = _pair(lbm, (33, 20, 7), 200.0, "f32s", 4)
+    ref.step(300)
+    c.step(300)
+    _, u0, v0, w0 = ref.moments()
+    _, u, v, w = c.moments()
+    assert max(np.abs(u - u0).max(), np.abs(v - v0).max(), np.abs(w - w0).max()) <= 1e-5 * U
+    c.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32s"])
+def test_graph_direct_and_monitors(lbm, dtype):
+    """Graph replay and direct launches agree bit for bit; mass and the
+    Eq. 6 residual equal their definitions on the library's own moments."""
+    nx, ny, nz = 40, 30, 12
+    a = lbm.Cube(nx, ny, nz, re=400.0, u_lid=U, dtype=dtype)
+    b = lbm.Cube(nx, ny, nz, re=400.0, u_lid=U, dtype=dtype)
+    b.set_option(lbm.LBM_OPT_USE_GRAPH, 0)
+    a.step(1900)
+    b.step(1900)
+    assert np.array_equal(a.get_populations(), b.get_populations())
+    _, u1, v1, w1 = a.moments()
+    a.step(100)
+    b.step(37)
+    b.step(63)
+    assert a.residual() == b.residual()
+    r2, u2, v2, w2 = a.moments()
+    num = math.fsum(((u2 - u1) ** 2 + (v2 - v1) ** 2 + (w2 - w1) ** 2).ravel().tolist())
+    den = math.fsum((u1 ** 2 + v1 ** 2 + w1 ** 2).ravel().tolist())
+    res, at = a.residual()
+    assert at == 2000 and abs(res - math.sqrt(num / den)) <= 1e-12 * res
+    assert abs(a.mass() - math.fsum(r2.ravel().tolist())) <= 1e-12 * nx * ny * nz
+    a.close()
+    b.close()
+
+
+def test_mirror_symmetry_in_z(lbm):
+    c = lbm.Cube(24, 20, 9, re=300.0, u_lid=U, dtype="f64")
+    c.step(1500)
+    r, u, v, w = c.moments()
+    assert np.abs(u - u[::-1]).max() <= 1e-14 and np.abs(w + w[::-1]).max() <= 1e-14
+    c.close()
+
+
+def test_autotune_keeps_the_state(lbm):
+    c = lbm.Cube(64, 48, 32, re=500.0, u_lid=U, dtype="f32s")
+    c.step(200)
+    f = c.get_populations()
+    best, ms = c.autotune(2)
+    assert 0 <= best < 3 and ms > 0 and c.steps_done() == 200
+    assert np.array_equal(c.get_populations(), f)
+    c.close()
+
+
+def test_errors(lbm):
+    for args in ((1, 4, 4, 100.0, U, "f64"), (4, 4, 4, -1.0, U, "f64"), (4, 4, 4, 100.0, 0.7, "f64"),
+                 (4, 4, 4, 100.0, U, 9)):
+        with pytest.raises(lbm.LbmError) as e:
+            lbm.lbm3d_create(*args)
+        assert e.value.code == lbm.LBM_EINVAL
