@@ -260,6 +260,11 @@ typedef struct {
   double amplitude;   /* max - min over the window */
   double mean, std;   /* over the window */
   double mismatch;    /* see above; 0 when steady */
+  double cycle;       /* dominant cycle: the refined lag of the first
+                         candidate whatever its mismatch (samples; 0 if none);
+                         a modulated oscillation repeats exactly (period)
+                         only after several cycles */
+  double cycle_mismatch;  /* the mismatch at that candidate (+inf if none) */
 } lbm_flow_state_t;
 
 /*

@@ -24,7 +24,11 @@ definition used here (and by the library) is:
 Returns a dict: state ("steady", "periodic", "drift", "aperiodic"), lag (the
 integer lag, periodic only), period (samples; 0 unless periodic), amplitude,
 mean, std, mismatch (at the chosen candidate; for an aperiodic series the
-smallest over all candidates; inf for a drift).
+smallest over all candidates; inf for a drift), and the dominant cycle:
+cycle (the refined lag of the first candidate whatever its mismatch, in
+samples; 0 if none) with cycle_mismatch.  A modulated oscillation repeats
+exactly only after several cycles: its period is that repeat, its cycle the
+oscillation itself.
 
 The parabola models D near a period well when the period spans a dozen or
 more samples; a period of a few samples can come out as a multiple of itself.
@@ -52,7 +56,7 @@ def classify(u, steady_tol, periodic_tol, min_lag=1, max_lag=None):
     mean = float(u.mean())
     std = float(u.std())
     out = {"state": "steady", "lag": 0, "period": 0.0, "amplitude": amp, "mean": mean,
-           "std": std, "mismatch": 0.0}
+           "std": std, "mismatch": 0.0, "cycle": 0.0, "cycle_mismatch": 0.0}
     if amp <= steady_tol:
         return out
     if max_lag is None:
@@ -72,9 +76,13 @@ def classify(u, steady_tol, periodic_tol, min_lag=1, max_lag=None):
             period = lags[j] + 0.5 * (D[j - 1] - D[j + 1]) / curv
             vertex = D[j] - (D[j - 1] - D[j + 1]) ** 2 / (8.0 * curv)
         mismatch = math.sqrt(max(vertex, 0.0))
+        if best == math.inf:
+            out.update(cycle=period, cycle_mismatch=mismatch)
         best = min(best, mismatch)
         if mismatch <= periodic_tol:
             out.update(state="periodic", lag=lags[j], period=period, mismatch=mismatch)
             return out
     out.update(state="drift" if best == math.inf else "aperiodic", mismatch=best)
+    if best == math.inf:
+        out["cycle_mismatch"] = math.inf
     return out

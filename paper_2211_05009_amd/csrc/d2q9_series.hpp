@@ -28,7 +28,7 @@ struct SeriesDesc {
 };
 
 struct SeriesOut {
-  double period, amplitude, mean, std, mismatch;
+  double period, amplitude, mean, std, mismatch, cycle, cycle_mismatch;
   int state, lag;
 };
 
@@ -91,6 +91,8 @@ static __global__ __launch_bounds__(kSeriesThreads) void k_classify_series(
   r.mean = mean;
   r.std = sd;
   r.mismatch = 0.0;
+  r.cycle = 0.0;
+  r.cycle_mismatch = 0.0;
   r.state = 0;
   r.lag = 0;
   if (amp <= steady_tol) {
@@ -126,6 +128,10 @@ static __global__ __launch_bounds__(kSeriesThreads) void k_classify_series(
       vertex = D[j] - (D[j - 1] - D[j + 1]) * (D[j - 1] - D[j + 1]) / (8.0 * curv);
     }
     const double mis = sqrt(fmax(vertex, 0.0));
+    if (best == INFINITY) {   // the first return: the dominant cycle
+      r.cycle = period;
+      r.cycle_mismatch = mis;
+    }
     best = fmin(best, mis);
     if (mis <= periodic_tol) {
       r.state = 1;
@@ -137,7 +143,10 @@ static __global__ __launch_bounds__(kSeriesThreads) void k_classify_series(
     }
   }
   r.mismatch = best;
-  if (best == INFINITY) r.state = 3;   // no return within the window: a drift
+  if (best == INFINITY) {   // no return within the window: a drift
+    r.state = 3;
+    r.cycle_mismatch = INFINITY;
+  }
   out[blockIdx.x] = r;
 }
 

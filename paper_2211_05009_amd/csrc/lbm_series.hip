@@ -55,6 +55,8 @@ int classify_series_descs(const SeriesDesc *descs_host, int nseries, long long n
     o.mean = res[s].mean;
     o.std = res[s].std;
     o.mismatch = res[s].mismatch;
+    o.cycle = res[s].cycle;
+    o.cycle_mismatch = res[s].cycle_mismatch;
   }
   return LBM_OK;
 }

@@ -38,8 +38,11 @@ def state_map(cases, nx=500, steps=3_000_000, window=10_000, dtype="f32s",
     100 steps, and classify u_x over the last `window` records.
 
     Returns a list of dicts: re, ar, nx, ny, state, period_steps (period x
-    100), amplitude and mean of u_x over the window (units of U), mismatch;
-    plus the run's wall time and aggregate MLUPS as a second value."""
+    100), cycle_steps and cycle_mismatch, amplitude and mean of u_x over the
+    window (units of U), mismatch;
+    plus the run's wall time and aggregate MLUPS as a second value.  The
+    dominant cycle (cycle_steps) is the first return of the lag mismatch,
+    also for modulated or aperiodic flows."""
     nxs = [nx] * len(cases)
     nys = [int(round(nx * ar)) for _, ar in cases]
     res = [re for re, _ in cases]
@@ -64,6 +67,8 @@ def state_map(cases, nx=500, steps=3_000_000, window=10_000, dtype="f32s",
         s = st[0]
         out.append({"re": re, "ar": ar, "nx": nx, "ny": ny, "state": s["state"],
                     "period_steps": round(100.0 * s["period"], 1),
+                    "cycle_steps": round(100.0 * s["cycle"], 1),
+                    "cycle_mismatch": s["cycle_mismatch"],
                     "amplitude_U": s["amplitude"] / U_LID, "mean_U": s["mean"] / U_LID,
                     "mismatch": s["mismatch"]})
     sites = sum(a * c for a, c in zip(nxs, nys))

@@ -334,12 +334,14 @@ class FlowState(ct.Structure):
     """lbm_flow_state_t."""
     _fields_ = [("state", ct.c_int), ("lag", ct.c_int), ("period", ct.c_double),
                 ("amplitude", ct.c_double), ("mean", ct.c_double), ("std", ct.c_double),
-                ("mismatch", ct.c_double)]
+                ("mismatch", ct.c_double), ("cycle", ct.c_double),
+                ("cycle_mismatch", ct.c_double)]
 
     def as_dict(self):
         return {"state": FLOW_STATES[self.state], "lag": self.lag, "period": self.period,
                 "amplitude": self.amplitude, "mean": self.mean, "std": self.std,
-                "mismatch": self.mismatch}
+                "mismatch": self.mismatch, "cycle": self.cycle,
+                "cycle_mismatch": self.cycle_mismatch}
 
 
 def lbm_classify_series(series_dev, steady_tol, periodic_tol, min_lag=1, max_lag=0,

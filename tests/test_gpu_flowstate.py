@@ -40,6 +40,7 @@ def _signals(n=3000):
         np.sin(2 * np.pi * k / 20) + np.sin(2 * np.pi * k * phi / 20),  # quasi-periodic
         1e-3 * k,                                                     # drift
         0.3 + 1e-4 * np.exp(-k / 2000.0),                             # approach
+        (1 + 0.2 * np.sin(2 * np.pi * k / 150)) * np.sin(2 * np.pi * k / 30),  # modulated
     ]
 
 
@@ -49,6 +50,11 @@ def _same(got, want):
     for key in ("amplitude", "mean", "std"):
         assert math.isclose(got[key], want[key], rel_tol=1e-12, abs_tol=1e-15), key
     assert math.isclose(got["period"], want["period"], rel_tol=1e-9, abs_tol=0)
+    assert math.isclose(got["cycle"], want["cycle"], rel_tol=1e-9, abs_tol=0)
+    if math.isinf(want["cycle_mismatch"]):
+        assert math.isinf(got["cycle_mismatch"])
+    else:
+        assert abs(got["cycle_mismatch"] - want["cycle_mismatch"]) <= 1e-7
     if math.isinf(want["mismatch"]):
         assert math.isinf(got["mismatch"])
     else:
@@ -64,7 +70,8 @@ def test_series_match_the_oracle(env, lags):
     for g, u in zip(got, sig):
         _same(g, F.classify(u, 1e-7, 0.02, min_lag=lags[0], max_lag=lags[1] or None))
     states = [g["state"] for g in got]
-    assert states == ["steady"] + ["periodic"] * 5 + ["aperiodic"] * 3 + ["drift"] * 2
+    assert states == ["steady"] + ["periodic"] * 5 + ["aperiodic"] * 3 + ["drift"] * 2 + \
+        ["periodic"]
 
 
 def test_strided_rows_and_errors(env):

@@ -48,6 +48,18 @@ def test_non_sinusoidal_and_period_doubled_signals():
     assert r["state"] == "periodic" and r["lag"] == 40
 
 
+def test_modulated_oscillation_cycle_and_period():
+    """A 30-sample oscillation whose amplitude repeats every 5 cycles: it
+    returns closely after one cycle (the dominant cycle) but exactly only
+    after five (the period)."""
+    u = (1 + 0.2 * np.sin(2 * np.pi * K / 150)) * np.sin(2 * np.pi * K / 30)
+    r = F.classify(u, 1e-7, 0.02)
+    assert r["state"] == "periodic" and r["lag"] == 150 and abs(r["period"] - 150) <= 0.01
+    assert abs(r["cycle"] - 30) <= 0.3 and 0.02 < r["cycle_mismatch"] < 0.5
+    s = F.classify(np.sin(2 * np.pi * K / 37.25), 1e-7, 0.02)
+    assert s["cycle"] == s["period"] and s["cycle_mismatch"] == s["mismatch"]
+
+
 def test_noisy_sinusoid_is_periodic():
     rng = np.random.default_rng(1)
     r = F.classify(np.sin(2 * np.pi * K / 63.7) + 1e-3 * rng.normal(size=K.size), 1e-7, 0.02)
