@@ -50,16 +50,21 @@ struct StepParams {
   T ulid = T(0);    // lid speed (non-equilibrium extrapolation walls)
 };
 
-// 1 / v for the collision: IEEE division in FP64; in FP32 the hardware
-// reciprocal (within 1 ulp), far inside the FP32 storage's own rounding and
-// about ten instructions shorter than the correctly rounded division.
+// 1 / v for the collision: IEEE division in FP64.  In FP32 the hardware
+// reciprocal estimate (within 1 ulp) refined by one Newton-Raphson step,
+// r <- r + r (1 - v r): the refined value is the correctly rounded
+// reciprocal but for rare last-bit ties, so u = j * (1/rho) rounds as it did
+// with the division, while taking two FMAs instead of the division's ten
+// instructions.  The unrefined estimate is not enough: its error has a
+// sign that repeats every step and shifts FP32 steady states by ~1e-5 U.
 template <typename T>
 __device__ __forceinline__ T recip(T v) {
   return T(1) / v;
 }
 template <>
 __device__ __forceinline__ float recip<float>(float v) {
-  return __builtin_amdgcn_rcpf(v);
+  const float r = __builtin_amdgcn_rcpf(v);
+  return __builtin_fmaf(__builtin_fmaf(-v, r, 1.0f), r, r);
 }
 
 // Collide one site.  f[0..8] in: populations after streaming (or their
