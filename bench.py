@@ -81,6 +81,9 @@ def parse():
                     help="run a flow-state map instead: 'fig17' (153 cavities) or "
                          "'Re1,Re2,...:Ar1,Ar2,...'; prints one JSON line")
     ap.add_argument("--flowmap-steps", type=int, default=3_000_000)
+    ap.add_argument("--large", type=int, default=1,
+                    help="also time the 4096 x 4096 Re = 1e4 cavity, FP32 and FP64, "
+                         "10,000 steps each (0: skip)")
     ap.add_argument("--cube", type=int, default=1,
                     help="also time the D3Q19 box: 256^3 FP32 and 192^3 FP64 (0: skip)")
     ap.add_argument("--aux", type=int, default=0,
@@ -356,6 +359,17 @@ def main():
         out["sweep_time_to_steady"] = warmstart.steady_sweep_study(
             normal_draws(npar, seed=0), threshold=args.tts_threshold, epochs=args.tts_epochs,
             modes=tuple(args.tts_modes.split(",")), dtype=args.tts_dtype, log=progress)
+    if args.large:
+        large = []
+        for dt in ("f32s", "f64"):
+            progress(f"4096 x 4096 {dt}")
+            sec, (v, k), _ = time_single(lbm, torch, 4096, 4096, 1e4, dt, 10000, 1000)
+            ml = 4096 * 4096 * 10000 / sec / 1e6
+            gbs = ml * BYTES_PER_SITE[dt] / 1e3
+            large.append({"nx": 4096, "ny": 4096, "re": 1e4, "storage": dt, "steps": 10000,
+                          "variant": v, "steps_per_launch": k, "MLUPS": round(ml, 1),
+                          "GB/s": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
+        out["large"] = large
     if args.cube:
         progress("D3Q19 box")
         out["cube"] = [time_cube(lbm, torch, n, dt, k) for n, dt, k in

@@ -37,6 +37,12 @@
  *   - work is issued on the handle's HIP stream (its own by default, see
  *     lbm_set_stream); every function that returns data to the host
  *     synchronises that stream before returning.
+ *
+ * Run log: when the environment variable LBM_LOG names a file at the first
+ * lbm_step / lbm_batch_step call, each such call appends one JSON line to it
+ * (kind, handle, lattice, steps of the call, step count, mass, last Eq. 6
+ * residual, wall seconds, MLUPS; batches: active cavities before and after,
+ * largest residual of the active ones).  Unset: nothing is written.
  */
 #ifndef LBM_H
 #define LBM_H

@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <mutex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -42,6 +44,37 @@ int lbm_fail(int code, const char *fmt, ...) {
   va_end(ap);
   g_lbm_err = buf;
   return code;
+}
+
+// ------------------------------------------------------------ run log
+// With $LBM_LOG naming a file, one JSON line is appended per lbm_step /
+// lbm_batch_step call (see lbm_log_line); the file is opened once, in append
+// mode, and written under a mutex.
+namespace {
+std::mutex g_log_mutex;
+FILE *g_log = nullptr;
+bool g_log_checked = false;
+}  // namespace
+
+void lbm_log_line(const char *fmt, ...) {
+  std::lock_guard<std::mutex> lock(g_log_mutex);
+  if (!g_log_checked) {
+    g_log_checked = true;
+    const char *path = std::getenv("LBM_LOG");
+    if (path && *path) g_log = std::fopen(path, "a");
+  }
+  if (!g_log) return;
+  va_list ap;
+  va_start(ap, fmt);
+  std::vfprintf(g_log, fmt, ap);
+  va_end(ap);
+  std::fputc('\n', g_log);
+  std::fflush(g_log);
+}
+
+double lbm_wall_seconds() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
+      .count();
 }
 
 // ------------------------------------------------------------ tune cache
@@ -608,10 +641,26 @@ static void note_monitor(lbm_cavity *h) {
   h->mon_t = h->t;
 }
 
+static int step_impl(lbm_t h, int64_t n);
+
 int lbm_step(lbm_t h, int64_t n) {
   if (!h) return lbm_fail(LBM_EINVAL, "handle is NULL");
   if (n < 0) return lbm_fail(LBM_EINVAL, "n = %lld < 0", (long long)n);
   if (n == 0) return LBM_OK;
+  const double t0 = lbm_wall_seconds();
+  const int rc = step_impl(h, n);
+  const double sec = lbm_wall_seconds() - t0;
+  lbm_log_line("{\"kind\": \"cavity\", \"handle\": \"%p\", \"nx\": %d, \"ny\": %d, "
+               "\"dtype\": %d, \"wall\": %d, \"steps\": %lld, \"step\": %lld, "
+               "\"mass\": %.17g, \"residual\": %.17g, \"residual_step\": %lld, "
+               "\"seconds\": %.6f, \"MLUPS\": %.1f, \"rc\": %d}",
+               (void *)h, h->nx, h->ny, h->dtype, h->wall, (long long)n, (long long)h->t,
+               h->last_mass, h->mon_t >= 0 ? h->last_res : INFINITY, (long long)h->mon_t, sec,
+               sec > 0 ? (double)h->nx * h->ny * n / sec / 1e6 : 0.0, rc);
+  return rc;
+}
+
+static int step_impl(lbm_t h, int64_t n) {
   bool monitored = false;
   hipError_t e;
   while (n > 0) {

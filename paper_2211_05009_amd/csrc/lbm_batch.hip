@@ -612,9 +612,37 @@ int lbm_batch_set_active(lbm_batch_t b, int k, int active) {
   return LBM_OK;
 }
 
+static int batch_step_impl(lbm_batch_t b, int64_t n);
+
 int lbm_batch_step(lbm_batch_t b, int64_t n) {
   if (!b) return lbm_fail(LBM_EINVAL, "batch is NULL");
   if (n < 0) return lbm_fail(LBM_EINVAL, "n = %lld < 0", (long long)n);
+  int active0 = 0;
+  long long sites = 0;
+  for (int c = 0; c < b->n; ++c)
+    if (b->active[c]) {
+      ++active0;
+      sites += (long long)b->nx[c] * b->ny[c];
+    }
+  const double t0 = lbm_wall_seconds();
+  const int rc = batch_step_impl(b, n);
+  const double sec = lbm_wall_seconds() - t0;
+  int active = 0;
+  double worst = 0.0;
+  for (int c = 0; c < b->n; ++c) {
+    active += b->active[c];
+    if (b->active[c] && b->mon_t[c] >= 0) worst = std::max(worst, b->last_res[c]);
+  }
+  lbm_log_line("{\"kind\": \"batch\", \"handle\": \"%p\", \"cavities\": %d, "
+               "\"active_before\": %d, \"active\": %d, \"steps\": %lld, \"step\": %lld, "
+               "\"max_active_residual\": %.17g, \"seconds\": %.6f, "
+               "\"MLUPS_upper\": %.1f, \"rc\": %d}",
+               (void *)b, b->n, active0, active, (long long)n, (long long)b->t_global, worst, sec,
+               sec > 0 ? (double)sites * n / sec / 1e6 : 0.0, rc);
+  return rc;
+}
+
+static int batch_step_impl(lbm_batch_t b, int64_t n) {
   bool monitored = false;
   while (n > 0) {
     if (b->tables_dirty) {

@@ -38,6 +38,12 @@ int classify_series_descs(const lbm::SeriesDesc *descs_host, int nseries, long l
                           double steady_tol, double periodic_tol, int min_lag, int max_lag,
                           hipStream_t st, lbm_flow_state_t *out_host);
 
+// Append one line (printf format, no newline) to the JSON-lines run log
+// named by $LBM_LOG; a no-op when it is unset.
+void lbm_log_line(const char *fmt, ...);
+// Monotonic wall clock in seconds.
+double lbm_wall_seconds();
+
 // Validate a series length and lag range (LBM_EINVAL with a message).
 int check_lags(long long n, int min_lag, int max_lag);
 

@@ -235,3 +235,35 @@ def test_cavity64_re100_golden(lbm, dtype):
         # FP32 storage adds rounding noise of ~1e-7 |u| to a 100-step change
         # of ~2e-7 |u|: only the order of magnitude is comparable
         assert 0.25 * g["residual_eq6"] <= r <= 4 * g["residual_eq6"]
+
+
+def test_run_log_jsonl(lbm, tmp_path):
+    """LBM_LOG: one JSON line per lbm_step / lbm_batch_step call, with the
+    monitors the handle reports.  Run in a child process, since the log is
+    opened at the process's first step."""
+    import subprocess
+    import sys
+    log = tmp_path / "run.jsonl"
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_2211_05009_amd import lbm\n"
+        "c = lbm.Cavity(40, 30, re=100.0, u_lid=0.1, dtype='f64')\n"
+        "c.step(250); c.step(50)\n"
+        "print(c.mass(), c.residual()[0], c.residual()[1])\n"
+        "b = lbm.Batch([20, 30], [20, 10], [50.0, 80.0], u_lid=0.1, dtype='f32s')\n"
+        "b.step(1000)\n"
+    ) % os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, LBM_LOG=str(log))
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                         timeout=120)
+    assert out.returncode == 0, out.stderr[-2000:]
+    mass, res, at = out.stdout.split()
+    lines = [json.loads(x) for x in log.read_text().splitlines()]
+    cav = [x for x in lines if x["kind"] == "cavity"]
+    bat = [x for x in lines if x["kind"] == "batch"]
+    assert [x["steps"] for x in cav] == [250, 50] and cav[-1]["step"] == 300
+    assert cav[-1]["residual_step"] == int(at) == 300
+    assert math.isclose(cav[-1]["residual"], float(res), rel_tol=1e-15)
+    assert abs(cav[-1]["mass"] - float(mass)) <= 1e-9
+    assert len(bat) == 1 and bat[0]["cavities"] == 2 and bat[0]["step"] == 1000
+    assert all(x["rc"] == 0 and x["seconds"] > 0 for x in lines)
