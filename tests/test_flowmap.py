@@ -28,3 +28,11 @@ def test_table3_fixture():
     rows = {k: v for k, v in t3.items() if k not in ("note", "re")}
     assert len(rows) == 11 and all(len(v) == 9 for v in rows.values())
     assert rows["0.6"][6] == 22.13 and rows["1.2"][4] == 31.16 and rows["0.4"][8] == 13.14
+
+
+def test_config_cli_usage():
+    """The per-workload runner rejects unknown configurations without
+    touching the device."""
+    from paper_2211_05009_amd import configs
+    assert configs.main([]) == 2 and configs.main(["9"]) == 2 and configs.main(["x"]) == 2
+    assert sorted(configs.RUNS) == [1, 2, 3, 4, 5]

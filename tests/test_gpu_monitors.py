@@ -267,3 +267,16 @@ def test_run_log_jsonl(lbm, tmp_path):
     assert abs(cav[-1]["mass"] - float(mass)) <= 1e-9
     assert len(bat) == 1 and bat[0]["cavities"] == 2 and bat[0]["step"] == 1000
     assert all(x["rc"] == 0 and x["seconds"] > 0 for x in lines)
+
+
+def test_config1_runner_matches_the_golden_file(lbm):
+    """python -m paper_2211_05009_amd.configs 1 reports the 64 x 64 Re 100
+    centre lines and mass of the golden file (written by the oracle)."""
+    from paper_2211_05009_amd import configs
+    out = configs.config1("f64")
+    g = json.load(open(os.path.join(GOLDEN, "cavity64_re100_20000.json")))
+    assert out["steps"] == 20000 and out["residual_step"] == 20000
+    assert np.max(np.abs(np.array(out["u_x_centre_over_U"]) * U_LID - g["u_centre"])) <= 1e-12 * U_LID
+    assert np.max(np.abs(np.array(out["u_y_centre_over_U"]) * U_LID - g["v_centre"])) <= 1e-12 * U_LID
+    assert abs(out["mass"][-1] - g["mass_every_1000"][-1]) <= 1e-9
+    assert abs(out["mass"][1] - g["mass_every_1000"][10]) <= 1e-9
