@@ -203,3 +203,32 @@ def test_square_cavity_against_table1(lbm, re):
     ghia = TABLE1[re]["a"]["primary"][0]
     assert abs(got["primary"].psi / scale - ghia) <= 0.03 * ghia
     c.close()
+
+
+def test_rectangular_cavity_against_table2_re4000(lbm):
+    """Physical check at the paper's production resolution: Ar = 1.2,
+    Re = 4000 (steady: Table 3 lists no period there) on 501 x 601 nodes
+    (L = 500) with the paper's walls, FP64, run to Eq. 6 < 1e-8 (about
+    4 M steps).  Table 2: Psi_max = 5.9998 (lattice units) at (0.518, 0.770),
+    two bottom vortices.  Measured 6.0040 at (0.518, 0.768): within 0.1 %
+    and one node.  The four vortex centres below the primary are two bottom
+    vortices (|Psi| 0.24 and 0.55) and two corner eddies (|Psi| <= 1.5e-3);
+    a floor of 1e-3 U L, below which Table 2's streamline plots show no
+    closed contour, gives the printed count."""
+    n = 501
+    c = lbm.Cavity(n, 601, re=4000.0, u_lid=U_LID, dtype="f64", wall="nee")
+    c.autotune(chunks=3)
+    for _ in range(30):
+        c.step(200_000)
+        if c.residual()[0] < 1e-8:
+            break
+    assert c.residual()[0] < 1e-8
+    p = c.vortex_extrema()[0]
+    print(f"Psi_max {p.psi:.4f} at ({p.x:.4f}, {p.y:.4f}); bottom vortices "
+          f"{c.bottom_vortex_count(1e-3 * U_LID * (n - 1))} (floor 1e-3 U L), "
+          f"{c.bottom_vortex_count(1e-9 * U_LID * (n - 1))} (floor 1e-9 U L)")
+    assert abs(p.psi - 5.9998) <= 1e-3 * 5.9998
+    node = 1.0 / (n - 1) + 1e-9
+    assert abs(p.x - 0.518) <= node and abs(p.y - 0.770) <= node
+    assert c.bottom_vortex_count(1e-3 * U_LID * (n - 1)) == 2
+    c.close()
