@@ -41,6 +41,14 @@ C = np.array([[0, 0], [1, 0], [0, 1], [-1, 0], [0, -1],
 W = np.array([4.0 / 9.0,
               1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
               1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0])
+# The same weights as whole 36ths, w_i = K36[i] / 36.  Eq. 2 is evaluated
+# with these (an exact integer multiple, then one correctly rounded division)
+# and with c_s^2 = 1/3 substituted (1/cs2 = 3, 1/(2 cs2^2) = 9/2, 1/(2 cs2) =
+# 3/2, all exact).  Multiplying by W itself would round every collision's
+# equilibrium the same way (the FP64 values of 4/9, 1/9 and 1/36 all lie
+# 5.6e-17 below the exact weights, relative), and over the 1e5-step
+# relaxation of a steady cavity that same-signed error adds up to ~1.5e-12 U.
+K36 = np.array([16, 4, 4, 4, 4, 1, 1, 1, 1], dtype=np.int64)
 # OPP[i] is the index of -c_i.
 OPP = np.array([0, 3, 4, 1, 2, 7, 8, 5, 6], dtype=np.int64)
 CS2 = 1.0 / 3.0   # c_s^2 = c^2 / 3 with c = 1
@@ -57,7 +65,8 @@ def relaxation_time(nx: int, re: float, u_lid: float) -> float:
 
 
 def equilibrium(rho, ux, uy):
-    """Eq. 2: f_i^eq = w_i rho [1 + c.u/cs2 + (c.u)^2/(2 cs2^2) - u.u/(2 cs2)]."""
+    """Eq. 2: f_i^eq = w_i rho [1 + c.u/cs2 + (c.u)^2/(2 cs2^2) - u.u/(2 cs2)],
+    with cs2 = 1/3: w_i rho [1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u], w_i = K36[i]/36."""
     rho = np.asarray(rho, dtype=np.float64)
     ux = np.asarray(ux, dtype=np.float64)
     uy = np.asarray(uy, dtype=np.float64)
@@ -65,8 +74,7 @@ def equilibrium(rho, ux, uy):
     feq = np.empty((9,) + rho.shape)
     for i in range(9):
         cu = C[i, 0] * ux + C[i, 1] * uy
-        feq[i] = W[i] * rho * (1.0 + cu / CS2 + cu * cu / (2.0 * CS2 * CS2)
-                               - uu / (2.0 * CS2))
+        feq[i] = K36[i] * (rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu)) / 36.0
     return feq
 
 
@@ -163,7 +171,7 @@ def stream(fs, u_lid=0.0, periodic_x=False, periodic_y=False, u_bottom=0.0,
         uwx[wall & (ys < 0)] = u_bottom
         # c_opp . u_w, with u_w = (uwx, 0)
         cu = C[j, 0] * uwx
-        out[i][wall] = fs[j][wall] - 6.0 * W[j] * 1.0 * cu[wall]
+        out[i][wall] = fs[j][wall] - (K36[j] * 1.0 * cu[wall]) / 6.0   # 6 w_j = K36[j] / 6
     return out
 
 

@@ -32,6 +32,11 @@ C = np.array([[0, 0, 0],
               [1, 0, 1], [-1, 0, -1], [1, 0, -1], [-1, 0, 1],
               [0, 1, 1], [0, -1, -1], [0, 1, -1], [0, -1, 1]], dtype=np.int64)
 W = np.array([1.0 / 3.0] + [1.0 / 18.0] * 6 + [1.0 / 36.0] * 12)
+# The weights as whole 36ths, w_i = K36[i] / 36: Eq. 2 multiplies by K36[i]
+# and divides by 36 once, with 1/cs2 = 3, 1/(2 cs2^2) = 9/2, 1/(2 cs2) = 3/2
+# exact, so no rounded weight biases every collision the same way (as in the
+# two-dimensional oracle).
+K36 = np.array([12] + [2] * 6 + [1] * 12, dtype=np.int64)
 OPP = np.array([0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17],
                dtype=np.int64)
 CS2 = 1.0 / 3.0
@@ -43,13 +48,14 @@ def relaxation_time(nx, re, u_lid):
 
 
 def equilibrium(rho, ux, uy, uz):
-    """Eq. 2 on the D3Q19 set."""
+    """Eq. 2 on the D3Q19 set, cs2 = 1/3 substituted:
+    w_i rho [1 + 3 c.u + 9/2 (c.u)^2 - 3/2 u.u], w_i = K36[i] / 36."""
     rho, ux, uy, uz = (np.asarray(a, dtype=np.float64) for a in (rho, ux, uy, uz))
     uu = ux * ux + uy * uy + uz * uz
     feq = np.empty((19,) + rho.shape)
     for i in range(19):
         cu = C[i, 0] * ux + C[i, 1] * uy + C[i, 2] * uz
-        feq[i] = W[i] * rho * (1.0 + cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2))
+        feq[i] = K36[i] * (rho * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu)) / 36.0
     return feq
 
 
@@ -84,7 +90,7 @@ def stream(fs, u_lid, periodic_x=False, periodic_z=False):
             continue
         j = OPP[i]
         uwx = np.where(wall & (ys >= ny), u_lid, 0.0)       # lid links first
-        out[i][wall] = fs[j][wall] - 6.0 * W[j] * (C[j, 0] * uwx[wall])
+        out[i][wall] = fs[j][wall] - (K36[j] * (C[j, 0] * uwx[wall])) / 6.0  # 6 w_j = K36[j]/6
     return out
 
 

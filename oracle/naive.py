@@ -24,13 +24,15 @@ def _reverse(i):
     return _VEL.index((-cx, -cy))
 
 
-def _feq_site(rho, ux, uy, wgt, one):
+def _feq_site(rho, ux, uy, one):
+    """Eq. 2 at one site; each weight a / b enters as a times the bracket,
+    divided by b (exact in rationals; in FP64 no rounded weight)."""
     out = []
     three = 3 * one
-    for (cx, cy), w in zip(_VEL, wgt):
+    for (cx, cy), a, b in zip(_VEL, _WGT_NUM, _WGT_DEN):
         cu = cx * ux + cy * uy
-        out.append(w * rho * (one + three * cu + (9 * one / 2) * cu * cu
-                              - (three / 2) * (ux * ux + uy * uy)))
+        out.append(a * (rho * (one + three * cu + (9 * one / 2) * cu * cu
+                               - (three / 2) * (ux * ux + uy * uy))) / b)
     return out
 
 
@@ -44,7 +46,6 @@ def naive_steps(f, tau, u_lid, nsteps, num=float):
     ny = len(f[0])
     nx = len(f[0][0])
     one = num(1)
-    wgt = [num(a) / num(b) for a, b in zip(_WGT_NUM, _WGT_DEN)]
     tau = num(tau)
     u_lid = num(u_lid)
     cur = [[[num(f[i][y][x]) for x in range(nx)] for y in range(ny)]
@@ -64,7 +65,7 @@ def naive_steps(f, tau, u_lid, nsteps, num=float):
                     jy += _VEL[i][1] * pops[i]
                 ux = jx / rho
                 uy = jy / rho
-                eq = _feq_site(rho, ux, uy, wgt, one)
+                eq = _feq_site(rho, ux, uy, one)
                 post = [pops[i] - (pops[i] - eq[i]) / tau for i in range(9)]
                 # push every population along its link
                 for i in range(9):
@@ -79,7 +80,8 @@ def naive_steps(f, tau, u_lid, nsteps, num=float):
                     else:
                         wall_u = num(0)       # bottom and side walls at rest
                     r = _reverse(i)
-                    nxt[r][y][x] = post[i] - 6 * wgt[i] * one * (cx * wall_u)
+                    # 6 w_i = 6 a / b
+                    nxt[r][y][x] = post[i] - 6 * _WGT_NUM[i] * one * (cx * wall_u) / _WGT_DEN[i]
         cur = nxt
     return cur
 
@@ -92,7 +94,6 @@ def naive_steps_nee(f, tau, u_lid, nsteps, num=float):
     ny = len(f[0])
     nx = len(f[0][0])
     one = num(1)
-    wgt = [num(a) / num(b) for a, b in zip(_WGT_NUM, _WGT_DEN)]
     tau = num(tau)
     u_lid = num(u_lid)
     cur = [[[num(f[i][y][x]) for x in range(nx)] for y in range(ny)]
@@ -113,7 +114,7 @@ def naive_steps_nee(f, tau, u_lid, nsteps, num=float):
             for x in range(nx):
                 pops = [cur[i][y][x] for i in range(9)]
                 rho, ux, uy = moments(pops)
-                eq = _feq_site(rho, ux, uy, wgt, one)
+                eq = _feq_site(rho, ux, uy, one)
                 for i in range(9):
                     tx, ty = x + _VEL[i][0], y + _VEL[i][1]
                     if fluid(tx, ty):
@@ -126,8 +127,8 @@ def naive_steps_nee(f, tau, u_lid, nsteps, num=float):
                 yr = min(max(y, 1), ny - 2)
                 ref = [nxt[i][yr][xr] for i in range(9)]
                 rho, ux, uy = moments(ref)
-                eq_ref = _feq_site(rho, ux, uy, wgt, one)
-                eq_wall = _feq_site(rho, u_lid if y == ny - 1 else num(0), num(0), wgt, one)
+                eq_ref = _feq_site(rho, ux, uy, one)
+                eq_wall = _feq_site(rho, u_lid if y == ny - 1 else num(0), num(0), one)
                 for i in range(9):
                     nxt[i][y][x] = eq_wall[i] + ref[i] - eq_ref[i]
         cur = nxt
@@ -148,7 +149,7 @@ def naive_steps_3d(f, tau, u_lid, nsteps, num=float):
     owning every link through its plane).  ``f`` is [19][nz][ny][nx]."""
     nz, ny, nx = len(f[0]), len(f[0][0]), len(f[0][0][0])
     one = num(1)
-    wgt = [num(1) / num(3)] + [num(1) / num(18)] * 6 + [num(1) / num(36)] * 12
+    den = [3] + [18] * 6 + [36] * 12          # weights 1/3, 1/18, 1/36
     tau, u_lid = num(tau), num(u_lid)
     cur = [[[[num(f[i][z][y][x]) for x in range(nx)] for y in range(ny)] for z in range(nz)]
            for i in range(19)]
@@ -165,8 +166,8 @@ def naive_steps_3d(f, tau, u_lid, nsteps, num=float):
                     for i in range(19):
                         c = _VEL3[i]
                         cu = c[0] * u[0] + c[1] * u[1] + c[2] * u[2]
-                        eq = wgt[i] * rho * (one + 3 * cu + (9 * one / 2) * cu * cu
-                                             - (3 * one / 2) * uu)
+                        eq = (rho * (one + 3 * cu + (9 * one / 2) * cu * cu
+                                     - (3 * one / 2) * uu)) / den[i]
                         post = pops[i] - (pops[i] - eq) / tau
                         tx, ty, tz = x + c[0], y + c[1], z + c[2]
                         if 0 <= tx < nx and 0 <= ty < ny and 0 <= tz < nz:
@@ -174,6 +175,6 @@ def naive_steps_3d(f, tau, u_lid, nsteps, num=float):
                         else:
                             wall_u = u_lid if ty >= ny else num(0)
                             r = _VEL3.index((-c[0], -c[1], -c[2]))
-                            nxt[r][z][y][x] = post - 6 * wgt[i] * one * (c[0] * wall_u)
+                            nxt[r][z][y][x] = post - 6 * one * (c[0] * wall_u) / den[i]
         cur = nxt
     return cur

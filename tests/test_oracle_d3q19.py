@@ -77,6 +77,20 @@ def test_mass_is_conserved_exactly():
     assert sum(v for a in out for b in a for c in b for v in c) == m0
 
 
+def test_collision_rounds_without_bias():
+    """The weights 1/3, 1/18, 1/36 enter as whole 36ths: one collision changes
+    the mass only by rounding noise that averages out over many sites (with
+    the weights rounded to FP64 constants every collision would remove ~1e-16
+    of each site's mass, the same way every step)."""
+    rng = np.random.default_rng(5)
+    shape = (8, 40, 50)
+    f = D.equilibrium(np.ones(shape), np.zeros(shape), np.zeros(shape), np.zeros(shape))
+    f = f + rng.uniform(-4e-3, 4e-3, f.shape)
+    for tau in (0.51875, 0.692):
+        dm = D.collide(f, tau).sum(0) - f.sum(0)
+        assert abs(np.mean(dm)) <= 1e-17, tau
+
+
 def test_first_step_closed_form_and_rest():
     """From rest the only change after one step is the lid term on the top
     row: f_9 (c = (1,-1,0)) gains U/6 and f_8 (c = (-1,-1,0)) loses U/6 at
