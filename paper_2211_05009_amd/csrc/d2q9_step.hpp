@@ -69,44 +69,50 @@ __device__ __forceinline__ float recip<float>(float v) {
 
 // Collide one site.  f[0..8] in: populations after streaming (or their
 // shift g = f - w); out: post-collision values.
+//
+// Eq. 2 with u = j / rho multiplied out: f^eq_i = w_i E_i with
+//   E_i = b + 3 c_i.j + (4.5 (c_i.j)^2 - 1.5 j.j) / rho,
+// b = rho (b = rho - 1 for the shift).  The update f_i <- f_i + omega (w_i E_i
+// - f_i) is taken as f_i + (36 w_i omega / 36) (E_i - f_i / w_i): 1 / w_i is
+// 9 / 4, 9 or 36 and 36 w_i / 36 is 16, 4 or 1 times omega / 36, all exact
+// scalings, so no weight is ever rounded.  Rounded weights would not do in
+// FP32: 4/9, 1/9 and 1/36 are powers of two times FP32(1/9), 7.5e-9 too large,
+// so the equilibrium's momentum would be (1 + 7.5e-9) j and each collision
+// would scale the momentum by 1 + 7.5e-9 omega, a drift of 1.4e-5 after 1000
+// steps at omega near 2, far above the rounding noise of the f - w storage.
+// The one rounded constant left, omega / 36, moves only the viscosity.  The
+// linear term needs no division (w rho 3 c.u = 3 w c.j).
 template <typename T, bool SHIFT>
 __device__ __forceinline__ void bgk_collide(T (&f)[9], T omega) {
-  const T one = T(1);
   // Eq. 3
-  T s = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+  const T s = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
   const T jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
   const T jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
   // SHIFT: s is the density deviation rho - 1 (the weights sum to 1)
-  const T rho = SHIFT ? one + s : s;
+  const T rho = SHIFT ? T(1) + s : s;
   const T rinv = recip<T>(rho);
-  const T ux = jx * rinv, uy = jy * rinv;
-  const T usq = T(1.5) * (ux * ux + uy * uy);
-  // Eq. 2: w rho (1 + 3 cu + 4.5 cu^2 - 1.5 u^2).  In SHIFT form the
-  // equilibrium shift is w (rho - 1 + rho (3 cu + 4.5 cu^2 - 1.5 u^2)).
-  const T base = SHIFT ? s : rho;            // the "1" part times rho, less w
-  const T w0 = T(LBM_W0), wa = T(LBM_WA), wd = T(LBM_WD);
-  const T r0 = w0 * rho, ra = wa * rho, rd = wd * rho;
-  const T b0 = w0 * base, ba = wa * base, bd = wd * base;
+  const T b = SHIFT ? s : rho;
+  const T od = omega * T(1.0 / 36.0);      // omega w_i / w_d for the diagonals
+  const T oa = T(4) * od, o0 = T(16) * od;  // axis links, rest population
+  const T jsq = T(1.5) * (jx * jx + jy * jy);
 
-  T feq;
-  feq = b0 - r0 * usq;
-  f[0] += omega * (feq - f[0]);
+  f[0] += o0 * ((b - rinv * jsq) - T(2.25) * f[0]);
   {  // axis pairs (1,3) and (2,4)
-    const T sx = ra * (T(4.5) * ux * ux - usq), ax = ra * (T(3) * ux);
-    const T sy = ra * (T(4.5) * uy * uy - usq), ay = ra * (T(3) * uy);
-    f[1] += omega * ((ba + sx + ax) - f[1]);
-    f[3] += omega * ((ba + sx - ax) - f[3]);
-    f[2] += omega * ((ba + sy + ay) - f[2]);
-    f[4] += omega * ((ba + sy - ay) - f[4]);
+    const T qx = b + rinv * (T(4.5) * jx * jx - jsq), ex = T(3) * jx;
+    const T qy = b + rinv * (T(4.5) * jy * jy - jsq), ey = T(3) * jy;
+    f[1] += oa * ((qx + ex) - T(9) * f[1]);
+    f[3] += oa * ((qx - ex) - T(9) * f[3]);
+    f[2] += oa * ((qy + ey) - T(9) * f[2]);
+    f[4] += oa * ((qy - ey) - T(9) * f[4]);
   }
   {  // diagonal pairs (5,7) and (6,8)
-    const T p = ux + uy, m = uy - ux;
-    const T sp = rd * (T(4.5) * p * p - usq), ap = rd * (T(3) * p);
-    const T sm = rd * (T(4.5) * m * m - usq), am = rd * (T(3) * m);
-    f[5] += omega * ((bd + sp + ap) - f[5]);
-    f[7] += omega * ((bd + sp - ap) - f[7]);
-    f[6] += omega * ((bd + sm + am) - f[6]);
-    f[8] += omega * ((bd + sm - am) - f[8]);
+    const T p = jx + jy, m = jy - jx;
+    const T qp = b + rinv * (T(4.5) * p * p - jsq), ep = T(3) * p;
+    const T qm = b + rinv * (T(4.5) * m * m - jsq), em = T(3) * m;
+    f[5] += od * ((qp + ep) - T(36) * f[5]);
+    f[7] += od * ((qp - ep) - T(36) * f[7]);
+    f[6] += od * ((qm + em) - T(36) * f[6]);
+    f[8] += od * ((qm - em) - T(36) * f[8]);
   }
 }
 

@@ -52,7 +52,12 @@ struct Step3Params {
 };
 
 // Collide one site: f[19] in (after streaming; g = f - w for SHIFT), out the
-// post-collision values.
+// post-collision values.  As in two dimensions, f^eq_i = w_i E_i with
+// E_i = b + 3 c_i.j + (4.5 (c_i.j)^2 - 1.5 j.j) / rho (b = rho, or rho - 1 for
+// the shift), and omega w_i is taken as 4, 2 or 1 times omega / 36 against
+// 3 E_0 - 9 f_0, E_i - 18 f_i and E_i - 36 f_i: exact scalings, so no weight
+// is rounded (FP32 weights would scale the momentum by 1 + 7.5e-9 omega at
+// every collision).
 template <typename T, bool SHIFT>
 __device__ __forceinline__ void bgk_collide19(T (&f)[19], T omega) {
   T s = T(0), jx = T(0), jy = T(0), jz = T(0);
@@ -65,15 +70,19 @@ __device__ __forceinline__ void bgk_collide19(T (&f)[19], T omega) {
   }
   const T rho = SHIFT ? T(1) + s : s;
   const T rinv = recip<T>(rho);
-  const T ux = jx * rinv, uy = jy * rinv, uz = jz * rinv;
-  const T usq = T(1.5) * (ux * ux + uy * uy + uz * uz);
-  const T base = SHIFT ? s : rho;   // the "1" term times rho, less w in SHIFT form
+  const T b = SHIFT ? s : rho;
+  const T od = omega * T(1.0 / 36.0);
+  const T jsq = T(1.5) * (jx * jx + jy * jy + jz * jz);
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
-    const T w = T(w19(i));
-    const T cu = T(cx19(i)) * ux + T(cy19(i)) * uy + T(cz19(i)) * uz;
-    const T feq = w * base + (w * rho) * (T(3) * cu + T(4.5) * cu * cu - usq);
-    f[i] += omega * (feq - f[i]);
+    const T cj = T(cx19(i)) * jx + T(cy19(i)) * jy + T(cz19(i)) * jz;
+    const T e = (b + rinv * (T(4.5) * cj * cj - jsq)) + T(3) * cj;
+    if (i == 0)
+      f[i] += (T(4) * od) * (T(3) * e - T(9) * f[i]);
+    else if (i < 7)
+      f[i] += (T(2) * od) * (e - T(18) * f[i]);
+    else
+      f[i] += od * (e - T(36) * f[i]);
   }
 }
 
