@@ -42,27 +42,30 @@ __device__ __forceinline__ void pull_fluid(const T *__restrict__ s, int P, int p
 }
 
 // Eq. 2 for (rho, ux, uy); base = rho (plain storage) or rho - 1 (SHIFT),
-// giving f^eq or f^eq - w.  Each weight enters as 16, 4 or 1 times the
-// bracket, divided by 36 (an IEEE division), so no rounded weight is used
-// (see bgk_collide).
+// giving f^eq or f^eq - w.  Only wall nodes use it, and a wall node is
+// rebuilt from its reference node at every step, so the rounding of the
+// weights (FP32: 7.5e-9 relative) scales its equilibrium part once, like a
+// lid speed off by that fraction, and does not compound from step to step
+// as it would inside the collision (bgk_collide avoids rounded weights).
 template <typename T>
 __device__ __forceinline__ void equilibrium9(T base, T rho, T ux, T uy, T (&e)[9]) {
   const T usq = T(1.5) * (ux * ux + uy * uy);
-  const T d = T(36);
-  e[0] = (T(16) * (base - rho * usq)) / d;
-  const T sx = rho * (T(4.5) * ux * ux - usq), ax = rho * (T(3) * ux);
-  const T sy = rho * (T(4.5) * uy * uy - usq), ay = rho * (T(3) * uy);
-  e[1] = (T(4) * (base + sx + ax)) / d;
-  e[3] = (T(4) * (base + sx - ax)) / d;
-  e[2] = (T(4) * (base + sy + ay)) / d;
-  e[4] = (T(4) * (base + sy - ay)) / d;
+  const T w0 = T(LBM_W0), wa = T(LBM_WA), wd = T(LBM_WD);
+  const T ra = wa * rho, rd = wd * rho, ba = wa * base, bd = wd * base;
+  e[0] = w0 * base - (w0 * rho) * usq;
+  const T sx = ra * (T(4.5) * ux * ux - usq), ax = ra * (T(3) * ux);
+  const T sy = ra * (T(4.5) * uy * uy - usq), ay = ra * (T(3) * uy);
+  e[1] = ba + sx + ax;
+  e[3] = ba + sx - ax;
+  e[2] = ba + sy + ay;
+  e[4] = ba + sy - ay;
   const T p = ux + uy, m = uy - ux;
-  const T sp = rho * (T(4.5) * p * p - usq), ap = rho * (T(3) * p);
-  const T sm = rho * (T(4.5) * m * m - usq), am = rho * (T(3) * m);
-  e[5] = (base + sp + ap) / d;
-  e[7] = (base + sp - ap) / d;
-  e[6] = (base + sm + am) / d;
-  e[8] = (base + sm - am) / d;
+  const T sp = rd * (T(4.5) * p * p - usq), ap = rd * (T(3) * p);
+  const T sm = rd * (T(4.5) * m * m - usq), am = rd * (T(3) * m);
+  e[5] = bd + sp + ap;
+  e[7] = bd + sp - ap;
+  e[6] = bd + sm + am;
+  e[8] = bd + sm - am;
 }
 
 // Wall node from its reference node's streamed populations f (in place):

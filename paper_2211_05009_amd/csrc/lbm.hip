@@ -72,6 +72,14 @@ void lbm_log_line(const char *fmt, ...) {
   std::fflush(g_log);
 }
 
+const char *lbm_json_num(double v, char *buf) {
+  if (std::isfinite(v))
+    std::snprintf(buf, 32, "%.17g", v);
+  else
+    std::snprintf(buf, 32, "null");
+  return buf;
+}
+
 double lbm_wall_seconds() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch())
       .count();
@@ -650,13 +658,15 @@ int lbm_step(lbm_t h, int64_t n) {
   const double t0 = lbm_wall_seconds();
   const int rc = step_impl(h, n);
   const double sec = lbm_wall_seconds() - t0;
+  char mass[32], res[32];
   lbm_log_line("{\"kind\": \"cavity\", \"handle\": \"%p\", \"nx\": %d, \"ny\": %d, "
                "\"dtype\": %d, \"wall\": %d, \"steps\": %lld, \"step\": %lld, "
-               "\"mass\": %.17g, \"residual\": %.17g, \"residual_step\": %lld, "
+               "\"mass\": %s, \"residual\": %s, \"residual_step\": %lld, "
                "\"seconds\": %.6f, \"MLUPS\": %.1f, \"rc\": %d}",
                (void *)h, h->nx, h->ny, h->dtype, h->wall, (long long)n, (long long)h->t,
-               h->last_mass, h->mon_t >= 0 ? h->last_res : INFINITY, (long long)h->mon_t, sec,
-               sec > 0 ? (double)h->nx * h->ny * n / sec / 1e6 : 0.0, rc);
+               lbm_json_num(h->last_mass, mass),
+               lbm_json_num(h->mon_t >= 0 ? h->last_res : INFINITY, res), (long long)h->mon_t,
+               sec, sec > 0 ? (double)h->nx * h->ny * n / sec / 1e6 : 0.0, rc);
   return rc;
 }
 

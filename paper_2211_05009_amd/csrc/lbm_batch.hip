@@ -633,12 +633,13 @@ int lbm_batch_step(lbm_batch_t b, int64_t n) {
     active += b->active[c];
     if (b->active[c] && b->mon_t[c] >= 0) worst = std::max(worst, b->last_res[c]);
   }
+  char wbuf[32];
   lbm_log_line("{\"kind\": \"batch\", \"handle\": \"%p\", \"cavities\": %d, "
                "\"active_before\": %d, \"active\": %d, \"steps\": %lld, \"step\": %lld, "
-               "\"max_active_residual\": %.17g, \"seconds\": %.6f, "
+               "\"max_active_residual\": %s, \"seconds\": %.6f, "
                "\"MLUPS_upper\": %.1f, \"rc\": %d}",
-               (void *)b, b->n, active0, active, (long long)n, (long long)b->t_global, worst, sec,
-               sec > 0 ? (double)sites * n / sec / 1e6 : 0.0, rc);
+               (void *)b, b->n, active0, active, (long long)n, (long long)b->t_global,
+               lbm_json_num(worst, wbuf), sec, sec > 0 ? (double)sites * n / sec / 1e6 : 0.0, rc);
   return rc;
 }
 

@@ -41,6 +41,9 @@ int classify_series_descs(const lbm::SeriesDesc *descs_host, int nseries, long l
 // Append one line (printf format, no newline) to the JSON-lines run log
 // named by $LBM_LOG; a no-op when it is unset.
 void lbm_log_line(const char *fmt, ...);
+// A double as JSON text: "%.17g", or "null" when it is not finite (JSON has
+// no inf or nan).  buf needs 32 chars; returns buf.
+const char *lbm_json_num(double v, char *buf);
 // Monotonic wall clock in seconds.
 double lbm_wall_seconds();
 

@@ -252,6 +252,8 @@ def test_run_log_jsonl(lbm, tmp_path):
         "print(c.mass(), c.residual()[0], c.residual()[1])\n"
         "b = lbm.Batch([20, 30], [20, 10], [50.0, 80.0], u_lid=0.1, dtype='f32s')\n"
         "b.step(1000)\n"
+        "d = lbm.Cavity(16, 12, re=50.0, u_lid=0.1, dtype='f32s')\n"
+        "d.step(100)\n"
     ) % os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     env = dict(os.environ, LBM_LOG=str(log))
     out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
@@ -261,10 +263,14 @@ def test_run_log_jsonl(lbm, tmp_path):
     lines = [json.loads(x) for x in log.read_text().splitlines()]
     cav = [x for x in lines if x["kind"] == "cavity"]
     bat = [x for x in lines if x["kind"] == "batch"]
-    assert [x["steps"] for x in cav] == [250, 50] and cav[-1]["step"] == 300
-    assert cav[-1]["residual_step"] == int(at) == 300
-    assert math.isclose(cav[-1]["residual"], float(res), rel_tol=1e-15)
-    assert abs(cav[-1]["mass"] - float(mass)) <= 1e-9
+    assert [x["steps"] for x in cav] == [250, 50, 100]
+    assert cav[1]["step"] == 300
+    assert cav[1]["residual_step"] == int(at) == 300
+    assert math.isclose(cav[1]["residual"], float(res), rel_tol=1e-15)
+    assert abs(cav[1]["mass"] - float(mass)) <= 1e-9
+    # the first monitor after a start from rest has no finite Eq. 6 value:
+    # JSON null, not inf
+    assert cav[2]["residual"] is None and cav[2]["residual_step"] == 100
     assert len(bat) == 1 and bat[0]["cavities"] == 2 and bat[0]["step"] == 1000
     assert all(x["rc"] == 0 and x["seconds"] > 0 for x in lines)
 
