@@ -325,7 +325,8 @@ def main():
                      "steps_per_launch": k, "bytes_per_launch": bpl,
                      "launch_us": round(per_launch * 1e6, 3),
                      "note": "launch time = HIP-event time of the timed region / launches "
-                             "(includes the monitor kernels every 100 steps and launch gaps); "
+                             "(includes the Eq. 6 monitor every 100 steps, carried by the "
+                             "first two launches of each 100-step chunk, and launch gaps); "
                              "algorithmic bytes count 72 B (FP32) / 144 B (FP64) per site "
                              "update, so a K-step launch can exceed the HBM peak"},
         "final_mass": mass,

@@ -75,8 +75,8 @@ __global__ __launch_bounds__(NT) void k_step_batch_tb(
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int4 te = tiles[tile];
   const CavityDesc<T> d = cav[te.x];
-  tb_tile<T, SHIFT, K, TX, TY, NT>(lds, src + d.base, dst + d.base, d.nx, d.ny, d.pitch,
-                                   d.plane, d.omega, d.u6, te.y, te.z);
+  tb_tile<T, SHIFT, K, TX, TY, NT, 0>(lds, src + d.base, dst + d.base, d.nx, d.ny, d.pitch,
+                                          d.plane, d.omega, d.u6, te.y, te.z, TbMonitor{});
 }
 
 // Monitor over a fixed 64 x 4 tiling (one site per thread): per-tile

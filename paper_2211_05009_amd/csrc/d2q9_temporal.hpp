@@ -17,9 +17,86 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "d2q9_monitor.hpp"
 #include "d2q9_step.hpp"
 
 namespace lbm {
+
+// The Eq. 6 monitor of the state a chunk starts from, carried by the chunk's
+// first two launches instead of a separate pass.  The first launch (MON = 1)
+// takes the per-site FP64 sums of k_monitor (sum (rho - 1), sum |u -
+// u_ref|^2, sum |u_ref|^2, then u_ref <- u) over each block's core sites,
+// from the region the block has just loaded into LDS, and stores one triple
+// of partials per block.  The second launch (MON = 2, same grid) adds them in
+// block order in its block 0 (deterministic) and writes out[3]; the kernel
+// boundary between the two makes the partials visible, so no block waits on
+// another.  Each thread's u_ref entries and block 0's partials are loaded
+// before the region, so their latency overlaps the region load.
+struct TbMonitor {
+  double2 *uref;      // dense [ny][nx] reference velocity
+  double *partials;   // [gridDim.x][3]
+  double *out;        // [3]
+};
+
+// Sum N values over an NT-thread block; thread 0 writes out[N].
+template <int NT, int N>
+__device__ __forceinline__ void block_sum_nt(double (&v)[N], double *out) {
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+  __shared__ double part[NT / 64][N];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < N; ++k) part[wave][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double a = 0.0;
+      for (int w = 0; w < NT / 64; ++w) a += part[w][k];
+      out[k] = a;
+    }
+  }
+}
+
+// Core-site test and dense index of region site q (the sites a block's
+// monitor covers).
+template <int K, int TX, int TY>
+__device__ __forceinline__ bool tb_core(int q, int X0, int Y0, int nx, int ny, int &k) {
+  constexpr int RW = TX + 2 * K;
+  const int ry = q / RW, rx = q - ry * RW;
+  const int gx = X0 + rx, gy = Y0 + ry;
+  k = gy * nx + gx;
+  return rx >= K && rx < K + TX && ry >= K && ry < K + TY && gx < nx && gy < ny;
+}
+
+template <typename T, bool SHIFT, int K, int TX, int TY, int NT>
+__device__ __forceinline__ void tb_monitor_sums(const T *lds, int X0, int Y0, int nx, int ny,
+                                                const TbMonitor &m,
+                                                const double2 (&ur)[(
+                                                    (TX + 2 * K) * (TY + 2 * K) + NT - 1) / NT]) {
+  constexpr int RS = (TX + 2 * K) * (TY + 2 * K);
+  constexpr int J = (RS + NT - 1) / NT;
+  double acc[kNumSums] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    const int q = threadIdx.x + j * NT;
+    int k;
+    if (q < RS && tb_core<K, TX, TY>(q, X0, Y0, nx, ny, k)) {
+      double drho, jx, jy;
+      site_moments<T, SHIFT>(lds, RS, q, drho, jx, jy);
+      const double rho = 1.0 + drho;
+      const double ux = jx / rho, uy = jy / rho;
+      const double dx = ux - ur[j].x, dy = uy - ur[j].y;
+      acc[0] += drho;
+      acc[1] += dx * dx + dy * dy;
+      acc[2] += ur[j].x * ur[j].x + ur[j].y * ur[j].y;
+      m.uref[k] = make_double2(ux, uy);
+    }
+  }
+  block_sum_nt<NT, kNumSums>(acc, m.partials + blockIdx.x * kNumSums);
+}
 
 // K steps on the region in LDS; the valid window shrinks by one site per
 // side and step.
@@ -83,14 +160,32 @@ __device__ __forceinline__ void tb_steps(T *lds, int X0, int Y0, int nx, int ny,
 
 // One tile (tile_x, tile_y) of TX x TY core sites advanced K steps; src and
 // dst point at plane 0 of the cavity.
-template <typename T, bool SHIFT, int K, int TX, int TY, int NT>
+// MON: 0, or 1 / 2 for the first / second launch of a monitored chunk.
+template <typename T, bool SHIFT, int K, int TX, int TY, int NT, int MON>
 __device__ __forceinline__ void tb_tile(T *lds, const T *__restrict__ src, T *__restrict__ dst,
                                         int nx, int ny, int pitch, int P, T omega, T u6,
-                                        int tile_x, int tile_y) {
+                                        int tile_x, int tile_y, const TbMonitor &mon) {
   constexpr int RW = TX + 2 * K, RH = TY + 2 * K, RS = RW * RH;
   constexpr int J = (RS + NT - 1) / NT;       // region sites per thread
   const int X0 = tile_x * TX - K;             // global x of region column 0
   const int Y0 = tile_y * TY - K;
+
+  // monitor inputs, loaded ahead of the region
+  double2 ur[J];
+  double fin[kNumSums] = {0.0, 0.0, 0.0};
+  if (MON == 1) {
+#pragma unroll
+    for (int j = 0; j < J; ++j) {
+      const int q = threadIdx.x + j * NT;
+      int k;
+      ur[j] = (q < RS && tb_core<K, TX, TY>(q, X0, Y0, nx, ny, k)) ? mon.uref[k]
+                                                                  : make_double2(0.0, 0.0);
+    }
+  }
+  if (MON == 2 && blockIdx.x == 0 && threadIdx.x < gridDim.x) {
+#pragma unroll
+    for (int k = 0; k < kNumSums; ++k) fin[k] = mon.partials[threadIdx.x * kNumSums + k];
+  }
 
   // load the region (sites inside the cavity)
 #pragma unroll
@@ -107,6 +202,13 @@ __device__ __forceinline__ void tb_tile(T *lds, const T *__restrict__ src, T *__
     }
   }
   __syncthreads();
+  if (MON == 1) tb_monitor_sums<T, SHIFT, K, TX, TY, NT>(lds, X0, Y0, nx, ny, mon, ur);
+  if (MON == 2 && blockIdx.x == 0) {
+    for (int b = threadIdx.x + NT; b < (int)gridDim.x; b += NT)
+#pragma unroll
+      for (int k = 0; k < kNumSums; ++k) fin[k] += mon.partials[b * kNumSums + k];
+    block_sum_nt<NT, kNumSums>(fin, mon.out);
+  }
 
   // Tiles whose region lies inside the cavity (no wall within reach) take a
   // branch-free pull with constant LDS offsets; the rest test the walls.
@@ -132,12 +234,14 @@ __device__ __forceinline__ void tb_tile(T *lds, const T *__restrict__ src, T *__
   }
 }
 
-template <typename T, bool SHIFT, int K, int TX, int TY, int NT>
-__global__ __launch_bounds__(NT) void k_step_tb(StepParams<T> p, int tiles_x) {
+// MON: 1 / 2 for the first / second launch of a chunk that carries the
+// monitor of its start state (see TbMonitor), else 0.
+template <typename T, bool SHIFT, int K, int TX, int TY, int NT, int MON = 0>
+__global__ __launch_bounds__(NT) void k_step_tb(StepParams<T> p, int tiles_x, TbMonitor mon) {
   __shared__ T lds[9 * (TX + 2 * K) * (TY + 2 * K)];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  tb_tile<T, SHIFT, K, TX, TY, NT>(lds, p.src, p.dst, p.nx, p.ny, p.pitch, p.plane, p.omega,
-                                   p.u6, tile % tiles_x, tile / tiles_x);
+  tb_tile<T, SHIFT, K, TX, TY, NT, MON>(lds, p.src, p.dst, p.nx, p.ny, p.pitch, p.plane,
+                                        p.omega, p.u6, tile % tiles_x, tile / tiles_x, mon);
 }
 
 }  // namespace lbm

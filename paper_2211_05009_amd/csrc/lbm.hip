@@ -221,9 +221,12 @@ static hipError_t launch_step_vec_t(const lbm_cavity *h, const void *src, void *
   return hipGetLastError();
 }
 
+// mon = 1 / 2: the first / second launch of a chunk that carries the Eq. 6
+// monitor of its start state (reference field uref, result in mon_dev; see
+// TbMonitor); 0: a plain launch.
 template <typename T, bool S, int K, int TX, int TY, int NT>
 static hipError_t launch_tb_t(const lbm_cavity *h, const void *src, void *dst,
-                              hipStream_t st) {
+                              hipStream_t st, int mon) {
   StepParams<T> p;
   p.src = (const T *)src;
   p.dst = (T *)dst;
@@ -235,34 +238,51 @@ static hipError_t launch_tb_t(const lbm_cavity *h, const void *src, void *dst,
   p.omega = (T)h->omega;
   p.u6 = (T)(h->u_lid / 6.0);
   const int tx = (h->nx + TX - 1) / TX, ty = (h->ny + TY - 1) / TY;
-  hipLaunchKernelGGL((k_step_tb<T, S, K, TX, TY, NT>), dim3(tx * ty), dim3(NT), 0, st, p, tx);
+  if (mon > 0 && tx * ty > h->partial_slots) return hipErrorInvalidValue;
+  const TbMonitor m{h->uref, h->partials, h->mon_dev};
+  if (mon == 1)
+    hipLaunchKernelGGL((k_step_tb<T, S, K, TX, TY, NT, 1>), dim3(tx * ty), dim3(NT), 0, st, p,
+                       tx, m);
+  else if (mon == 2)
+    hipLaunchKernelGGL((k_step_tb<T, S, K, TX, TY, NT, 2>), dim3(tx * ty), dim3(NT), 0, st, p,
+                       tx, m);
+  else
+    hipLaunchKernelGGL((k_step_tb<T, S, K, TX, TY, NT, 0>), dim3(tx * ty), dim3(NT), 0, st, p,
+                       tx, m);
   return hipGetLastError();
 }
 
+// mon applies to the multi-step shapes (12-23) only.
 template <typename T, bool S>
 static hipError_t launch_step_variant(const lbm_cavity *h, int v, const void *src,
-                                      void *dst, hipStream_t st) {
+                                      void *dst, hipStream_t st, int mon) {
   switch (v) {
-    case 12: return launch_tb_t<T, S, 4, 32, 32, 512>(h, src, dst, st);
-    case 13: return launch_tb_t<T, S, 4, 32, 32, 1024>(h, src, dst, st);
-    case 14: return launch_tb_t<T, S, 2, 32, 32, 512>(h, src, dst, st);
-    case 15: return launch_tb_t<T, S, 5, 32, 32, 512>(h, src, dst, st);
-    case 16: return launch_tb_t<T, S, 4, 64, 16, 512>(h, src, dst, st);
-    case 17: return launch_tb_t<T, S, 4, 16, 16, 256>(h, src, dst, st);
-    case 18: return launch_tb_t<T, S, 5, 64, 16, 512>(h, src, dst, st);
-    case 19: return launch_tb_t<T, S, 5, 16, 16, 256>(h, src, dst, st);
-    case 22: return launch_tb_t<T, S, 5, 32, 32, 1024>(h, src, dst, st);
+    case 12: return launch_tb_t<T, S, 4, 32, 32, 512>(h, src, dst, st, mon);
+    case 13: return launch_tb_t<T, S, 4, 32, 32, 1024>(h, src, dst, st, mon);
+    case 14: return launch_tb_t<T, S, 2, 32, 32, 512>(h, src, dst, st, mon);
+    case 15: return launch_tb_t<T, S, 5, 32, 32, 512>(h, src, dst, st, mon);
+    case 16: return launch_tb_t<T, S, 4, 64, 16, 512>(h, src, dst, st, mon);
+    case 17: return launch_tb_t<T, S, 4, 16, 16, 256>(h, src, dst, st, mon);
+    case 18: return launch_tb_t<T, S, 5, 64, 16, 512>(h, src, dst, st, mon);
+    case 19: return launch_tb_t<T, S, 5, 16, 16, 256>(h, src, dst, st, mon);
+    case 22: return launch_tb_t<T, S, 5, 32, 32, 1024>(h, src, dst, st, mon);
     // FP64 regions hold twice the bytes per site: smaller tiles keep the
     // LDS of the K = 10 and 64 x 32 shapes within 160 KiB
     case 20:
-      if constexpr (sizeof(T) == 8) return launch_tb_t<T, S, 10, 32, 16, 512>(h, src, dst, st);
-      else return launch_tb_t<T, S, 10, 32, 32, 512>(h, src, dst, st);
+      if constexpr (sizeof(T) == 8)
+        return launch_tb_t<T, S, 10, 32, 16, 512>(h, src, dst, st, mon);
+      else
+        return launch_tb_t<T, S, 10, 32, 32, 512>(h, src, dst, st, mon);
     case 21:
-      if constexpr (sizeof(T) == 8) return launch_tb_t<T, S, 10, 16, 16, 256>(h, src, dst, st);
-      else return launch_tb_t<T, S, 10, 64, 32, 1024>(h, src, dst, st);
+      if constexpr (sizeof(T) == 8)
+        return launch_tb_t<T, S, 10, 16, 16, 256>(h, src, dst, st, mon);
+      else
+        return launch_tb_t<T, S, 10, 64, 32, 1024>(h, src, dst, st, mon);
     case 23:
-      if constexpr (sizeof(T) == 8) return launch_tb_t<T, S, 5, 64, 16, 1024>(h, src, dst, st);
-      else return launch_tb_t<T, S, 5, 64, 32, 1024>(h, src, dst, st);
+      if constexpr (sizeof(T) == 8)
+        return launch_tb_t<T, S, 5, 64, 16, 1024>(h, src, dst, st, mon);
+      else
+        return launch_tb_t<T, S, 5, 64, 32, 1024>(h, src, dst, st, mon);
     case 0: return launch_step_t<T, S, 4, 1>(h, src, dst, st);
     case 1: return launch_step_t<T, S, 4, 2>(h, src, dst, st);
     case 2: return launch_step_t<T, S, 4, 4>(h, src, dst, st);
@@ -278,15 +298,16 @@ static hipError_t launch_step_variant(const lbm_cavity *h, int v, const void *sr
   }
 }
 
-// One launch of variant v (steps_per_launch(v) steps).
+// One launch of variant v (steps_per_launch(v) steps); mon (multi-step
+// shapes only): see launch_tb_t.
 static hipError_t launch_variant(const lbm_cavity *h, int v, const void *src, void *dst,
-                                 hipStream_t st) {
+                                 hipStream_t st, int mon = 0) {
   if (h->wall == LBM_WALL_NEE) {
     if (h->dtype == LBM_F64) return launch_nee_variant<double, false>(h, v, src, dst, st);
     return launch_nee_variant<float, true>(h, v, src, dst, st);
   }
-  if (h->dtype == LBM_F64) return launch_step_variant<double, false>(h, v, src, dst, st);
-  return launch_step_variant<float, true>(h, v, src, dst, st);
+  if (h->dtype == LBM_F64) return launch_step_variant<double, false>(h, v, src, dst, st, mon);
+  return launch_step_variant<float, true>(h, v, src, dst, st, mon);
 }
 
 // One step (a one-step variant: the chosen one, or the default).
@@ -377,14 +398,26 @@ static int chunk_end(const lbm_cavity *h, int c) {
   return (launches & 1) ? 1 - c : c;
 }
 
+// Whether chunks take the Eq. 6 monitor of their start state within their
+// first two launches (multi-step shapes: at least ten launches per chunk),
+// instead of a separate monitor pass at their end.  The state a fused chunk
+// ends in is then monitored by the next chunk, or by a separate pass
+// (step_impl's `pending`).
+static bool fused_monitor(const lbm_cavity *h) {
+  return h->wall != LBM_WALL_NEE && launch_steps(h, chunk_variant(h)) > 1;
+}
+
 // Issue one 100-step chunk starting from buf[c] on stream st (either
-// directly or under capture), ending with the monitor.
+// directly or under capture): with the monitor of the start state carried
+// by the first two launches, or ending with the monitor of the end state.
 static hipError_t issue_chunk(lbm_cavity *h, int c, hipStream_t st) {
   const int v = chunk_variant(h);
   const int K = launch_steps(h, v);
+  const bool fused = fused_monitor(h);
   int cur = c;
   for (int k = K; k <= kChunk; k += K) {
-    hipError_t e = launch_variant(h, v, h->buf[cur], h->buf[1 - cur], st);
+    const int mon = !fused ? 0 : k == K ? 1 : k == 2 * K ? 2 : 0;
+    hipError_t e = launch_variant(h, v, h->buf[cur], h->buf[1 - cur], st, mon);
     if (e != hipSuccess) return e;
     cur = 1 - cur;
     if (h->probe_n > 0 && h->probe_every <= kChunk && k % h->probe_every == 0) {
@@ -392,6 +425,7 @@ static hipError_t issue_chunk(lbm_cavity *h, int c, hipStream_t st) {
       if (e != hipSuccess) return e;
     }
   }
+  if (fused) return hipSuccess;
   return launch_monitor(h, h->buf[cur], true, h->mon_dev, st);
 }
 
@@ -502,7 +536,10 @@ static int create_impl(int nx, int ny, double tau, double re, double u_lid,
     TRY(hipMemsetAsync(h->buf[c], 0, h->buf_bytes, h->stream));
   }
   TRY(hipMalloc(&h->uref, sizeof(double2) * (size_t)nx * ny));
-  TRY(hipMalloc(&h->partials, sizeof(double) * kRedBlocks * kNumSums));
+  // partial sums: the monitor's fixed grid, or one triple per tile of the
+  // smallest multi-step tile (16 x 16) for the fused monitor
+  h->partial_slots = std::max(kRedBlocks, ((nx + 15) / 16) * ((ny + 15) / 16));
+  TRY(hipMalloc(&h->partials, sizeof(double) * kNumSums * (size_t)h->partial_slots));
   TRY(hipMalloc(&h->mon_dev, sizeof(double) * 4));
   TRY(hipMalloc(&h->aux_dev, sizeof(double) * 4));
   TRY(hipHostMalloc(&h->mon_host, sizeof(double) * 8, hipHostMallocDefault));
@@ -672,10 +709,30 @@ int lbm_step(lbm_t h, int64_t n) {
 
 static int step_impl(lbm_t h, int64_t n) {
   bool monitored = false;
+  // The state at h->t is a monitor point (a multiple of 100) that no monitor
+  // has seen yet: a fused chunk leaves its end state so.  The next fused
+  // chunk's first launch takes it, or a separate pass before single steps
+  // and at the end of the call.  (A fused chunk also re-monitors a start
+  // state that was seen already: u_ref receives the same values and the
+  // sums it writes are overwritten by a later monitor of this call.)
+  bool pending = false;
   hipError_t e;
+  auto monitor_now = [&]() -> int {
+    hipError_t me = launch_monitor(h, h->buf[h->cur], true, h->mon_dev, h->stream);
+    if (me != hipSuccess) return lbm_fail(LBM_EDEVICE, "monitor: %s", hipGetErrorString(me));
+    note_monitor(h);
+    monitored = true;
+    pending = false;
+    return LBM_OK;
+  };
   while (n > 0) {
     const bool aligned = (h->t % kChunk) == 0;
     if (aligned && n >= kChunk) {
+      const bool fused = fused_monitor(h);
+      if (fused && pending) {   // the chunk's first launch monitors the state at t
+        note_monitor(h);
+        pending = false;
+      }
       if (h->use_graph) {
         if (!h->graph[h->cur]) {
           int rc = build_graph(h, h->cur);
@@ -689,7 +746,10 @@ static int step_impl(lbm_t h, int64_t n) {
       h->cur = chunk_end(h, h->cur);
       h->t += kChunk;
       n -= kChunk;
-      note_monitor(h);
+      if (fused)
+        pending = true;
+      else
+        note_monitor(h);
       monitored = true;
       if (h->probe_n > 0 && h->probe_every > kChunk && h->t % h->probe_every == 0) {
         e = launch_probe_ring(h, h->buf[h->cur], h->stream);
@@ -698,6 +758,10 @@ static int step_impl(lbm_t h, int64_t n) {
       continue;
     }
     // single steps up to the next chunk boundary
+    if (pending) {
+      const int rc = monitor_now();
+      if (rc != LBM_OK) return rc;
+    }
     e = launch_step(h, h->buf[h->cur], h->buf[1 - h->cur], h->stream);
     if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "step launch: %s", hipGetErrorString(e));
     h->cur = 1 - h->cur;
@@ -708,11 +772,13 @@ static int step_impl(lbm_t h, int64_t n) {
       if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "probe: %s", hipGetErrorString(e));
     }
     if (h->t % kChunk == 0) {
-      e = launch_monitor(h, h->buf[h->cur], true, h->mon_dev, h->stream);
-      if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "monitor: %s", hipGetErrorString(e));
-      note_monitor(h);
-      monitored = true;
+      const int rc = monitor_now();
+      if (rc != LBM_OK) return rc;
     }
+  }
+  if (pending) {
+    const int rc = monitor_now();
+    if (rc != LBM_OK) return rc;
   }
   if (monitored) {
     HIPC(hipMemcpyAsync(h->mon_host, h->mon_dev, 3 * sizeof(double),

@@ -64,6 +64,7 @@ struct lbm_cavity {
   // reduction scratch
   double2 *uref = nullptr;
   double *partials = nullptr;
+  int partial_slots = 0;        // triples in partials
   double *mon_dev = nullptr;    // chunk monitor sums: sum(rho-1), num, den
   double *aux_dev = nullptr;    // on-demand reductions
   double *mon_host = nullptr;   // pinned

@@ -131,7 +131,11 @@ def test_autotune_keeps_state_and_results(lbm, dtype, tmp_path, monkeypatch):
     a.step(300)
     ref.step(300)
     assert np.array_equal(a.get_populations(), ref.get_populations())
-    assert a.residual() == ref.residual()
+    # the populations agree bit for bit; the Eq. 6 sums of a multi-step shape
+    # are added per tile (fused monitor), so two shapes may round them
+    # differently in the last bits
+    (ra, ta), (rr, tr) = a.residual(), ref.residual()
+    assert ta == tr and math.isclose(ra, rr, rel_tol=1e-12)
     # the cached choice is applied without timing
     c = lbm.Cavity(nx, ny, re=900.0, u_lid=U_LID, dtype=dtype)
     best2, ms2 = c.autotune(chunks=3, use_cache=True)

@@ -210,6 +210,47 @@ def test_blow_up_is_reported(lbm):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32s"])
+@pytest.mark.parametrize("nx,ny,variant", [(131, 77, 22), (600, 520, 19), (64, 64, 21)])
+def test_fused_monitor_matches_separate_pass(lbm, dtype, nx, ny, variant):
+    """Multi-step shapes take the Eq. 6 monitor inside the first launch of
+    each 100-step chunk (of the state the chunk starts from); the one-step
+    shape takes it in a separate pass at the chunk's end.  Over calls that
+    mix whole chunks, single steps and odd lengths, with and without graphs,
+    both report the same mass, residual and residual step (to rounding: the
+    sums are split differently), and their states agree bit for bit.
+    600 x 520 on 16 x 16 tiles has more tiles (1,254) than the separate
+    pass has blocks."""
+    f0 = W[:, None, None] + random_shift(nx, ny, 17)
+    a = lbm.Cavity(nx, ny, re=700.0, u_lid=U_LID, dtype=dtype)
+    b = lbm.Cavity(nx, ny, re=700.0, u_lid=U_LID, dtype=dtype)
+    a.set_option(lbm.LBM_OPT_STEP_VARIANT, variant)
+    b.set_option(lbm.LBM_OPT_STEP_VARIANT, 0)
+    for c in (a, b):
+        c.set_populations(f0)
+    for k, n in enumerate([250, 100, 1000, 37, 163, 300, 1, 99, 200]):
+        graph = k % 3 != 2
+        for c in (a, b):
+            c.set_option(lbm.LBM_OPT_USE_GRAPH, int(graph))
+            c.step(n)
+        (ra, ta), (rb, tb) = a.residual(), b.residual()
+        assert ta == tb == a.steps_done // 100 * 100, (k, ta, tb)
+        if math.isinf(rb):
+            assert math.isinf(ra)
+        else:
+            assert math.isclose(ra, rb, rel_tol=1e-12), (k, ra, rb)
+        assert abs(a.mass() - b.mass()) <= 1e-12 * nx * ny
+    assert np.array_equal(a.get_populations(), b.get_populations())
+    # and against the oracle's Eq. 6 on the library's own fields (2200 ->
+    # 2300: one fused chunk, then the separate pass at the call's end)
+    a.step(2200 - a.steps_done)
+    r0, u0, v0 = a.moments()
+    a.step(100)
+    r1, u1, v1 = a.moments()
+    ref = monitors.residual(u1, v1, u0, v0)
+    assert math.isclose(a.residual()[0], ref, rel_tol=1e-12)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32s"])
 def test_cavity64_re100_golden(lbm, dtype):
     """20,000 steps of the 64 x 64, Re = 100 cavity against the stored
     oracle run (tests/golden/make_golden.py): centre lines and mass."""

@@ -227,13 +227,15 @@ def test_taylor_green_viscosity(tau):
                                          (5, 5, 1.3, -0.05), (7, 4, 0.75, 0.2)])
 def test_vectorised_matches_naive_twin(nx, ny, tau, u):
     """The vectorised oracle (pull form) against the pure-Python push-form
-    twin, from a random state, for 200 steps."""
+    twin, from a random state, for 200 steps.  Both apply the weights
+    exactly, so they differ only in the order of their roundings: measured
+    at most 8.9e-16 (16 ulps of the largest population)."""
     f0 = W[:, None, None] + random_shift(nx, ny, seed=nx * 10 + ny)
     c = Cavity(nx, ny, tau=tau, u_lid=u)
     c.set_state(f0)
     c.step(200)
     ref = np.array(naive_steps(f0, tau, u, 200))
-    assert np.max(np.abs(c.f - ref)) <= 1e-14
+    assert np.max(np.abs(c.f - ref)) <= 1e-15
 
 
 # ------------------------------------------- period-two invariants -------
