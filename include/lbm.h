@@ -184,8 +184,11 @@ int lbm_autotune(lbm_t h, int chunks, int use_cache, int *best_variant,
 /*
  * Advance n >= 0 steps of Eq. 1 with the wall treatment above.  At every
  * step count t that is a multiple of 100 the monitors run: total mass and
- * the Eq. 6 residual against the velocity field of step t - 100.  If probes
- * are configured (lbm_probe_config) they are recorded every `every` steps.
+ * the Eq. 6 residual against the velocity field of step t - 100 (with the
+ * multi-step shapes the monitor of step t runs inside the first two launches
+ * of the next 100 steps, or in a separate pass at the end of the call).  If
+ * probes are configured (lbm_probe_config) they are recorded every `every`
+ * steps.
  * Returns after the work has finished; LBM_EUNSTABLE if the last monitor
  * (or the final state's mass) is not finite.
  */
