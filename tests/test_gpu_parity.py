@@ -146,6 +146,73 @@ def test_full_size_single_launch(lbm, dtype, ar):
         assert np.max(np.abs(got - ref)) <= 16 * 2.0 ** -24 * gmax
 
 
+def _light_cone_check(f_start, f_end, tau, n, width, dtype, what):
+    """Compare the GPU's f*(t + n) with the oracle on windows of the lattice.
+
+    In n steps information moves at most n sites, so the oracle can evolve a
+    width x width window cut out of the GPU's f*(t): where a window edge is
+    not a wall of the cavity the oracle's wall there is wrong, but its effect
+    reaches at most n sites in.  Sites further than n + 1 from such an edge
+    come out exactly as on the whole lattice.  Windows: the four corners
+    (two walls and, at the top, the lid) and the centre."""
+    _, ny, nx = f_start.shape
+    m = n + 1
+    xs = sorted({0, (nx - width) // 2, nx - width})
+    ys = sorted({0, (ny - width) // 2, ny - width})
+    wins = [(x0, y0) for x0 in xs for y0 in ys
+            if (x0, y0) in {(xs[0], ys[0]), (xs[0], ys[-1]), (xs[-1], ys[0]),
+                            (xs[-1], ys[-1]), (xs[1], ys[1])}]
+    worst = 0.0
+    for x0, y0 in wins:
+        x1, y1 = x0 + width, y0 + width
+        o = d2q9.Cavity(width, width, tau=tau, u_lid=U_LID)
+        o.set_state(o.stream(f_start[:, y0:y1, x0:x1]), t=1)
+        o.step(n - 1)
+        ref = o.post_collision()
+        # exact region: n + 1 sites away from window edges that are not walls
+        ex0 = 0 if x0 == 0 else m
+        ex1 = width if x1 == nx else width - m
+        ey0 = 0 if y0 == 0 else m
+        ey1 = width if y1 == ny else width - m
+        got = f_end[:, y0 + ey0:y0 + ey1, x0 + ex0:x0 + ex1]
+        want = ref[:, ey0:ey1, ex0:ex1]
+        assert got.size > 0
+        if dtype == "f64":
+            d = np.max(np.abs(got - want))
+            assert d <= F64_TOL, (what, x0, y0, d)
+        else:
+            rg, ug, vg = d2q9.macroscopic(got)
+            rw, uw, vw = d2q9.macroscopic(want)
+            d = max(np.abs(ug - uw).max(), np.abs(vg - vw).max())
+            assert d <= F32_UTOL, (what, x0, y0, d)
+        worst = max(worst, d)
+    return worst
+
+
+@pytest.mark.parametrize("dtype,nx,ny,variant", [
+    ("f32s", 500, 500, 22), ("f64", 500, 500, 22), ("f32s", 500, 1000, 21),
+    ("f64", 500, 1000, 19), ("f32s", 4096, 4096, 22), ("f64", 4096, 4096, 19)])
+def test_full_size_chunk_in_the_timed_shape(lbm, dtype, nx, ny, variant):
+    """A 100-step chunk as the benchmark runs it (graph replay, the
+    multi-step shape the autotuner picks for this lattice and storage, the
+    Eq. 6 monitor inside the chunk's first two launches) on the full
+    lattices of the single-cavity and long-run workloads, from a random
+    low-Mach state, checked against the oracle on light-cone windows.  Bars:
+    FP64 populations <= 1e-12, FP32 velocity <= 1e-5 U."""
+    tau = d2q9.relaxation_time(nx, 8000.0 if nx == 500 else 1e4, U_LID)
+    c = lbm.Cavity(nx, ny, tau=tau, u_lid=U_LID, dtype=dtype)
+    c.set_option(lbm.LBM_OPT_STEP_VARIANT, variant)
+    c.set_populations(W[:, None, None] + random_shift(nx, ny, 23))
+    c.step(100)
+    f_start = c.get_populations()                 # f*(100)
+    c.step(100)                                   # one graph chunk
+    f_end = c.get_populations()                   # f*(200)
+    assert c.residual()[1] == 200
+    c.close()
+    worst = _light_cone_check(f_start, f_end, tau, 100, 234, dtype, f"{nx}x{ny} {dtype}")
+    print(f"{nx}x{ny} {dtype} shape {variant}: worst window difference {worst:.3e}")
+
+
 @pytest.fixture(scope="module")
 def re8000_oracle():
     """Oracle run: 500 x 200 (Ar = 0.4), Re = 8000, 1000 steps from rest."""
