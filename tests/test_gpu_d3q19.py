@@ -117,3 +117,52 @@ def test_errors(lbm):
         with pytest.raises(lbm.LbmError) as e:
             lbm.lbm3d_create(*args)
         assert e.value.code == lbm.LBM_EINVAL
+
+
+@pytest.mark.parametrize("dtype,n,variant", [("f32s", 256, 2), ("f64", 192, 1)])
+def test_full_size_box_light_cone(lbm, dtype, n, variant):
+    """The boxes the benchmark times (256^3 FP32, 192^3 FP64, in the tile
+    shape it picks) from a random state: one 100-step graph chunk, then ten
+    direct launches, checked against the oracle on 42^3 windows cut from the
+    GPU's state.  In ten steps information moves at most ten sites, so sites
+    more than eleven sites from a cut face are exact.  Windows: the lid
+    corner at x = z = 0, the opposite bottom corner, the centre.  Bars: FP64
+    populations <= 1e-12, FP32 velocity <= 1e-5 U."""
+    steps, w = 10, 42
+    m = steps + 1
+    tau = D.relaxation_time(n, 1000.0, U)
+    c = lbm.Cube(n, n, n, re=1000.0, u_lid=U, dtype=dtype)
+    c.set_option(lbm.LBM_OPT_STEP_VARIANT, variant)
+    rng = np.random.default_rng(29)
+    f0 = rng.uniform(-4e-3, 4e-3, (19, n, n, n))
+    f0 += D.W[:, None, None, None]
+    c.set_populations(f0)
+    del f0
+    c.step(100)
+    f_start = c.get_populations()
+    c.set_option(lbm.LBM_OPT_USE_GRAPH, 0)
+    c.step(steps)
+    f_end = c.get_populations()
+    c.close()
+    worst = 0.0
+    for x0, y0, z0 in ((0, n - w, 0), (n - w, 0, n - w), ((n - w) // 2,) * 3):
+        o = D.Cube(w, w, w, tau=tau, u_lid=U)
+        o.set_state(D.stream(f_start[:, z0:z0 + w, y0:y0 + w, x0:x0 + w], U), t=1)
+        o.step(steps - 1)
+        ref = o.post_collision()
+        lo = [0 if a == 0 else m for a in (z0, y0, x0)]
+        hi = [w if a + w == n else w - m for a in (z0, y0, x0)]
+        sl = (slice(None), slice(lo[0], hi[0]), slice(lo[1], hi[1]), slice(lo[2], hi[2]))
+        got = f_end[:, z0:z0 + w, y0:y0 + w, x0:x0 + w][sl]
+        want = ref[sl]
+        if dtype == "f64":
+            d = np.abs(got - want).max()
+            assert d <= 1e-12, (x0, y0, z0, d)
+        else:
+            _, ug, vg, wg = D.macroscopic(got)
+            _, uw, vw, ww = D.macroscopic(want)
+            d = max(np.abs(ug - uw).max(), np.abs(vg - vw).max(), np.abs(wg - ww).max())
+            assert d <= 1e-5 * U, (x0, y0, z0, d)
+        worst = max(worst, d)
+    print(f"{n}^3 {dtype} shape {variant}: worst window difference {worst:.3e}")
+
