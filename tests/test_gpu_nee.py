@@ -8,7 +8,7 @@ import pytest
 
 from cavity_inputs import U_LID, random_points, random_shift
 from oracle import monitors, nee
-from oracle.d2q9 import W
+from oracle.d2q9 import W, macroscopic
 
 pytestmark = pytest.mark.gpu
 
@@ -232,3 +232,49 @@ def test_rectangular_cavity_against_table2_re4000(lbm):
     assert abs(p.x - 0.518) <= node and abs(p.y - 0.770) <= node
     assert c.bottom_vortex_count(1e-3 * U_LID * (n - 1)) == 2
     c.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32s"])
+def test_full_size_light_cone(lbm, dtype):
+    """The 501 x 601 node lattice of the Table 2 run (Re 4000) from a random
+    state: two 100-step graph chunks, the second checked against the oracle
+    on 240 x 240 windows cut from the GPU's state after the first.  The
+    oracle treats a window's outer ring as walls; where that ring is not a
+    wall of the cavity its effect moves one node per step, so nodes more
+    than 102 nodes from such an edge are exact after 100 steps.  Windows:
+    the two lid corners, the two bottom corners, the centre.  Bars: FP64
+    populations <= 1e-12, FP32 velocity <= 1e-5 U."""
+    nx, ny, n, w = 501, 601, 100, 240
+    m = n + 2
+    tau = nee.relaxation_time(nx, 4000.0, U_LID)
+    c = lbm.Cavity(nx, ny, re=4000.0, u_lid=U_LID, dtype=dtype, wall="nee")
+    c.set_populations(nee.CavityNEE(nx, ny, tau=tau, u_lid=U_LID).f + random_shift(nx, ny, 41))
+    c.step(n)
+    f_start = c.get_populations()
+    c.step(n)
+    f_end = c.get_populations()
+    c.close()
+    worst = 0.0
+    for x0, y0 in ((0, 0), (nx - w, 0), (0, ny - w), (nx - w, ny - w),
+                   ((nx - w) // 2, (ny - w) // 2)):
+        x1, y1 = x0 + w, y0 + w
+        o = nee.CavityNEE(w, w, tau=tau, u_lid=U_LID)
+        f1 = nee.stream_fluid(f_start[:, y0:y1, x0:x1])
+        o.set_state(nee.extrapolate_walls(f1, U_LID), t=1)
+        o.step(n - 1)
+        ref = o.post_collision()
+        ex0, ex1 = (0 if x0 == 0 else m), (w if x1 == nx else w - m)
+        ey0, ey1 = (0 if y0 == 0 else m), (w if y1 == ny else w - m)
+        got = f_end[:, y0 + ey0:y0 + ey1, x0 + ex0:x0 + ex1]
+        want = ref[:, ey0:ey1, ex0:ex1]
+        if dtype == "f64":
+            d = np.abs(got - want).max()
+            assert d <= 1e-12, (x0, y0, d)
+        else:
+            _, ug, vg = macroscopic(got)
+            _, uw, vw = macroscopic(want)
+            d = max(np.abs(ug - uw).max(), np.abs(vg - vw).max())
+            assert d <= 1e-5 * U_LID, (x0, y0, d)
+        worst = max(worst, d)
+    print(f"{nx}x{ny} NEE {dtype}: worst window difference {worst:.3e}")
+
