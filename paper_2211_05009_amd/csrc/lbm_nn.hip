@@ -30,6 +30,10 @@ namespace {
 
 inline unsigned blocks_for(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
+inline int wgrad_chunks(const ConvArgs &a) {
+  return (int)(((long long)a.n * a.h * a.w + a.kchunk - 1) / a.kchunk);
+}
+
 hipError_t conv_launch(int mode, const ConvArgs &a, hipStream_t st) {
   const int HW = a.h * a.w;
   if (mode == FWD) {
@@ -38,12 +42,35 @@ hipError_t conv_launch(int mode, const ConvArgs &a, hipStream_t st) {
   } else if (mode == DGRAD) {
     dim3 grid((a.n * HW + 63) / 64, (a.ci + 63) / 64);
     hipLaunchKernelGGL(k_conv3x3<DGRAD>, grid, dim3(256), 0, st, a);
-  } else {
-    const int npix = a.n * HW;
-    dim3 grid((9 * a.ci + 63) / 64, (a.co + 63) / 64, (npix + a.kchunk - 1) / a.kchunk);
+  } else {   // per-chunk partials into a.part, then added into GW in chunk order
+    const int nz = wgrad_chunks(a);
+    dim3 grid((9 * a.ci + 63) / 64, (a.co + 63) / 64, nz);
     hipLaunchKernelGGL(k_conv3x3<WGRAD>, grid, dim3(256), 0, st, a);
+    const long long mn = 9LL * a.ci * a.co;
+    hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(mn, kSumOut)), dim3(256), 0, st, a.part, nz,
+                       mn, (float *)a.out);
   }
   return hipGetLastError();
+}
+
+// Bias gradient: per-chunk sums into part [blocks][co], then added into gb in
+// chunk order.
+hipError_t bias_grad_launch(const uint16_t *g, int gs, int go, long long npix, int co,
+                            float *part, float *gb, hipStream_t st) {
+  const int chunk = 256, nb = (int)blocks_for(npix, chunk);
+  hipLaunchKernelGGL(k_bias_grad, dim3(nb), dim3(256), 0, st, g, gs, go, (int)npix, co, chunk,
+                     part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(co, kSumOut)), dim3(256), 0, st, part, nb,
+                     (long long)co, gb);
+  return hipGetLastError();
+}
+
+// Floats of partials a weight or bias gradient needs.
+size_t wgrad_part_floats(int n, int h, int w, int ci, int co) {
+  const long long npix = (long long)n * h * w;
+  const size_t wg = (size_t)((npix + 2047) / 2048) * 9 * ci * co;
+  const size_t bg = (size_t)blocks_for(npix, 256) * co;
+  return std::max(wg, bg);
 }
 
 bool chan_ok(int c) { return c >= 32 && c <= 1024 && c % 32 == 0; }
@@ -85,6 +112,7 @@ struct lbm_surrogate {
   uint16_t *wb = nullptr;                        // bf16 copy of the params
   float *target = nullptr, *mask = nullptr, *out3 = nullptr;
   float *loss_dev = nullptr, *loss_host = nullptr;
+  float *part = nullptr;   // partials of the split reductions (see k_sum_parts)
   double *rearr = nullptr;                       // [2 nmax] (Re, Ar)
   double *field = nullptr;                       // warm-start fields
   size_t field_doubles = 0;
@@ -290,11 +318,9 @@ int backward(lbm_surrogate *s, int n) {
       a.go = o.out.co;
       a.out = s->gw + o.woff;
       a.kchunk = 2048;
+      a.part = s->part;
       HIPC(conv_launch(WGRAD, a, st));
-      const int chunk = 256;
-      hipLaunchKernelGGL(k_bias_grad, dim3(blocks_for(npix, chunk)), dim3(256), 0, st, gy,
-                         o.out.cs, o.out.co, (int)npix, o.co, chunk, s->gw + o.boff);
-      HIPC(hipGetLastError());
+      HIPC(bias_grad_launch(gy, o.out.cs, o.out.co, npix, o.co, s->part, s->gw + o.boff, st));
       if (k > 0) {   // the network input needs no gradient
         ConvArgs d{};
         d.n = n;
@@ -385,15 +411,30 @@ int lbm_nn_conv3x3(int mode, int n, int h, int w, int ci, int co, const void *x,
   if (mode != WGRAD && (xs < cin || xo < 0 || xo + cin > xs || xs % 8 || xo % 8 || os < cout ||
                         oo < 0 || oo + cout > os))
     return lbm_fail(LBM_EINVAL, "bad channel stride / offset");
-  HIPC(conv_launch(mode, a, (hipStream_t)stream));
+  if (mode != WGRAD) {
+    HIPC(conv_launch(mode, a, (hipStream_t)stream));
+    return LBM_OK;
+  }
+  // WGRAD: partials in a workspace of this call, freed once the work is done
+  float *part = nullptr;
+  HIPC(hipMalloc(&part, sizeof(float) * wgrad_part_floats(n, h, w, ci, co)));
+  a.part = part;
+  hipError_t e = conv_launch(mode, a, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  (void)hipFree(part);
+  if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "%s", hipGetErrorString(e));
   return LBM_OK;
 }
 
 int lbm_nn_bias_grad(int npix, int co, const void *g, int gs, int go, float *gb, void *stream) {
   if (npix < 1 || co < 1 || co > 256 || !g || !gb) return lbm_fail(LBM_EINVAL, "bad arguments");
-  hipLaunchKernelGGL(k_bias_grad, dim3(blocks_for(npix, 256)), dim3(256), 0, (hipStream_t)stream,
-                     (const uint16_t *)g, gs, go, npix, co, 256, gb);
-  HIPC(hipGetLastError());
+  float *part = nullptr;
+  HIPC(hipMalloc(&part, sizeof(float) * (size_t)blocks_for(npix, 256) * co));
+  hipError_t e = bias_grad_launch((const uint16_t *)g, gs, go, npix, co, part, gb,
+                                  (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  (void)hipFree(part);
+  if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "%s", hipGetErrorString(e));
   return LBM_OK;
 }
 
@@ -433,7 +474,7 @@ int lbm_sur_destroy(lbm_sur_t s) {
   if (!s) return LBM_OK;
   if (s->stream) (void)hipStreamSynchronize(s->stream);
   void *ptrs[] = {s->act, s->gact, s->w, s->m, s->v, s->gw, s->wb, s->target, s->mask, s->out3,
-                  s->loss_dev, s->rearr, s->field};
+                  s->loss_dev, s->rearr, s->field, s->part};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (s->loss_host) (void)hipHostFree(s->loss_host);
@@ -470,6 +511,14 @@ int lbm_sur_create(int max_batch, lbm_sur_t *out) {
                           s->nparams * 4,   s->nparams * 4,   s->nparams * 2, npix * 3 * 4,
                           npix * 4,         npix * 3 * 4,     16,             (size_t)max_batch * 16};
   for (int i = 0; i < 12 && e == hipSuccess; ++i) e = hipMalloc(allocs[i], sizes[i]);
+  // partials of the split reductions: the largest weight / bias gradient, or
+  // the loss's per-block sums
+  size_t part_floats = blocks_for((long long)npix);
+  for (const Op &o : s->ops)
+    if (o.type == OP_CONV)
+      part_floats = std::max(part_floats, wgrad_part_floats(max_batch, level_h(o.level),
+                                                            level_w(o.level), o.ci, o.co));
+  if (e == hipSuccess) e = hipMalloc(&s->part, part_floats * sizeof(float));
   if (e == hipSuccess) e = hipMemsetAsync(s->act, 0, s->act_elems * 2, s->stream);
   if (e == hipSuccess) e = hipMemsetAsync(s->gact, 0, s->act_elems * 2, s->stream);
   if (e == hipSuccess) e = hipMemsetAsync(s->w, 0, s->nparams * 4, s->stream);
@@ -575,7 +624,9 @@ int lbm_sur_train_step(lbm_sur_t s, int n, const double *re, const double *ar,
   const View &hv = head_view(s);
   hipLaunchKernelGGL(k_mse, dim3(blocks_for(npix)), dim3(256), 0, s->stream,
                      bptr(s, s->act, hv), hv.cs, target_dev, mask_dev, npix, kOutCh,
-                     (float)(1.0 / count), bptr(s, s->gact, hv), hv.cs, s->loss_dev);
+                     (float)(1.0 / count), bptr(s, s->gact, hv), hv.cs, s->part);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s->stream, s->part,
+                     (int)blocks_for(npix), 1LL, s->loss_dev);
   HIPC(hipGetLastError());
   rc = backward(s, n);
   if (rc) return rc;

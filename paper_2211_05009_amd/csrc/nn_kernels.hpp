@@ -48,6 +48,8 @@ struct ConvArgs {
   int os, oo;
   int accumulate;      // DGRAD: add into GX
   int kchunk;          // WGRAD: pixels per block (multiple of 32)
+  float *part;         // WGRAD: per-chunk partials [gridDim.z][9 ci][co], added
+                       // into GW in chunk order by k_sum_parts (deterministic)
 };
 
 constexpr int kLdsK = 32 + 8;   // padded row of a staged 64 x 32 operand slice
@@ -195,21 +197,46 @@ __global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
           if (a.accumulate) v += bf2f(*o);
           *o = f2bf(v);
         } else {
-          atomicAdd((float *)a.out + (size_t)m * a.co + n, v);
+          a.part[((size_t)blockIdx.z * M + m) * N + n] = v;
         }
       }
 }
 
-// Bias gradient: gb[o] += sum_p GY[p][o]; block = 256 threads over a chunk of
-// pixels, one channel per thread (c < 256), FP32 atomics.
+// out[i] += sum over k of part[k][i] for i < n: the deterministic second half
+// of the split reductions (weight and bias gradients, loss).  A block takes
+// 16 outputs; its 16 thread groups sum the k = g, g + 16, ... in order, and
+// the group sums are added in group order, so the result is fixed while
+// 16 loads per output are in flight.
+constexpr int kSumOut = 16, kSumGroups = 16;
+__global__ __launch_bounds__(256) void k_sum_parts(const float *part, int nparts, long long n,
+                                                   float *out) {
+  const int o = threadIdx.x % kSumOut, g = threadIdx.x / kSumOut;
+  const long long i = blockIdx.x * (long long)kSumOut + o;
+  float s = 0.f;
+  if (i < n)
+    for (int k = g; k < nparts; k += kSumGroups) s += part[(size_t)k * n + i];
+  __shared__ float sh[kSumGroups][kSumOut];
+  sh[g][o] = s;
+  __syncthreads();
+  if (g == 0 && i < n) {
+    float t = 0.f;
+#pragma unroll
+    for (int q = 0; q < kSumGroups; ++q) t += sh[q][o];
+    out[i] += t;
+  }
+}
+
+// Bias gradient, first half: part[block][o] = sum of GY[p][o] over the
+// block's chunk of pixels; one channel per thread (c < 256).  k_sum_parts
+// adds the chunks into gb.
 __global__ __launch_bounds__(256) void k_bias_grad(const uint16_t *g, int gs, int go, int npix,
-                                                   int co, int chunk, float *gb) {
+                                                   int co, int chunk, float *part) {
   const int o = threadIdx.x;
   if (o >= co) return;
   const int p0 = blockIdx.x * chunk, p1 = min(p0 + chunk, npix);
   float s = 0.f;
   for (int p = p0; p < p1; ++p) s += bf2f(g[(size_t)p * gs + go + o]);
-  atomicAdd(gb + o, s);
+  part[(size_t)blockIdx.x * co + o] = s;
 }
 
 // 2 x 2 average pooling (h, w: input size, even).
@@ -284,8 +311,9 @@ __global__ void k_relu_bwd(const uint16_t *y, int ys, int yo, uint16_t *g, int g
 }
 
 // Masked mean-squared error over the first `cu` channels of pred (stride
-// ps): loss += sum mask (pred - t)^2 / count; grad = 2 mask (pred - t) / count
-// (bf16, stride gs, zero elsewhere).  t: FP32 [npix][cu]; mask FP32 [npix].
+// ps): loss[block] = the block's sum of mask (pred - t)^2 / count (k_sum_parts
+// adds the blocks); grad = 2 mask (pred - t) / count (bf16, stride gs, zero
+// elsewhere).  t: FP32 [npix][cu]; mask FP32 [npix].
 __global__ __launch_bounds__(256) void k_mse(const uint16_t *pred, int ps, const float *t,
                                              const float *mask, long long npix, int cu,
                                              float inv_count, uint16_t *grad, int gs,
@@ -308,7 +336,7 @@ __global__ __launch_bounds__(256) void k_mse(const uint16_t *pred, int ps, const
   __shared__ float part[4];
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = l;
   __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(loss, (part[0] + part[1] + part[2] + part[3]) * inv_count);
+  if (threadIdx.x == 0) loss[blockIdx.x] = (part[0] + part[1] + part[2] + part[3]) * inv_count;
 }
 
 // Adam on FP32 master weights; refreshes the bf16 copy (may be null).

@@ -169,6 +169,29 @@ def test_training_reduces_loss(env):
     assert all(math.isfinite(v) for v in losses)
 
 
+def test_training_is_bit_reproducible(env):
+    """Every reduction of a training step (weight and bias gradients split
+    over pixel chunks, the loss over blocks) adds its partials in a fixed
+    order, so two networks trained from the same weights on the same data
+    end with the same weights, bit for bit."""
+    torch, lbm = env
+    re, ar = np.array([300.0, 2000.0, 900.0, 1500.0]), np.array([0.5, 1.0, 1.5, 2.0])
+    x = S.encode(re, ar)
+    mask = torch.tensor(x[..., 0], dtype=torch.float32).cuda()
+    yy = x[..., 2:3]
+    tgt = torch.tensor(np.concatenate([0.1 * yy, np.sin(3 * yy), x[..., 1:2] * yy], axis=-1),
+                       dtype=torch.float32).cuda()
+    out = []
+    for _ in range(2):
+        sur = lbm.Surrogate(max_batch=4)
+        sur.set_params(S.he_init(2))
+        losses = [sur.train_step(re, ar, tgt, mask, lr=1e-3) for _ in range(8)]
+        out.append((np.array(losses), sur.get_params()))
+        sur.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+
+
 def test_warm_start_maps_prediction_onto_the_lattice(env):
     """lbm_sur_warm_start = bilinear map of the prediction onto site
     centres, mass renormalised, staggered momenta removed, f = f^eq
