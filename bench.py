@@ -277,7 +277,7 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the lattice of one cavity fits one "
-              "MI355X; multi-GPU runs are not part of this build", file=sys.stderr)
+              "MI355X; multi-GPU runs are not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     if args.flowmap:
