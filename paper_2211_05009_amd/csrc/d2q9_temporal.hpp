@@ -99,21 +99,31 @@ __device__ __forceinline__ void tb_monitor_sums(const T *lds, int X0, int Y0, in
 }
 
 // K steps on the region in LDS; the valid window shrinks by one site per
-// side and step.
+// side and step.  At step s the threads take the sites of that window,
+// (RW - 2s) x (RH - 2s) of them, in row-major order, so a wavefront holds 64
+// sites of the window rather than 64 sites of the region of which a shrinking
+// share is idle; the step loop is unrolled, so the window width is a
+// compile-time constant in the index arithmetic.
 template <typename T, bool SHIFT, int K, int RW, int RH, int NT, bool INTERIOR>
 __device__ __forceinline__ void tb_steps(T *lds, int X0, int Y0, int nx, int ny, T omega,
                                          T u6) {
   constexpr int RS = RW * RH;
-  constexpr int J = (RS + NT - 1) / NT;
-  for (int s = 1; s <= K; ++s) {
-    T v[J][9];
-    bool act[J];
+  constexpr int JM = ((RW - 2) * (RH - 2) + NT - 1) / NT;   // sites per thread at s = 1
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-      const int q = threadIdx.x + j * NT;
-      const int ry = q / RW, rx = q - ry * RW;
+  for (int s = 1; s <= K; ++s) {
+    const int ws = RW - 2 * s, ns = ws * (RH - 2 * s);
+    T v[JM][9];
+    bool act[JM];
+    int qs[JM];
+#pragma unroll
+    for (int j = 0; j < JM; ++j) {
+      const int c = threadIdx.x + j * NT;
+      const int wy = c / ws, wx = c - wy * ws;
+      const int rx = s + wx, ry = s + wy;
+      const int q = ry * RW + rx;
       const int gx = X0 + rx, gy = Y0 + ry;
-      act[j] = q < RS && rx >= s && rx < RW - s && ry >= s && ry < RH - s;
+      qs[j] = q;
+      act[j] = c < ns;
       if (!INTERIOR) act[j] = act[j] && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
       if (act[j]) {
         T *f = v[j];
@@ -148,12 +158,10 @@ __device__ __forceinline__ void tb_steps(T *lds, int X0, int Y0, int nx, int ny,
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
-      const int q = threadIdx.x + j * NT;
+    for (int j = 0; j < JM; ++j)
       if (act[j])
 #pragma unroll
-        for (int i = 0; i < 9; ++i) lds[i * RS + q] = v[j][i];
-    }
+        for (int i = 0; i < 9; ++i) lds[i * RS + qs[j]] = v[j][i];
     __syncthreads();
   }
 }
