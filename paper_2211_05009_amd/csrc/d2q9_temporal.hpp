@@ -195,20 +195,31 @@ __device__ __forceinline__ void tb_tile(T *lds, const T *__restrict__ src, T *__
     for (int k = 0; k < kNumSums; ++k) fin[k] = mon.partials[threadIdx.x * kNumSums + k];
   }
 
-  // load the region (sites inside the cavity)
+  // Load the region (sites inside the cavity) straight from global memory
+  // into LDS: global_load_lds_dword writes lane l's word at the wavefront's
+  // LDS base + 4 l, with no round trip through registers and no LDS stores.
+  // Thread c takes word c of each plane's region: site c in FP32, the low
+  // (c even) or high half of site c / 2 in FP64, so the 64 lanes of a
+  // wavefront fill 64 consecutive LDS words.
+  constexpr int WPS = sizeof(T) / 4;             // words per site
+  constexpr int JW = (WPS * RS + NT - 1) / NT;   // words per thread and plane
 #pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int q = threadIdx.x + j * NT;
+  for (int j = 0; j < JW; ++j) {
+    const int c = threadIdx.x + j * NT;
+    const int q = c / WPS;
     if (q < RS) {
       const int ry = q / RW, rx = q - ry * RW;
       const int gx = X0 + rx, gy = Y0 + ry;
       if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-        const int o = gy * pitch + gx;
+        const float *g = reinterpret_cast<const float *>(src + gy * pitch + gx) + c % WPS;
+        float *w0 = reinterpret_cast<float *>(lds) + (c - (threadIdx.x & 63));
 #pragma unroll
-        for (int i = 0; i < 9; ++i) lds[i * RS + q] = src[i * P + o];
+        for (int i = 0; i < 9; ++i)
+          __builtin_amdgcn_global_load_lds(g + WPS * i * P, w0 + WPS * i * RS, 4, 0, 0);
       }
     }
   }
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (MON == 1) tb_monitor_sums<T, SHIFT, K, TX, TY, NT>(lds, X0, Y0, nx, ny, mon, ur);
   if (MON == 2 && blockIdx.x == 0) {
