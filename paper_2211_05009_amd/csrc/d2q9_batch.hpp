@@ -67,16 +67,31 @@ __global__ __launch_bounds__(64 * BY) void k_step_batch_vec(
 }
 
 // Temporal form (see k_step_tb): K steps per launch on TX x TY tiles.
-template <typename T, bool SHIFT, int K, int TX, int TY, int NT>
+// MON = 1 / 2: the first / second launch of a chunk that carries the Eq. 6
+// monitor of every listed cavity's start state (see TbMonitor): tile entry
+// t stores partial triple t (a cavity's tiles are listed together, so its
+// partials form one run), and the block of a cavity's first tile, whose
+// entry holds the cavity's tile count in .w (0 elsewhere), adds that run
+// in order into out[cavity].  uref is the batch's reference field, each
+// cavity's at its uref_off.
+template <typename T, bool SHIFT, int K, int TX, int TY, int NT, int MON = 0>
 __global__ __launch_bounds__(NT) void k_step_batch_tb(
     const T *__restrict__ src, T *__restrict__ dst,
-    const CavityDesc<T> *__restrict__ cav, const int4 *__restrict__ tiles) {
+    const CavityDesc<T> *__restrict__ cav, const int4 *__restrict__ tiles, TbMonitor mon) {
   __shared__ T lds[9 * (TX + 2 * K) * (TY + 2 * K)];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int4 te = tiles[tile];
   const CavityDesc<T> d = cav[te.x];
-  tb_tile<T, SHIFT, K, TX, TY, NT, 0>(lds, src + d.base, dst + d.base, d.nx, d.ny, d.pitch,
-                                          d.plane, d.omega, d.u6, te.y, te.z, TbMonitor{});
+  TbMonBlock mb{nullptr, nullptr, nullptr, 0, nullptr};
+  if (MON != 0) {
+    mb.uref = mon.uref + d.uref_off;
+    mb.part = mon.partials + (size_t)tile * kNumSums;
+    mb.fin = mb.part;
+    mb.nfin = te.w;
+    mb.out = mon.out + (size_t)te.x * kNumSums;
+  }
+  tb_tile<T, SHIFT, K, TX, TY, NT, MON>(lds, src + d.base, dst + d.base, d.nx, d.ny, d.pitch,
+                                        d.plane, d.omega, d.u6, te.y, te.z, mb);
 }
 
 // Monitor over a fixed 64 x 4 tiling (one site per thread): per-tile

@@ -38,6 +38,18 @@ struct TbMonitor {
   double *out;        // [3]
 };
 
+// One block's share of that monitor: the reference field of its cavity, the
+// triple of partials it stores (MON = 1) and, on the block that completes a
+// cavity's sum (MON = 2), that cavity's nfin partials in the order they are
+// added and the triple they go to.  nfin is 0 on every other block.
+struct TbMonBlock {
+  double2 *uref;
+  double *part;
+  const double *fin;
+  int nfin;
+  double *out;
+};
+
 // Sum N values over an NT-thread block; thread 0 writes out[N].
 template <int NT, int N>
 __device__ __forceinline__ void block_sum_nt(double (&v)[N], double *out) {
@@ -73,7 +85,7 @@ __device__ __forceinline__ bool tb_core(int q, int X0, int Y0, int nx, int ny, i
 
 template <typename T, bool SHIFT, int K, int TX, int TY, int NT>
 __device__ __forceinline__ void tb_monitor_sums(const T *lds, int X0, int Y0, int nx, int ny,
-                                                const TbMonitor &m,
+                                                const TbMonBlock &m,
                                                 const double2 (&ur)[(
                                                     (TX + 2 * K) * (TY + 2 * K) + NT - 1) / NT]) {
   constexpr int RS = (TX + 2 * K) * (TY + 2 * K);
@@ -95,7 +107,7 @@ __device__ __forceinline__ void tb_monitor_sums(const T *lds, int X0, int Y0, in
       m.uref[k] = make_double2(ux, uy);
     }
   }
-  block_sum_nt<NT, kNumSums>(acc, m.partials + blockIdx.x * kNumSums);
+  block_sum_nt<NT, kNumSums>(acc, m.part);
 }
 
 // K steps on the region in LDS; the valid window shrinks by one site per
@@ -172,7 +184,7 @@ __device__ __forceinline__ void tb_steps(T *lds, int X0, int Y0, int nx, int ny,
 template <typename T, bool SHIFT, int K, int TX, int TY, int NT, int MON>
 __device__ __forceinline__ void tb_tile(T *lds, const T *__restrict__ src, T *__restrict__ dst,
                                         int nx, int ny, int pitch, int P, T omega, T u6,
-                                        int tile_x, int tile_y, const TbMonitor &mon) {
+                                        int tile_x, int tile_y, const TbMonBlock &mon) {
   constexpr int RW = TX + 2 * K, RH = TY + 2 * K, RS = RW * RH;
   constexpr int J = (RS + NT - 1) / NT;       // region sites per thread
   const int X0 = tile_x * TX - K;             // global x of region column 0
@@ -190,9 +202,9 @@ __device__ __forceinline__ void tb_tile(T *lds, const T *__restrict__ src, T *__
                                                                   : make_double2(0.0, 0.0);
     }
   }
-  if (MON == 2 && blockIdx.x == 0 && threadIdx.x < gridDim.x) {
+  if (MON == 2 && threadIdx.x < mon.nfin) {
 #pragma unroll
-    for (int k = 0; k < kNumSums; ++k) fin[k] = mon.partials[threadIdx.x * kNumSums + k];
+    for (int k = 0; k < kNumSums; ++k) fin[k] = mon.fin[threadIdx.x * kNumSums + k];
   }
 
   // Load the region (sites inside the cavity) straight from global memory
@@ -222,10 +234,10 @@ __device__ __forceinline__ void tb_tile(T *lds, const T *__restrict__ src, T *__
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (MON == 1) tb_monitor_sums<T, SHIFT, K, TX, TY, NT>(lds, X0, Y0, nx, ny, mon, ur);
-  if (MON == 2 && blockIdx.x == 0) {
-    for (int b = threadIdx.x + NT; b < (int)gridDim.x; b += NT)
+  if (MON == 2 && mon.nfin > 0) {
+    for (int b = threadIdx.x + NT; b < mon.nfin; b += NT)
 #pragma unroll
-      for (int k = 0; k < kNumSums; ++k) fin[k] += mon.partials[b * kNumSums + k];
+      for (int k = 0; k < kNumSums; ++k) fin[k] += mon.fin[b * kNumSums + k];
     block_sum_nt<NT, kNumSums>(fin, mon.out);
   }
 
@@ -259,8 +271,11 @@ template <typename T, bool SHIFT, int K, int TX, int TY, int NT, int MON = 0>
 __global__ __launch_bounds__(NT) void k_step_tb(StepParams<T> p, int tiles_x, TbMonitor mon) {
   __shared__ T lds[9 * (TX + 2 * K) * (TY + 2 * K)];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  // block b stores partial triple b; block 0 adds all of them
+  const TbMonBlock mb{mon.uref, mon.partials + blockIdx.x * kNumSums, mon.partials,
+                      blockIdx.x == 0 ? (int)gridDim.x : 0, mon.out};
   tb_tile<T, SHIFT, K, TX, TY, NT, MON>(lds, p.src, p.dst, p.nx, p.ny, p.pitch, p.plane,
-                                        p.omega, p.u6, tile % tiles_x, tile / tiles_x, mon);
+                                        p.omega, p.u6, tile % tiles_x, tile / tiles_x, mb);
 }
 
 }  // namespace lbm

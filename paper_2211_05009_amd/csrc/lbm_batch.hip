@@ -48,7 +48,8 @@ struct lbm_batch {
   int *fin = nullptr;                   // [3][n]: first, count, cavity
   int nfin = 0;
   double2 *uref = nullptr;
-  double *partials = nullptr;           // max(total monitor tiles, kRedBlocks) x 3
+  double *partials = nullptr;           // partials_cap x 3
+  long long partials_cap = 0;           // max(monitor tiles, 16 x 16 step tiles, kRedBlocks)
   double *mon_dev = nullptr;            // [n][3] chunk monitors
   double *aux_dev = nullptr;            // on-demand reductions
   double *mon_host = nullptr;           // pinned [n][3] + 4
@@ -111,28 +112,43 @@ hipError_t launch_bv(const lbm_batch *b, const void *src, void *dst, hipStream_t
   return hipGetLastError();
 }
 
+// mon: 1 / 2 for the first / second launch of a chunk that carries the
+// monitor of its start state (see k_step_batch_tb), 0 for a plain launch.
 template <typename T, bool S, int K, int TX, int TY, int NT>
-hipError_t launch_bt(const lbm_batch *b, const void *src, void *dst, hipStream_t st) {
-  hipLaunchKernelGGL((k_step_batch_tb<T, S, K, TX, TY, NT>), dim3(b->ntiles), dim3(NT), 0, st,
-                     (const T *)src, (T *)dst, (const CavityDesc<T> *)b->desc,
-                     (const int4 *)b->tiles);
+hipError_t launch_bt(const lbm_batch *b, const void *src, void *dst, hipStream_t st, int mon) {
+  if (mon > 0 && b->ntiles > b->partials_cap) return hipErrorInvalidValue;
+  const TbMonitor m{b->uref, b->partials, b->mon_dev};
+  if (mon == 1)
+    hipLaunchKernelGGL((k_step_batch_tb<T, S, K, TX, TY, NT, 1>), dim3(b->ntiles), dim3(NT), 0,
+                       st, (const T *)src, (T *)dst, (const CavityDesc<T> *)b->desc,
+                       (const int4 *)b->tiles, m);
+  else if (mon == 2)
+    hipLaunchKernelGGL((k_step_batch_tb<T, S, K, TX, TY, NT, 2>), dim3(b->ntiles), dim3(NT), 0,
+                       st, (const T *)src, (T *)dst, (const CavityDesc<T> *)b->desc,
+                       (const int4 *)b->tiles, m);
+  else
+    hipLaunchKernelGGL((k_step_batch_tb<T, S, K, TX, TY, NT, 0>), dim3(b->ntiles), dim3(NT), 0,
+                       st, (const T *)src, (T *)dst, (const CavityDesc<T> *)b->desc,
+                       (const int4 *)b->tiles, m);
   return hipGetLastError();
 }
 
+// mon applies to the multi-step shapes (12-17) only.
 template <typename T, bool S>
-hipError_t launch_b_variant(const lbm_batch *b, const void *src, void *dst, hipStream_t st) {
+hipError_t launch_b_variant(const lbm_batch *b, const void *src, void *dst, hipStream_t st,
+                            int mon) {
   constexpr bool D = sizeof(T) == 8;
   switch (b->variant) {
-    case 12: return launch_bt<T, S, 5, 32, 32, 1024>(b, src, dst, st);
-    case 13: return launch_bt<T, S, 5, 64, 16, 512>(b, src, dst, st);
-    case 14: return launch_bt<T, S, 5, 16, 16, 256>(b, src, dst, st);
+    case 12: return launch_bt<T, S, 5, 32, 32, 1024>(b, src, dst, st, mon);
+    case 13: return launch_bt<T, S, 5, 64, 16, 512>(b, src, dst, st, mon);
+    case 14: return launch_bt<T, S, 5, 16, 16, 256>(b, src, dst, st, mon);
     case 15:
-      if constexpr (D) return launch_bt<T, S, 10, 32, 16, 512>(b, src, dst, st);
-      else return launch_bt<T, S, 10, 32, 32, 512>(b, src, dst, st);
-    case 16: return launch_bt<T, S, 2, 32, 32, 512>(b, src, dst, st);
+      if constexpr (D) return launch_bt<T, S, 10, 32, 16, 512>(b, src, dst, st, mon);
+      else return launch_bt<T, S, 10, 32, 32, 512>(b, src, dst, st, mon);
+    case 16: return launch_bt<T, S, 2, 32, 32, 512>(b, src, dst, st, mon);
     case 17:
-      if constexpr (D) return launch_bt<T, S, 5, 64, 16, 1024>(b, src, dst, st);
-      else return launch_bt<T, S, 5, 64, 32, 1024>(b, src, dst, st);
+      if constexpr (D) return launch_bt<T, S, 5, 64, 16, 1024>(b, src, dst, st, mon);
+      else return launch_bt<T, S, 5, 64, 32, 1024>(b, src, dst, st, mon);
     case 8: return launch_bv<T, S, 1>(b, src, dst, st);
     case 9: return launch_bv<T, S, 2>(b, src, dst, st);
     case 10: return launch_bv<T, S, 4>(b, src, dst, st);
@@ -149,12 +165,13 @@ hipError_t launch_b_variant(const lbm_batch *b, const void *src, void *dst, hipS
 }
 
 
-// One launch of the chosen shape (shape_steps(variant) steps).
-hipError_t batch_launch(const lbm_batch *b, int from, hipStream_t st) {
+// One launch of the chosen shape (shape_steps(variant) steps); mon (the
+// multi-step shapes only): see launch_bt.
+hipError_t batch_launch(const lbm_batch *b, int from, hipStream_t st, int mon = 0) {
   if (b->ntiles == 0) return hipSuccess;
   if (b->dtype == LBM_F64)
-    return launch_b_variant<double, false>(b, b->buf[from], b->buf[1 - from], st);
-  return launch_b_variant<float, true>(b, b->buf[from], b->buf[1 - from], st);
+    return launch_b_variant<double, false>(b, b->buf[from], b->buf[1 - from], st, mon);
+  return launch_b_variant<float, true>(b, b->buf[from], b->buf[1 - from], st, mon);
 }
 
 // One step with shape 0 (for steps off the 100-step grid).
@@ -240,8 +257,10 @@ int rebuild_tables(lbm_batch *b) {
     if (!b->active[c]) continue;
     const int tx = (b->nx[c] + tw - 1) / tw;
     const int ty = (b->ny[c] + th - 1) / th;
+    // .w: the cavity's tile count on its first tile (the in-chunk monitor
+    // adds the cavity's partials there), 0 on the others
     for (int y = 0; y < ty; ++y)
-      for (int x = 0; x < tx; ++x) st.push_back(make_int4(c, x, y, 0));
+      for (int x = 0; x < tx; ++x) st.push_back(make_int4(c, x, y, x == 0 && y == 0 ? tx * ty : 0));
     const int mx = (b->nx[c] + 63) / 64;
     const int my = (b->ny[c] + 3) / 4;
     first[nfin] = (int)mt.size();
@@ -293,14 +312,24 @@ int rebuild_tables(lbm_batch *b) {
   return LBM_OK;
 }
 
+// graph_steps steps from a monitored state at a multiple of 100, ending
+// with every cavity's monitor of each later multiple of 100.  Multi-step
+// shapes carry the monitor of a chunk's start state in the chunk's first
+// two launches (k_step_batch_tb, MON = 1 and 2) from the second chunk on,
+// and the state the graph ends in gets the separate pass, which the host
+// reads.  Probe series are recorded by the separate pass, so with probes
+// every chunk ends with it.
 hipError_t issue_chunk(lbm_batch *b, hipStream_t st) {
   const int K = shape_steps(b->variant);
+  const bool fused = kShapes[b->variant].kind == 2 && b->probe_n == 0;
   int cur = 0;
   for (int k = K; k <= b->graph_steps; k += K) {
-    hipError_t e = batch_launch(b, cur, st);
+    const int done = (k - K) % kChunk;   // steps of this chunk before the launch
+    const int mon = (fused && k > kChunk) ? (done == 0 ? 1 : done == K ? 2 : 0) : 0;
+    hipError_t e = batch_launch(b, cur, st, mon);
     if (e != hipSuccess) return e;
     cur = 1 - cur;
-    if (k % kChunk == 0) {
+    if (k % kChunk == 0 && (!fused || k == b->graph_steps)) {
       e = batch_monitor(b, cur, st);
       if (e != hipSuccess) return e;
     }
@@ -471,7 +500,7 @@ int lbm_batch_create(int n, const int *nx, const int *ny, const double *re, doub
   b->n = n;
   b->dtype = dtype;
   b->u_lid = u_lid;
-  long long elems = 0, sites = 0, mt_total = 0;
+  long long elems = 0, sites = 0, mt_total = 0, t16_total = 0;
   for (int c = 0; c < n; ++c) {
     if (nx[c] < 2 || ny[c] < 2 || nx[c] > 65536 || ny[c] > 65536)
       return bail(lbm_fail(LBM_EINVAL, "cavity %d: lattice %d x %d outside [2, 65536]", c,
@@ -492,6 +521,7 @@ int lbm_batch_create(int n, const int *nx, const int *ny, const double *re, doub
     elems += 9LL * p * ny[c];
     sites += (long long)nx[c] * ny[c];
     mt_total += (long long)((nx[c] + 63) / 64) * ((ny[c] + 3) / 4);
+    t16_total += (long long)((nx[c] + 15) / 16) * ((ny[c] + 15) / 16);
   }
   if (elems >= (1LL << 31) || sites >= (1LL << 31))
     return bail(lbm_fail(LBM_EINVAL, "batch too large for 32-bit element offsets"));
@@ -521,8 +551,9 @@ int lbm_batch_create(int n, const int *nx, const int *ny, const double *re, doub
     TRY(hipMemsetAsync(b->buf[c], 0, b->buf_bytes, b->stream));
   }
   TRY(hipMalloc(&b->uref, sizeof(double2) * (size_t)sites));
-  TRY(hipMalloc(&b->partials,
-                sizeof(double) * kNumSums * (size_t)std::max<long long>(mt_total, kRedBlocks)));
+  // the step tiles of every shape are at least 16 x 16 sites
+  b->partials_cap = std::max<long long>(std::max(mt_total, t16_total), kRedBlocks);
+  TRY(hipMalloc(&b->partials, sizeof(double) * kNumSums * (size_t)b->partials_cap));
   TRY(hipMalloc(&b->mon_dev, sizeof(double) * kNumSums * n));
   TRY(hipMemsetAsync(b->mon_dev, 0, sizeof(double) * kNumSums * n, b->stream));
   TRY(hipMalloc(&b->aux_dev, sizeof(double) * 4));
