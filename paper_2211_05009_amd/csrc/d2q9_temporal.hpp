@@ -115,10 +115,12 @@ __device__ __forceinline__ void tb_monitor_sums(const T *lds, int X0, int Y0, in
 // (RW - 2s) x (RH - 2s) of them, in row-major order, so a wavefront holds 64
 // sites of the window rather than 64 sites of the region of which a shrinking
 // share is idle; the step loop is unrolled, so the window width is a
-// compile-time constant in the index arithmetic.
+// compile-time constant in the index arithmetic.  The last window is the
+// tile's core: its sites go from registers straight to dst (pitch, plane
+// stride P), with no write-back to LDS and no barrier after it.
 template <typename T, bool SHIFT, int K, int RW, int RH, int NT, bool INTERIOR>
-__device__ __forceinline__ void tb_steps(T *lds, int X0, int Y0, int nx, int ny, T omega,
-                                         T u6) {
+__device__ __forceinline__ void tb_steps(T *lds, T *__restrict__ dst, int pitch, int P, int X0,
+                                         int Y0, int nx, int ny, T omega, T u6) {
   constexpr int RS = RW * RH;
   constexpr int JM = ((RW - 2) * (RH - 2) + NT - 1) / NT;   // sites per thread at s = 1
 #pragma unroll
@@ -126,7 +128,7 @@ __device__ __forceinline__ void tb_steps(T *lds, int X0, int Y0, int nx, int ny,
     const int ws = RW - 2 * s, ns = ws * (RH - 2 * s);
     T v[JM][9];
     bool act[JM];
-    int qs[JM];
+    int qs[JM], go[JM];
 #pragma unroll
     for (int j = 0; j < JM; ++j) {
       const int c = threadIdx.x + j * NT;
@@ -135,6 +137,7 @@ __device__ __forceinline__ void tb_steps(T *lds, int X0, int Y0, int nx, int ny,
       const int q = ry * RW + rx;
       const int gx = X0 + rx, gy = Y0 + ry;
       qs[j] = q;
+      go[j] = gy * pitch + gx;
       act[j] = c < ns;
       if (!INTERIOR) act[j] = act[j] && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
       if (act[j]) {
@@ -168,13 +171,21 @@ __device__ __forceinline__ void tb_steps(T *lds, int X0, int Y0, int nx, int ny,
         bgk_collide<T, SHIFT>(v[j], omega);
       }
     }
-    __syncthreads();
+    if (s == K) {
 #pragma unroll
-    for (int j = 0; j < JM; ++j)
-      if (act[j])
+      for (int j = 0; j < JM; ++j)
+        if (act[j])
 #pragma unroll
-        for (int i = 0; i < 9; ++i) lds[i * RS + qs[j]] = v[j][i];
-    __syncthreads();
+          for (int i = 0; i < 9; ++i) dst[i * P + go[j]] = v[j][i];
+    } else {
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < JM; ++j)
+        if (act[j])
+#pragma unroll
+          for (int i = 0; i < 9; ++i) lds[i * RS + qs[j]] = v[j][i];
+      __syncthreads();
+    }
   }
 }
 
@@ -243,26 +254,12 @@ __device__ __forceinline__ void tb_tile(T *lds, const T *__restrict__ src, T *__
 
   // Tiles whose region lies inside the cavity (no wall within reach) take a
   // branch-free pull with constant LDS offsets; the rest test the walls.
+  // The last step stores the core.
   const bool interior = X0 >= 0 && X0 + RW <= nx && Y0 >= 0 && Y0 + RH <= ny;
   if (interior)
-    tb_steps<T, SHIFT, K, RW, RH, NT, true>(lds, X0, Y0, nx, ny, omega, u6);
+    tb_steps<T, SHIFT, K, RW, RH, NT, true>(lds, dst, pitch, P, X0, Y0, nx, ny, omega, u6);
   else
-    tb_steps<T, SHIFT, K, RW, RH, NT, false>(lds, X0, Y0, nx, ny, omega, u6);
-
-  // store the core
-#pragma unroll
-  for (int j = 0; j < J; ++j) {
-    const int q = threadIdx.x + j * NT;
-    if (q < RS) {
-      const int ry = q / RW, rx = q - ry * RW;
-      const int gx = X0 + rx, gy = Y0 + ry;
-      if (rx >= K && rx < K + TX && ry >= K && ry < K + TY && gx < nx && gy < ny) {
-        const int o = gy * pitch + gx;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) dst[i * P + o] = lds[i * RS + q];
-      }
-    }
-  }
+    tb_steps<T, SHIFT, K, RW, RH, NT, false>(lds, dst, pitch, P, X0, Y0, nx, ny, omega, u6);
 }
 
 // MON: 1 / 2 for the first / second launch of a chunk that carries the
