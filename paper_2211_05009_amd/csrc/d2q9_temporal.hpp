@@ -118,13 +118,14 @@ __device__ __forceinline__ void tb_monitor_sums(const T *lds, int X0, int Y0, in
 // compile-time constant in the index arithmetic.  The last window is the
 // tile's core: its sites go from registers straight to dst (pitch, plane
 // stride P), with no write-back to LDS and no barrier after it.
-template <typename T, bool SHIFT, int K, int RW, int RH, int NT, bool INTERIOR>
+// Steps S0 ... K (S0 = 2 after tb_first_step).
+template <typename T, bool SHIFT, int K, int RW, int RH, int NT, int S0, bool INTERIOR>
 __device__ __forceinline__ void tb_steps(T *lds, T *__restrict__ dst, int pitch, int P, int X0,
                                          int Y0, int nx, int ny, T omega, T u6) {
   constexpr int RS = RW * RH;
   constexpr int JM = ((RW - 2) * (RH - 2) + NT - 1) / NT;   // sites per thread at s = 1
 #pragma unroll
-  for (int s = 1; s <= K; ++s) {
+  for (int s = S0; s <= K; ++s) {
     const int ws = RW - 2 * s, ns = ws * (RH - 2 * s);
     T v[JM][9];
     bool act[JM];
@@ -189,8 +190,52 @@ __device__ __forceinline__ void tb_steps(T *lds, T *__restrict__ dst, int pitch,
   }
 }
 
+// Step 1 without the region in LDS: each site of the first window,
+// (RW - 2) x (RH - 2) in row-major order, pulls its nine populations from
+// global memory exactly as k_step does (pull; the +-1 neighbours come from
+// L1 / L2), collides, and leaves the result in LDS for step 2.  No load
+// phase and no barrier precede the first collision: a wavefront computes as
+// soon as its own loads arrive.
+template <typename T, bool SHIFT, int K, int RW, int RH, int NT, bool INTERIOR>
+__device__ __forceinline__ void tb_first_step(T *lds, const T *__restrict__ src, int pitch,
+                                              int P, int X0, int Y0, int nx, int ny, T omega,
+                                              T u6) {
+  constexpr int RS = RW * RH, W1 = RW - 2, N1 = W1 * (RH - 2);
+  constexpr int JM = (N1 + NT - 1) / NT;
+  T v[JM][9];
+  bool act[JM];
+  int qs[JM];
+#pragma unroll
+  for (int j = 0; j < JM; ++j) {
+    const int c = threadIdx.x + j * NT;
+    const int wy = c / W1, wx = c - wy * W1;
+    const int rx = 1 + wx, ry = 1 + wy;
+    const int gx = X0 + rx, gy = Y0 + ry;
+    qs[j] = ry * RW + rx;
+    act[j] = c < N1;
+    if (!INTERIOR) act[j] = act[j] && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    if (act[j]) {
+      // an interior region keeps the first window one site away from every wall
+      if (INTERIOR)
+        pull<T>(src, P, pitch, gy * pitch + gx, true, true, true, true, u6, v[j]);
+      else
+        pull<T>(src, P, pitch, gy * pitch + gx, gx > 0, gx < nx - 1, gy > 0, gy < ny - 1, u6,
+                v[j]);
+      bgk_collide<T, SHIFT>(v[j], omega);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < JM; ++j)
+    if (act[j])
+#pragma unroll
+      for (int i = 0; i < 9; ++i) lds[i * RS + qs[j]] = v[j][i];
+  __syncthreads();
+}
+
 // One tile (tile_x, tile_y) of TX x TY core sites advanced K steps; src and
-// dst point at plane 0 of the cavity.
+// dst point at plane 0 of the cavity.  The launch that takes the monitor
+// sums (MON = 1) loads the region into LDS, since the sums need the start
+// state of every core site; the others take step 1 from global memory.
 // MON: 0, or 1 / 2 for the first / second launch of a monitored chunk.
 template <typename T, bool SHIFT, int K, int TX, int TY, int NT, int MON>
 __device__ __forceinline__ void tb_tile(T *lds, const T *__restrict__ src, T *__restrict__ dst,
@@ -198,6 +243,7 @@ __device__ __forceinline__ void tb_tile(T *lds, const T *__restrict__ src, T *__
                                         int tile_x, int tile_y, const TbMonBlock &mon) {
   constexpr int RW = TX + 2 * K, RH = TY + 2 * K, RS = RW * RH;
   constexpr int J = (RS + NT - 1) / NT;       // region sites per thread
+  static_assert(K >= 2, "the first and the last step take separate paths");
   const int X0 = tile_x * TX - K;             // global x of region column 0
   const int Y0 = tile_y * TY - K;
 
@@ -216,6 +262,28 @@ __device__ __forceinline__ void tb_tile(T *lds, const T *__restrict__ src, T *__
   if (MON == 2 && threadIdx.x < mon.nfin) {
 #pragma unroll
     for (int k = 0; k < kNumSums; ++k) fin[k] = mon.fin[threadIdx.x * kNumSums + k];
+  }
+
+  // Tiles whose region lies inside the cavity (no wall within reach) take a
+  // branch-free pull with constant offsets; the rest test the walls.  The
+  // last step stores the core.
+  const bool interior = X0 >= 0 && X0 + RW <= nx && Y0 >= 0 && Y0 + RH <= ny;
+  if (MON != 1) {
+    if (MON == 2 && mon.nfin > 0) {
+      for (int b = threadIdx.x + NT; b < mon.nfin; b += NT)
+#pragma unroll
+        for (int k = 0; k < kNumSums; ++k) fin[k] += mon.fin[b * kNumSums + k];
+      block_sum_nt<NT, kNumSums>(fin, mon.out);
+    }
+    if (interior) {
+      tb_first_step<T, SHIFT, K, RW, RH, NT, true>(lds, src, pitch, P, X0, Y0, nx, ny, omega, u6);
+      tb_steps<T, SHIFT, K, RW, RH, NT, 2, true>(lds, dst, pitch, P, X0, Y0, nx, ny, omega, u6);
+    } else {
+      tb_first_step<T, SHIFT, K, RW, RH, NT, false>(lds, src, pitch, P, X0, Y0, nx, ny, omega,
+                                                    u6);
+      tb_steps<T, SHIFT, K, RW, RH, NT, 2, false>(lds, dst, pitch, P, X0, Y0, nx, ny, omega, u6);
+    }
+    return;
   }
 
   // Load the region (sites inside the cavity) straight from global memory
@@ -244,22 +312,11 @@ __device__ __forceinline__ void tb_tile(T *lds, const T *__restrict__ src, T *__
   }
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
-  if (MON == 1) tb_monitor_sums<T, SHIFT, K, TX, TY, NT>(lds, X0, Y0, nx, ny, mon, ur);
-  if (MON == 2 && mon.nfin > 0) {
-    for (int b = threadIdx.x + NT; b < mon.nfin; b += NT)
-#pragma unroll
-      for (int k = 0; k < kNumSums; ++k) fin[k] += mon.fin[b * kNumSums + k];
-    block_sum_nt<NT, kNumSums>(fin, mon.out);
-  }
-
-  // Tiles whose region lies inside the cavity (no wall within reach) take a
-  // branch-free pull with constant LDS offsets; the rest test the walls.
-  // The last step stores the core.
-  const bool interior = X0 >= 0 && X0 + RW <= nx && Y0 >= 0 && Y0 + RH <= ny;
+  tb_monitor_sums<T, SHIFT, K, TX, TY, NT>(lds, X0, Y0, nx, ny, mon, ur);
   if (interior)
-    tb_steps<T, SHIFT, K, RW, RH, NT, true>(lds, dst, pitch, P, X0, Y0, nx, ny, omega, u6);
+    tb_steps<T, SHIFT, K, RW, RH, NT, 1, true>(lds, dst, pitch, P, X0, Y0, nx, ny, omega, u6);
   else
-    tb_steps<T, SHIFT, K, RW, RH, NT, false>(lds, dst, pitch, P, X0, Y0, nx, ny, omega, u6);
+    tb_steps<T, SHIFT, K, RW, RH, NT, 1, false>(lds, dst, pitch, P, X0, Y0, nx, ny, omega, u6);
 }
 
 // MON: 1 / 2 for the first / second launch of a chunk that carries the
