@@ -95,7 +95,8 @@ def parse():
                          "500 x (500 Ar) cavities (Ar 0.4/1.0/2.0 x Re 1000/4000/8000) after "
                          "1000 and 200,000 steps; prints one JSON line")
     ap.add_argument("--cpu-baseline", type=int, default=1)
-    ap.add_argument("--cpu-steps", type=int, default=700)
+    ap.add_argument("--cpu-steps", type=int, default=500)
+    ap.add_argument("--cpu-sweep-steps", type=int, default=150)
     ap.add_argument("--copy-probe", type=int, default=0)
     return ap.parse_args()
 
@@ -126,9 +127,10 @@ def events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
-def time_single(lbm, torch, nx, ny, re, dtype, steps, warmup, variant=-1):
+def time_single(lbm, torch, nx, ny, re, dtype, steps, warmup, variant=-1, record=None):
     """Seconds for `steps` steps (HIP events on the library's stream), the
-    shape used and its steps per launch."""
+    shape used and its steps per launch.  `record`, a dict, receives what the
+    timed lbm_step call launched (lbm_last_launches)."""
     stream = torch.cuda.Stream()
     c = lbm.Cavity(nx, ny, re=re, u_lid=0.1, dtype=dtype)
     c.set_stream(stream)
@@ -149,6 +151,8 @@ def time_single(lbm, torch, nx, ny, re, dtype, steps, warmup, variant=-1):
     torch.cuda.synchronize()
     sec = e0.elapsed_time(e1) / 1e3
     assert c.steps_done == t_start + steps
+    if record is not None:
+        record.update(c.last_launches())
     mass = c.mass()
     c.close()
     return sec, (v, k), mass
@@ -161,6 +165,45 @@ def kernel_of(variant, k):
     if variant >= 8:
         return "lbm::k_step_vec (16-byte loads)"
     return "lbm::k_step"
+
+
+def roofline(rec, sec, sites, dtype, nx, ny):
+    """Roofline block of the timed region from what it launched (rec:
+    lbm_last_launches of the timed call).  The dominant kernel is the step
+    kernel that applied most of the steps; its launch time is the region's
+    HIP-event time over its launches when the region ran nothing else,
+    otherwise the region's time per K steps (an upper bound)."""
+    multi = rec["multi_launches"] * rec["steps_per_launch"]
+    if multi >= rec["single_launches"]:
+        v, k, launches = rec["multi_variant"], rec["steps_per_launch"], rec["multi_launches"]
+        others = rec["single_launches"]
+    else:
+        v, k, launches = rec["single_variant"], 1, rec["single_launches"]
+        others = rec["multi_launches"]
+    pure = (others == 0 and rec["monitor_passes"] == 0 and rec["multi_monitor_launches"] == 0
+            and rec["probe_launches"] == 0)
+    bpl = BYTES_PER_SITE[dtype] * sites * k               # algorithmic bytes per launch
+    launch_s = sec / launches if pure else sec * k / rec["steps"]
+    achieved = bpl / launch_s / 1e9
+    traffic = stored_traffic(v, 0, nx, ny, dtype) if pure else None
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+           "kernel": kernel_of(v, k), "variant": v, "steps_per_launch": k,
+           "launches": launches, "bytes_per_launch": bpl,
+           "launch_us": round(launch_s * 1e6, 3), "region_launches": rec,
+           "note": ("launch time = HIP-event time of the timed region / its launches "
+                    "(launch gaps included); the region ran only these launches"
+                    if pure else
+                    "launch time = HIP-event time of the timed region per K steps: the "
+                    "region also ran other launches (region_launches)") +
+                   "; algorithmic bytes count 72 B (FP32) / 144 B (FP64) per site update, "
+                   "so a K-step launch can exceed the HBM peak; traffic = rocprofv3 "
+                   "FETCH_SIZE + WRITE_SIZE per launch of this kernel, calibrated on a "
+                   "plain copy"}
+    if traffic:
+        out["traffic_GBs"] = round(traffic / launch_s / 1e9, 1)
+        out["traffic_frac"] = round(traffic / launch_s / 1e9 / HBM_PEAK_GBS, 4)
+    return out
 
 
 def time_sweep(lbm, torch, re_cases, dtype, steps):
@@ -233,20 +276,63 @@ def copy_bandwidth(torch, nbytes=1 << 30):
     return round(2 * nbytes * 10 / sec / 1e9, 1)
 
 
-def cpu_baseline(nx, ny, re, steps):
-    """The CPU oracle, untouched, on a bounded sample of the same workload."""
+def host_cpu():
+    """Model name of the host CPU and the CPUs this process may use."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count(), len(os.sched_getaffinity(0))
+
+
+def _oracle_run(args):
+    """One oracle cavity (one process, one thread): site updates and seconds."""
+    nx, ny, re, steps = args
     from threadpoolctl import threadpool_limits
     from oracle import d2q9
     with threadpool_limits(limits=1):
         o = d2q9.Cavity(nx, ny, re=re, u_lid=0.1)
-        o.step(10)
+        o.step(2)
         t0 = time.perf_counter()
         o.step(steps)
-        dt = time.perf_counter() - t0
-    return {"value": round(nx * ny * steps / dt / 1e6, 4), "unit": "MLUPS", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{steps} steps of the {nx}x{ny} Re={re:g} cavity after 10 warm-up "
-                      f"steps, NumPy FP64, one thread ({dt:.1f} s)"}
+        return nx * ny * steps, time.perf_counter() - t0
+
+
+def cpu_baseline(nx, ny, re, steps, sweep, sweep_steps):
+    """The CPU oracle, untouched, on bounded samples of the workloads: the
+    headline lattice in one process and one thread, and the 25-cavity sweep
+    with one cavity per process over the CPUs available (at most 16: the
+    host's share of one GPU).  Runs before anything touches the GPU, so the
+    worker processes are plain forks."""
+    import multiprocessing as mp
+    model, nproc, avail = host_cpu()
+    upd, dt = _oracle_run((nx, ny, re, steps))
+    out = {"value": round(upd / dt / 1e6, 4), "unit": "MLUPS", "cores": 1, "kind": "oracle",
+           "sample": f"{steps} steps of the {nx}x{ny} Re={re:g} cavity after 2 warm-up "
+                     f"steps, NumPy FP64, one process, one thread ({dt:.1f} s)",
+           "cpu_model": model, "nproc": nproc, "cpus_available": avail}
+    if sweep:
+        workers = max(1, min(16, avail))
+        jobs = [(x, y, r, sweep_steps) for (x, y, r) in sweep]
+        t0 = time.perf_counter()
+        with mp.get_context("fork").Pool(workers) as pool:
+            res = pool.map(_oracle_run, jobs, chunksize=1)
+        wall = time.perf_counter() - t0
+        total = sum(u for u, _ in res)
+        out["sweep_aggregate"] = {
+            "value": round(total / wall / 1e6, 3), "unit": "MLUPS", "cores": workers,
+            "sample": f"the {len(jobs)} sweep cavities, {sweep_steps} steps each after 2 "
+                      f"warm-up steps, one cavity per process, {workers} processes of one "
+                      f"thread; aggregate = site updates / wall time of the pool "
+                      f"({wall:.1f} s)",
+            "per_process_MLUPS_mean": round(float(sum(u / t for u, t in res)) / len(res)
+                                            / 1e6, 3)}
+    return out
 
 
 def copy_probe(nbytes):
@@ -259,18 +345,21 @@ def copy_probe(nbytes):
     print(json.dumps({"copy_probe_bytes": nbytes, "launches": 10}), flush=True)
 
 
-def stored_traffic(kernel_variant, nx, ny, dtype):
-    """Per-launch HBM traffic measured by rocprofv3 for exactly this kernel
-    source, shape and lattice, else None."""
+def stored_traffic(variant, mon, nx, ny, dtype):
+    """Per-launch HBM traffic (calibrated FETCH_SIZE + WRITE_SIZE bytes)
+    measured by rocprofv3 for exactly this kernel source, shape, monitor
+    form (0: plain launch) and lattice, else None."""
     try:
         with open(TRAFFIC_FILE) as fh:
-            t = json.load(fh)
-    except (OSError, ValueError):
+            entries = json.load(fh)["entries"]
+    except (OSError, ValueError, KeyError, TypeError):
         return None
-    if (t.get("source_hash") != source_hash() or t.get("variant") != kernel_variant
-            or t.get("nx") != nx or t.get("ny") != ny or t.get("storage") != dtype):
-        return None
-    return t.get("bytes_per_launch")
+    for t in entries:
+        if (t.get("source_hash") == source_hash() and t.get("variant") == variant
+                and t.get("mon") == mon and t.get("nx") == nx and t.get("ny") == ny
+                and t.get("storage") == dtype):
+            return t.get("bytes_per_launch")
+    return None
 
 
 def main():
@@ -279,6 +368,15 @@ def main():
         print("bench.py runs on one GPU only: the lattice of one cavity fits one "
               "MI355X; multi-GPU runs are not implemented", file=sys.stderr)
         sys.exit(2)
+    cpu = None
+    if (args.cpu_baseline and not (args.flowmap or args.aux or args.precision
+                                   or args.copy_probe)):
+        # the oracle first: its worker processes are forked before the GPU is touched
+        from cavity_inputs import sweep_cases
+        progress("CPU oracle baseline")
+        ny0 = int(round(args.nx * args.ar))
+        cpu = cpu_baseline(args.nx, ny0, args.re, args.cpu_steps,
+                           sweep_cases(args.nx) if args.sweep else None, args.cpu_sweep_steps)
     import torch
     if args.flowmap:
         return run_flowmap(args)
@@ -299,15 +397,11 @@ def main():
     sites = nx * ny
 
     progress(f"headline {nx}x{ny} {args.dtype}, {args.steps} steps")
+    rec = {}
     sec, (variant, k), mass = time_single(lbm, torch, nx, ny, args.re, args.dtype, args.steps,
-                                          args.warmup, args.variant)
+                                          args.warmup, args.variant, record=rec)
     mlups = sites * args.steps / sec / 1e6
     per_step = sec / args.steps
-    kname = kernel_of(variant, k)
-    bpl = BYTES_PER_SITE[args.dtype] * sites * k          # algorithmic bytes per launch
-    per_launch = per_step * k
-    achieved = bpl / per_launch / 1e9
-    traffic = stored_traffic(variant, nx, ny, args.dtype)
     out = {
         "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
@@ -319,16 +413,7 @@ def main():
                                f"{'FP32 f-w' if args.dtype == 'f32s' else 'FP64'} populations, "
                                f"from rest", "nx": nx, "ny": ny, "re": args.re,
                    "storage": args.dtype, "monitors_every": 100},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": kname, "variant": variant,
-                     "steps_per_launch": k, "bytes_per_launch": bpl,
-                     "launch_us": round(per_launch * 1e6, 3),
-                     "note": "launch time = HIP-event time of the timed region / launches "
-                             "(includes the Eq. 6 monitor every 100 steps, carried by the "
-                             "first two launches of each 100-step chunk, and launch gaps); "
-                             "algorithmic bytes count 72 B (FP32) / 144 B (FP64) per site "
-                             "update, so a K-step launch can exceed the HBM peak"},
+        "roofline": roofline(rec, sec, sites, args.dtype, nx, ny),
         "final_mass": mass,
         "source_hash": source_hash(),
     }
@@ -380,9 +465,8 @@ def main():
         progress("long unsteady cavity with probes")
         out["long_unsteady"] = flowmap.long_unsteady(log=progress)
     out["copy_GBs"] = copy_bandwidth(torch)
-    if args.cpu_baseline:
-        progress("CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(nx, ny, args.re, args.cpu_steps)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

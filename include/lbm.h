@@ -154,6 +154,9 @@ int lbm_info(lbm_t h, lbm_info_t *info);
  *   LBM_OPT_STEPS_PER_LAUNCH  read-only: steps of Eq. 1 one launch of the
  *                         current shape applies (1, or K for the shapes that
  *                         keep a tile in LDS for K steps).
+ *   LBM_OPT_TILE_X, LBM_OPT_TILE_Y  read-only: sites along x and y that one
+ *                         block of the current shape updates (a K-step
+ *                         shape reads a region K sites wider on every side).
  * LBM_EINVAL for an unknown option or an out-of-range value.
  */
 enum {
@@ -162,7 +165,9 @@ enum {
   LBM_OPT_NUM_VARIANTS = 3,
   LBM_OPT_GRAPH_STEPS = 4, /* batches only: steps per captured graph, a
                               multiple of 100 in [100, 100000] (default 1000) */
-  LBM_OPT_STEPS_PER_LAUNCH = 5
+  LBM_OPT_STEPS_PER_LAUNCH = 5,
+  LBM_OPT_TILE_X = 6,
+  LBM_OPT_TILE_Y = 7
 };
 int lbm_set_option(lbm_t h, int option, int64_t value);
 int lbm_get_option(lbm_t h, int option, int64_t *value);
@@ -186,13 +191,40 @@ int lbm_autotune(lbm_t h, int chunks, int use_cache, int *best_variant,
  * step count t that is a multiple of 100 the monitors run: total mass and
  * the Eq. 6 residual against the velocity field of step t - 100 (with the
  * multi-step shapes the monitor of step t runs inside the first two launches
- * of the next 100 steps, or in a separate pass at the end of the call).  If
- * probes are configured (lbm_probe_config) they are recorded every `every`
- * steps.
+ * of the next 100 steps, or in a separate pass before further steps or at
+ * the end of the call).  If probes are configured (lbm_probe_config) they
+ * are recorded every `every` steps.
+ * Execution (results do not depend on it): 100-step chunks starting at a
+ * multiple of 100 are replayed from a captured graph; steps off that grid
+ * run as launches of the current shape's K steps while t is a multiple of K
+ * and K steps remain, and as one-step launches otherwise (a multi-step
+ * shape is used only if its K divides a probe cadence of at most 100).
  * Returns after the work has finished; LBM_EUNSTABLE if the last monitor
  * (or the final state's mass) is not finite.
  */
 int lbm_step(lbm_t h, int64_t n);
+
+/*
+ * What the last lbm_step call on h launched, counting the launches inside
+ * replayed graphs, so that a timing of the call can be attributed to the
+ * kernels that ran.  Shapes are LBM_OPT_STEP_VARIANT indices.  A call that
+ * failed leaves the counts of what was issued before the failure.
+ * Not a passage of the paper: execution bookkeeping only.
+ */
+typedef struct {
+  int64_t steps;                  /* steps of Eq. 1 the call applied */
+  int multi_variant;              /* shape of the K-step launches; -1: none */
+  int steps_per_launch;           /* K of that shape; 0: none */
+  int64_t multi_launches;         /* K-step launches */
+  int64_t multi_monitor_launches; /* of those, launches that also took the
+                                     Eq. 6 monitor sums (two per fused chunk) */
+  int single_variant;             /* shape of the one-step launches; -1: none */
+  int64_t single_launches;        /* one-step launches */
+  int64_t graph_replays;          /* 100-step chunks replayed from a graph */
+  int64_t monitor_passes;         /* separate monitor passes (mass, Eq. 6) */
+  int64_t probe_launches;         /* probe records written */
+} lbm_launch_record_t;
+int lbm_last_launches(lbm_t h, lbm_launch_record_t *out);
 
 /* Number of steps applied since creation or the last lbm_set_populations /
  * lbm_init_fields / lbm_load. */

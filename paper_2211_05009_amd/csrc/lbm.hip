@@ -140,6 +140,29 @@ static int steps_per_launch(int v) {
   return (v >= 0 && v < kNumVariants) ? k[v] : 1;
 }
 
+// Core tile (sites along x, along y) of variant v: the sites one block
+// updates (launch_step_variant's table; FP64 takes smaller tiles for some
+// multi-step shapes).
+static void tile_of(int v, int dtype, int &tx, int &ty) {
+  static const int one[8] = {4, 8, 16, 8, 8, 8, 16, 16};   // k_step: 64 x (BY RY)
+  static const int tb[12][2] = {{32, 32}, {32, 32}, {32, 32}, {32, 32}, {64, 16}, {16, 16},
+                                {64, 16}, {16, 16}, {32, 32}, {64, 32}, {32, 32}, {64, 32}};
+  const bool f64 = dtype == LBM_F64;
+  if (v < 8) {
+    tx = 64;
+    ty = one[v < 0 ? 0 : v];
+  } else if (v < 12) {
+    tx = 64 * (f64 ? 2 : 4);                                // 16-byte vectors
+    ty = 1 << (v - 8);
+  } else {
+    tx = tb[v - 12][0];
+    ty = tb[v - 12][1];
+    if (f64 && v == 20) ty = 16;
+    if (f64 && v == 21) tx = ty = 16;
+    if (f64 && v == 23) ty = 16;
+  }
+}
+
 // Non-equilibrium extrapolation handles have their own one-step shapes.
 static const int kNumNeeVariants = 4;
 
@@ -310,10 +333,15 @@ static hipError_t launch_variant(const lbm_cavity *h, int v, const void *src, vo
   return launch_step_variant<float, true>(h, v, src, dst, st, mon);
 }
 
+// The one-step shape: the chosen shape if it is one, else shape 0.
+static int one_step_variant(const lbm_cavity *h) {
+  return launch_steps(h, h->variant) == 1 ? h->variant : 0;
+}
+
 // One step (a one-step variant: the chosen one, or the default).
 static hipError_t launch_step(const lbm_cavity *h, const void *src, void *dst,
                               hipStream_t st) {
-  return launch_variant(h, launch_steps(h, h->variant) == 1 ? h->variant : 0, src, dst, st);
+  return launch_variant(h, one_step_variant(h), src, dst, st);
 }
 
 // Variant used for 100-step chunks: a multi-step variant only if the probe
@@ -427,6 +455,26 @@ static hipError_t issue_chunk(lbm_cavity *h, int c, hipStream_t st) {
   }
   if (fused) return hipSuccess;
   return launch_monitor(h, h->buf[cur], true, h->mon_dev, st);
+}
+
+// Add one 100-step chunk's launches (issue_chunk) to the call's record.
+static void record_chunk(lbm_cavity *h) {
+  lbm_launch_record_t &rec = h->last_call;
+  const int v = chunk_variant(h);
+  const int K = launch_steps(h, v);
+  if (K > 1) {
+    rec.multi_variant = v;
+    rec.steps_per_launch = K;
+    rec.multi_launches += kChunk / K;
+  } else {
+    rec.single_variant = v;
+    rec.single_launches += kChunk;
+  }
+  if (fused_monitor(h))
+    rec.multi_monitor_launches += 2;
+  else
+    rec.monitor_passes += 1;
+  if (h->probe_n > 0 && h->probe_every <= kChunk) rec.probe_launches += kChunk / h->probe_every;
 }
 
 static int build_graph(lbm_cavity *h, int c) {
@@ -674,6 +722,18 @@ int lbm_get_option(lbm_t h, int option, int64_t *value) {
     case LBM_OPT_STEP_VARIANT: *value = h->variant; return LBM_OK;
     case LBM_OPT_NUM_VARIANTS: *value = num_variants(h); return LBM_OK;
     case LBM_OPT_STEPS_PER_LAUNCH: *value = launch_steps(h, h->variant); return LBM_OK;
+    case LBM_OPT_TILE_X:
+    case LBM_OPT_TILE_Y: {
+      int tx = 64, ty = 4;
+      if (h->wall == LBM_WALL_NEE) {
+        static const int nee[4] = {4, 8, 8, 8};              // k_step_nee: 64 x (BY RY)
+        ty = nee[h->variant];
+      } else {
+        tile_of(h->variant, h->dtype, tx, ty);
+      }
+      *value = option == LBM_OPT_TILE_X ? tx : ty;
+      return LBM_OK;
+    }
     default: return lbm_fail(LBM_EINVAL, "unknown option %d", option);
   }
 }
@@ -692,8 +752,13 @@ int lbm_step(lbm_t h, int64_t n) {
   if (!h) return lbm_fail(LBM_EINVAL, "handle is NULL");
   if (n < 0) return lbm_fail(LBM_EINVAL, "n = %lld < 0", (long long)n);
   if (n == 0) return LBM_OK;
+  h->last_call = lbm_launch_record_t{};
+  h->last_call.multi_variant = -1;
+  h->last_call.single_variant = -1;
+  const int64_t t_start = h->t;
   const double t0 = lbm_wall_seconds();
   const int rc = step_impl(h, n);
+  h->last_call.steps = h->t - t_start;
   const double sec = lbm_wall_seconds() - t0;
   char mass[32], res[32];
   lbm_log_line("{\"kind\": \"cavity\", \"handle\": \"%p\", \"nx\": %d, \"ny\": %d, "
@@ -710,19 +775,29 @@ int lbm_step(lbm_t h, int64_t n) {
 static int step_impl(lbm_t h, int64_t n) {
   bool monitored = false;
   // The state at h->t is a monitor point (a multiple of 100) that no monitor
-  // has seen yet: a fused chunk leaves its end state so.  The next fused
-  // chunk's first launch takes it, or a separate pass before single steps
-  // and at the end of the call.  (A fused chunk also re-monitors a start
-  // state that was seen already: u_ref receives the same values and the
-  // sums it writes are overwritten by a later monitor of this call.)
+  // has seen yet: a fused chunk leaves its end state so, and so does a
+  // multi-step launch off the chunk grid that ends on a multiple of 100.  The
+  // next fused chunk's first launch takes it, or a separate pass before
+  // further launches off the grid and at the end of the call.  (A fused
+  // chunk also re-monitors a start state that was seen already: u_ref
+  // receives the same values and the sums it writes are overwritten by a
+  // later monitor of this call.)
   bool pending = false;
+  lbm_launch_record_t &rec = h->last_call;
   hipError_t e;
   auto monitor_now = [&]() -> int {
     hipError_t me = launch_monitor(h, h->buf[h->cur], true, h->mon_dev, h->stream);
     if (me != hipSuccess) return lbm_fail(LBM_EDEVICE, "monitor: %s", hipGetErrorString(me));
     note_monitor(h);
+    rec.monitor_passes += 1;
     monitored = true;
     pending = false;
+    return LBM_OK;
+  };
+  auto probe_now = [&]() -> int {
+    hipError_t pe = launch_probe_ring(h, h->buf[h->cur], h->stream);
+    if (pe != hipSuccess) return lbm_fail(LBM_EDEVICE, "probe: %s", hipGetErrorString(pe));
+    rec.probe_launches += 1;
     return LBM_OK;
   };
   while (n > 0) {
@@ -739,10 +814,12 @@ static int step_impl(lbm_t h, int64_t n) {
           if (rc != LBM_OK) return rc;
         }
         HIPC(hipGraphLaunch(h->graph[h->cur], h->stream));
+        rec.graph_replays += 1;
       } else {
         e = issue_chunk(h, h->cur, h->stream);
         if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "launch: %s", hipGetErrorString(e));
       }
+      record_chunk(h);
       h->cur = chunk_end(h, h->cur);
       h->t += kChunk;
       n -= kChunk;
@@ -752,28 +829,50 @@ static int step_impl(lbm_t h, int64_t n) {
         note_monitor(h);
       monitored = true;
       if (h->probe_n > 0 && h->probe_every > kChunk && h->t % h->probe_every == 0) {
-        e = launch_probe_ring(h, h->buf[h->cur], h->stream);
-        if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "probe: %s", hipGetErrorString(e));
+        const int rc = probe_now();
+        if (rc != LBM_OK) return rc;
       }
       continue;
     }
-    // single steps up to the next chunk boundary
+    // Off the 100-step grid, up to the next chunk boundary: launches of the
+    // chunk's multi-step shape while t is a multiple of its K and K steps
+    // remain (K divides 100, so no launch crosses a monitor point, and the
+    // chunk shape's K divides the probe cadence), one-step launches for the
+    // rest.
     if (pending) {
       const int rc = monitor_now();
       if (rc != LBM_OK) return rc;
     }
-    e = launch_step(h, h->buf[h->cur], h->buf[1 - h->cur], h->stream);
+    const int v = chunk_variant(h);
+    const int K = launch_steps(h, v);
+    const bool multi = K > 1 && h->t % K == 0 && n >= K;
+    if (multi) {
+      e = launch_variant(h, v, h->buf[h->cur], h->buf[1 - h->cur], h->stream, 0);
+      rec.multi_variant = v;
+      rec.steps_per_launch = K;
+      rec.multi_launches += 1;
+    } else {
+      e = launch_step(h, h->buf[h->cur], h->buf[1 - h->cur], h->stream);
+      rec.single_variant = one_step_variant(h);
+      rec.single_launches += 1;
+    }
     if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "step launch: %s", hipGetErrorString(e));
+    const int done = multi ? K : 1;
     h->cur = 1 - h->cur;
-    h->t += 1;
-    n -= 1;
+    h->t += done;
+    n -= done;
     if (h->probe_n > 0 && h->t % h->probe_every == 0) {
-      e = launch_probe_ring(h, h->buf[h->cur], h->stream);
-      if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "probe: %s", hipGetErrorString(e));
+      const int rc = probe_now();
+      if (rc != LBM_OK) return rc;
     }
     if (h->t % kChunk == 0) {
-      const int rc = monitor_now();
-      if (rc != LBM_OK) return rc;
+      if (fused_monitor(h)) {   // taken by the next fused chunk, or a separate pass
+        pending = true;
+        monitored = true;
+      } else {
+        const int rc = monitor_now();
+        if (rc != LBM_OK) return rc;
+      }
     }
   }
   if (pending) {
@@ -881,6 +980,12 @@ int lbm_autotune(lbm_t h, int chunks, int use_cache, int *best_variant, double *
   tune_cache_store(key, best);
   if (best_variant) *best_variant = best;
   if (ms_per_step) *ms_per_step = best_ms;
+  return LBM_OK;
+}
+
+int lbm_last_launches(lbm_t h, lbm_launch_record_t *out) {
+  if (!h || !out) return lbm_fail(LBM_EINVAL, "NULL argument");
+  *out = h->last_call;
   return LBM_OK;
 }
 

@@ -84,4 +84,6 @@ struct lbm_cavity {
   int64_t t = 0, snap_t = 0, mon_t = -1;
   bool mon_valid = false;
   double last_res = 0, last_mass = 0;
+  // what the last lbm_step call launched
+  lbm_launch_record_t last_call{0, -1, 0, 0, 0, -1, 0, 0, 0, 0};
 };

@@ -24,7 +24,7 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_EIO, LBM_ESTATE 
     0, -1, -2, -3, -4, -5, -6
 LBM_F64, LBM_F32_SHIFTED = 0, 1
 LBM_OPT_USE_GRAPH, LBM_OPT_STEP_VARIANT, LBM_OPT_NUM_VARIANTS, LBM_OPT_GRAPH_STEPS = 1, 2, 3, 4
-LBM_OPT_STEPS_PER_LAUNCH = 5
+LBM_OPT_STEPS_PER_LAUNCH, LBM_OPT_TILE_X, LBM_OPT_TILE_Y = 5, 6, 7
 LBM_INIT_RENORMALISE_MASS, LBM_INIT_ZERO_STAGGERED = 1, 2
 LBM_WALL_BOUNCE_BACK, LBM_WALL_NEE = 0, 1
 WALLS = {"bounce-back": LBM_WALL_BOUNCE_BACK, "nee": LBM_WALL_NEE}
@@ -47,6 +47,17 @@ class lbm_info_t(ct.Structure):
                 ("tau", ct.c_double), ("omega", ct.c_double),
                 ("steps_done", ct.c_int64), ("device_bytes", ct.c_size_t),
                 ("wall", ct.c_int)]
+
+
+class lbm_launch_record_t(ct.Structure):
+    _fields_ = [("steps", ct.c_int64), ("multi_variant", ct.c_int),
+                ("steps_per_launch", ct.c_int), ("multi_launches", ct.c_int64),
+                ("multi_monitor_launches", ct.c_int64), ("single_variant", ct.c_int),
+                ("single_launches", ct.c_int64), ("graph_replays", ct.c_int64),
+                ("monitor_passes", ct.c_int64), ("probe_launches", ct.c_int64)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 def _load():
@@ -84,6 +95,7 @@ SIGNATURES = {
     "lbm_set_option": [_h, ct.c_int, _i64],
     "lbm_get_option": [_h, ct.c_int, ct.POINTER(_i64)],
     "lbm_step": [_h, _i64],
+    "lbm_last_launches": [_h, ct.POINTER(lbm_launch_record_t)],
     "lbm_steps_done": [_h, ct.POINTER(_i64)],
     "lbm_moments": [_h, ct.c_void_p, ct.c_void_p, ct.c_void_p],
     "lbm_moments_device": [_h, ct.c_void_p, ct.c_void_p, ct.c_void_p],
@@ -261,6 +273,13 @@ def lbm_get_option(h, option):
 
 def lbm_step(h, n):
     _check(_lib.lbm_step(h, int(n)))
+
+
+def lbm_last_launches(h):
+    """What the last lbm_step call launched (a dict of the record's fields)."""
+    rec = lbm_launch_record_t()
+    _check(_lib.lbm_last_launches(h, ct.byref(rec)))
+    return rec.as_dict()
 
 
 def lbm_steps_done(h):
@@ -733,6 +752,9 @@ class Cavity:
     def step(self, n=1):
         lbm_step(self.h, n)
         return self
+
+    def last_launches(self):
+        return lbm_last_launches(self.h)
 
     def moments(self):
         return lbm_moments(self.h, self.nx, self.ny)

@@ -97,25 +97,105 @@ def test_parity_random_state(lbm, dtype, nx, ny, tau, seed):
     compare(c, o, dtype, "t=257")
 
 
+def interior_tiles(nx, ny, tx, ty, k):
+    """Tiles of a K-step shape whose region (the tile plus K sites on every
+    side) lies inside the cavity: the ones that take the wall-free pull."""
+    n = 0
+    for by in range((ny + ty - 1) // ty):
+        for bx in range((nx + tx - 1) // tx):
+            x0, y0 = bx * tx - k, by * ty - k
+            n += x0 >= 0 and x0 + tx + 2 * k <= nx and y0 >= 0 and y0 + ty + 2 * k <= ny
+    return n
+
+
 @pytest.mark.parametrize("dtype", ["f64", "f32s"])
-def test_variants_graph_and_direct_launch_agree_bitwise(lbm, dtype):
+@pytest.mark.parametrize("nx,ny", [(131, 77), (260, 150)])
+def test_variants_graph_and_direct_launch_agree_bitwise(lbm, dtype, nx, ny):
     """Every tile shape and both launch paths compute the same per-site
-    arithmetic, so their results agree bit for bit."""
-    nx, ny = 131, 77
+    arithmetic, so their results agree bit for bit.  On 260 x 150 every
+    multi-step shape has tiles away from the walls (the wall-free pull) as
+    well as wall tiles and ragged edge tiles; 230 steps are two chunks and a
+    30-step span off the chunk grid."""
     f0 = W[:, None, None] + random_shift(nx, ny, 7)
     ref = None
     c = lbm.Cavity(nx, ny, tau=0.56, u_lid=U_LID, dtype=dtype)
     nvar = c.get_option(lbm.LBM_OPT_NUM_VARIANTS)
     for v in range(nvar):
+        c.set_option(lbm.LBM_OPT_STEP_VARIANT, v)
+        k = c.get_option(lbm.LBM_OPT_STEPS_PER_LAUNCH)
+        tx, ty = c.get_option(lbm.LBM_OPT_TILE_X), c.get_option(lbm.LBM_OPT_TILE_Y)
+        if k > 1 and nx >= 260:
+            assert interior_tiles(nx, ny, tx, ty, k) > 0, (v, tx, ty, k)
+            assert nx % tx and ny % ty, "ragged edge tiles"
         for graph in (1, 0):
-            c.set_option(lbm.LBM_OPT_STEP_VARIANT, v)
             c.set_option(lbm.LBM_OPT_USE_GRAPH, graph)
             c.set_populations(f0)
             c.step(230)
+            rec = c.last_launches()
+            if k > 1:   # the 30-step span: 30 // K launches of K steps, the rest single
+                assert rec["multi_variant"] == v and rec["single_launches"] == 30 % k, rec
+                assert rec["multi_launches"] * k + rec["single_launches"] == 230, rec
             f = c.get_populations()
             if ref is None:
                 ref = f
             assert np.array_equal(f, ref), (v, graph)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32s"])
+@pytest.mark.parametrize("variant", [22, 12, 20, 14])
+def test_short_and_unaligned_calls(lbm, dtype, variant):
+    """Calls shorter than or off the 100-step chunk grid run the multi-step
+    shape's K-step launches wherever t is a multiple of K and K steps remain
+    (one-step launches otherwise), and give the same populations, bit for
+    bit, as one-step launches of shape 0; monitors land on the same steps
+    and agree to 1e-12 relative; probe records every 10 steps (a multiple of
+    K = 2, 5, 10; not of K = 4, which falls back to one-step launches) are
+    identical.  FP64 is checked against the oracle at the end."""
+    nx, ny, tau = 131, 77, 0.56
+    f0 = W[:, None, None] + random_shift(nx, ny, 31)
+    calls = [20, 37, 3, 140, 45, 7, 250, 1, 99]
+    pts = np.array([[0.5, 0.5], [0.1, 0.55], [0.9, 0.1]])
+    runs = {}
+    for v in (0, variant):
+        c = lbm.Cavity(nx, ny, tau=tau, u_lid=U_LID, dtype=dtype)
+        c.set_option(lbm.LBM_OPT_STEP_VARIANT, v)
+        c.set_populations(f0)
+        c.probe_config(pts, 10, 1000)
+        k = c.get_option(lbm.LBM_OPT_STEPS_PER_LAUNCH)
+        states, mons, recs = [], [], []
+        for n in calls:
+            t0 = c.steps_done
+            c.step(n)
+            rec = c.last_launches()
+            assert rec["steps"] == n
+            assert rec["single_launches"] + k * rec["multi_launches"] == n, rec
+            recs.append(rec)
+            states.append(c.get_populations())
+            mons.append((c.mass(), *c.residual()))
+            if v == variant and k > 1 and 10 % k == 0 and t0 % k == 0 and n % k == 0:
+                assert rec["single_launches"] == 0, (t0, n, rec)
+        runs[v] = (states, mons, recs, c.probe_read(1000), k)
+        c.close()
+    s0, m0, _, p0, _ = runs[0]
+    s1, m1, r1, p1, k = runs[variant]
+    for a, b, n in zip(s0, s1, calls):
+        assert np.array_equal(a, b), n
+    for (ma, ra, ta), (mb, rb, tb) in zip(m0, m1):
+        assert ta == tb
+        assert abs(ma - mb) <= 1e-12 * nx * ny
+        assert (math.isinf(ra) and math.isinf(rb)) or abs(ra - rb) <= 1e-12 * abs(ra)
+    assert np.array_equal(p0, p1)
+    # the first call (20 steps from t = 0) is K-step launches only when K
+    # divides both 20 and the probe cadence
+    if 10 % k == 0:
+        assert r1[0]["multi_launches"] == 20 // k and r1[0]["single_launches"] == 0
+        assert r1[0]["multi_variant"] == variant
+    else:
+        assert r1[0]["multi_launches"] == 0 and r1[0]["single_launches"] == 20
+    if dtype == "f64":
+        o = oracle_from(f0, tau).step(sum(calls))
+        fo = o.post_collision()
+        assert np.max(np.abs(s1[-1] - fo)) <= F64_TOL
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32s"])
@@ -191,7 +271,9 @@ def _light_cone_check(f_start, f_end, tau, n, width, dtype, what):
 
 @pytest.mark.parametrize("dtype,nx,ny,variant", [
     ("f32s", 500, 500, 22), ("f64", 500, 500, 22), ("f32s", 500, 1000, 21),
-    ("f64", 500, 1000, 19), ("f32s", 4096, 4096, 22), ("f64", 4096, 4096, 19)])
+    ("f64", 500, 1000, 19), ("f32s", 4096, 4096, 22), ("f64", 4096, 4096, 19),
+    ("f32s", 4096, 4096, 16), ("f32s", 4096, 4096, 18), ("f32s", 4096, 4096, 23),
+    ("f64", 4096, 4096, 16), ("f64", 4096, 4096, 18), ("f64", 4096, 4096, 23)])
 def test_full_size_chunk_in_the_timed_shape(lbm, dtype, nx, ny, variant):
     """A 100-step chunk as the benchmark runs it (graph replay, the
     multi-step shape the autotuner picks for this lattice and storage, the
