@@ -322,6 +322,31 @@ int lbm_classify_series(const double *series_dev, int nseries, int64_t n, int64_
                         lbm_flow_state_t *out_host, void *hip_stream);
 
 /*
+ * lbm_classify_series for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same inputs, definition and results, bit for bit; but:
+ *   - out_dev: nseries records in caller-owned DEVICE memory, written by
+ *     the kernel;
+ *   - asynchronous: the work is only issued on hip_stream (NULL: the
+ *     default stream) of the current device; read out_dev after that stream
+ *     has finished.  No allocation, no host copy, no synchronisation.
+ *   - its work memory is a fixed 32 MiB array per device (held from the
+ *     library's load until the process ends): nseries * (2 n + 8) doubles
+ *     must not exceed 4 Mi (4,194,304) doubles, e.g. 209 series of 10,000
+ *     samples; LBM_EINVAL otherwise, checked before anything is issued;
+ *   - every call on a device shares that device's array: calls that overlap
+ *     in time on one device (on different streams, or from several host
+ *     threads) race and give undefined results; calls issued one after
+ *     another on one stream are safe.  Nothing in the array needs clearing
+ *     between calls (each call writes every value it reads).
+ * Errors: as lbm_classify_series; LBM_EDEVICE if the array's device address
+ * cannot be obtained or the launch fails.
+ */
+int lbm_classify_series_noalloc(const double *series_dev, int nseries, int64_t n, int64_t ld,
+                                double steady_tol, double periodic_tol, int min_lag,
+                                int max_lag, lbm_flow_state_t *out_dev, void *hip_stream);
+
+/*
  * Classify the recorded probe series of h (lbm_probe_config) directly on
  * the device: for each probe point, component c (0: rho, 1: u_x, 2: u_y)
  * over the most recent `window` records, one record per `every` steps (so

@@ -54,15 +54,15 @@ __device__ __forceinline__ void series_reduce(double &sum, double &mn, double &m
   __syncthreads();
 }
 
-// work: per series, n doubles (the unwrapped series) followed by the D
-// values of lags min_lag .. max_lag; work_stride doubles per series.
-static __global__ __launch_bounds__(kSeriesThreads) void k_classify_series(
-    const SeriesDesc *__restrict__ desc, double steady_tol, double periodic_tol, int min_lag,
-    int max_lag_req, double *__restrict__ work, long long work_stride,
-    SeriesOut *__restrict__ out) {
+// One block classifies series d; u: n + (number of lags) doubles of scratch
+// (the unwrapped series, then the D values of lags min_lag .. max_lag).
+// Returns true on thread 0, which holds the result in r; the other threads
+// return false.
+__device__ __forceinline__ bool classify_block(const SeriesDesc &d, double steady_tol,
+                                               double periodic_tol, int min_lag,
+                                               int max_lag_req, double *__restrict__ u,
+                                               SeriesOut &r) {
   __shared__ double s0[kSeriesThreads], s1[kSeriesThreads], s2[kSeriesThreads];
-  const SeriesDesc d = desc[blockIdx.x];
-  double *u = work + (long long)blockIdx.x * work_stride;
   const long long n = d.n;
   for (long long k = threadIdx.x; k < n; k += kSeriesThreads)
     u[k] = d.base[((d.start + k) % d.cap) * d.stride];
@@ -85,7 +85,6 @@ static __global__ __launch_bounds__(kSeriesThreads) void k_classify_series(
   series_reduce(ss, dummy0, dummy1, s0, s1, s2);
   const double sd = sqrt(ss / (double)n);
   const double amp = mx - mn;
-  SeriesOut r;
   r.period = 0.0;
   r.amplitude = amp;
   r.mean = mean;
@@ -95,10 +94,7 @@ static __global__ __launch_bounds__(kSeriesThreads) void k_classify_series(
   r.cycle_mismatch = 0.0;
   r.state = 0;
   r.lag = 0;
-  if (amp <= steady_tol) {
-    if (threadIdx.x == 0) out[blockIdx.x] = r;
-    return;
-  }
+  if (amp <= steady_tol) return threadIdx.x == 0;
   long long max_lag = max_lag_req > 0 ? max_lag_req : n / 3;
   if (max_lag > n - 2) max_lag = n - 2;
   const long long nlags = max_lag - min_lag + 1;
@@ -114,7 +110,7 @@ static __global__ __launch_bounds__(kSeriesThreads) void k_classify_series(
     D[j] = acc / (double)(n - T) * inv_var;
   }
   __syncthreads();
-  if (threadIdx.x != 0) return;
+  if (threadIdx.x != 0) return false;
   double best = INFINITY;
   bool decorrelated = false;
   r.state = 2;
@@ -138,8 +134,7 @@ static __global__ __launch_bounds__(kSeriesThreads) void k_classify_series(
       r.lag = (int)(min_lag + j);
       r.period = period;
       r.mismatch = mis;
-      out[blockIdx.x] = r;
-      return;
+      return true;
     }
   }
   r.mismatch = best;
@@ -147,7 +142,44 @@ static __global__ __launch_bounds__(kSeriesThreads) void k_classify_series(
     r.state = 3;
     r.cycle_mismatch = INFINITY;
   }
-  out[blockIdx.x] = r;
+  return true;
+}
+
+// Series described by desc[]; work_stride doubles of scratch per series.
+static __global__ __launch_bounds__(kSeriesThreads) void k_classify_series(
+    const SeriesDesc *__restrict__ desc, double steady_tol, double periodic_tol, int min_lag,
+    int max_lag_req, double *__restrict__ work, long long work_stride,
+    SeriesOut *__restrict__ out) {
+  SeriesOut r;
+  if (classify_block(desc[blockIdx.x], steady_tol, periodic_tol, min_lag, max_lag_req,
+                     work + (long long)blockIdx.x * work_stride, r))
+    out[blockIdx.x] = r;
+}
+
+// Plain strided series: series s at series + s * ld, n samples; the result
+// of series s goes to out[s] in the ABI's record layout (OutRec: the fields
+// of lbm_flow_state_t).
+template <typename OutRec>
+__global__ __launch_bounds__(kSeriesThreads) void k_classify_strided(
+    const double *__restrict__ series, long long n, long long ld, double steady_tol,
+    double periodic_tol, int min_lag, int max_lag_req, double *__restrict__ work,
+    long long work_stride, OutRec *__restrict__ out) {
+  const SeriesDesc d{series + (long long)blockIdx.x * ld, n, 0, n, 1};
+  SeriesOut r;
+  if (classify_block(d, steady_tol, periodic_tol, min_lag, max_lag_req,
+                     work + (long long)blockIdx.x * work_stride, r)) {
+    OutRec o;
+    o.state = r.state;
+    o.lag = r.lag;
+    o.period = r.period;
+    o.amplitude = r.amplitude;
+    o.mean = r.mean;
+    o.std = r.std;
+    o.mismatch = r.mismatch;
+    o.cycle = r.cycle;
+    o.cycle_mismatch = r.cycle_mismatch;
+    out[blockIdx.x] = o;
+  }
 }
 
 }  // namespace lbm

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "../../include/lbm.h"
@@ -87,4 +88,75 @@ int lbm_classify_series(const double *series_dev, int nseries, int64_t n, int64_
   for (int s = 0; s < nseries; ++s) d[s] = SeriesDesc{series_dev + (long long)s * ld, n, 0, n, 1};
   return classify_series_descs(d.data(), nseries, n, steady_tol, periodic_tol, min_lag, max_lag,
                                (hipStream_t)hip_stream, out_host);
+}
+
+// ------------------------------------------------ no-allocation classifier
+// Work memory of lbm_classify_series_noalloc: one array per device, held
+// from the library's load until the process ends.  Host code never uses the
+// name `scratch` as an address (in host code it is a stand-in, not device
+// memory): each device's address comes from hipGetSymbolAddress, taken once
+// per device on that entry point's first call there.
+constexpr long long kNoAllocScratchDoubles = 4LL << 20;   // 32 MiB
+static __device__ __align__(256) double scratch[kNoAllocScratchDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mutex;
+static double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (nullptr and an
+// error message on failure).
+static double *scratch_for_current_device(int &rc) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    rc = lbm_fail(LBM_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    return nullptr;
+  }
+  if (dev < 0 || dev >= kMaxDevices) {
+    rc = lbm_fail(LBM_EDEVICE, "device %d beyond the %d this entry point supports", dev,
+                  kMaxDevices);
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      rc = lbm_fail(LBM_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                    hipGetErrorString(e));
+      return nullptr;
+    }
+    g_scratch_ptr[dev] = static_cast<double *>(p);
+  }
+  rc = LBM_OK;
+  return g_scratch_ptr[dev];
+}
+
+int lbm_classify_series_noalloc(const double *series_dev, int nseries, int64_t n, int64_t ld,
+                                double steady_tol, double periodic_tol, int min_lag,
+                                int max_lag, lbm_flow_state_t *out_dev, void *hip_stream) {
+  if (!series_dev || !out_dev) return lbm_fail(LBM_EINVAL, "NULL argument");
+  if (nseries < 1) return lbm_fail(LBM_EINVAL, "nseries = %d < 1", nseries);
+  if (ld < n) return lbm_fail(LBM_EINVAL, "ld = %lld < n = %lld", (long long)ld, (long long)n);
+  if (!(steady_tol >= 0.0) || !(periodic_tol >= 0.0))
+    return lbm_fail(LBM_EINVAL, "tolerances must be >= 0 (steady %g, periodic %g)", steady_tol,
+                    periodic_tol);
+  int rc = check_lags(n, min_lag, max_lag);
+  if (rc) return rc;
+  // the same work layout as lbm_classify_series: the series, then its lags
+  const long long stride = 2 * (long long)n + 8;
+  if ((long long)nseries > kNoAllocScratchDoubles / stride)
+    return lbm_fail(LBM_EINVAL,
+                    "nseries * (2 n + 8) = %d * %lld doubles exceeds the %lld-double (32 MiB) "
+                    "work array of the no-allocation classifier; classify fewer or shorter "
+                    "series per call",
+                    nseries, stride, kNoAllocScratchDoubles);
+  double *work = scratch_for_current_device(rc);
+  if (!work) return rc;
+  hipLaunchKernelGGL(k_classify_strided<lbm_flow_state_t>, dim3(nseries), dim3(kSeriesThreads), 0,
+                     (hipStream_t)hip_stream, series_dev, (long long)n, (long long)ld, steady_tol,
+                     periodic_tol, min_lag, max_lag, work, stride, out_dev);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "classify launch: %s", hipGetErrorString(e));
+  return LBM_OK;
 }

@@ -107,6 +107,8 @@ SIGNATURES = {
     "lbm_stream_function": [_h, ct.c_void_p],
     "lbm_classify_series": [ct.c_void_p, ct.c_int, _i64, _i64, ct.c_double, ct.c_double,
                             ct.c_int, ct.c_int, ct.c_void_p, ct.c_void_p],
+    "lbm_classify_series_noalloc": [ct.c_void_p, ct.c_int, _i64, _i64, ct.c_double,
+                                    ct.c_double, ct.c_int, ct.c_int, ct.c_void_p, ct.c_void_p],
     "lbm_probe_classify": [_h, ct.c_int, _i64, ct.c_double, ct.c_double, ct.c_int, ct.c_int,
                            ct.c_void_p],
     "lbm_vortex_extrema": [_h, ct.c_void_p],
@@ -375,6 +377,29 @@ def lbm_classify_series(series_dev, steady_tol, periodic_tol, min_lag=1, max_lag
                                     float(periodic_tol), int(min_lag), int(max_lag), out,
                                     _stream_ptr(stream)))
     return [o.as_dict() for o in out]
+
+
+def lbm_classify_series_noalloc(series_dev, steady_tol, periodic_tol, out_dev, min_lag=1,
+                                max_lag=0, stream=None):
+    """lbm_classify_series into out_dev, a device tensor of at least
+    nseries * sizeof(FlowState) bytes, issued on `stream` without allocating
+    or synchronising (read out_dev after the stream has finished; see
+    flow_states_from_bytes)."""
+    ns, n = int(series_dev.shape[0]), int(series_dev.shape[1])
+    if series_dev.stride(1) != 1:
+        raise ValueError("rows must be contiguous")
+    if out_dev.numel() * out_dev.element_size() < ns * ct.sizeof(FlowState):
+        raise ValueError(f"out_dev holds fewer than {ns} records")
+    _check(_lib.lbm_classify_series_noalloc(
+        ct.c_void_p(series_dev.data_ptr()), ns, n, int(series_dev.stride(0)),
+        float(steady_tol), float(periodic_tol), int(min_lag), int(max_lag),
+        ct.c_void_p(out_dev.data_ptr()), _stream_ptr(stream)))
+
+
+def flow_states_from_bytes(raw, n):
+    """The first n lbm_flow_state_t records of a host byte buffer, as dicts."""
+    recs = (FlowState * n).from_buffer_copy(bytes(raw[:n * ct.sizeof(FlowState)]))
+    return [r.as_dict() for r in recs]
 
 
 def lbm_probe_classify(h, npts, component, window, steady_tol, periodic_tol, min_lag=1,
