@@ -128,15 +128,15 @@ void tune_cache_store(const std::string &key, int variant) {
 // 64 x BY threads.  Vector (k_step_vec): tile (64 V) x BY sites, V = 16 B /
 // element, block 64 x BY.  Temporal (k_step_tb, variants 12-23): K steps per
 // launch on TX x TY tiles held in LDS.  All give bit-identical results.
-static const int kNumVariants = 24;
+static const int kNumVariants = 29;
 // K = 5 steps per launch on 32 x 32 tiles, 1024 threads: the fastest shape
 // on the 500 x (500 Ar) lattices on gfx950 (lbm_autotune refines it).
 static const int kDefaultVariant = 22;
 
 // Steps applied by one launch of variant v.
 static int steps_per_launch(int v) {
-  static const int k[kNumVariants] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1,
-                                      4, 4, 2, 5, 4, 4, 5, 5, 10, 10, 5, 5};
+  static const int k[kNumVariants] = {1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 1, 4, 4, 2,
+                                      5, 4, 4, 5, 5, 10, 10, 5, 5, 5, 4, 5, 5, 5};
   return (v >= 0 && v < kNumVariants) ? k[v] : 1;
 }
 
@@ -145,8 +145,9 @@ static int steps_per_launch(int v) {
 // multi-step shapes).
 static void tile_of(int v, int dtype, int &tx, int &ty) {
   static const int one[8] = {4, 8, 16, 8, 8, 8, 16, 16};   // k_step: 64 x (BY RY)
-  static const int tb[12][2] = {{32, 32}, {32, 32}, {32, 32}, {32, 32}, {64, 16}, {16, 16},
-                                {64, 16}, {16, 16}, {32, 32}, {64, 32}, {32, 32}, {64, 32}};
+  static const int tb[17][2] = {{32, 32}, {32, 32}, {32, 32}, {32, 32}, {64, 16}, {16, 16},
+                                {64, 16}, {16, 16}, {32, 32}, {64, 32}, {32, 32}, {64, 32},
+                                {32, 32}, {32, 32}, {32, 16}, {32, 48}, {32, 64}};
   const bool f64 = dtype == LBM_F64;
   if (v < 8) {
     tx = 64;
@@ -160,6 +161,8 @@ static void tile_of(int v, int dtype, int &tx, int &ty) {
     if (f64 && v == 20) ty = 16;
     if (f64 && v == 21) tx = ty = 16;
     if (f64 && v == 23) ty = 16;
+    if (f64 && (v == 24 || v == 25)) tx = ty = 16;
+    if (f64 && (v == 27 || v == 28)) tx = 16;
   }
 }
 
@@ -247,7 +250,7 @@ static hipError_t launch_step_vec_t(const lbm_cavity *h, const void *src, void *
 // mon = 1 / 2: the first / second launch of a chunk that carries the Eq. 6
 // monitor of its start state (reference field uref, result in mon_dev; see
 // TbMonitor); 0: a plain launch.
-template <typename T, bool S, int K, int TX, int TY, int NT>
+template <typename T, bool S, int K, int TX, int TY, int NT, bool PP = false>
 static hipError_t launch_tb_t(const lbm_cavity *h, const void *src, void *dst,
                               hipStream_t st, int mon) {
   StepParams<T> p;
@@ -264,14 +267,14 @@ static hipError_t launch_tb_t(const lbm_cavity *h, const void *src, void *dst,
   if (mon > 0 && tx * ty > h->partial_slots) return hipErrorInvalidValue;
   const TbMonitor m{h->uref, h->partials, h->mon_dev};
   if (mon == 1)
-    hipLaunchKernelGGL((k_step_tb<T, S, K, TX, TY, NT, 1>), dim3(tx * ty), dim3(NT), 0, st, p,
-                       tx, m);
+    hipLaunchKernelGGL((k_step_tb<T, S, K, TX, TY, NT, 1, PP>), dim3(tx * ty), dim3(NT), 0,
+                       st, p, tx, m);
   else if (mon == 2)
-    hipLaunchKernelGGL((k_step_tb<T, S, K, TX, TY, NT, 2>), dim3(tx * ty), dim3(NT), 0, st, p,
-                       tx, m);
+    hipLaunchKernelGGL((k_step_tb<T, S, K, TX, TY, NT, 2, PP>), dim3(tx * ty), dim3(NT), 0,
+                       st, p, tx, m);
   else
-    hipLaunchKernelGGL((k_step_tb<T, S, K, TX, TY, NT, 0>), dim3(tx * ty), dim3(NT), 0, st, p,
-                       tx, m);
+    hipLaunchKernelGGL((k_step_tb<T, S, K, TX, TY, NT, 0, PP>), dim3(tx * ty), dim3(NT), 0,
+                       st, p, tx, m);
   return hipGetLastError();
 }
 
@@ -306,6 +309,33 @@ static hipError_t launch_step_variant(const lbm_cavity *h, int v, const void *sr
         return launch_tb_t<T, S, 5, 64, 16, 1024>(h, src, dst, st, mon);
       else
         return launch_tb_t<T, S, 5, 64, 32, 1024>(h, src, dst, st, mon);
+    // two LDS buffers (one barrier per in-LDS step)
+    case 24:
+      if constexpr (sizeof(T) == 8)
+        return launch_tb_t<T, S, 5, 16, 16, 256, true>(h, src, dst, st, mon);
+      else
+        return launch_tb_t<T, S, 5, 32, 32, 1024, true>(h, src, dst, st, mon);
+    case 25:
+      if constexpr (sizeof(T) == 8)
+        return launch_tb_t<T, S, 4, 16, 16, 256, true>(h, src, dst, st, mon);
+      else
+        return launch_tb_t<T, S, 4, 32, 32, 1024, true>(h, src, dst, st, mon);
+    case 26:
+      if constexpr (sizeof(T) == 8)
+        return launch_tb_t<T, S, 5, 32, 16, 512>(h, src, dst, st, mon);
+      else
+        return launch_tb_t<T, S, 5, 32, 16, 512, true>(h, src, dst, st, mon);
+    // tall tiles: one tile per CU on 500 x 750 (32 x 48) and 500 x 1000 (32 x 64)
+    case 27:
+      if constexpr (sizeof(T) == 8)
+        return launch_tb_t<T, S, 5, 16, 48, 512>(h, src, dst, st, mon);
+      else
+        return launch_tb_t<T, S, 5, 32, 48, 1024>(h, src, dst, st, mon);
+    case 28:
+      if constexpr (sizeof(T) == 8)
+        return launch_tb_t<T, S, 5, 16, 64, 512>(h, src, dst, st, mon);
+      else
+        return launch_tb_t<T, S, 5, 32, 64, 1024>(h, src, dst, st, mon);
     case 0: return launch_step_t<T, S, 4, 1>(h, src, dst, st);
     case 1: return launch_step_t<T, S, 4, 2>(h, src, dst, st);
     case 2: return launch_step_t<T, S, 4, 4>(h, src, dst, st);
@@ -317,7 +347,8 @@ static hipError_t launch_step_variant(const lbm_cavity *h, int v, const void *sr
     case 8: return launch_step_vec_t<T, S, 1>(h, src, dst, st);
     case 9: return launch_step_vec_t<T, S, 2>(h, src, dst, st);
     case 10: return launch_step_vec_t<T, S, 4>(h, src, dst, st);
-    default: return launch_step_vec_t<T, S, 8>(h, src, dst, st);
+    case 11: return launch_step_vec_t<T, S, 8>(h, src, dst, st);
+    default: return hipErrorInvalidValue;   // a shape without a kernel
   }
 }
 
