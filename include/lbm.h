@@ -357,7 +357,8 @@ int lbm_probe_classify(lbm_t h, int component, int64_t window, double steady_tol
                        double periodic_tol, int min_lag, int max_lag,
                        lbm_flow_state_t *out_host);
 
-/* Total mass sum_x rho(x) now, accumulated in FP64. */
+/* Total mass sum_x rho(x) now, rho the zeroth moment of Eq. 3 (Sec. 2.1),
+ * accumulated in FP64 (a fixed-order reduction on the device). */
 int lbm_mass(lbm_t h, double *mass);
 
 /*

@@ -19,6 +19,20 @@ import numpy as np
 
 from . import lbm
 
+
+def _inputs():
+    """The repository's seeded-input module (cavity_inputs.py beside the
+    package), found from this file's location, so the runner works from any
+    working directory."""
+    import importlib.util
+    import os
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                        "cavity_inputs.py")
+    spec = importlib.util.spec_from_file_location("cavity_inputs", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
 U = 0.1
 
 
@@ -91,11 +105,10 @@ def config4(threshold=1e-8):
     """Learned warm start: train on 200 solver fields, then steps to Eq. 6 <
     threshold for the steady sweep (FP64 storage), cold and warm-started."""
     from . import warmstart
-    from cavity_inputs import normal_draws
     npar = lbm.Surrogate(1).num_params
     return {"config": 4, **warmstart.steady_sweep_study(
-        normal_draws(npar, seed=0), threshold=threshold, dtype="f64",
-        modes=("batch-cold", "batch-warm"))}
+        _inputs().normal_draws(npar, seed=0), threshold=threshold, dtype="f64",
+        modes=("batch-cold", "batch-warm", "batch-warm-fallback"))}
 
 
 def config5():

@@ -77,9 +77,14 @@ def state_map(cases, nx=500, steps=3_000_000, window=10_000, dtype="f32s",
                  "MLUPS": round(sites * steps / seconds / 1e6, 1)}
 
 
+# Probes of the long unsteady run, in units of L: the paper's three
+# observing points (0.5, 0.5), (0.5, 0.3), (0.5, 0.2) (Sec. 3.3) and two
+# points near the bottom corner eddies.
+LONG_PROBES = ((0.5, 0.5), (0.5, 0.3), (0.5, 0.2), (0.1, 0.1), (0.9, 0.1))
+
+
 def long_unsteady(nx=500, ar=1.5, re=8000.0, steps=2_000_000, dtype="f32s", window=10_000,
-                  points=((0.5, 0.5), (0.5, 1.0), (0.25, 0.25), (0.75, 0.25), (0.5, 1.4)),
-                  steady_tol=1e-4 * U_LID, periodic_tol=0.05, log=None):
+                  points=LONG_PROBES, steady_tol=1e-4 * U_LID, periodic_tol=0.05, log=None):
     """One long unsteady cavity with probes every 100 steps (FP64-interpolated
     moments), timed with the probes inside the run, then classified."""
     import torch

@@ -78,16 +78,18 @@ def sample_cases(n, seed, re_range=(100.0, 3000.0), ar_range=(0.4, 2.0)):
 
 
 def solve_steady(nx, ny, re, threshold, max_steps, dtype="f32s", chunk=10000,
-                 warm=None, log=None, log_every=30.0):
+                 warm=None, log=None, log_every=30.0, warm_mask=None):
     """Run a batch of cavities (lists nx, ny, re) from rest (or warm-started
-    by `warm`, a Surrogate) until every Eq. 6 residual is below `threshold`
-    or `max_steps` is reached.  Returns the batch (kept alive) and a list of
-    per-cavity dicts with the steps taken and the final residual.  With
-    `log`, reports the number of running cavities every `log_every` s."""
+    by `warm`, a Surrogate: every cavity, or those whose `warm_mask` entry is
+    true) until every Eq. 6 residual is below `threshold` or `max_steps` is
+    reached.  Returns the batch (kept alive) and a list of per-cavity dicts
+    with the steps taken and the final residual.  With `log`, reports the
+    number of running cavities every `log_every` s."""
     b = lbm.Batch(nx, ny, re, u_lid=U_LID, dtype=dtype)
     if warm is not None:
         for k in range(len(nx)):
-            warm.warm_start_batch(b, k)
+            if warm_mask is None or warm_mask[k]:
+                warm.warm_start_batch(b, k)
     b.set_threshold(threshold)
     done = 0
     t_log = time.perf_counter()
@@ -173,15 +175,17 @@ def evaluate(sur, data):
     return float((((out - data["target"]) ** 2) * m).sum() / data["mask"].sum())
 
 
-def time_to_steady(cases, threshold, max_steps, mode, sur=None, dtype="f32s", log=None):
+def time_to_steady(cases, threshold, max_steps, mode, sur=None, dtype="f32s", log=None,
+                   ar_cut=None):
     """Wall time and steps to reach Eq. 6 residual < threshold for every
     cavity in `cases` ((nx, ny, re) list).
 
     mode: "single-cold" (one cavity after another, from rest: the plain
-    method), "single-warm", "batch-cold", "batch-warm".  Warm starts include
-    the surrogate inference and the mapping onto the lattice in the time.
-    `log` receives a progress line per cavity (single modes) or every 30 s
-    (batch modes)."""
+    method), "single-warm", "batch-cold", "batch-warm", "batch-warm-fallback"
+    (warm start only for cavities with Ny / Nx >= ar_cut, the others from
+    rest).  Warm starts include the surrogate inference and the mapping onto
+    the lattice in the time.  `log` receives a progress line per cavity
+    (single modes) or every 30 s (batch modes)."""
     import torch
     if mode not in TTS_MODES:
         raise ValueError(f"unknown mode {mode!r}: one of {TTS_MODES}")
@@ -206,9 +210,12 @@ def time_to_steady(cases, threshold, max_steps, mode, sur=None, dtype="f32s", lo
                 log(f"{mode} {len(steps)}/{len(cases)}: {nx} x {ny}, Re {re:g}: {done} steps")
     else:
         nx, ny, re = zip(*cases)
+        mask = None
+        if mode == "batch-warm-fallback":
+            mask = [y / x >= ar_cut for x, y in zip(nx, ny)]
         b, st = solve_steady(list(nx), list(ny), list(re), threshold, max_steps, dtype,
-                             chunk=1000, warm=sur if mode == "batch-warm" else None,
-                             log=log)
+                             chunk=1000, warm=sur if mode.startswith("batch-warm") else None,
+                             log=log, warm_mask=mask)
         steps = [s["steps_done"] for s in st]
         b.close()
     torch.cuda.synchronize()
@@ -234,12 +241,61 @@ def make_surrogate(normals, max_batch=8):
     return sur
 
 
-TTS_MODES = ("single-cold", "batch-warm", "batch-cold", "single-warm")
+TTS_MODES = ("single-cold", "batch-warm", "batch-cold", "single-warm", "batch-warm-fallback")
+
+
+def calibrate_fallback(sur, held, threshold, max_steps=2_000_000, dtype="f32s"):
+    """The aspect ratio below which the warm start is not used, chosen on the
+    held-out cavities (never on the cavities it is then applied to): their
+    cold step counts come with `held` (training_data), their warm ones from a
+    batched warm-started run; the cut a (one of their Ar values, or 0: warm
+    everywhere) minimises the total steps of 'cold where Ar < a, warm
+    elsewhere' on them (the smallest such a on ties)."""
+    nx = 200
+    nys = [int(round(nx * a)) for a in held["ar"]]
+    b, st = solve_steady([nx] * len(nys), nys, list(held["re"]), threshold, max_steps, dtype,
+                         warm=sur)
+    b.close()
+    warm = [s["steps_done"] for s in st]
+    cold = list(held["steps"])
+    ars = [y / nx for y in nys]
+    best_cut, best = 0.0, sum(warm)
+    for a in sorted(set(ars)):
+        tot = sum(c if r < a else w for r, c, w in zip(ars, cold, warm))
+        if tot < best:
+            best_cut, best = a, tot
+    return {"ar_cut": best_cut, "held_cold_total": int(sum(cold)),
+            "held_warm_total": int(sum(warm)), "held_fallback_total": int(best),
+            "held_cases": len(ars)}
+
+
+STRICT_RE = (1000.0, 2000.0, 3000.0)
+STRICT_AR = (0.4, 0.8, 1.2)
+
+
+def strict_subset_cases(nx=500):
+    """The nine cavities of the bounded FP64 Eq. 6 < 1e-8 study: Re 1000,
+    2000, 3000 x Ar 0.4, 0.8, 1.2 of the steady sweep (the Ar 1.6 and 2.0
+    cavities take most of the full sweep's time at this threshold)."""
+    return [(nx, int(round(nx * ar)), re) for ar in STRICT_AR for re in STRICT_RE]
+
+
+def _study_modes(cases, threshold, max_steps, modes, sur, dtype, log, ar_cut):
+    res = {}
+    for m in modes:
+        r = time_to_steady(cases, threshold, max_steps, m, sur=sur, dtype=dtype, log=log,
+                           ar_cut=ar_cut)
+        res[m] = {"seconds": round(r["seconds"], 3), "steps_total": int(sum(r["steps"])),
+                  "steps_median": float(np.median(r["steps"])),
+                  "max_steps_hit": r["max_steps_hit"], "steps": [int(v) for v in r["steps"]]}
+        if log:
+            log(m, {k: v for k, v in res[m].items() if k != "steps"})
+    return res
 
 
 def steady_sweep_study(normals, threshold=1e-6, ntrain=200, epochs=150, nx=500,
                        max_steps=5_000_000, modes=TTS_MODES, dtype="f32s",
-                       data_threshold=1e-6, log=None):
+                       data_threshold=1e-6, log=None, strict=None):
     """Time-to-steady of the steady sweep (25 cavities, Re 1000-3000 x Ar
     0.4-2.0 at nx x (nx Ar)): plain = single cavities one after another from
     rest; treatment = one batch, every cavity warm-started by the surrogate
@@ -264,22 +320,40 @@ def steady_sweep_study(normals, threshold=1e-6, ntrain=200, epochs=150, nx=500,
         log(f"trained {epochs} epochs in {t_train:.1f} s, loss {hist[-1]:.5f}")
     held = training_data(20, seed=1, threshold=data_threshold)
     perf = surrogate_throughput(sur)
+    fallback = calibrate_fallback(sur, held, data_threshold)
+    if log:
+        log(f"cold-start fallback below Ar {fallback['ar_cut']:g} (held-out calibration)")
     cases = steady_sweep_cases(nx)
-    res = {}
-    for m in modes:
-        r = time_to_steady(cases, threshold, max_steps, m, sur=sur, dtype=dtype, log=log)
-        res[m] = {"seconds": round(r["seconds"], 3), "steps_total": int(sum(r["steps"])),
-                  "steps_median": float(np.median(r["steps"])),
-                  "max_steps_hit": r["max_steps_hit"], "steps": [int(v) for v in r["steps"]]}
-        if log:
-            log(m, {k: v for k, v in res[m].items() if k != "steps"})
+    res = _study_modes(cases, threshold, max_steps, modes, sur, dtype, log, fallback["ar_cut"])
     out = {"cases": len(cases), "lattice": f"{nx} x ({nx} Ar)", "threshold_eq6": threshold,
-           "storage": dtype, "modes": res,
+           "storage": dtype, "modes": res, "fallback": fallback,
+           "case_list": [[x, y, r] for x, y, r in cases],
            "speedup": (round(res["single-cold"]["seconds"] / res["batch-warm"]["seconds"], 3)
                        if "single-cold" in res and "batch-warm" in res else None),
+           "speedup_with_fallback": (round(res["single-cold"]["seconds"]
+                                           / res["batch-warm-fallback"]["seconds"], 3)
+                                     if "single-cold" in res and "batch-warm-fallback" in res
+                                     else None),
            "surrogate": {"train_samples": ntrain, "epochs": epochs,
                          "data_seconds": round(t_data, 2), "train_seconds": round(t_train, 2),
                          "final_train_loss": round(hist[-1], 6),
                          "heldout_mse": round(evaluate(sur, held), 6), **perf}}
+    if strict:
+        # the same surrogate, a second threshold and storage (e.g. FP64 to 1e-8)
+        sc = strict.get("cases") or strict_subset_cases(nx)
+        sres = _study_modes(sc, strict["threshold"], strict.get("max_steps", max_steps),
+                            strict["modes"], sur, strict["dtype"], log, fallback["ar_cut"])
+        cold, warm = sres.get("batch-cold"), sres.get("batch-warm")
+        out["strict"] = {"cases": len(sc), "case_list": [[x, y, r] for x, y, r in sc],
+                         "threshold_eq6": strict["threshold"], "storage": strict["dtype"],
+                         "modes": sres,
+                         "steps_saved_warm": (round(1 - warm["steps_total"]
+                                                    / cold["steps_total"], 4)
+                                              if cold and warm else None),
+                         "speedup_warm_vs_cold": (round(cold["seconds"] / warm["seconds"], 3)
+                                                  if cold and warm else None)}
+        fb = sres.get("batch-warm-fallback")
+        if cold and fb:
+            out["strict"]["speedup_fallback_vs_cold"] = round(cold["seconds"] / fb["seconds"], 3)
     sur.close()
     return out

@@ -361,6 +361,41 @@ def test_full_size_fp32_at_steady_state(lbm, ny, steps):
     assert du <= F32_UTOL
 
 
+def test_fp32_gap_at_the_paper_steady_criterion(lbm):
+    """The FP32 f - w field against the FP64 one at the paper's own steady
+    criterion (Sec. 2.2 (iii): Eq. 6 below 1e-6): 500 x 500, Re 1000, from
+    rest, FP64 monitored every 100 steps until its Eq. 6 first drops below
+    1e-6, FP32 run the same number of steps.  A KNOWN EXCEEDANCE of the
+    1e-5 U bar: during the slow final approach the two fields sit at slightly
+    different points of the slowest decaying mode (a smooth difference, not
+    a checkerboard), which peaks near 2.1e-5 U around 600 k steps and
+    settles at 2-3e-6 U once FP64 reaches its rounding floor
+    (test_full_size_fp32_at_steady_state).  Measured 1.006e-5 U after
+    370,100 steps (FP64 monitored every 100 steps); asserted <= 2e-5 U so
+    that a regression shows."""
+    c64 = lbm.Cavity(500, 500, re=1000.0, u_lid=U_LID, dtype="f64")
+    steps = 0
+    while True:
+        c64.step(100)
+        steps += 100
+        res, at = c64.residual()
+        assert at == steps
+        if res < 1e-6:
+            break
+        assert steps < 2_000_000, "FP64 never reached Eq. 6 < 1e-6"
+    c32 = lbm.Cavity(500, 500, re=1000.0, u_lid=U_LID, dtype="f32s")
+    c32.step(steps)
+    (r0, u0, v0), (r1, u1, v1) = c64.moments(), c32.moments()
+    res32 = c32.residual()[0]
+    c64.close()
+    c32.close()
+    du = max(np.abs(u1 - u0).max(), np.abs(v1 - v0).max())
+    print(f"500x500 Re 1000: FP64 Eq. 6 < 1e-6 after {steps} steps (FP32 Eq. 6 {res32:.2e}); "
+          f"max|du|/U {du / U_LID:.3e}")
+    assert 300_000 <= steps <= 600_000
+    assert du <= 2e-5 * U_LID
+
+
 def test_mass_conservation_long_run(lbm):
     """20,000 steps of the 64 x 64, Re = 100 cavity.  The collision applies
     the weights exactly, so its rounding has no preferred sign: FP64 storage
