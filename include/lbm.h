@@ -665,21 +665,28 @@ int lbm_sur_warm_start_batch(lbm_sur_t s, lbm_batch_t b, int k);
  *   mode 1 dgrad:    out[p, oo+c] (+)= sum_{t,o} x[p-d_t, xo+o] w[t][c][o]
  *                    (x is the output gradient, accumulate adds)
  *   mode 2 wgrad:    out[t][c][o] += sum_p x[p+d_t, xo+c] g[p, go+o]
- *                    (out FP32 [9][ci][co]; per-chunk partials of 2048
- *                    pixels added in chunk order, so the result does not
+ *                    (out FP32 [9][ci][co]; per-chunk partials (a chunk
+ *                    of pixels per block chain, sized from the layer's
+ *                    shape) added in chunk order, so the result does not
  *                    depend on scheduling; the call allocates the partials,
  *                    synchronises the stream and frees them)
+ *   (mode 0 likewise allocates a transposed copy of w for the call,
+ *   synchronises the stream and frees it; mode 1 only issues the work)
  * d_t = (dy - 1, dx - 1) for tap t = 3 dy + dx, zero outside the image. */
 int lbm_nn_conv3x3(int mode, int n, int h, int w, int ci, int co,
                    const void *x, int xs, int xo, const void *g, int gs, int go,
                    const void *wt, const float *bias, int relu, void *out,
                    int os, int oo, int accumulate, void *stream);
-/* gb[o] += sum_p g[p, go+o] over npix pixels, co <= 256; per-chunk partial
- * sums added in chunk order (deterministic; the call allocates the partials,
- * synchronises the stream and frees them). */
+/* gb[o] += sum_p g[p, go+o] over npix pixels; co a multiple of 8 in
+ * [8, 256], gs and go multiples of 8 with go + co <= gs, g 16-byte aligned
+ * (LBM_EINVAL otherwise); per-chunk partial sums added in chunk order
+ * (deterministic; the call allocates the partials, synchronises the stream
+ * and frees them). */
 int lbm_nn_bias_grad(int npix, int co, const void *g, int gs, int go,
                      float *gb, void *stream);
-/* 2 x 2 average pooling of an h x w (even) image: forward reads a slice
+/* (pooling and upsampling: c, channel strides and offsets multiples of 8,
+ * tensors 16-byte aligned; LBM_EINVAL otherwise)
+ * 2 x 2 average pooling of an h x w (even) image: forward reads a slice
  * (is, io) and writes dense [n][h/2][w/2][c]; backward reads the dense
  * gradient and writes (or adds into, accumulate) the slice (os, oo). */
 int lbm_nn_pool2(int backward, int n, int h, int w, int c, const void *in,

@@ -30,22 +30,103 @@ namespace {
 
 inline unsigned blocks_for(long long n, int t = 256) { return (unsigned)((n + t - 1) / t); }
 
+// Pixels per weight-gradient chunk: about 2048 blocks over the layer's
+// (9 ci / 64) x (co / BN) output tiles, in multiples of 64 pixels, at least
+// 256 (each chunk is one chain of dependent loads; more chains hide more
+// latency, at the cost of more partials for k_sum_parts to add).
+inline int wgrad_kchunk(int n, int h, int w, int ci, int co) {
+  const long long npix = (long long)n * h * w;
+  const long long tiles = (long long)((9 * ci + 63) / 64) * (co % 64 == 0 ? co / 64 : (co + 31) / 32);
+  const long long nz = std::max(1LL, 2048 / tiles);
+  long long k = (npix + nz - 1) / nz;
+  k = (k + 63) / 64 * 64;
+  return (int)std::max(256LL, k);
+}
+
 inline int wgrad_chunks(const ConvArgs &a) {
   return (int)(((long long)a.n * a.h * a.w + a.kchunk - 1) / a.kchunk);
 }
 
+// One forward or input-gradient pass with tile shape <WM, WN, TM, TN>.
+template <int MODE, int WM, int WN, int TM, int TN>
+void conv_mn(const ConvArgs &a, int M, int N, hipStream_t st) {
+  constexpr int BM = 16 * WM * TM, BN = 16 * WN * TN;
+  dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN);
+  hipLaunchKernelGGL((k_conv_mn<MODE, WM, WN, TM, TN>), grid, dim3(256), 0, st, a);
+}
+
+// Tile shape for an M x N product: N tiles as wide as the channel count
+// allows (no MFMA on padding), and the larger M tile while it still gives
+// at least two blocks per CU.
+template <int MODE, int W, int BN>
+void conv_patch(const ConvArgs &a, int M, int N, hipStream_t st) {
+  constexpr int TPIX = W == 128 ? 256 : W == 16 ? 64 : 128;   // as in k_conv_patch
+  dim3 grid(M / TPIX, (N + BN - 1) / BN);
+  hipLaunchKernelGGL((k_conv_patch<MODE, W, BN>), grid, dim3(256), 0, st, a);
+}
+
+template <int MODE>
+void conv_fd(const ConvArgs &a, hipStream_t st) {
+  const int M = a.n * a.h * a.w, N = MODE == FWD ? a.co : a.ci;
+  // direct convolution from an LDS patch of whole rows: 256-pixel tiles of
+  // 32 channels on 128-wide images, 128-pixel tiles on 64- and 32-wide
+  // ones, 64-pixel tiles on 16-wide ones (64 channels where N allows)
+  const bool out_ok = MODE == WGRAD || (a.os % 8 == 0 && a.oo % 8 == 0);
+  const bool n64 = N % 64 == 0;
+  if (out_ok && a.w == 128 && a.h % 2 == 0) {
+    conv_patch<MODE, 128, 32>(a, M, N, st);
+    return;
+  }
+  if (out_ok && a.w == 64 && a.h % 2 == 0) {
+    if (n64) conv_patch<MODE, 64, 64>(a, M, N, st);
+    else conv_patch<MODE, 64, 32>(a, M, N, st);
+    return;
+  }
+  if (out_ok && a.w == 32 && a.h % 4 == 0) {
+    if (n64) conv_patch<MODE, 32, 64>(a, M, N, st);
+    else conv_patch<MODE, 32, 32>(a, M, N, st);
+    return;
+  }
+  if (out_ok && a.w == 16 && a.h % 4 == 0) {
+    if (n64) conv_patch<MODE, 16, 64>(a, M, N, st);
+    else conv_patch<MODE, 16, 32>(a, M, N, st);
+    return;
+  }
+  const long long big = 512;
+  if (N % 128 == 0) {
+    if ((long long)((M + 127) / 128) * (N / 128) >= big)
+      conv_mn<MODE, 2, 2, 4, 4>(a, M, N, st);          // 128 x 128
+    else if ((long long)((M + 63) / 64) * (N / 128) >= big / 2)
+      conv_mn<MODE, 2, 2, 2, 4>(a, M, N, st);          // 64 x 128
+    else
+      conv_mn<MODE, 2, 2, 2, 2>(a, M, N, st);          // 64 x 64
+  } else if (N % 64 == 0) {
+    if ((long long)((M + 127) / 128) * (N / 64) >= big)
+      conv_mn<MODE, 4, 1, 2, 4>(a, M, N, st);          // 128 x 64
+    else
+      conv_mn<MODE, 2, 2, 2, 2>(a, M, N, st);          // 64 x 64
+  } else {
+    if ((long long)((M + 255) / 256) * (N / 32) >= big)
+      conv_mn<MODE, 4, 1, 4, 2>(a, M, N, st);          // 256 x 32
+    else
+      conv_mn<MODE, 4, 1, 2, 2>(a, M, N, st);          // 128 x 32
+  }
+}
+
 hipError_t conv_launch(int mode, const ConvArgs &a, hipStream_t st) {
-  const int HW = a.h * a.w;
   if (mode == FWD) {
-    dim3 grid((a.n * HW + 63) / 64, (a.co + 63) / 64);
-    hipLaunchKernelGGL(k_conv3x3<FWD>, grid, dim3(256), 0, st, a);
+    conv_fd<FWD>(a, st);
   } else if (mode == DGRAD) {
-    dim3 grid((a.n * HW + 63) / 64, (a.ci + 63) / 64);
-    hipLaunchKernelGGL(k_conv3x3<DGRAD>, grid, dim3(256), 0, st, a);
+    conv_fd<DGRAD>(a, st);
   } else {   // per-chunk partials into a.part, then added into GW in chunk order
     const int nz = wgrad_chunks(a);
-    dim3 grid((9 * a.ci + 63) / 64, (a.co + 63) / 64, nz);
-    hipLaunchKernelGGL(k_conv3x3<WGRAD>, grid, dim3(256), 0, st, a);
+    if (a.co % 64 == 0) {
+      dim3 grid((9 * a.ci + 63) / 64, a.co / 64, nz);
+      hipLaunchKernelGGL(k_wgrad<64>, grid, dim3(256), 0, st, a);
+    } else {
+      dim3 grid((9 * a.ci + 63) / 64, (a.co + 31) / 32, nz);
+      hipLaunchKernelGGL(k_wgrad<32>, grid, dim3(256), 0, st, a);
+    }
     const long long mn = 9LL * a.ci * a.co;
     hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(mn, kSumOut)), dim3(256), 0, st, a.part, nz,
                        mn, (float *)a.out);
@@ -57,7 +138,7 @@ hipError_t conv_launch(int mode, const ConvArgs &a, hipStream_t st) {
 // chunk order.
 hipError_t bias_grad_launch(const uint16_t *g, int gs, int go, long long npix, int co,
                             float *part, float *gb, hipStream_t st) {
-  const int chunk = 256, nb = (int)blocks_for(npix, chunk);
+  const int chunk = 512, nb = (int)blocks_for(npix, chunk);
   hipLaunchKernelGGL(k_bias_grad, dim3(nb), dim3(256), 0, st, g, gs, go, (int)npix, co, chunk,
                      part);
   hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(co, kSumOut)), dim3(256), 0, st, part, nb,
@@ -68,7 +149,8 @@ hipError_t bias_grad_launch(const uint16_t *g, int gs, int go, long long npix, i
 // Floats of partials a weight or bias gradient needs.
 size_t wgrad_part_floats(int n, int h, int w, int ci, int co) {
   const long long npix = (long long)n * h * w;
-  const size_t wg = (size_t)((npix + 2047) / 2048) * 9 * ci * co;
+  const int kc = wgrad_kchunk(n, h, w, ci, co);
+  const size_t wg = (size_t)((npix + kc - 1) / kc) * 9 * ci * co;
   const size_t bg = (size_t)blocks_for(npix, 256) * co;
   return std::max(wg, bg);
 }
@@ -110,6 +192,8 @@ struct lbm_surrogate {
   uint16_t *act = nullptr, *gact = nullptr;     // activations and their gradients
   float *w = nullptr, *m = nullptr, *v = nullptr, *gw = nullptr;   // FP32 params
   uint16_t *wb = nullptr;                        // bf16 copy of the params
+  uint16_t *wbt = nullptr;                       // bf16 conv weights as [9][co][ci]
+  ConvTable convs{};                             // offsets and shapes of the convs
   float *target = nullptr, *mask = nullptr, *out3 = nullptr;
   float *loss_dev = nullptr, *loss_host = nullptr;
   float *part = nullptr;   // partials of the split reductions (see k_sum_parts)
@@ -268,6 +352,7 @@ int forward(lbm_surrogate *s, int n) {
       a.xs = o.in.cs;
       a.xo = o.in.co;
       a.wt = s->wb + o.woff;
+      a.wtt = s->wbt + o.woff;
       a.bias = s->w + o.boff;
       a.relu = o.relu;
       a.out = bptr(s, s->act, o.out);
@@ -275,12 +360,12 @@ int forward(lbm_surrogate *s, int n) {
       a.oo = o.out.co;
       HIPC(conv_launch(FWD, a, st));
     } else if (o.type == OP_POOL) {
-      hipLaunchKernelGGL(k_pool_fwd, dim3(blocks_for((long long)n * h * w * o.ci / 4)), dim3(256),
+      hipLaunchKernelGGL(k_pool_fwd, dim3(blocks_for((long long)n * h * w * o.ci / 32)), dim3(256),
                          0, st, bptr(s, s->act, o.in), o.in.cs, o.in.co, n, h, w, o.ci,
                          bptr(s, s->act, o.out));
       HIPC(hipGetLastError());
     } else {
-      hipLaunchKernelGGL(k_up_fwd, dim3(blocks_for((long long)n * 4 * h * w * o.ci)), dim3(256), 0,
+      hipLaunchKernelGGL(k_up_fwd, dim3(blocks_for((long long)n * 4 * h * w * o.ci / 8)), dim3(256), 0,
                          st, bptr(s, s->act, o.in), n, h, w, o.ci, bptr(s, s->act, o.out),
                          o.out.cs, o.out.co);
       HIPC(hipGetLastError());
@@ -299,7 +384,7 @@ int backward(lbm_surrogate *s, int n) {
       const long long npix = (long long)n * h * w;
       uint16_t *gy = bptr(s, s->gact, o.out);
       if (o.relu) {
-        hipLaunchKernelGGL(k_relu_bwd, dim3(blocks_for(npix * o.co)), dim3(256), 0, st,
+        hipLaunchKernelGGL(k_relu_bwd, dim3(blocks_for(npix * o.co / 8)), dim3(256), 0, st,
                            bptr(s, s->act, o.out), o.out.cs, o.out.co, gy, o.out.cs, o.out.co,
                            npix, o.co);
         HIPC(hipGetLastError());
@@ -317,7 +402,7 @@ int backward(lbm_surrogate *s, int n) {
       a.gs = o.out.cs;
       a.go = o.out.co;
       a.out = s->gw + o.woff;
-      a.kchunk = 2048;
+      a.kchunk = wgrad_kchunk(n, h, w, o.ci, o.co);
       a.part = s->part;
       HIPC(conv_launch(WGRAD, a, st));
       HIPC(bias_grad_launch(gy, o.out.cs, o.out.co, npix, o.co, s->part, s->gw + o.boff, st));
@@ -340,12 +425,12 @@ int backward(lbm_surrogate *s, int n) {
       }
     } else if (o.type == OP_POOL) {
       // skip slice: add to the gradient the decoder already wrote there
-      hipLaunchKernelGGL(k_pool_bwd, dim3(blocks_for((long long)n * h * w * o.ci)), dim3(256), 0,
+      hipLaunchKernelGGL(k_pool_bwd, dim3(blocks_for((long long)n * h * w * o.ci / 8)), dim3(256), 0,
                          st, bptr(s, s->gact, o.out), n, h, w, o.ci, bptr(s, s->gact, o.in),
                          o.in.cs, o.in.co, 1);
       HIPC(hipGetLastError());
     } else {
-      hipLaunchKernelGGL(k_up_bwd, dim3(blocks_for((long long)n * h * w * o.ci)), dim3(256), 0, st,
+      hipLaunchKernelGGL(k_up_bwd, dim3(blocks_for((long long)n * h * w * o.ci / 8)), dim3(256), 0, st,
                          bptr(s, s->gact, o.out), o.out.cs, o.out.co, n, h, w, o.ci,
                          bptr(s, s->gact, o.in));
       HIPC(hipGetLastError());
@@ -355,6 +440,15 @@ int backward(lbm_surrogate *s, int n) {
 }
 
 const View &head_view(lbm_surrogate *s) { return s->ops.back().out; }
+
+// Refresh the transposed bf16 weights after the bf16 copy changed.
+hipError_t transpose_weights(lbm_surrogate *s) {
+  long long total = 0;
+  for (int k = 0; k < s->convs.count; ++k) total += 9LL * s->convs.ci[k] * s->convs.co[k];
+  hipLaunchKernelGGL(k_transpose_weights, dim3(blocks_for(total)), dim3(256), 0, s->stream,
+                     s->wb, s->wbt, s->convs, total);
+  return hipGetLastError();
+}
 
 int encode(lbm_surrogate *s, int n, const double *re, const double *ar) {
   std::vector<double> ra(2 * n);
@@ -406,13 +500,31 @@ int lbm_nn_conv3x3(int mode, int n, int h, int w, int ci, int co, const void *x,
   a.os = os;
   a.oo = oo;
   a.accumulate = accumulate;
-  a.kchunk = 2048;
+  a.kchunk = wgrad_kchunk(n, h, w, ci, co);
   const int cin = mode == DGRAD ? co : ci, cout = mode == DGRAD ? ci : co;
   if (mode != WGRAD && (xs < cin || xo < 0 || xo + cin > xs || xs % 8 || xo % 8 || os < cout ||
                         oo < 0 || oo + cout > os))
     return lbm_fail(LBM_EINVAL, "bad channel stride / offset");
-  if (mode != WGRAD) {
+  if (mode == DGRAD) {
     HIPC(conv_launch(mode, a, (hipStream_t)stream));
+    return LBM_OK;
+  }
+  if (mode == FWD) {   // the weights transposed in a workspace of this call
+    uint16_t *wtt = nullptr;
+    HIPC(hipMalloc(&wtt, sizeof(uint16_t) * 9 * (size_t)ci * co));
+    ConvTable tb{};
+    tb.count = 1;
+    tb.ci[0] = ci;
+    tb.co[0] = co;
+    const long long total = 9LL * ci * co;
+    hipLaunchKernelGGL(k_transpose_weights, dim3(blocks_for(total)), dim3(256), 0,
+                       (hipStream_t)stream, (const uint16_t *)wt, wtt, tb, total);
+    a.wtt = wtt;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = conv_launch(mode, a, (hipStream_t)stream);
+    if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+    (void)hipFree(wtt);
+    if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "%s", hipGetErrorString(e));
     return LBM_OK;
   }
   // WGRAD: partials in a workspace of this call, freed once the work is done
@@ -427,7 +539,11 @@ int lbm_nn_conv3x3(int mode, int n, int h, int w, int ci, int co, const void *x,
 }
 
 int lbm_nn_bias_grad(int npix, int co, const void *g, int gs, int go, float *gb, void *stream) {
-  if (npix < 1 || co < 1 || co > 256 || !g || !gb) return lbm_fail(LBM_EINVAL, "bad arguments");
+  if (npix < 1 || co < 8 || co > 256 || co % 8 || gs < co || gs % 8 || go < 0 || go % 8 ||
+      go + co > gs || !g || !gb || (uintptr_t)g % 16)
+    return lbm_fail(LBM_EINVAL,
+                    "bad arguments (co a multiple of 8 in [8, 256], gs and go multiples of 8, "
+                    "g 16-byte aligned)");
   float *part = nullptr;
   HIPC(hipMalloc(&part, sizeof(float) * (size_t)blocks_for(npix, 256) * co));
   hipError_t e = bias_grad_launch((const uint16_t *)g, gs, go, npix, co, part, gb,
@@ -440,14 +556,15 @@ int lbm_nn_bias_grad(int npix, int co, const void *g, int gs, int go, float *gb,
 
 int lbm_nn_pool2(int backward, int n, int h, int w, int c, const void *in, int is, int io,
                  void *out, int os, int oo, int accumulate, void *stream) {
-  if (n < 1 || h < 2 || w < 2 || h % 2 || w % 2 || c < 1 || !in || !out)
-    return lbm_fail(LBM_EINVAL, "bad pool arguments");
+  if (n < 1 || h < 2 || w < 2 || h % 2 || w % 2 || c < 8 || c % 8 || is % 8 || io % 8 ||
+      os % 8 || oo % 8 || !in || !out)
+    return lbm_fail(LBM_EINVAL, "bad pool arguments (c, strides and offsets multiples of 8)");
   hipStream_t st = (hipStream_t)stream;
   if (!backward) {   // in: [n][h][w] slice (is, io); out dense [n][h/2][w/2][c]
-    hipLaunchKernelGGL(k_pool_fwd, dim3(blocks_for((long long)n * h * w * c / 4)), dim3(256), 0,
+    hipLaunchKernelGGL(k_pool_fwd, dim3(blocks_for((long long)n * h * w * c / 32)), dim3(256), 0,
                        st, (const uint16_t *)in, is, io, n, h, w, c, (uint16_t *)out);
   } else {           // in: dense gradient [n][h/2][w/2][c]; out: slice (os, oo)
-    hipLaunchKernelGGL(k_pool_bwd, dim3(blocks_for((long long)n * h * w * c)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_pool_bwd, dim3(blocks_for((long long)n * h * w * c / 8)), dim3(256), 0, st,
                        (const uint16_t *)in, n, h, w, c, (uint16_t *)out, os, oo, accumulate);
   }
   HIPC(hipGetLastError());
@@ -456,14 +573,15 @@ int lbm_nn_pool2(int backward, int n, int h, int w, int c, const void *in, int i
 
 int lbm_nn_up2(int backward, int n, int h, int w, int c, const void *in, int is, int io,
                void *out, int os, int oo, void *stream) {
-  if (n < 1 || h < 1 || w < 1 || c < 1 || !in || !out)
-    return lbm_fail(LBM_EINVAL, "bad upsample arguments");
+  if (n < 1 || h < 1 || w < 1 || c < 8 || c % 8 || is % 8 || io % 8 || os % 8 || oo % 8 ||
+      !in || !out)
+    return lbm_fail(LBM_EINVAL, "bad upsample arguments (c, strides and offsets multiples of 8)");
   hipStream_t st = (hipStream_t)stream;
   if (!backward)   // in dense [n][h][w][c] -> out slice of [n][2h][2w]
-    hipLaunchKernelGGL(k_up_fwd, dim3(blocks_for((long long)n * 4 * h * w * c)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_up_fwd, dim3(blocks_for((long long)n * 4 * h * w * c / 8)), dim3(256), 0, st,
                        (const uint16_t *)in, n, h, w, c, (uint16_t *)out, os, oo);
   else             // in: gradient slice of [n][2h][2w] -> out dense [n][h][w][c]
-    hipLaunchKernelGGL(k_up_bwd, dim3(blocks_for((long long)n * h * w * c)), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_up_bwd, dim3(blocks_for((long long)n * h * w * c / 8)), dim3(256), 0, st,
                        (const uint16_t *)in, is, io, n, h, w, c, (uint16_t *)out);
   HIPC(hipGetLastError());
   return LBM_OK;
@@ -473,8 +591,8 @@ int lbm_nn_up2(int backward, int n, int h, int w, int c, const void *in, int is,
 int lbm_sur_destroy(lbm_sur_t s) {
   if (!s) return LBM_OK;
   if (s->stream) (void)hipStreamSynchronize(s->stream);
-  void *ptrs[] = {s->act, s->gact, s->w, s->m, s->v, s->gw, s->wb, s->target, s->mask, s->out3,
-                  s->loss_dev, s->rearr, s->field, s->part};
+  void *ptrs[] = {s->act, s->gact, s->w, s->m, s->v, s->gw, s->wb, s->wbt, s->target, s->mask,
+                  s->out3, s->loss_dev, s->rearr, s->field, s->part};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (s->loss_host) (void)hipHostFree(s->loss_host);
@@ -492,6 +610,13 @@ int lbm_sur_create(int max_batch, lbm_sur_t *out) {
   if (!s) return lbm_fail(LBM_ENOMEM, "host allocation");
   s->nmax = max_batch;
   build_net(s);
+  for (const Op &o : s->ops) {   // the convs are laid out one after another
+    if (o.type != OP_CONV) continue;
+    const int k = s->convs.count++;
+    s->convs.off[k] = (long long)o.woff;
+    s->convs.ci[k] = o.ci;
+    s->convs.co[k] = o.co;
+  }
   for (const Buf &b : s->bufs) {
     s->act_off.push_back(s->act_elems);
     s->act_elems += (size_t)max_batch * level_h(b.level) * level_w(b.level) * b.ch;
@@ -519,6 +644,8 @@ int lbm_sur_create(int max_batch, lbm_sur_t *out) {
       part_floats = std::max(part_floats, wgrad_part_floats(max_batch, level_h(o.level),
                                                             level_w(o.level), o.ci, o.co));
   if (e == hipSuccess) e = hipMalloc(&s->part, part_floats * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc(&s->wbt, s->nparams * 2);
+  if (e == hipSuccess) e = hipMemsetAsync(s->wbt, 0, s->nparams * 2, s->stream);
   if (e == hipSuccess) e = hipMemsetAsync(s->act, 0, s->act_elems * 2, s->stream);
   if (e == hipSuccess) e = hipMemsetAsync(s->gact, 0, s->act_elems * 2, s->stream);
   if (e == hipSuccess) e = hipMemsetAsync(s->w, 0, s->nparams * 4, s->stream);
@@ -557,6 +684,7 @@ int lbm_sur_set_params(lbm_sur_t s, const float *params_host, int64_t n) {
   hipLaunchKernelGGL(k_to_bf16, dim3(blocks_for((long long)s->nparams)), dim3(256), 0, s->stream,
                      s->w, s->wb, (long long)s->nparams);
   HIPC(hipGetLastError());
+  HIPC(transpose_weights(s));
   s->adam_t = 0;
   HIPC(hipStreamSynchronize(s->stream));
   return LBM_OK;
@@ -639,6 +767,7 @@ int lbm_sur_train_step(lbm_sur_t s, int n, const double *re, const double *ar,
                        s->w, s->m, s->v, s->gw, s->wb, (long long)s->nparams, (float)lr, (float)b1,
                        (float)b2, 1e-8f, (float)c1, (float)c2);
     HIPC(hipGetLastError());
+    HIPC(transpose_weights(s));
   }
   HIPC(hipMemcpyAsync(s->loss_host, s->loss_dev, sizeof(float), hipMemcpyDeviceToHost, s->stream));
   HIPC(hipStreamSynchronize(s->stream));

@@ -6,13 +6,15 @@
 // concatenation buffer.  Weights of a 3x3 convolution are [9][ci][co]
 // (tap = 3 dy + dx, dy, dx in {0, 1, 2} for offsets -1, 0, +1).
 //
-// The three passes of a convolution are one implicit-GEMM kernel:
+// The three passes of a convolution:
 //   forward : Y[p, o]      = sum_{t,c} X[p + d_t, c] W[t, c, o]  (+ bias, ReLU)
 //   dgrad   : GX[p, c]     = sum_{t,o} GY[p - d_t, o] W[t, c, o]
 //   wgrad   : GW[t, c, o] += sum_p     X[p + d_t, c] GY[p, o]
-// A block computes a 64 x 64 tile of the GEMM with four waves, each a 32 x 32
-// sub-tile of 2 x 2 v_mfma_f32_16x16x32_bf16 (FP32 accumulate), staging
-// 64 x 32 slices of both operands through LDS with 16-byte global loads.
+// all on v_mfma_f32_16x16x32_bf16 (FP32 accumulate): forward and dgrad as a
+// direct convolution from an LDS patch of whole image rows (k_conv_patch)
+// or, for widths it does not serve, a pipelined implicit GEMM (k_conv_mn);
+// wgrad as a pipelined GEMM over pixel chunks (k_wgrad) whose per-chunk
+// partials are added in a fixed order (k_sum_parts).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -42,6 +44,7 @@ struct ConvArgs {
   const uint16_t *g;   // WGRAD: output gradient
   int gs, go;
   const uint16_t *wt;  // FWD / DGRAD: bf16 weights [9][ci][co]
+  const uint16_t *wtt; // FWD (optional): the same weights as [9][co][ci]
   const float *bias;   // FWD: per output channel (may be null)
   int relu;            // FWD: apply max(0, .)
   void *out;           // FWD: bf16 Y; DGRAD: bf16 GX; WGRAD: float GW [9 ci][co]
@@ -54,152 +57,478 @@ struct ConvArgs {
 
 constexpr int kLdsK = 32 + 8;   // padded row of a staged 64 x 32 operand slice
 
-template <int MODE>
-__global__ __launch_bounds__(256) void k_conv3x3(ConvArgs a) {
-  __shared__ uint16_t As[64 * kLdsK];   // [row m][k]
-  __shared__ uint16_t Bs[64 * kLdsK];   // [col n][k]
-  const int tid = threadIdx.x;
-  const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
-  const int HW = a.h * a.w;
-  const int M = MODE == WGRAD ? 9 * a.ci : a.n * HW;
-  const int N = MODE == DGRAD ? a.ci : a.co;
-  const int m0 = blockIdx.x * 64, n0 = blockIdx.y * 64;
-  int k_begin = 0, k_end;
-  if (MODE == WGRAD) {
-    k_begin = blockIdx.z * a.kchunk;
-    k_end = min(k_begin + a.kchunk, a.n * HW);
-  } else {
-    k_end = 9 * (MODE == FWD ? a.ci : a.co);
+// ---------------------------------------------------------------------------
+// Forward and input-gradient passes as one pipelined implicit GEMM.
+//   FWD  : M = pixels, N = co, K = 9 ci;  A(p, (t,c)) = X[p + d_t][c],
+//          B((t,c), o) = W[t][c][o] (16-byte vectors along n, stored into
+//          LDS transposed, element by element: the weights are small).
+//   DGRAD: M = pixels, N = ci, K = 9 co;  A(p, (t,o)) = GY[p - d_t][o],
+//          B((t,o), c) = W[t][c][o] (contiguous along k = o).
+// A block of 256 threads (WM x WN waves, each TM x TN MFMA 16 x 16 x 32
+// tiles) computes a BM x BN tile, BM = 16 WM TM, BN = 16 WN TN.  K advances
+// in slices of 32 (one tap, 32 channels: channel counts are multiples of 32,
+// so a slice never straddles a tap); each slice is loaded from global memory
+// into registers while the previous one is multiplied out of LDS, and the
+// two LDS buffers alternate, so one barrier per slice suffices.
+constexpr int kBK = 32;
+
+template <int MODE, int WM, int WN, int TM, int TN>
+__global__ __launch_bounds__(256) void k_conv_mn(ConvArgs a) {
+  static_assert(WM * WN == 4, "four waves");
+  constexpr int BM = 16 * WM * TM, BN = 16 * WN * TN;
+  // 16-byte vectors per thread and operand (4 per row of 32 k)
+  constexpr int AV = (BM * 4 + 255) / 256, BV = (BN * 4 + 255) / 256;
+  __shared__ uint16_t As[2][BM * kLdsK];
+  __shared__ uint16_t Bs[2][BN * kLdsK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / WN, wn = wave % WN;
+  const int HW = a.h * a.w, M = a.n * HW;
+  const int C = MODE == FWD ? a.ci : a.co;      // channels along k within a tap
+  const int N = MODE == FWD ? a.co : a.ci;
+  const int m0 = blockIdx.x * BM, n0 = blockIdx.y * BN;
+  const int nk = 9 * C / kBK;
+
+  // staging: vector v of this thread covers row r = (tid + 256 v) / 4, k = 8 ((tid) % 4)
+  const int kq = (tid & 3) * 8;
+  int apix[AV], ay[AV], ax[AV];
+#pragma unroll
+  for (int v = 0; v < AV; ++v) {   // rows beyond BM or M load zeros (ay out of range)
+    const int m = (tid >> 2) + 64 * v < BM ? m0 + (tid >> 2) + 64 * v : M;
+    const int b = m / HW, r = m - b * HW;
+    ay[v] = m < M ? r / a.w : -1000000;
+    ax[v] = r - (r / a.w) * a.w;
+    apix[v] = b * HW;
   }
-  floatx4 acc[2][2];
+  uint4 ra[AV], rb[BV];
+  auto load = [&](int ks) {
+    const int k0 = ks * kBK, tap = k0 / C, c0 = k0 - tap * C + kq;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+    for (int v = 0; v < AV; ++v) {
+      const int qy = MODE == FWD ? ay[v] + dy : ay[v] - dy;
+      const int qx = MODE == FWD ? ax[v] + dx : ax[v] - dx;
+      if (qy >= 0 && qy < a.h && qx >= 0 && qx < a.w)
+        ra[v] = *(const uint4 *)(a.x + (size_t)(apix[v] + qy * a.w + qx) * a.xs + a.xo + c0);
+      else
+        ra[v] = make_uint4(0, 0, 0, 0);
+    }
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int v = 0; v < BV; ++v) {
+      if (MODE == FWD) {   // W[tap][c][o]: row k = tid % 32, 8 n from 8 (tid / 32 + 8 v)
+        const int kb = tid & 31, nb = 8 * ((tid >> 5) + 8 * v);
+        const int cc = k0 - tap * C + kb;
+        rb[v] = (nb < BN && n0 + nb < N)
+                    ? *(const uint4 *)(a.wt + ((size_t)tap * a.ci + cc) * a.co + n0 + nb)
+                    : make_uint4(0, 0, 0, 0);
+      } else {             // W[tap][c][o], k = o: row n = tid / 4 + 64 v, 8 k
+        const int n = n0 + (tid >> 2) + 64 * v;
+        rb[v] = ((tid >> 2) + 64 * v < BN && n < N)
+                    ? *(const uint4 *)(a.wt + ((size_t)tap * a.ci + n) * a.co + c0)
+                    : make_uint4(0, 0, 0, 0);
+      }
+    }
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int v = 0; v < AV; ++v)
+      if ((tid >> 2) + 64 * v < BM)
+        *(uint4 *)&As[buf][((tid >> 2) + 64 * v) * kLdsK + kq] = ra[v];
+#pragma unroll
+    for (int v = 0; v < BV; ++v) {
+      if (MODE == FWD) {
+        const int kb = tid & 31, nb = 8 * ((tid >> 5) + 8 * v);
+        if (nb < BN) {
+          const uint16_t *e = (const uint16_t *)&rb[v];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) Bs[buf][(nb + j) * kLdsK + kb] = e[j];
+        }
+      } else if ((tid >> 2) + 64 * v < BN) {
+        *(uint4 *)&Bs[buf][((tid >> 2) + 64 * v) * kLdsK + kq] = rb[v];
+      }
+    }
+  };
 
-  // this thread's staging slot: one 8-element vector of each operand
-  const int sr = tid >> 2, sk = (tid & 3) * 8;      // rows along m / n, 8 k
-  const int vk = tid >> 3, vr = (tid & 7) * 8;      // 8 rows along m / n, one k
+  floatx4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  for (int k0 = k_begin; k0 < k_end; k0 += 32) {
-    // ---- A slice [64 m][32 k] ------------------------------------------------
-    uint16_t av[8];
-    if (MODE != WGRAD) {
-      // k = tap * C + c, contiguous in c; the 32-chunk lies in one tap
-      const int C = MODE == FWD ? a.ci : a.co;
-      const int tap = k0 / C, c0 = k0 - tap * C + sk;
-      const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-      const int m = m0 + sr;
-      const int b = m / HW, r = m - b * HW, py = r / a.w, px = r - py * a.w;
-      const int qy = MODE == FWD ? py + dy : py - dy, qx = MODE == FWD ? px + dx : px - dx;
-      if (m < M && qy >= 0 && qy < a.h && qx >= 0 && qx < a.w) {
-        const uint16_t *src = a.x + (size_t)((b * a.h + qy) * a.w + qx) * a.xs + a.xo + c0;
-        *(uint4 *)av = *(const uint4 *)src;
-      } else {
+  const int fr = lane & 15, fk = (lane >> 4) * 8;
+  load(0);
+  stage(0);
+  __syncthreads();
+  for (int ks = 0; ks < nk; ++ks) {
+    const int buf = ks & 1;
+    if (ks + 1 < nk) load(ks + 1);
+    bf16x8 fa[TM], fb[TN];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) av[j] = 0;
-      }
-      *(uint4 *)&As[sr * kLdsK + sk] = *(uint4 *)av;
-    } else {
-      // m = tap * ci + c (8 consecutive c share a tap), k = pixel
-      const int m = m0 + vr, p = k0 + vk;
-      const int tap = m / a.ci, c0 = m - tap * a.ci;
-      bool ok = m < M && p < k_end;
-      int qy = 0, qx = 0, b = 0;
-      if (ok) {
-        b = p / HW;
-        const int r = p - b * HW, py = r / a.w, px = r - py * a.w;
-        qy = py + tap / 3 - 1;
-        qx = px + tap % 3 - 1;
-        ok = qy >= 0 && qy < a.h && qx >= 0 && qx < a.w;
-      }
-      if (ok) {
-        *(uint4 *)av =
-            *(const uint4 *)(a.x + (size_t)((b * a.h + qy) * a.w + qx) * a.xs + a.xo + c0);
-      } else {
+    for (int i = 0; i < TM; ++i)
+      fa[i] = *(const bf16x8 *)&As[buf][(wm * TM * 16 + i * 16 + fr) * kLdsK + fk];
 #pragma unroll
-        for (int j = 0; j < 8; ++j) av[j] = 0;
-      }
+    for (int j = 0; j < TN; ++j)
+      fb[j] = *(const bf16x8 *)&Bs[buf][(wn * TN * 16 + j * 16 + fr) * kLdsK + fk];
 #pragma unroll
-      for (int j = 0; j < 8; ++j) As[(vr + j) * kLdsK + vk] = av[j];
-    }
-    // ---- B slice, stored [64 n][32 k] ------------------------------------------
-    uint16_t bv[8];
-    if (MODE == FWD) {
-      // B(k, n) = W[k][n], contiguous in n
-      const int n = n0 + vr, k = k0 + vk;
-      if (n < N) {
-        *(uint4 *)bv = *(const uint4 *)(a.wt + (size_t)k * a.co + n);
-      } else {
+    for (int i = 0; i < TM; ++i)
 #pragma unroll
-        for (int j = 0; j < 8; ++j) bv[j] = 0;
-      }
-#pragma unroll
-      for (int j = 0; j < 8; ++j) Bs[(vr + j) * kLdsK + vk] = bv[j];
-    } else if (MODE == DGRAD) {
-      // B(k = tap * co + o, n = c) = W[tap][c][o], contiguous in o (k)
-      const int n = n0 + sr, k = k0 + sk;
-      const int tap = k / a.co, o = k - tap * a.co;
-      if (n < N) {
-        *(uint4 *)bv = *(const uint4 *)(a.wt + ((size_t)tap * a.ci + n) * a.co + o);
-      } else {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) bv[j] = 0;
-      }
-      *(uint4 *)&Bs[sr * kLdsK + sk] = *(uint4 *)bv;
-    } else {
-      // B(k = pixel, n = o) = GY[p][o], contiguous in o
-      const int n = n0 + vr, p = k0 + vk;
-      if (n < N && p < k_end) {
-        *(uint4 *)bv = *(const uint4 *)(a.g + (size_t)p * a.gs + a.go + n);
-      } else {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) bv[j] = 0;
-      }
-#pragma unroll
-      for (int j = 0; j < 8; ++j) Bs[(vr + j) * kLdsK + vk] = bv[j];
-    }
-    __syncthreads();
-    // ---- 2 x 2 MFMA tiles per wave --------------------------------------------
-    const int fr = lane & 15, fk = (lane >> 4) * 8;
-    bf16x8 fa[2], fb[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      fa[i] = *(const bf16x8 *)&As[(wm * 32 + i * 16 + fr) * kLdsK + fk];
-      fb[i] = *(const bf16x8 *)&Bs[(wn * 32 + i * 16 + fr) * kLdsK + fk];
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < TN; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    if (ks + 1 < nk) stage(buf ^ 1);
     __syncthreads();
   }
 
-  // ---- epilogue: lane holds rows 4 (lane/16) + e, column lane % 16 -------------
+  // epilogue: lane holds rows 4 (lane / 16) + e, column lane % 16 of each tile
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+      const int n = n0 + wn * TN * 16 + j * 16 + (lane & 15);
+      if (n >= N) continue;
+      const float bn = (MODE == FWD && a.bias) ? a.bias[n] : 0.f;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int m = m0 + wm * TM * 16 + i * 16 + (lane >> 4) * 4 + e;
+        if (m >= M) continue;
+        float v = acc[i][j][e];
+        uint16_t *o = (uint16_t *)a.out + (size_t)m * a.os + a.oo + n;
+        if (MODE == FWD) {
+          v += bn;
+          if (a.relu) v = fmaxf(v, 0.f);
+        } else if (a.accumulate) {
+          v += bf2f(*o);
+        }
+        *o = f2bf(v);
+      }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The same two passes as direct convolutions: a block takes TPIX = R w
+// pixels (R whole rows of one image; w a multiple of 16, R dividing h) and
+// BN output channels; per chunk of 32 input channels it loads the
+// (R + 2) x (w + 2) patch of the input (zero halo) and the 9 taps' weights
+// into LDS once, and runs the 9 taps' MFMAs out of LDS, instead of gathering
+// a shifted copy of the input from global memory for every tap.  Four waves
+// split the TPIX pixels (TPIX / 64 MFMA row tiles each) and share all BN
+// columns.  The epilogue stages the FP32 tile in LDS (over the patch) and
+// writes whole 16-byte vectors of 8 channels.
+//   FWD  : out[p][o] = sum_{t,c} X[p + d_t][c] W[t][c][o]   (N = co, chunks of ci)
+//   DGRAD: out[p][c] = sum_{t,o} GY[p - d_t][o] W[t][c][o]  (N = ci, chunks of co)
+constexpr int kPatchMax = 4 * 130;   // patch pixels at TPIX = 256, w = 128
+
+template <int MODE, int W, int BN>
+__global__ __launch_bounds__(256) void k_conv_patch(ConvArgs a) {
+  // tile: R whole rows of W pixels, TPIX = R W (256 at W = 128, 128 at
+  // W = 64 and 32, 64 at W = 16)
+  constexpr int TPIX = W == 128 ? 256 : W == 16 ? 64 : 128;
+  constexpr int R = TPIX / W, PW = W + 2, PP = (R + 2) * PW;
+  constexpr int TM = TPIX / 64, TN = BN / 16;
+  static_assert(TM >= 1 && PP <= kPatchMax && TPIX * BN * 4 <= kPatchMax * 32 * 2,
+                "patch and FP32 tile fit the LDS patch buffer");
+  constexpr int PV = (PP * 4 + 255) / 256;            // patch vectors per thread
+  constexpr int WV = (9 * 32 * (BN / 8) + 255) / 256;  // weight vectors per thread
+  __shared__ __align__(16) uint16_t Ps[kPatchMax * 32];   // [patch pixel][32 channels]
+  __shared__ uint16_t Ws[9 * BN * kLdsK];                 // [tap][n][k]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int HW = a.h * W;
+  const int C = MODE == FWD ? a.ci : a.co;
+  const int N = MODE == FWD ? a.co : a.ci;
+  const int m0 = blockIdx.x * TPIX, n0 = blockIdx.y * BN;
+  const int img = m0 / HW, y0 = (m0 - img * HW) / W;   // first row of the tile
+
+  // Patch vectors of this thread: element offsets of their 8 channels at
+  // channel 0 (-1: halo outside the image, or beyond the patch), the same
+  // for every chunk.
+  long long poff[PV];
+#pragma unroll
+  for (int u = 0; u < PV; ++u) {
+    const int v = tid + 256 * u;
+    const int pp = v >> 2, kq = (v & 3) * 8;
+    const int py = pp / PW, px = pp - py * PW;
+    const int gy = y0 + py - 1, gx = px - 1;
+    poff[u] = (pp < PP && gy >= 0 && gy < a.h && gx >= 0 && gx < W)
+                  ? ((long long)img * HW + (long long)gy * W + gx) * a.xs + a.xo + kq
+                  : -1;
+  }
+
+  // One chunk of 32 channels: all its loads are issued into registers
+  // first (unrolled, so they are in flight together), then stored to LDS.
+  uint4 rp[PV], rw[WV];
+  auto load = [&](int c0) {
+#pragma unroll
+    for (int u = 0; u < PV; ++u)
+      rp[u] = poff[u] >= 0 ? *(const uint4 *)(a.x + poff[u] + c0) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int u = 0; u < WV; ++u) {
+      const int v = tid + 256 * u;
+      rw[u] = make_uint4(0, 0, 0, 0);
+      if (MODE == FWD && a.wtt) {   // WT[t][n0 + n][c0 + kq .. + 7]
+        const int t = v / (BN * 4), r = v - t * BN * 4;
+        const int n = r >> 2, kq = (r & 3) * 8;
+        if (t < 9 && n0 + n < N)
+          rw[u] = *(const uint4 *)(a.wtt + ((size_t)t * a.co + n0 + n) * a.ci + c0 + kq);
+      } else if (MODE == FWD) {     // W[t][c0 + k][n0 + nb .. + 7]
+        const int t = v / (32 * (BN / 8)), r = v - t * 32 * (BN / 8);
+        const int k = r / (BN / 8), nb = (r - k * (BN / 8)) * 8;
+        if (t < 9 && n0 + nb < N)
+          rw[u] = *(const uint4 *)(a.wt + ((size_t)t * a.ci + c0 + k) * a.co + n0 + nb);
+      } else {             // W[t][n0 + n][c0 + kq .. + 7]
+        const int t = v / (BN * 4), r = v - t * BN * 4;
+        const int n = r >> 2, kq = (r & 3) * 8;
+        if (t < 9 && n0 + n < N)
+          rw[u] = *(const uint4 *)(a.wt + ((size_t)t * a.ci + n0 + n) * a.co + c0 + kq);
+      }
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int u = 0; u < PV; ++u) {
+      const int v = tid + 256 * u;
+      if ((v >> 2) < PP) *(uint4 *)&Ps[(v >> 2) * 32 + (v & 3) * 8] = rp[u];
+    }
+#pragma unroll
+    for (int u = 0; u < WV; ++u) {
+      const int v = tid + 256 * u;
+      if (MODE == FWD && !a.wtt) {   // stored transposed: Ws[t][n][k]
+        const int t = v / (32 * (BN / 8)), r = v - t * 32 * (BN / 8);
+        const int k = r / (BN / 8), nb = (r - k * (BN / 8)) * 8;
+        if (t < 9) {
+          const uint16_t *e = (const uint16_t *)&rw[u];
+#pragma unroll
+          for (int j = 0; j < 8; ++j) Ws[(t * BN + nb + j) * kLdsK + k] = e[j];
+        }
+      } else {
+        const int t = v / (BN * 4), r = v - t * BN * 4;
+        if (t < 9) *(uint4 *)&Ws[(t * BN + (r >> 2)) * kLdsK + (r & 3) * 8] = rw[u];
+      }
+    }
+  };
+
+  floatx4 acc[TM][TN];
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  const int fr = lane & 15, fk = (lane >> 4) * 8;
+  // LDS element offset of this lane's A fragment in each row tile at tap
+  // (1, 1) (the pixel itself)
+  int aoff[TM];
+#pragma unroll
+  for (int i = 0; i < TM; ++i) {
+    const int q = wave * (TPIX / 4) + i * 16 + fr;
+    aoff[i] = ((q / W + 1) * PW + q % W + 1) * 32 + fk;
+  }
+  load(0);
+  stage();
+  __syncthreads();
+  for (int c0 = 0; c0 < C; c0 += 32) {
+    const bool more = c0 + 32 < C;
+    if (more) load(c0 + 32);          // next chunk in flight during the taps
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      const int dy = t / 3, dx = t % 3;
+      // FWD reads pixel p + d_t, DGRAD p - d_t
+      const int oy = MODE == FWD ? dy - 1 : 1 - dy, ox = MODE == FWD ? dx - 1 : 1 - dx;
+      bf16x8 fa[TM], fb[TN];
+#pragma unroll
+      for (int i = 0; i < TM; ++i) fa[i] = *(const bf16x8 *)&Ps[aoff[i] + (oy * PW + ox) * 32];
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        fb[j] = *(const bf16x8 *)&Ws[(t * BN + j * 16 + fr) * kLdsK + fk];
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+    __syncthreads();
+    if (more) {
+      stage();
+      __syncthreads();
+    }
+  }
+
+  // epilogue: lane holds rows 4 (lane / 16) + e, column lane % 16 of each
+  // tile; the FP32 tile goes to LDS [TPIX][BN] (the patch is free after the
+  // last barrier), then each thread writes 8 consecutive channels of a pixel
+  float *Os = reinterpret_cast<float *>(Ps);
+#pragma unroll
+  for (int i = 0; i < TM; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        Os[(wave * (TPIX / 4) + i * 16 + (lane >> 4) * 4 + e) * BN + j * 16 + (lane & 15)] =
+            acc[i][j][e];
+  __syncthreads();
+  for (int v = tid; v < TPIX * (BN / 8); v += 256) {
+    const int pl = v / (BN / 8), nq = (v - pl * (BN / 8)) * 8;
+    if (n0 + nq >= N) continue;
+    const float *src = Os + pl * BN + nq;
+    uint16_t *o = (uint16_t *)a.out + (size_t)(m0 + pl) * a.os + a.oo + n0 + nq;
+    float r[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) r[j] = src[j];
+    if (MODE == FWD) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (a.bias) r[j] += a.bias[n0 + nq + j];
+        if (a.relu) r[j] = fmaxf(r[j], 0.f);
+      }
+    } else if (a.accumulate) {
+      const uint4 old = *(const uint4 *)o;
+      const uint16_t *ov = (const uint16_t *)&old;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) r[j] += bf2f(ov[j]);
+    }
+    uint4 pk;
+    uint16_t *pv = (uint16_t *)&pk;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) pv[j] = f2bf(r[j]);
+    *(uint4 *)o = pk;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient as a pipelined GEMM over a chunk of pixels:
+//   part[z][m = (t, c)][o] = sum_{p in chunk z} X[p + d_t][c] GY[p][o]
+// M = 9 ci, N = co, K = pixels.  Both operands are pixel-major in memory
+// (NHWC) while the MFMA takes 8 consecutive k per lane, so each operand is
+// transposed on its way into LDS: a loader thread reads 4 consecutive
+// pixels x 8 channels (four 16-byte loads) and writes, per channel, the 4
+// pixels as one 64-bit LDS store (As[m][k], Bs[n][k], k contiguous).  A
+// block computes a 64 x BN tile with four waves (2 x 2), K advances by 64
+// pixels; the next slice is loaded into registers while the current one is
+// multiplied out of the other LDS buffer.
+constexpr int kWBK = 64, kWLd = kWBK + 8;   // pixels per slice, padded LDS row
+
+template <int BN>
+__global__ __launch_bounds__(256) void k_wgrad(ConvArgs a) {
+  constexpr int TN = BN / 32;                       // 16-wide n tiles per wave (2 x 2 waves)
+  __shared__ __align__(16) uint16_t As[2][64 * kWLd];
+  __shared__ __align__(16) uint16_t Bs[2][BN * kWLd];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int HW = a.h * a.w, M = 9 * a.ci, N = a.co;
+  const int m0 = blockIdx.x * 64, n0 = blockIdx.y * BN;
+  const int p_begin = blockIdx.z * a.kchunk;
+  const int p_end = min(p_begin + a.kchunk, a.n * HW);
+  // loader roles: threads 0-127 take A (8 rows x 4 pixels each), threads
+  // 128 .. 128 + 2 BN - 1 take B (8 columns x 4 pixels each)
+  const bool isA = tid < 128;
+  const int li = isA ? tid : tid - 128;
+  const int rg = li >> 4, pq = li & 15;            // row / column group, pixel quad
+  const bool active = isA || li < 2 * BN;
+  // A rows 8 rg .. 8 rg + 7: tap and first channel (8 rows share a tap)
+  const int am = m0 + 8 * rg;
+  const int atap = am / a.ci, ac = am - atap * a.ci;
+  const int ady = atap / 3 - 1, adx = atap % 3 - 1;
+  const bool arow_ok = am < M;
+  const int bn = n0 + 8 * rg;
+  const bool bcol_ok = bn < N;
+
+  uint4 r[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int p = k0 + 4 * pq + j;
+      r[j] = make_uint4(0, 0, 0, 0);
+      if (!active || p >= p_end) continue;
+      if (isA) {
+        if (!arow_ok) continue;
+        const int b = p / HW, q = p - b * HW, py = q / a.w, px = q - py * a.w;
+        const int qy = py + ady, qx = px + adx;
+        if (qy >= 0 && qy < a.h && qx >= 0 && qx < a.w)
+          r[j] = *(const uint4 *)(a.x + ((size_t)b * HW + (size_t)qy * a.w + qx) * a.xs + a.xo +
+                                  ac);
+      } else if (bcol_ok) {
+        r[j] = *(const uint4 *)(a.g + (size_t)p * a.gs + a.go + bn);
+      }
+    }
+  };
+  auto stage = [&](int buf) {
+    if (!active) return;
+    uint16_t *dst = isA ? &As[buf][0] : &Bs[buf][0];
+    const uint16_t *e0 = (const uint16_t *)&r[0], *e1 = (const uint16_t *)&r[1];
+    const uint16_t *e2 = (const uint16_t *)&r[2], *e3 = (const uint16_t *)&r[3];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      uint2 v;
+      v.x = (uint32_t)e0[c] | ((uint32_t)e1[c] << 16);
+      v.y = (uint32_t)e2[c] | ((uint32_t)e3[c] << 16);
+      *(uint2 *)&dst[(8 * rg + c) * kWLd + 4 * pq] = v;
+    }
+  };
+
+  floatx4 acc[2][TN];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int fr = lane & 15, fk = (lane >> 4) * 8;
+  load(p_begin);
+  stage(0);
+  __syncthreads();
+  int buf = 0;
+  for (int k0 = p_begin; k0 < p_end; k0 += kWBK) {
+    const bool more = k0 + kWBK < p_end;
+    if (more) load(k0 + kWBK);
+#pragma unroll
+    for (int kk = 0; kk < kWBK; kk += 32) {
+      bf16x8 fa[2], fb[TN];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        fa[i] = *(const bf16x8 *)&As[buf][(wm * 32 + i * 16 + fr) * kWLd + kk + fk];
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+        fb[j] = *(const bf16x8 *)&Bs[buf][(wn * TN * 16 + j * 16 + fr) * kWLd + kk + fk];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) stage(buf ^ 1);
+    __syncthreads();
+    buf ^= 1;
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < TN; ++j)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int m = m0 + wm * 32 + i * 16 + (lane >> 4) * 4 + e;
-        const int n = n0 + wn * 32 + j * 16 + (lane & 15);
-        if (m >= M || n >= N) continue;
-        float v = acc[i][j][e];
-        if (MODE == FWD) {
-          if (a.bias) v += a.bias[n];
-          if (a.relu) v = fmaxf(v, 0.f);
-          ((uint16_t *)a.out)[(size_t)m * a.os + a.oo + n] = f2bf(v);
-        } else if (MODE == DGRAD) {
-          uint16_t *o = (uint16_t *)a.out + (size_t)m * a.os + a.oo + n;
-          if (a.accumulate) v += bf2f(*o);
-          *o = f2bf(v);
-        } else {
-          a.part[((size_t)blockIdx.z * M + m) * N + n] = v;
-        }
+        const int n = n0 + wn * TN * 16 + j * 16 + (lane & 15);
+        if (m < M && n < N) a.part[((size_t)blockIdx.z * M + m) * N + n] = acc[i][j][e];
       }
+}
+
+// Transposed bf16 weight copies WT[t][o][c] = W[t][c][o] of up to 16
+// convolutions at once (the parameter layout of the surrogate: conv k's
+// weights at element off[k]).
+struct ConvTable {
+  int count;
+  long long off[16];
+  int ci[16], co[16];
+};
+__global__ void k_transpose_weights(const uint16_t *w, uint16_t *wt, ConvTable tb,
+                                    long long total) {
+  const long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (g >= total) return;
+  long long i = g;
+  int k = 0;
+  while (k < tb.count && i >= 9LL * tb.ci[k] * tb.co[k]) {
+    i -= 9LL * tb.ci[k] * tb.co[k];
+    ++k;
+  }
+  if (k >= tb.count) return;
+  const int ci = tb.ci[k], co = tb.co[k];
+  const int c = i % ci;
+  const long long r = i / ci;
+  const int o = r % co, t = r / co;
+  wt[tb.off[k] + i] = w[tb.off[k] + ((long long)t * ci + c) * co + o];
 }
 
 // out[i] += sum over k of part[k][i] for i < n: the deterministic second half
@@ -227,87 +556,158 @@ __global__ __launch_bounds__(256) void k_sum_parts(const float *part, int nparts
 }
 
 // Bias gradient, first half: part[block][o] = sum of GY[p][o] over the
-// block's chunk of pixels; one channel per thread (c < 256).  k_sum_parts
-// adds the chunks into gb.
+// block's chunk of pixels (co a multiple of 8, at most 256; gs, go multiples
+// of 8).  Thread t takes channels 8 (t % (co / 8)) .. + 7 of the pixels
+// p0 + t / (co / 8), + 256 / (co / 8), ... with 16-byte loads (the 256
+// threads cover whole pixel rows, so a wavefront reads contiguous memory),
+// then the pixel groups are added in a fixed tree order.  k_sum_parts adds
+// the chunks into gb.
 __global__ __launch_bounds__(256) void k_bias_grad(const uint16_t *g, int gs, int go, int npix,
                                                    int co, int chunk, float *part) {
-  const int o = threadIdx.x;
-  if (o >= co) return;
+  const int cv = co / 8, groups = 256 / cv;
+  const int t = threadIdx.x, q = t % cv, grp = t / cv;
   const int p0 = blockIdx.x * chunk, p1 = min(p0 + chunk, npix);
-  float s = 0.f;
-  for (int p = p0; p < p1; ++p) s += bf2f(g[(size_t)p * gs + go + o]);
-  part[(size_t)blockIdx.x * co + o] = s;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  if (grp < groups)
+    for (int p = p0 + grp; p < p1; p += groups) {
+      const uint4 v = *(const uint4 *)(g + (size_t)p * gs + go + 8 * q);
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        s[2 * j] += __uint_as_float(w[j] << 16);
+        s[2 * j + 1] += __uint_as_float(w[j] & 0xFFFF0000u);
+      }
+    }
+  __shared__ float sh[256][9];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) sh[t][j] = s[j];
+  __syncthreads();
+  int top = 1;
+  while (top < groups) top <<= 1;
+  for (int h = top / 2; h > 0; h >>= 1) {   // fixed tree over the pixel groups
+    if (grp < h && grp + h < groups)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) sh[t][j] += sh[t + h * cv][j];
+    __syncthreads();
+  }
+  if (grp == 0)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) part[(size_t)blockIdx.x * co + 8 * q + j] = sh[t][j];
 }
+
+// Elementwise kernels over groups of 8 channels (16 bytes; channel counts,
+// strides and offsets are multiples of 8): thread i takes group i % (c / 8)
+// of pixel i / (c / 8).
+struct Bf8 {
+  uint16_t v[8];
+};
+__device__ __forceinline__ Bf8 ld8(const uint16_t *p) {
+  Bf8 r;
+  *(uint4 *)r.v = *(const uint4 *)p;
+  return r;
+}
+__device__ __forceinline__ void st8(uint16_t *p, const Bf8 &r) { *(uint4 *)p = *(const uint4 *)r.v; }
 
 // 2 x 2 average pooling (h, w: input size, even).
 __global__ void k_pool_fwd(const uint16_t *x, int xs, int xo, int n, int h, int w, int c,
                            uint16_t *y) {
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  const int ho = h / 2, wo = w / 2;
-  if (i >= (long long)n * ho * wo * c) return;
-  const int ch = i % c;
-  const long long pix = i / c;
-  const int ox = pix % wo, oy = (pix / wo) % ho, b = pix / ((long long)wo * ho);
-  float s = 0.f;
+  const int cg = c / 8, ho = h / 2, wo = w / 2;
+  if (i >= (long long)n * ho * wo * cg) return;
+  const int g = (int)(i % cg);
+  const long long pix = i / cg;
+  const int ox = (int)(pix % wo), oy = (int)((pix / wo) % ho), b = (int)(pix / ((long long)wo * ho));
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
-    for (int dx = 0; dx < 2; ++dx)
-      s += bf2f(x[((size_t)(b * h + 2 * oy + dy) * w + 2 * ox + dx) * xs + xo + ch]);
-  y[i] = f2bf(0.25f * s);
+    for (int dx = 0; dx < 2; ++dx) {
+      const Bf8 v = ld8(x + ((size_t)(b * h + 2 * oy + dy) * w + 2 * ox + dx) * xs + xo + 8 * g);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s[j] += bf2f(v.v[j]);
+    }
+  Bf8 r;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) r.v[j] = f2bf(0.25f * s[j]);
+  st8(y + pix * c + 8 * g, r);
 }
 
 __global__ void k_pool_bwd(const uint16_t *gy, int n, int h, int w, int c, uint16_t *gx, int gxs,
                            int gxo, int accumulate) {
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= (long long)n * h * w * c) return;
-  const int ch = i % c;
-  const long long pix = i / c;
-  const int px = pix % w, py = (pix / w) % h, b = pix / ((long long)w * h);
+  const int cg = c / 8;
+  if (i >= (long long)n * h * w * cg) return;
+  const int g = (int)(i % cg);
+  const long long pix = i / cg;
+  const int px = (int)(pix % w), py = (int)((pix / w) % h), b = (int)(pix / ((long long)w * h));
   const int ho = h / 2, wo = w / 2;
-  float v = 0.25f * bf2f(gy[((size_t)(b * ho + py / 2) * wo + px / 2) * c + ch]);
-  uint16_t *o = gx + (size_t)pix * gxs + gxo + ch;
-  if (accumulate) v += bf2f(*o);
-  *o = f2bf(v);
+  const Bf8 v = ld8(gy + ((size_t)(b * ho + py / 2) * wo + px / 2) * c + 8 * g);
+  uint16_t *o = gx + (size_t)pix * gxs + gxo + 8 * g;
+  Bf8 old{};
+  if (accumulate) old = ld8(o);
+  Bf8 r;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    float t = 0.25f * bf2f(v.v[j]);
+    if (accumulate) t += bf2f(old.v[j]);
+    r.v[j] = f2bf(t);
+  }
+  st8(o, r);
 }
 
 // Nearest 2x upsampling (h, w: input size) into a channel slice of y.
 __global__ void k_up_fwd(const uint16_t *x, int n, int h, int w, int c, uint16_t *y, int ys,
                          int yo) {
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  const int H = 2 * h, W = 2 * w;
-  if (i >= (long long)n * H * W * c) return;
-  const int ch = i % c;
-  const long long pix = i / c;
-  const int px = pix % W, py = (pix / W) % H, b = pix / ((long long)W * H);
-  y[(size_t)pix * ys + yo + ch] = x[((size_t)(b * h + py / 2) * w + px / 2) * c + ch];
+  const int H = 2 * h, W = 2 * w, cg = c / 8;
+  if (i >= (long long)n * H * W * cg) return;
+  const int g = (int)(i % cg);
+  const long long pix = i / cg;
+  const int px = (int)(pix % W), py = (int)((pix / W) % H), b = (int)(pix / ((long long)W * H));
+  st8(y + (size_t)pix * ys + yo + 8 * g,
+      ld8(x + ((size_t)(b * h + py / 2) * w + px / 2) * c + 8 * g));
 }
 
 __global__ void k_up_bwd(const uint16_t *gy, int gys, int gyo, int n, int h, int w, int c,
                          uint16_t *gx) {
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= (long long)n * h * w * c) return;
-  const int ch = i % c;
-  const long long pix = i / c;
-  const int px = pix % w, py = (pix / w) % h, b = pix / ((long long)w * h);
+  const int cg = c / 8;
+  if (i >= (long long)n * h * w * cg) return;
+  const int g = (int)(i % cg);
+  const long long pix = i / cg;
+  const int px = (int)(pix % w), py = (int)((pix / w) % h), b = (int)(pix / ((long long)w * h));
   const int W = 2 * w;
-  float s = 0.f;
+  float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int dy = 0; dy < 2; ++dy)
 #pragma unroll
-    for (int dx = 0; dx < 2; ++dx)
-      s += bf2f(gy[((size_t)(b * 2 * h + 2 * py + dy) * W + 2 * px + dx) * gys + gyo + ch]);
-  gx[i] = f2bf(s);
+    for (int dx = 0; dx < 2; ++dx) {
+      const Bf8 v =
+          ld8(gy + ((size_t)(b * 2 * h + 2 * py + dy) * W + 2 * px + dx) * gys + gyo + 8 * g);
+#pragma unroll
+      for (int j = 0; j < 8; ++j) s[j] += bf2f(v.v[j]);
+    }
+  Bf8 r;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) r.v[j] = f2bf(s[j]);
+  st8(gx + pix * c + 8 * g, r);
 }
 
 // g *= (y > 0) over a channel slice [npix][c] of both tensors.
 __global__ void k_relu_bwd(const uint16_t *y, int ys, int yo, uint16_t *g, int gs, int go,
                            long long npix, int c) {
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (i >= npix * c) return;
-  const long long p = i / c;
-  const int ch = i % c;
-  if (!(bf2f(y[p * ys + yo + ch]) > 0.f)) g[p * gs + go + ch] = 0;
+  const int cg = c / 8;
+  if (i >= npix * cg) return;
+  const long long p = i / cg;
+  const int k = (int)(i % cg);
+  const Bf8 yv = ld8(y + p * ys + yo + 8 * k);
+  uint16_t *gp = g + p * gs + go + 8 * k;
+  Bf8 gv = ld8(gp);
+#pragma unroll
+  for (int j = 0; j < 8; ++j)
+    if (!(bf2f(yv.v[j]) > 0.f)) gv.v[j] = 0;
+  st8(gp, gv);
 }
 
 // Masked mean-squared error over the first `cu` channels of pred (stride

@@ -32,8 +32,22 @@ def f64(t):
 
 
 @pytest.mark.parametrize("n,h,w,ci,co", [(2, 12, 8, 32, 32), (1, 10, 7, 96, 96),
-                                         (2, 8, 8, 64, 160)])
+                                         (2, 8, 8, 64, 160), (3, 29, 17, 32, 32),
+                                         (2, 23, 19, 32, 64), (1, 21, 13, 64, 128),
+                                         (2, 9, 11, 128, 256), (8, 128, 128, 32, 32),
+                                         (4, 128, 128, 32, 64), (4, 64, 64, 64, 128),
+                                         (16, 64, 64, 64, 128), (2, 4, 128, 96, 32),
+                                         (2, 6, 64, 192, 64), (2, 8, 32, 64, 128),
+                                         (3, 8, 16, 128, 256), (2, 12, 16, 96, 32)])
 def test_conv_forward_dgrad_wgrad(env, n, h, w, ci, co):
+    """Each pass against the FP64 reference on bf16-rounded inputs.  The
+    shapes cover every kernel of the forward / input-gradient passes: the
+    direct convolution from an LDS patch on 128-, 64-, 32- and 16-wide images
+    (32- and 64-channel tiles, one and several 32-channel chunks) and the
+    implicit
+    GEMM elsewhere (256 x 32, 128 x 32, 128 x 64, 64 x 64, 64 x 128,
+    128 x 128 tiles, chosen by channel count and pixel count), ragged pixel
+    tails, and slices of wider tensors."""
     torch, lbm = env
     rng = np.random.default_rng(n * 1000 + ci + co)
     xs, xo = ci + 32, 32                       # input is a slice of a wider tensor
