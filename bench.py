@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--sweep", type=int, default=1,
                     help="also time the 25-cavity batch against sequential runs (0: skip)")
     ap.add_argument("--sweep-steps", type=int, default=50000)
+    ap.add_argument("--sweep-sequential", type=int, default=1,
+                    help="also time the same 25 cavities one after another (0: the batch only)")
     ap.add_argument("--tts", type=int, default=1,
                     help="time-to-steady of the steady sweep, batched + warm-started vs "
                          "plain (0: skip)")
@@ -219,7 +221,7 @@ def roofline(rec, sec, sites, dtype, nx, ny):
     return out
 
 
-def time_sweep(lbm, torch, re_cases, dtype, steps):
+def time_sweep(lbm, torch, re_cases, dtype, steps, sequential=True):
     """25-cavity sweep: one batch vs the same cavities one after another."""
     nx, ny, re = zip(*re_cases)
     sites = sum(a * b for a, b in zip(nx, ny))
@@ -237,16 +239,19 @@ def time_sweep(lbm, torch, re_cases, dtype, steps):
     torch.cuda.synchronize()
     t_batch = e0.elapsed_time(e1) / 1e3
     b.close()
+    out = {"cavities": len(re_cases), "sites": sites, "steps": steps, "storage": dtype,
+           "batch_variant": bv,
+           "batch_MLUPS": round(sites * steps / t_batch / 1e6, 1),
+           "batch_GBs_effective": round(sites * steps * BYTES_PER_SITE[dtype] / t_batch / 1e9, 1)}
+    if not sequential:
+        return out
     t_seq = 0.0
     for (x, y, r) in re_cases:
         s, _, _ = time_single(lbm, torch, x, y, r, dtype, steps, 1000)
         t_seq += s
-    return {"cavities": len(re_cases), "sites": sites, "steps": steps, "storage": dtype,
-            "batch_variant": bv,
-            "batch_MLUPS": round(sites * steps / t_batch / 1e6, 1),
-            "sequential_MLUPS": round(sites * steps / t_seq / 1e6, 1),
-            "speedup": round(t_seq / t_batch, 3),
-            "batch_GBs_effective": round(sites * steps * BYTES_PER_SITE[dtype] / t_batch / 1e9, 1)}
+    out["sequential_MLUPS"] = round(sites * steps / t_seq / 1e6, 1)
+    out["speedup"] = round(t_seq / t_batch, 3)
+    return out
 
 
 def time_cube(lbm, torch, n, dtype, steps):
@@ -446,7 +451,8 @@ def main():
         out["cases"] = cases
     if args.sweep:
         progress("25-cavity sweep: batch vs sequential")
-        out["sweep"] = time_sweep(lbm, torch, sweep_cases(nx), "f32s", args.sweep_steps)
+        out["sweep"] = time_sweep(lbm, torch, sweep_cases(nx), "f32s", args.sweep_steps,
+                                  sequential=bool(args.sweep_sequential))
     if args.tts:
         from paper_2211_05009_amd import warmstart
         from cavity_inputs import normal_draws
