@@ -659,7 +659,9 @@ int lbm_sur_warm_start_batch(lbm_sur_t s, lbm_batch_t b, int k);
 
 /* Single layer kernels (device pointers, bf16 stored as 16-bit words;
  * tensors NHWC with a channel stride and offset so slices of a
- * concatenation can be read or written; channel counts multiples of 32):
+ * concatenation can be read or written; channel counts multiples of 32,
+ * the strides and offsets of the tensors read multiples of 8 and the
+ * tensors 16-byte aligned; LBM_EINVAL for a bad shape, stride or offset):
  *   mode 0 forward:  out[p, oo+o] = relu?(sum_{t,c} x[p+d_t, xo+c] w[t][c][o]
  *                                   + bias[o])
  *   mode 1 dgrad:    out[p, oo+c] (+)= sum_{t,o} x[p-d_t, xo+o] w[t][c][o]

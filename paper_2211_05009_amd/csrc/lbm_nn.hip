@@ -47,6 +47,46 @@ inline int wgrad_chunks(const ConvArgs &a) {
   return (int)(((long long)a.n * a.h * a.w + a.kchunk - 1) / a.kchunk);
 }
 
+// Strips of the row-streamed weight gradient (k_wgrad_rows): widths 16,
+// 32, 64 and 128 (an iteration is 128 pixels = U rows, U <= h), NT = 2
+// (64-channel output tiles) where co allows; strips of whole iterations,
+// about kRowsBlocks blocks over the (ci / 32) x (co / 32 NT) tiles.
+constexpr long long kRowsBlocks = 512;
+struct RowsPlan {
+  bool ok;
+  int nt, rows, nz;
+  int nz_bound;   // bound on nz over every n up to this one (partials sizing)
+};
+inline RowsPlan wgrad_rows_plan(int n, int h, int w, int ci, int co) {
+  RowsPlan p{false, 1, 0, 0, 0};
+  if (!(w == 16 || w == 32 || w == 64 || w == 128) || ci % 32 || co % 32) return p;
+  const int U = 128 / w;
+  if (h < U) return p;
+  p.nt = co % 64 == 0 ? 2 : 1;
+  const long long tiles = (long long)(ci / 32) * (co / (32 * p.nt));
+  const long long nrow = (long long)n * h;
+  long long nz = std::max(1LL, (kRowsBlocks + tiles - 1) / tiles);
+  nz = std::min(nz, (nrow + U - 1) / U);   // grows with n; p.nz <= it
+  p.nz_bound = (int)nz;
+  long long rows = (nrow + nz - 1) / nz;
+  rows = (rows + U - 1) / U * U;
+  p.rows = (int)rows;
+  p.nz = (int)((nrow + rows - 1) / rows);
+  p.ok = true;
+  return p;
+}
+
+template <int W, int U>
+void wgrad_rows(const ConvArgs &a, const RowsPlan &p, float *bpart, hipStream_t st) {
+  const unsigned grid = (unsigned)((a.ci / 32) * (a.co / (32 * p.nt)) * p.nz);
+  if (p.nt == 2)
+    hipLaunchKernelGGL((k_wgrad_rows<W, U, 2>), dim3(grid), dim3(256), 0, st, a, p.rows, bpart);
+  else
+    hipLaunchKernelGGL((k_wgrad_rows<W, U, 1>), dim3(grid), dim3(256), 0, st, a, p.rows, bpart);
+}
+
+hipError_t wgrad_launch(const ConvArgs &a, float *gbias, hipStream_t st);
+
 // One forward or input-gradient pass with tile shape <WM, WN, TM, TN>.
 template <int MODE, int WM, int WN, int TM, int TN>
 void conv_mn(const ConvArgs &a, int M, int N, hipStream_t st) {
@@ -58,11 +98,16 @@ void conv_mn(const ConvArgs &a, int M, int N, hipStream_t st) {
 // Tile shape for an M x N product: N tiles as wide as the channel count
 // allows (no MFMA on padding), and the larger M tile while it still gives
 // at least two blocks per CU.
+// Persistent patch-kernel blocks: two per CU (their LDS and registers allow
+// two), each walking its share of the tiles.
+constexpr int kPatchBlocks = 2 * 256;
+
 template <int MODE, int W, int BN>
 void conv_patch(const ConvArgs &a, int M, int N, hipStream_t st) {
   constexpr int TPIX = W == 128 ? 256 : W == 16 ? 64 : 128;   // as in k_conv_patch
-  dim3 grid(M / TPIX, (N + BN - 1) / BN);
-  hipLaunchKernelGGL((k_conv_patch<MODE, W, BN>), grid, dim3(256), 0, st, a);
+  const int ntiles = M / TPIX * ((N + BN - 1) / BN);
+  const int grid = std::min(ntiles, kPatchBlocks);
+  hipLaunchKernelGGL((k_conv_patch<MODE, W, BN>), dim3(grid), dim3(256), 0, st, a, ntiles);
 }
 
 template <int MODE>
@@ -71,7 +116,8 @@ void conv_fd(const ConvArgs &a, hipStream_t st) {
   // direct convolution from an LDS patch of whole rows: 256-pixel tiles of
   // 32 channels on 128-wide images, 128-pixel tiles on 64- and 32-wide
   // ones, 64-pixel tiles on 16-wide ones (64 channels where N allows)
-  const bool out_ok = MODE == WGRAD || (a.os % 8 == 0 && a.oo % 8 == 0);
+  // (the forward patch kernel reads the transposed weight copy a.wtt)
+  const bool out_ok = a.os % 8 == 0 && a.oo % 8 == 0 && (MODE != FWD || a.wtt);
   const bool n64 = N % 64 == 0;
   if (out_ok && a.w == 128 && a.h % 2 == 0) {
     conv_patch<MODE, 128, 32>(a, M, N, st);
@@ -113,23 +159,30 @@ void conv_fd(const ConvArgs &a, hipStream_t st) {
   }
 }
 
+// Weight gradient by k_wgrad: 64 x BN tiles of the [9 ci][co] result over
+// pixel chunks, per-chunk partials added into GW in chunk order.
+hipError_t wgrad_tiles_launch(const ConvArgs &a, hipStream_t st) {
+  const int nz = wgrad_chunks(a);
+  if (a.co % 64 == 0) {
+    dim3 grid((9 * a.ci + 63) / 64, a.co / 64, nz);
+    hipLaunchKernelGGL(k_wgrad<64>, grid, dim3(256), 0, st, a);
+  } else {
+    dim3 grid((9 * a.ci + 63) / 64, (a.co + 31) / 32, nz);
+    hipLaunchKernelGGL(k_wgrad<32>, grid, dim3(256), 0, st, a);
+  }
+  const long long mn = 9LL * a.ci * a.co;
+  hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(mn, kSumOut)), dim3(256), 0, st, a.part, nz,
+                     mn, (float *)a.out);
+  return hipGetLastError();
+}
+
 hipError_t conv_launch(int mode, const ConvArgs &a, hipStream_t st) {
   if (mode == FWD) {
     conv_fd<FWD>(a, st);
   } else if (mode == DGRAD) {
     conv_fd<DGRAD>(a, st);
-  } else {   // per-chunk partials into a.part, then added into GW in chunk order
-    const int nz = wgrad_chunks(a);
-    if (a.co % 64 == 0) {
-      dim3 grid((9 * a.ci + 63) / 64, a.co / 64, nz);
-      hipLaunchKernelGGL(k_wgrad<64>, grid, dim3(256), 0, st, a);
-    } else {
-      dim3 grid((9 * a.ci + 63) / 64, (a.co + 31) / 32, nz);
-      hipLaunchKernelGGL(k_wgrad<32>, grid, dim3(256), 0, st, a);
-    }
-    const long long mn = 9LL * a.ci * a.co;
-    hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(mn, kSumOut)), dim3(256), 0, st, a.part, nz,
-                       mn, (float *)a.out);
+  } else {
+    return wgrad_launch(a, nullptr, st);
   }
   return hipGetLastError();
 }
@@ -146,13 +199,45 @@ hipError_t bias_grad_launch(const uint16_t *g, int gs, int go, long long npix, i
   return hipGetLastError();
 }
 
+// Weight gradient of a layer into a.out (FP32 [9 ci][co], added), and with
+// gbias set also its bias gradient (added into gbias): k_wgrad_rows where the
+// width allows (the bias sums then ride along with its loads of GY), else
+// k_wgrad and k_bias_grad.  Partials in a.part (wgrad_part_floats).
+hipError_t wgrad_launch(const ConvArgs &a, float *gbias, hipStream_t st) {
+  const RowsPlan p = wgrad_rows_plan(a.n, a.h, a.w, a.ci, a.co);
+  if (!p.ok) {
+    hipError_t e = wgrad_tiles_launch(a, st);
+    if (e == hipSuccess && gbias)
+      e = bias_grad_launch(a.g, a.gs, a.go, (long long)a.n * a.h * a.w, a.co, a.part, gbias, st);
+    return e;
+  }
+  const long long mn = 9LL * a.ci * a.co;
+  float *bpart = gbias ? a.part + (size_t)p.nz * mn : nullptr;
+  switch (a.w) {
+    case 16: wgrad_rows<16, 8>(a, p, bpart, st); break;
+    case 32: wgrad_rows<32, 4>(a, p, bpart, st); break;
+    case 64: wgrad_rows<64, 2>(a, p, bpart, st); break;
+    default: wgrad_rows<128, 1>(a, p, bpart, st); break;
+  }
+  const unsigned nbw = blocks_for(mn, kSumOut);
+  if (gbias)
+    hipLaunchKernelGGL(k_sum_parts2, dim3(nbw + blocks_for(a.co, kSumOut)), dim3(256), 0, st,
+                       a.part, mn, (float *)a.out, (int)nbw, bpart, (long long)a.co, gbias, p.nz);
+  else
+    hipLaunchKernelGGL(k_sum_parts, dim3(nbw), dim3(256), 0, st, a.part, p.nz, mn,
+                       (float *)a.out);
+  return hipGetLastError();
+}
+
 // Floats of partials a weight or bias gradient needs.
 size_t wgrad_part_floats(int n, int h, int w, int ci, int co) {
   const long long npix = (long long)n * h * w;
   const int kc = wgrad_kchunk(n, h, w, ci, co);
   const size_t wg = (size_t)((npix + kc - 1) / kc) * 9 * ci * co;
   const size_t bg = (size_t)blocks_for(npix, 256) * co;
-  return std::max(wg, bg);
+  const RowsPlan p = wgrad_rows_plan(n, h, w, ci, co);
+  const size_t rg = p.ok ? (size_t)p.nz_bound * (9LL * ci * co + co) : 0;
+  return std::max(std::max(wg, bg), rg);
 }
 
 bool chan_ok(int c) { return c >= 32 && c <= 1024 && c % 32 == 0; }
@@ -404,8 +489,7 @@ int backward(lbm_surrogate *s, int n) {
       a.out = s->gw + o.woff;
       a.kchunk = wgrad_kchunk(n, h, w, o.ci, o.co);
       a.part = s->part;
-      HIPC(conv_launch(WGRAD, a, st));
-      HIPC(bias_grad_launch(gy, o.out.cs, o.out.co, npix, o.co, s->part, s->gw + o.boff, st));
+      HIPC(wgrad_launch(a, s->gw + o.boff, st));
       if (k > 0) {   // the network input needs no gradient
         ConvArgs d{};
         d.n = n;
@@ -504,6 +588,9 @@ int lbm_nn_conv3x3(int mode, int n, int h, int w, int ci, int co, const void *x,
   const int cin = mode == DGRAD ? co : ci, cout = mode == DGRAD ? ci : co;
   if (mode != WGRAD && (xs < cin || xo < 0 || xo + cin > xs || xs % 8 || xo % 8 || os < cout ||
                         oo < 0 || oo + cout > os))
+    return lbm_fail(LBM_EINVAL, "bad channel stride / offset");
+  if (mode == WGRAD && (xs % 8 || xo % 8 || xo < 0 || xo + ci > xs || gs % 8 || go % 8 ||
+                        go < 0 || go + co > gs))
     return lbm_fail(LBM_EINVAL, "bad channel stride / offset");
   if (mode == DGRAD) {
     HIPC(conv_launch(mode, a, (hipStream_t)stream));

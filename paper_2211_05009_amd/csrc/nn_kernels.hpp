@@ -13,8 +13,10 @@
 // all on v_mfma_f32_16x16x32_bf16 (FP32 accumulate): forward and dgrad as a
 // direct convolution from an LDS patch of whole image rows (k_conv_patch)
 // or, for widths it does not serve, a pipelined implicit GEMM (k_conv_mn);
-// wgrad as a pipelined GEMM over pixel chunks (k_wgrad) whose per-chunk
-// partials are added in a fixed order (k_sum_parts).
+// wgrad streamed over strips of image rows with all nine taps per block
+// (k_wgrad_rows: widths 16-128) or as a pipelined GEMM over pixel chunks
+// (k_wgrad: any width), the per-strip or per-chunk partials added in a
+// fixed order (k_sum_parts).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -56,6 +58,15 @@ struct ConvArgs {
 };
 
 constexpr int kLdsK = 32 + 8;   // padded row of a staged 64 x 32 operand slice
+
+// The hardware deals the blocks of a launch round-robin over the 8 XCDs
+// (block L to XCD L % 8), each with its own L2.  xcd_block maps L to a
+// block index such that each XCD runs one contiguous range of indices, so
+// neighbouring tiles, which share halo rows and input strips, meet in one L2.
+__device__ __forceinline__ int xcd_block(int L, int nb) {
+  const int k = L & 7, q = nb >> 3, r = nb & 7;
+  return k * q + (k < r ? k : r) + (L >> 3);
+}
 
 // ---------------------------------------------------------------------------
 // Forward and input-gradient passes as one pipelined implicit GEMM.
@@ -203,104 +214,109 @@ __global__ __launch_bounds__(256) void k_conv_mn(ConvArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// The same two passes as direct convolutions: a block takes TPIX = R w
-// pixels (R whole rows of one image; w a multiple of 16, R dividing h) and
-// BN output channels; per chunk of 32 input channels it loads the
+// The same two passes as direct convolutions: a tile is TPIX = R w pixels
+// (R whole rows of one image; w a multiple of 16, R dividing h) by BN
+// output channels; per chunk of 32 input channels the block loads the
 // (R + 2) x (w + 2) patch of the input (zero halo) and the 9 taps' weights
 // into LDS once, and runs the 9 taps' MFMAs out of LDS, instead of gathering
 // a shifted copy of the input from global memory for every tap.  Four waves
 // split the TPIX pixels (TPIX / 64 MFMA row tiles each) and share all BN
-// columns.  The epilogue stages the FP32 tile in LDS (over the patch) and
-// writes whole 16-byte vectors of 8 channels.
+// columns.  The epilogue stages the FP32 tile in LDS (over patch and
+// weights) and writes whole 16-byte vectors of 8 channels.  Patch pixels
+// and FP32 rows are padded in LDS so that neither the MFMA operand reads
+// nor the epilogue's writes conflict on banks.
+// The blocks are persistent: block b takes tiles b, b + G, b + 2 G, ... (G
+// blocks, numbered so that each XCD holds a contiguous range of tiles) and
+// walks their (tile, chunk) steps in order, loading the next step's patch
+// and weights into registers while the current step's MFMAs and, at a
+// tile's last chunk, its epilogue run; so memory and matrix cores stay busy
+// together instead of every block loading, then computing, then storing.
 //   FWD  : out[p][o] = sum_{t,c} X[p + d_t][c] W[t][c][o]   (N = co, chunks of ci)
 //   DGRAD: out[p][c] = sum_{t,o} GY[p - d_t][o] W[t][c][o]  (N = ci, chunks of co)
-constexpr int kPatchMax = 4 * 130;   // patch pixels at TPIX = 256, w = 128
+// LDS elements per patch pixel: 32 channels + 8 pad, so the 16-byte reads of
+// 8 lanes at consecutive pixels (80-byte stride) cover all 32 banks once
+constexpr int kPs = 40;
 
 template <int MODE, int W, int BN>
-__global__ __launch_bounds__(256) void k_conv_patch(ConvArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k_conv_patch(
+    ConvArgs a, int ntiles) {
   // tile: R whole rows of W pixels, TPIX = R W (256 at W = 128, 128 at
   // W = 64 and 32, 64 at W = 16)
   constexpr int TPIX = W == 128 ? 256 : W == 16 ? 64 : 128;
   constexpr int R = TPIX / W, PW = W + 2, PP = (R + 2) * PW;
   constexpr int TM = TPIX / 64, TN = BN / 16;
-  static_assert(TM >= 1 && PP <= kPatchMax && TPIX * BN * 4 <= kPatchMax * 32 * 2,
-                "patch and FP32 tile fit the LDS patch buffer");
+  constexpr int OS = BN + 4;   // padded FP32 row: the 4 lane groups' writes fill 2 bank cycles
+  // one LDS buffer: the patch [pixel][32 channels + pad] and the weights
+  // [tap][n][k] while the taps run, the FP32 tile [pixel][OS] in the epilogue
+  constexpr int PS_EL = PP * kPs, WS_EL = 9 * BN * kLdsK;
+  constexpr int SM_EL = PS_EL + WS_EL > TPIX * OS * 2 ? PS_EL + WS_EL : TPIX * OS * 2;
+  static_assert(TM >= 1 && SM_EL * 2 <= 80 * 1024, "two blocks per CU");
   constexpr int PV = (PP * 4 + 255) / 256;            // patch vectors per thread
   constexpr int WV = (9 * 32 * (BN / 8) + 255) / 256;  // weight vectors per thread
-  __shared__ __align__(16) uint16_t Ps[kPatchMax * 32];   // [patch pixel][32 channels]
-  __shared__ uint16_t Ws[9 * BN * kLdsK];                 // [tap][n][k]
+  __shared__ __align__(16) uint16_t Sm[SM_EL];
+  uint16_t *const Ps = Sm, *const Ws = Sm + PS_EL;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int HW = a.h * W;
   const int C = MODE == FWD ? a.ci : a.co;
   const int N = MODE == FWD ? a.co : a.ci;
-  const int m0 = blockIdx.x * TPIX, n0 = blockIdx.y * BN;
-  const int img = m0 / HW, y0 = (m0 - img * HW) / W;   // first row of the tile
+  const int ntn = (N + BN - 1) / BN;   // column tiles per pixel tile (adjacent tile numbers)
 
-  // Patch vectors of this thread: element offsets of their 8 channels at
-  // channel 0 (-1: halo outside the image, or beyond the patch), the same
-  // for every chunk.
-  long long poff[PV];
+  // Tile being loaded: its first output channel, and the image pixels of
+  // this thread's patch vectors (-1: halo outside the image, or beyond the
+  // patch); a thread's vectors all hold channels pkq .. pkq + 7 of a chunk.
+  int ln0 = 0;
+  int ppix[PV];
+  const int pkq = (tid & 3) * 8;
+  auto set_load_tile = [&](int tile) {
+    const int lm0 = tile / ntn * TPIX;
+    ln0 = tile % ntn * BN;
+    const int img = lm0 / HW, y0 = (lm0 - img * HW) / W;   // first row of the tile
 #pragma unroll
-  for (int u = 0; u < PV; ++u) {
-    const int v = tid + 256 * u;
-    const int pp = v >> 2, kq = (v & 3) * 8;
-    const int py = pp / PW, px = pp - py * PW;
-    const int gy = y0 + py - 1, gx = px - 1;
-    poff[u] = (pp < PP && gy >= 0 && gy < a.h && gx >= 0 && gx < W)
-                  ? ((long long)img * HW + (long long)gy * W + gx) * a.xs + a.xo + kq
-                  : -1;
-  }
+    for (int u = 0; u < PV; ++u) {
+      const int pp = (tid + 256 * u) >> 2;
+      const int py = pp / PW, px = pp - py * PW;
+      const int gy = y0 + py - 1, gx = px - 1;
+      ppix[u] = (pp < PP && gy >= 0 && gy < a.h && gx >= 0 && gx < W) ? img * HW + gy * W + gx
+                                                                        : -1;
+    }
+  };
 
   // One chunk of 32 channels: all its loads are issued into registers
   // first (unrolled, so they are in flight together), then stored to LDS.
   uint4 rp[PV], rw[WV];
   auto load = [&](int c0) {
+    const int n0 = ln0;
 #pragma unroll
-    for (int u = 0; u < PV; ++u)
-      rp[u] = poff[u] >= 0 ? *(const uint4 *)(a.x + poff[u] + c0) : make_uint4(0, 0, 0, 0);
+    for (int u = 0; u < PV; ++u) {   // halo vectors read pixel 0 and are zeroed
+      const uint4 x = *(const uint4 *)(a.x + (size_t)(ppix[u] >= 0 ? ppix[u] : 0) * a.xs + a.xo +
+                                       pkq + c0);
+      rp[u] = ppix[u] >= 0 ? x : make_uint4(0, 0, 0, 0);
+    }
+    // weights as [tap][n][k] rows: FWD from the transposed copy WT[t][co][ci]
+    // (required), DGRAD from W[t][ci][co]; rows beyond the taps or N read row
+    // 0 and are zeroed, so every load is issued without a branch
+    const uint16_t *wsrc = MODE == FWD ? a.wtt : a.wt;
 #pragma unroll
     for (int u = 0; u < WV; ++u) {
       const int v = tid + 256 * u;
-      rw[u] = make_uint4(0, 0, 0, 0);
-      if (MODE == FWD && a.wtt) {   // WT[t][n0 + n][c0 + kq .. + 7]
-        const int t = v / (BN * 4), r = v - t * BN * 4;
-        const int n = r >> 2, kq = (r & 3) * 8;
-        if (t < 9 && n0 + n < N)
-          rw[u] = *(const uint4 *)(a.wtt + ((size_t)t * a.co + n0 + n) * a.ci + c0 + kq);
-      } else if (MODE == FWD) {     // W[t][c0 + k][n0 + nb .. + 7]
-        const int t = v / (32 * (BN / 8)), r = v - t * 32 * (BN / 8);
-        const int k = r / (BN / 8), nb = (r - k * (BN / 8)) * 8;
-        if (t < 9 && n0 + nb < N)
-          rw[u] = *(const uint4 *)(a.wt + ((size_t)t * a.ci + c0 + k) * a.co + n0 + nb);
-      } else {             // W[t][n0 + n][c0 + kq .. + 7]
-        const int t = v / (BN * 4), r = v - t * BN * 4;
-        const int n = r >> 2, kq = (r & 3) * 8;
-        if (t < 9 && n0 + n < N)
-          rw[u] = *(const uint4 *)(a.wt + ((size_t)t * a.ci + n0 + n) * a.co + c0 + kq);
-      }
+      const int t = v / (BN * 4), r = v - t * BN * 4;
+      const int n = r >> 2, kq = (r & 3) * 8;
+      const bool ok = t < 9 && n0 + n < N;
+      const uint4 w = *(const uint4 *)(wsrc + ((size_t)(ok ? t * N + n0 + n : 0)) * C + c0 + kq);
+      rw[u] = ok ? w : make_uint4(0, 0, 0, 0);
     }
   };
   auto stage = [&]() {
 #pragma unroll
     for (int u = 0; u < PV; ++u) {
       const int v = tid + 256 * u;
-      if ((v >> 2) < PP) *(uint4 *)&Ps[(v >> 2) * 32 + (v & 3) * 8] = rp[u];
+      if ((v >> 2) < PP) *(uint4 *)&Ps[(v >> 2) * kPs + (v & 3) * 8] = rp[u];
     }
 #pragma unroll
     for (int u = 0; u < WV; ++u) {
       const int v = tid + 256 * u;
-      if (MODE == FWD && !a.wtt) {   // stored transposed: Ws[t][n][k]
-        const int t = v / (32 * (BN / 8)), r = v - t * 32 * (BN / 8);
-        const int k = r / (BN / 8), nb = (r - k * (BN / 8)) * 8;
-        if (t < 9) {
-          const uint16_t *e = (const uint16_t *)&rw[u];
-#pragma unroll
-          for (int j = 0; j < 8; ++j) Ws[(t * BN + nb + j) * kLdsK + k] = e[j];
-        }
-      } else {
-        const int t = v / (BN * 4), r = v - t * BN * 4;
-        if (t < 9) *(uint4 *)&Ws[(t * BN + (r >> 2)) * kLdsK + (r & 3) * 8] = rw[u];
-      }
+      const int t = v / (BN * 4), r = v - t * BN * 4;
+      if (t < 9) *(uint4 *)&Ws[(t * BN + (r >> 2)) * kLdsK + (r & 3) * 8] = rw[u];
     }
   };
 
@@ -317,22 +333,86 @@ __global__ __launch_bounds__(256) void k_conv_patch(ConvArgs a) {
 #pragma unroll
   for (int i = 0; i < TM; ++i) {
     const int q = wave * (TPIX / 4) + i * 16 + fr;
-    aoff[i] = ((q / W + 1) * PW + q % W + 1) * 32 + fk;
+    aoff[i] = ((q / W + 1) * PW + q % W + 1) * kPs + fk;
   }
+
+  // epilogue of the tile at (m0, n0): lane holds rows 4 (lane / 16) + e,
+  // column lane % 16 of each MFMA tile; the FP32 tile goes to LDS
+  // [TPIX][OS], then each thread writes 8 consecutive channels of a pixel
+  auto epilogue = [&](int m0, int n0) {
+    float *Os = reinterpret_cast<float *>(Sm);
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+      for (int j = 0; j < TN; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          Os[(wave * (TPIX / 4) + i * 16 + (lane >> 4) * 4 + e) * OS + j * 16 + (lane & 15)] =
+              acc[i][j][e];
+    // a thread always writes channels nq .. nq + 7 (256 is a multiple of
+    // BN / 8): their bias values are loaded once, all in flight together
+    const int nq = (tid % (BN / 8)) * 8;
+    float bv[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (MODE == FWD && a.bias && n0 + nq < N) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) bv[j] = a.bias[n0 + nq + j];
+    }
+    __syncthreads();
+    if (n0 + nq >= N) return;
+    for (int v = tid; v < TPIX * (BN / 8); v += 256) {
+      const int pl = v / (BN / 8);
+      const float *src = Os + pl * OS + nq;
+      uint16_t *o = (uint16_t *)a.out + (size_t)(m0 + pl) * a.os + a.oo + n0 + nq;
+      float r[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) r[j] = src[j];
+      if (MODE == FWD) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          r[j] += bv[j];
+          if (a.relu) r[j] = fmaxf(r[j], 0.f);
+        }
+      } else if (a.accumulate) {
+        const uint4 old = *(const uint4 *)o;
+        const uint16_t *ov = (const uint16_t *)&old;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) r[j] += bf2f(ov[j]);
+      }
+      uint4 pk;
+      uint16_t *pv = (uint16_t *)&pk;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) pv[j] = f2bf(r[j]);
+      *(uint4 *)o = pk;
+    }
+  };
+
+  int tile = xcd_block(blockIdx.x, gridDim.x);   // gridDim.x <= ntiles
+  int c0 = 0;
+  set_load_tile(tile);
+  int em0 = tile / ntn * TPIX, en0 = ln0;        // tile whose sums acc holds
   load(0);
   stage();
   __syncthreads();
-  for (int c0 = 0; c0 < C; c0 += 32) {
-    const bool more = c0 + 32 < C;
-    if (more) load(c0 + 32);          // next chunk in flight during the taps
-#pragma unroll
+  for (;;) {
+    // the step after (tile, c0)
+    int ntile = tile, nc0 = c0 + 32;
+    if (nc0 >= C) {
+      ntile = tile + gridDim.x;
+      nc0 = 0;
+    }
+    const bool more = ntile < ntiles;
+    if (more) {   // in flight during this step's taps and epilogue
+      if (ntile != tile) set_load_tile(ntile);
+      load(nc0);
+    }
+#pragma unroll 3
     for (int t = 0; t < 9; ++t) {
       const int dy = t / 3, dx = t % 3;
       // FWD reads pixel p + d_t, DGRAD p - d_t
       const int oy = MODE == FWD ? dy - 1 : 1 - dy, ox = MODE == FWD ? dx - 1 : 1 - dx;
       bf16x8 fa[TM], fb[TN];
 #pragma unroll
-      for (int i = 0; i < TM; ++i) fa[i] = *(const bf16x8 *)&Ps[aoff[i] + (oy * PW + ox) * 32];
+      for (int i = 0; i < TM; ++i) fa[i] = *(const bf16x8 *)&Ps[aoff[i] + (oy * PW + ox) * kPs];
 #pragma unroll
       for (int j = 0; j < TN; ++j)
         fb[j] = *(const bf16x8 *)&Ws[(t * BN + j * 16 + fr) * kLdsK + fk];
@@ -342,51 +422,22 @@ __global__ __launch_bounds__(256) void k_conv_patch(ConvArgs a) {
         for (int j = 0; j < TN; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
     }
+    __syncthreads();   // patch and weights read by every wave
+    if (nc0 == 0) {    // the tile's last chunk: write it out
+      epilogue(em0, en0);
+#pragma unroll
+      for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+      em0 = ntile / ntn * TPIX;
+      en0 = ntile % ntn * BN;
+      __syncthreads();   // the FP32 tile read by every thread
+    }
+    if (!more) break;
+    stage();
     __syncthreads();
-    if (more) {
-      stage();
-      __syncthreads();
-    }
-  }
-
-  // epilogue: lane holds rows 4 (lane / 16) + e, column lane % 16 of each
-  // tile; the FP32 tile goes to LDS [TPIX][BN] (the patch is free after the
-  // last barrier), then each thread writes 8 consecutive channels of a pixel
-  float *Os = reinterpret_cast<float *>(Ps);
-#pragma unroll
-  for (int i = 0; i < TM; ++i)
-#pragma unroll
-    for (int j = 0; j < TN; ++j)
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        Os[(wave * (TPIX / 4) + i * 16 + (lane >> 4) * 4 + e) * BN + j * 16 + (lane & 15)] =
-            acc[i][j][e];
-  __syncthreads();
-  for (int v = tid; v < TPIX * (BN / 8); v += 256) {
-    const int pl = v / (BN / 8), nq = (v - pl * (BN / 8)) * 8;
-    if (n0 + nq >= N) continue;
-    const float *src = Os + pl * BN + nq;
-    uint16_t *o = (uint16_t *)a.out + (size_t)(m0 + pl) * a.os + a.oo + n0 + nq;
-    float r[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) r[j] = src[j];
-    if (MODE == FWD) {
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        if (a.bias) r[j] += a.bias[n0 + nq + j];
-        if (a.relu) r[j] = fmaxf(r[j], 0.f);
-      }
-    } else if (a.accumulate) {
-      const uint4 old = *(const uint4 *)o;
-      const uint16_t *ov = (const uint16_t *)&old;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) r[j] += bf2f(ov[j]);
-    }
-    uint4 pk;
-    uint16_t *pv = (uint16_t *)&pk;
-#pragma unroll
-    for (int j = 0; j < 8; ++j) pv[j] = f2bf(r[j]);
-    *(uint4 *)o = pk;
+    tile = ntile;
+    c0 = nc0;
   }
 }
 
@@ -505,6 +556,225 @@ __global__ __launch_bounds__(256) void k_wgrad(ConvArgs a) {
       }
 }
 
+// Weight gradient streamed over image rows, for widths 16, 32, 64 and 128.
+//   part[z][(t, c)][o] = sum over the pixels p of strip z of X[p + d_t][c] GY[p][o]
+// A strip is `rows` consecutive image rows of the batch (it may run on from
+// one image into the next); a block owns one strip, 32 input channels
+// (c0 ..), NB = 32 NT output channels (o0 ..) and all nine taps, so each
+// input and output-gradient element of the strip is loaded once per block
+// (k_wgrad loads them once per 64-row tile of the 9 ci taps x channels).
+// The reduction runs over pixels: a lane's 8 consecutive MFMA k are 8
+// consecutive x of one row, so both operands are stored into LDS with x
+// contiguous (channel rows):
+//   input rows in a ring of 2U + 2 image rows, each [32 c][W + 8], the 8
+//   zeros after a channel row doubling as the pad before the next one, so
+//   x = -1 and x = W read zeros;
+//   output-gradient rows of the current and the next iteration.
+// Per tap row the three x offsets come from one aligned 16-byte read and
+// two 4-byte reads by funnel shifts (v_alignbit); rows above the top or
+// below the bottom of a pixel's image give zero operands.  An iteration
+// covers U rows (U W = 128 pixels, 4 k-steps): the next iteration's rows
+// are loaded into registers while the current one is multiplied out, then
+// written into ring slots the current iteration does not read, so one
+// barrier per iteration suffices.  With bpart set, blocks of the first
+// channel tile also add up GY of their strip in FP32, the bias gradient's
+// partial bpart[z][o] (fixed order: per thread, then a fixed LDS tree).
+template <int W, int U, int NT>
+__global__ __launch_bounds__(256) void k_wgrad_rows(ConvArgs a, int rows, float *bpart) {
+  static_assert(U * W == 128 && W % 16 == 0, "an iteration is 128 pixels");
+  constexpr int RP = W + 8, NR = 2 * U + 2, NB = 32 * NT, KS = U * W / 32;
+  constexpr int NIN = U * W, NGO = U * W * NT;   // loader tasks: 4 pixels x 8 channels
+  constexpr int IN_T = (NIN + 255) / 256, GO_T = (NGO + 255) / 256;
+  constexpr int GCG = 4 * NT;                    // 8-channel groups of the NB outputs
+  __shared__ __align__(16) uint16_t Is[NR * 32 * RP + 8];
+  __shared__ __align__(16) uint16_t Gs[2][U * NB * RP];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wc = wave & 1, wn = wave >> 1;
+  const int fr = lane & 15, fk = (lane >> 4) * 8;
+  // block -> (strip, output tile, channel tile); consecutive blocks of one
+  // XCD (the hardware deals blocks round-robin over 8) share a strip
+  const int tcn = a.ci / 32, ton = a.co / NB;
+  const int id = xcd_block(blockIdx.x, gridDim.x);
+  const int z = id / (tcn * ton), cx = id % tcn, ox = (id / tcn) % ton;
+  const int c0 = 32 * cx, o0 = NB * ox;
+  const int nrow = a.n * a.h;
+  const int r0 = z * rows, r1 = min(r0 + rows, nrow);
+  const int nit = (r1 - r0 + U - 1) / U;
+  const bool do_bias = bpart != nullptr && cx == 0;
+
+  float bs[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  // 4 consecutive pixels x 8 channels of one row -> channel rows of LDS
+  auto put = [&](uint16_t *dst, const uint4 (&r)[4]) {
+    const uint16_t *e0 = (const uint16_t *)&r[0], *e1 = (const uint16_t *)&r[1];
+    const uint16_t *e2 = (const uint16_t *)&r[2], *e3 = (const uint16_t *)&r[3];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      uint2 v;
+      v.x = (uint32_t)e0[c] | ((uint32_t)e1[c] << 16);
+      v.y = (uint32_t)e2[c] | ((uint32_t)e3[c] << 16);
+      *(uint2 *)&dst[c * RP] = v;
+    }
+  };
+  auto bias_add = [&](const uint4 (&r)[4]) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t w4[4] = {r[e].x, r[e].y, r[e].z, r[e].w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        bs[2 * j] += __uint_as_float(w4[j] << 16);
+        bs[2 * j + 1] += __uint_as_float(w4[j] & 0xFFFF0000u);
+      }
+    }
+  };
+  auto fetch = [&](const uint16_t *base, int stride, int row, int quad, uint4 (&r)[4]) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) r[e] = make_uint4(0, 0, 0, 0);
+    if (row < 0 || row >= nrow) return;
+    const uint16_t *src = base + ((size_t)row * W + 4 * quad) * stride;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) r[e] = *(const uint4 *)(src + (size_t)e * stride);
+  };
+  const uint16_t *xb = a.x + a.xo + c0, *gyb = a.g + a.go + o0;
+  // ring slot of image row `row`: rows r0 - 1, r0, ... take slots 0, 1, ...
+  auto slot_of = [&](int row) { return (row - r0 + 1) % NR; };
+
+  // prologue: zero pads, input rows r0 - 1 .. r0 + U, GY rows r0 .. r0 + U - 1
+  for (int i = tid; i < NR * 32 + 1; i += 256)
+    *(uint4 *)&Is[i * RP] = make_uint4(0, 0, 0, 0);
+  __syncthreads();
+  for (int q = tid; q < (U + 2) * W; q += 256) {
+    const int cg = q & 3, quad = (q >> 2) % (W / 4), u = (q >> 2) / (W / 4);
+    uint4 r[4];
+    fetch(xb + 8 * cg, a.xs, r0 - 1 + u, quad, r);
+    put(&Is[(slot_of(r0 - 1 + u) * 32 + 8 * cg) * RP + 8 + 4 * quad], r);
+  }
+  for (int q = tid; q < NGO; q += 256) {
+    const int cg = q % GCG, quad = (q / GCG) % (W / 4), u = q / GCG / (W / 4);
+    uint4 r[4];
+    fetch(gyb + 8 * cg, a.gs, r0 + u, quad, r);
+    put(&Gs[0][(u * NB + 8 * cg) * RP + 4 * quad], r);
+    if (do_bias) bias_add(r);
+  }
+
+  floatx4 acc[9][NT];
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[t][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+  uint4 rin[IN_T][4], rgo[GO_T][4];
+  __syncthreads();
+
+  for (int it = 0; it < nit; ++it) {
+    const int rb = r0 + it * U, buf = it & 1;
+    const bool more = it + 1 < nit;
+    if (more) {   // rows of the next iteration: input rb + U + 1 .., GY rb + U ..
+#pragma unroll
+      for (int j = 0; j < IN_T; ++j) {
+        const int q = tid + 256 * j;
+        if (q < NIN) {
+          const int cg = q & 3, quad = (q >> 2) % (W / 4), u = (q >> 2) / (W / 4);
+          fetch(xb + 8 * cg, a.xs, rb + U + 1 + u, quad, rin[j]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < GO_T; ++j) {
+        const int q = tid + 256 * j;
+        if (q < NGO) {
+          const int cg = q % GCG, quad = (q / GCG) % (W / 4), u = q / GCG / (W / 4);
+          fetch(gyb + 8 * cg, a.gs, rb + U + u, quad, rgo[j]);
+        }
+      }
+    }
+    const int yb = rb % a.h, sb = (it * U) % NR;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      const int j0 = ks * 32 + fk, u = j0 / W, x0 = j0 % W;
+      int y = yb + u;
+      if (y >= a.h) y -= a.h;
+      bf16x8 fb[NT];
+#pragma unroll
+      for (int nt = 0; nt < NT; ++nt)
+        fb[nt] = *(const bf16x8 *)&Gs[buf][(u * NB + wn * 16 * NT + nt * 16 + fr) * RP + x0];
+#pragma unroll
+      for (int dy = 0; dy < 3; ++dy) {
+        const int yy = y + dy - 1;
+        int s = sb + u + dy;
+        if (s >= NR) s -= NR;
+        const uint16_t *p = &Is[(s * 32 + wc * 16 + fr) * RP + 8 + x0];
+        uint4 d = *(const uint4 *)p;
+        uint32_t e = *(const uint32_t *)(p + 8), f = *(const uint32_t *)(p - 2);
+        if (yy < 0 || yy >= a.h) {
+          d = make_uint4(0, 0, 0, 0);
+          e = f = 0;
+        }
+        const uint32_t s1 = __builtin_amdgcn_alignbit(d.y, d.x, 16);
+        const uint32_t s2 = __builtin_amdgcn_alignbit(d.z, d.y, 16);
+        const uint32_t s3 = __builtin_amdgcn_alignbit(d.w, d.z, 16);
+        const uint4 am = make_uint4(__builtin_amdgcn_alignbit(d.x, f, 16), s1, s2, s3);
+        const uint4 ap = make_uint4(s1, s2, s3, __builtin_amdgcn_alignbit(e, d.w, 16));
+        const bf16x8 fm = __builtin_bit_cast(bf16x8, am), f0 = __builtin_bit_cast(bf16x8, d),
+                     fp = __builtin_bit_cast(bf16x8, ap);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+          acc[3 * dy][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fm, fb[nt], acc[3 * dy][nt], 0, 0, 0);
+          acc[3 * dy + 1][nt] =
+              __builtin_amdgcn_mfma_f32_16x16x32_bf16(f0, fb[nt], acc[3 * dy + 1][nt], 0, 0, 0);
+          acc[3 * dy + 2][nt] =
+              __builtin_amdgcn_mfma_f32_16x16x32_bf16(fp, fb[nt], acc[3 * dy + 2][nt], 0, 0, 0);
+        }
+      }
+    }
+    if (more) {
+#pragma unroll
+      for (int j = 0; j < IN_T; ++j) {
+        const int q = tid + 256 * j;
+        if (q < NIN) {
+          const int cg = q & 3, quad = (q >> 2) % (W / 4), u = (q >> 2) / (W / 4);
+          put(&Is[(slot_of(rb + U + 1 + u) * 32 + 8 * cg) * RP + 8 + 4 * quad], rin[j]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < GO_T; ++j) {
+        const int q = tid + 256 * j;
+        if (q < NGO) {
+          const int cg = q % GCG, quad = (q / GCG) % (W / 4), u = q / GCG / (W / 4);
+          put(&Gs[buf ^ 1][(u * NB + 8 * cg) * RP + 4 * quad], rgo[j]);
+          if (do_bias) bias_add(rgo[j]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  const int N = a.co;
+  float *dst = a.part + (size_t)z * 9 * a.ci * N;
+#pragma unroll
+  for (int t = 0; t < 9; ++t)
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int c = c0 + wc * 16 + (lane >> 4) * 4 + e;
+        const int o = o0 + wn * 16 * NT + nt * 16 + (lane & 15);
+        dst[(size_t)(t * a.ci + c) * N + o] = acc[t][nt][e];
+      }
+  if (do_bias) {   // threads tid = g (mod GCG) hold channel group g
+    float *red = (float *)Is;   // 256 x 9 floats; the loop ended on a barrier
+#pragma unroll
+    for (int j = 0; j < 8; ++j) red[tid * 9 + j] = bs[j];
+    __syncthreads();
+    for (int h = 256 / GCG / 2; h > 0; h >>= 1) {
+      if (tid / GCG < h)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) red[tid * 9 + j] += red[(tid + h * GCG) * 9 + j];
+      __syncthreads();
+    }
+    if (tid < GCG)
+#pragma unroll
+      for (int j = 0; j < 8; ++j) bpart[(size_t)z * N + o0 + 8 * tid + j] = red[tid * 9 + j];
+  }
+}
+
 // Transposed bf16 weight copies WT[t][o][c] = W[t][c][o] of up to 16
 // convolutions at once (the parameter layout of the surrogate: conv k's
 // weights at element off[k]).
@@ -541,6 +811,32 @@ __global__ __launch_bounds__(256) void k_sum_parts(const float *part, int nparts
                                                    float *out) {
   const int o = threadIdx.x % kSumOut, g = threadIdx.x / kSumOut;
   const long long i = blockIdx.x * (long long)kSumOut + o;
+  float s = 0.f;
+  if (i < n)
+    for (int k = g; k < nparts; k += kSumGroups) s += part[(size_t)k * n + i];
+  __shared__ float sh[kSumGroups][kSumOut];
+  sh[g][o] = s;
+  __syncthreads();
+  if (g == 0 && i < n) {
+    float t = 0.f;
+#pragma unroll
+    for (int q = 0; q < kSumGroups; ++q) t += sh[q][o];
+    out[i] += t;
+  }
+}
+
+// Two k_sum_parts in one launch (the weight and the bias partials of a
+// layer): blocks below nb1 add part1 into out1, the others part2 into out2,
+// so the bias gradient's short sums run beside the weights' long ones.
+__global__ __launch_bounds__(256) void k_sum_parts2(const float *part1, long long n1, float *out1,
+                                                    int nb1, const float *part2, long long n2,
+                                                    float *out2, int nparts) {
+  const bool first = (int)blockIdx.x < nb1;
+  const float *part = first ? part1 : part2;
+  const long long n = first ? n1 : n2;
+  float *out = first ? out1 : out2;
+  const int o = threadIdx.x % kSumOut, g = threadIdx.x / kSumOut;
+  const long long i = (first ? blockIdx.x : blockIdx.x - nb1) * (long long)kSumOut + o;
   float s = 0.f;
   if (i < n)
     for (int k = g; k < nparts; k += kSumGroups) s += part[(size_t)k * n + i];
