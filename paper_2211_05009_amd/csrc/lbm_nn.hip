@@ -50,8 +50,11 @@ inline int wgrad_chunks(const ConvArgs &a) {
 // Strips of the row-streamed weight gradient (k_wgrad_rows): widths 16,
 // 32, 64 and 128 (an iteration is 128 pixels = U rows, U <= h), NT = 2
 // (64-channel output tiles) where co allows; strips of whole iterations,
-// about kRowsBlocks blocks over the (ci / 32) x (co / 32 NT) tiles.
-constexpr long long kRowsBlocks = 512;
+// about kRowsBlocks blocks of kRowsKW four-wave groups over the (ci / 32) x
+// (co / 32 NT) tiles: two groups per block halve the strips (and the
+// partials) at the same number of waves as 512 one-group blocks.
+constexpr int kRowsKW = 2;
+constexpr long long kRowsBlocks = 512 / kRowsKW;
 struct RowsPlan {
   bool ok;
   int nt, rows, nz;
@@ -76,16 +79,28 @@ inline RowsPlan wgrad_rows_plan(int n, int h, int w, int ci, int co) {
   return p;
 }
 
+// One segment of k_sum_parts_v4: groups per output vector chosen so that
+// about 64 k threads run (at most 16 groups, at most the number of parts).
+inline SumSeg sum_seg(const float *part, long long n, float *out, int nparts, bool add) {
+  const long long n4 = n / 4;
+  int g = 1;
+  while (g < 16 && g < nparts && n4 * g < 65536) g *= 2;
+  const int V = 256 / g;
+  return SumSeg{part, n, out, g, (int)((n4 + V - 1) / V), add ? 1 : 0};
+}
+
 template <int W, int U>
 void wgrad_rows(const ConvArgs &a, const RowsPlan &p, float *bpart, hipStream_t st) {
   const unsigned grid = (unsigned)((a.ci / 32) * (a.co / (32 * p.nt)) * p.nz);
   if (p.nt == 2)
-    hipLaunchKernelGGL((k_wgrad_rows<W, U, 2>), dim3(grid), dim3(256), 0, st, a, p.rows, bpart);
+    hipLaunchKernelGGL((k_wgrad_rows<W, U, 2, kRowsKW>), dim3(grid), dim3(256 * kRowsKW), 0, st, a,
+                       p.rows, bpart);
   else
-    hipLaunchKernelGGL((k_wgrad_rows<W, U, 1>), dim3(grid), dim3(256), 0, st, a, p.rows, bpart);
+    hipLaunchKernelGGL((k_wgrad_rows<W, U, 1, kRowsKW>), dim3(grid), dim3(256 * kRowsKW), 0, st, a,
+                       p.rows, bpart);
 }
 
-hipError_t wgrad_launch(const ConvArgs &a, float *gbias, hipStream_t st);
+hipError_t wgrad_launch(const ConvArgs &a, float *gbias, hipStream_t st, bool add = true);
 
 // One forward or input-gradient pass with tile shape <WM, WN, TM, TN>.
 template <int MODE, int WM, int WN, int TM, int TN>
@@ -199,12 +214,19 @@ hipError_t bias_grad_launch(const uint16_t *g, int gs, int go, long long npix, i
   return hipGetLastError();
 }
 
-// Weight gradient of a layer into a.out (FP32 [9 ci][co], added), and with
-// gbias set also its bias gradient (added into gbias): k_wgrad_rows where the
-// width allows (the bias sums then ride along with its loads of GY), else
-// k_wgrad and k_bias_grad.  Partials in a.part (wgrad_part_floats).
-hipError_t wgrad_launch(const ConvArgs &a, float *gbias, hipStream_t st) {
+// Weight gradient of a layer into a.out (FP32 [9 ci][co]), and with gbias
+// set also its bias gradient into gbias, added to what they hold (add) or
+// replacing it: k_wgrad_rows where the width allows (the bias sums then
+// ride along with its loads of GY), else k_wgrad and k_bias_grad.  Partials
+// in a.part (wgrad_part_floats).
+hipError_t wgrad_launch(const ConvArgs &a, float *gbias, hipStream_t st, bool add) {
   const RowsPlan p = wgrad_rows_plan(a.n, a.h, a.w, a.ci, a.co);
+  const bool v4 = (uintptr_t)a.out % 16 == 0 && (!gbias || (uintptr_t)gbias % 16 == 0);
+  if (!add && !(p.ok && v4)) {   // the paths below add: clear the targets first
+    hipError_t e = hipMemsetAsync(a.out, 0, sizeof(float) * 9 * a.ci * a.co, st);
+    if (e == hipSuccess && gbias) e = hipMemsetAsync(gbias, 0, sizeof(float) * a.co, st);
+    if (e != hipSuccess) return e;
+  }
   if (!p.ok) {
     hipError_t e = wgrad_tiles_launch(a, st);
     if (e == hipSuccess && gbias)
@@ -219,13 +241,19 @@ hipError_t wgrad_launch(const ConvArgs &a, float *gbias, hipStream_t st) {
     case 64: wgrad_rows<64, 2>(a, p, bpart, st); break;
     default: wgrad_rows<128, 1>(a, p, bpart, st); break;
   }
-  const unsigned nbw = blocks_for(mn, kSumOut);
-  if (gbias)
-    hipLaunchKernelGGL(k_sum_parts2, dim3(nbw + blocks_for(a.co, kSumOut)), dim3(256), 0, st,
-                       a.part, mn, (float *)a.out, (int)nbw, bpart, (long long)a.co, gbias, p.nz);
-  else
-    hipLaunchKernelGGL(k_sum_parts, dim3(nbw), dim3(256), 0, st, a.part, p.nz, mn,
-                       (float *)a.out);
+  if (v4) {   // mn and co are multiples of 4 (channel counts multiples of 32)
+    const SumSeg s1 = sum_seg(a.part, mn, (float *)a.out, p.nz, add);
+    const SumSeg s2 =
+        gbias ? sum_seg(bpart, a.co, gbias, p.nz, add) : SumSeg{nullptr, 0, nullptr, 1, 0, 0};
+    hipLaunchKernelGGL(k_sum_parts_v4, dim3(s1.blocks + s2.blocks), dim3(256), 0, st, s1, s2,
+                       p.nz);
+  } else {
+    hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(mn, kSumOut)), dim3(256), 0, st, a.part, p.nz,
+                       mn, (float *)a.out);
+    if (gbias)
+      hipLaunchKernelGGL(k_sum_parts, dim3(blocks_for(a.co, kSumOut)), dim3(256), 0, st, bpart,
+                         p.nz, (long long)a.co, gbias);
+  }
   return hipGetLastError();
 }
 
@@ -282,6 +310,11 @@ struct lbm_surrogate {
   float *target = nullptr, *mask = nullptr, *out3 = nullptr;
   float *loss_dev = nullptr, *loss_host = nullptr;
   float *part = nullptr;   // partials of the split reductions (see k_sum_parts)
+  // ReLU gradients fused into the pass that writes the last contribution to
+  // a ReLU conv's output gradient: mask_of[j] = that conv for op j (else -1),
+  // relu_fused[p] set for such a conv p (its separate ReLU pass is skipped)
+  std::vector<int> mask_of;
+  std::vector<char> relu_fused;
   double *rearr = nullptr;                       // [2 nmax] (Re, Ar)
   double *field = nullptr;                       // warm-start fields
   size_t field_doubles = 0;
@@ -382,8 +415,13 @@ __global__ void k_encode(const double *ra, int n, uint16_t *x) {
   const int ny = (int)rint(128.0 * ar);
   float ch[kInCh] = {y < ny ? 1.f : 0.f, (xx + 0.5f) / 128.f, (y + 0.5f) / 128.f,
                      (float)(re / 3000.0), (float)(ar / 2.0)};
-  uint16_t *o = x + i * 32;
-  for (int c = 0; c < 32; ++c) o[c] = c < kInCh ? f2bf(ch[c]) : (uint16_t)0;
+  static_assert(kInCh == 5, "channels 0-4 packed below");
+  uint4 *o = (uint4 *)(x + i * 32);   // channels 0-7, then three vectors of zeros
+  o[0] = make_uint4(f2bf(ch[0]) | ((uint32_t)f2bf(ch[1]) << 16),
+                    f2bf(ch[2]) | ((uint32_t)f2bf(ch[3]) << 16), f2bf(ch[4]), 0);
+  o[1] = make_uint4(0, 0, 0, 0);
+  o[2] = make_uint4(0, 0, 0, 0);
+  o[3] = make_uint4(0, 0, 0, 0);
 }
 
 // Head output channels 0..2 -> FP32 [n][H][W][3].
@@ -459,16 +497,42 @@ int forward(lbm_surrogate *s, int n) {
   return LBM_OK;
 }
 
+// For each ReLU conv p: its output gradient is complete once the consumer
+// with the smallest op index (the last one the backward pass visits) has
+// written or added its part.  If that consumer reads exactly p's output view,
+// its backward pass applies p's ReLU mask while writing (same bits as a
+// separate pass: the masked values are zero before rounding).
+void plan_relu_masks(lbm_surrogate *s) {
+  const int nop = (int)s->ops.size();
+  s->mask_of.assign(nop, -1);
+  s->relu_fused.assign(nop, 0);
+  for (int p = 0; p < nop; ++p) {
+    const Op &o = s->ops[p];
+    if (o.type != OP_CONV || !o.relu) continue;
+    int last = -1;
+    for (int j = p + 1; j < nop && last < 0; ++j) {
+      const View &v = s->ops[j].in;
+      if (v.buf == o.out.buf && v.co < o.out.co + o.co && o.out.co < v.co + s->ops[j].ci) last = j;
+    }
+    if (last < 0) continue;
+    const Op &q = s->ops[last];
+    if (q.in.cs == o.out.cs && q.in.co == o.out.co && q.ci == o.co) {
+      s->mask_of[last] = p;
+      s->relu_fused[p] = 1;
+    }
+  }
+}
+
 int backward(lbm_surrogate *s, int n) {
   hipStream_t st = s->stream;
-  HIPC(hipMemsetAsync(s->gw, 0, s->nparams * sizeof(float), st));
+  // every conv's weight and bias gradients are written once (not added)
   for (int k = (int)s->ops.size() - 1; k >= 0; --k) {
     const Op &o = s->ops[k];
     const int h = level_h(o.level), w = level_w(o.level);
     if (o.type == OP_CONV) {
       const long long npix = (long long)n * h * w;
       uint16_t *gy = bptr(s, s->gact, o.out);
-      if (o.relu) {
+      if (o.relu && !s->relu_fused[k]) {
         hipLaunchKernelGGL(k_relu_bwd, dim3(blocks_for(npix * o.co / 8)), dim3(256), 0, st,
                            bptr(s, s->act, o.out), o.out.cs, o.out.co, gy, o.out.cs, o.out.co,
                            npix, o.co);
@@ -489,7 +553,7 @@ int backward(lbm_surrogate *s, int n) {
       a.out = s->gw + o.woff;
       a.kchunk = wgrad_kchunk(n, h, w, o.ci, o.co);
       a.part = s->part;
-      HIPC(wgrad_launch(a, s->gw + o.boff, st));
+      HIPC(wgrad_launch(a, s->gw + o.boff, st, false));
       if (k > 0) {   // the network input needs no gradient
         ConvArgs d{};
         d.n = n;
@@ -505,18 +569,21 @@ int backward(lbm_surrogate *s, int n) {
         d.os = o.in.cs;
         d.oo = o.in.co;
         d.accumulate = 0;
+        d.mask = s->mask_of[k] >= 0 ? bptr(s, s->act, o.in) : nullptr;
         HIPC(conv_launch(DGRAD, d, st));
       }
     } else if (o.type == OP_POOL) {
       // skip slice: add to the gradient the decoder already wrote there
       hipLaunchKernelGGL(k_pool_bwd, dim3(blocks_for((long long)n * h * w * o.ci / 8)), dim3(256), 0,
                          st, bptr(s, s->gact, o.out), n, h, w, o.ci, bptr(s, s->gact, o.in),
-                         o.in.cs, o.in.co, 1);
+                         o.in.cs, o.in.co, 1,
+                         s->mask_of[k] >= 0 ? bptr(s, s->act, o.in) : nullptr);
       HIPC(hipGetLastError());
     } else {
       hipLaunchKernelGGL(k_up_bwd, dim3(blocks_for((long long)n * h * w * o.ci / 8)), dim3(256), 0, st,
                          bptr(s, s->gact, o.out), o.out.cs, o.out.co, n, h, w, o.ci,
-                         bptr(s, s->gact, o.in));
+                         bptr(s, s->gact, o.in),
+                         s->mask_of[k] >= 0 ? bptr(s, s->act, o.in) : nullptr);
       HIPC(hipGetLastError());
     }
   }
@@ -652,7 +719,8 @@ int lbm_nn_pool2(int backward, int n, int h, int w, int c, const void *in, int i
                        st, (const uint16_t *)in, is, io, n, h, w, c, (uint16_t *)out);
   } else {           // in: dense gradient [n][h/2][w/2][c]; out: slice (os, oo)
     hipLaunchKernelGGL(k_pool_bwd, dim3(blocks_for((long long)n * h * w * c / 8)), dim3(256), 0, st,
-                       (const uint16_t *)in, n, h, w, c, (uint16_t *)out, os, oo, accumulate);
+                       (const uint16_t *)in, n, h, w, c, (uint16_t *)out, os, oo, accumulate,
+                       nullptr);
   }
   HIPC(hipGetLastError());
   return LBM_OK;
@@ -669,7 +737,7 @@ int lbm_nn_up2(int backward, int n, int h, int w, int c, const void *in, int is,
                        (const uint16_t *)in, n, h, w, c, (uint16_t *)out, os, oo);
   else             // in: gradient slice of [n][2h][2w] -> out dense [n][h][w][c]
     hipLaunchKernelGGL(k_up_bwd, dim3(blocks_for((long long)n * h * w * c / 8)), dim3(256), 0, st,
-                       (const uint16_t *)in, is, io, n, h, w, c, (uint16_t *)out);
+                       (const uint16_t *)in, is, io, n, h, w, c, (uint16_t *)out, nullptr);
   HIPC(hipGetLastError());
   return LBM_OK;
 }
@@ -697,6 +765,7 @@ int lbm_sur_create(int max_batch, lbm_sur_t *out) {
   if (!s) return lbm_fail(LBM_ENOMEM, "host allocation");
   s->nmax = max_batch;
   build_net(s);
+  plan_relu_masks(s);
   for (const Op &o : s->ops) {   // the convs are laid out one after another
     if (o.type != OP_CONV) continue;
     const int k = s->convs.count++;
@@ -837,6 +906,7 @@ int lbm_sur_train_step(lbm_sur_t s, int n, const double *re, const double *ar,
   const long long npix = (long long)n * kH * kW;
   HIPC(hipMemsetAsync(s->loss_dev, 0, sizeof(float), s->stream));
   const View &hv = head_view(s);
+  static_assert(kOutCh <= 8, "k_mse reads the head's first 8 channels");
   hipLaunchKernelGGL(k_mse, dim3(blocks_for(npix)), dim3(256), 0, s->stream,
                      bptr(s, s->act, hv), hv.cs, target_dev, mask_dev, npix, kOutCh,
                      (float)(1.0 / count), bptr(s, s->gact, hv), hv.cs, s->part);

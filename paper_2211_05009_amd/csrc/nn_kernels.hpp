@@ -52,6 +52,9 @@ struct ConvArgs {
   void *out;           // FWD: bf16 Y; DGRAD: bf16 GX; WGRAD: float GW [9 ci][co]
   int os, oo;
   int accumulate;      // DGRAD: add into GX
+  const uint16_t *mask;  // DGRAD (optional): zero GX where mask <= 0 (the
+                         // ReLU of the layer that produced the input; same
+                         // stride and offset as out), before the bf16 rounding
   int kchunk;          // WGRAD: pixels per block (multiple of 32)
   float *part;         // WGRAD: per-chunk partials [gridDim.z][9 ci][co], added
                        // into GW in chunk order by k_sum_parts (deterministic)
@@ -205,8 +208,9 @@ __global__ __launch_bounds__(256) void k_conv_mn(ConvArgs a) {
         if (MODE == FWD) {
           v += bn;
           if (a.relu) v = fmaxf(v, 0.f);
-        } else if (a.accumulate) {
-          v += bf2f(*o);
+        } else {
+          if (a.accumulate) v += bf2f(*o);
+          if (a.mask && !(bf2f(a.mask[o - (uint16_t *)a.out]) > 0.f)) v = 0.f;
         }
         *o = f2bf(v);
       }
@@ -372,11 +376,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
           r[j] += bv[j];
           if (a.relu) r[j] = fmaxf(r[j], 0.f);
         }
-      } else if (a.accumulate) {
-        const uint4 old = *(const uint4 *)o;
-        const uint16_t *ov = (const uint16_t *)&old;
+      } else {
+        if (a.accumulate) {
+          const uint4 old = *(const uint4 *)o;
+          const uint16_t *ov = (const uint16_t *)&old;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) r[j] += bf2f(ov[j]);
+          for (int j = 0; j < 8; ++j) r[j] += bf2f(ov[j]);
+        }
+        if (a.mask) {
+          const uint4 mv = *(const uint4 *)(a.mask + (o - (uint16_t *)a.out));
+          const uint16_t *mk = (const uint16_t *)&mv;
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (!(bf2f(mk[j]) > 0.f)) r[j] = 0.f;
+        }
       }
       uint4 pk;
       uint16_t *pv = (uint16_t *)&pk;
@@ -576,23 +589,30 @@ __global__ __launch_bounds__(256) void k_wgrad(ConvArgs a) {
 // covers U rows (U W = 128 pixels, 4 k-steps): the next iteration's rows
 // are loaded into registers while the current one is multiplied out, then
 // written into ring slots the current iteration does not read, so one
-// barrier per iteration suffices.  With bpart set, blocks of the first
+// barrier per iteration suffices.  KW groups of four waves split each
+// iteration's k-steps and add their sums in LDS at the end (fixed order),
+// so a block does KW times the work of one group and the strips, hence the
+// partials, are KW times fewer.  With bpart set, blocks of the first
 // channel tile also add up GY of their strip in FP32, the bias gradient's
 // partial bpart[z][o] (fixed order: per thread, then a fixed LDS tree).
-template <int W, int U, int NT>
-__global__ __launch_bounds__(256) void k_wgrad_rows(ConvArgs a, int rows, float *bpart) {
+template <int W, int U, int NT, int KW>
+__global__ __launch_bounds__(256 * KW) void k_wgrad_rows(ConvArgs a, int rows, float *bpart) {
   static_assert(U * W == 128 && W % 16 == 0, "an iteration is 128 pixels");
+  constexpr int NTH = 256 * KW;
   constexpr int RP = W + 8, NR = 2 * U + 2, NB = 32 * NT, KS = U * W / 32;
+  static_assert(KS % KW == 0, "groups share the k-steps evenly");
   constexpr int NIN = U * W, NGO = U * W * NT;   // loader tasks: 4 pixels x 8 channels
-  constexpr int IN_T = (NIN + 255) / 256, GO_T = (NGO + 255) / 256;
+  constexpr int IN_T = (NIN + NTH - 1) / NTH, GO_T = (NGO + NTH - 1) / NTH;
   constexpr int GCG = 4 * NT;                    // 8-channel groups of the NB outputs
-  __shared__ __align__(16) uint16_t Is[NR * 32 * RP + 8];
-  __shared__ __align__(16) uint16_t Gs[2][U * NB * RP];
+  constexpr int IS_EL = NR * 32 * RP + 8, GS_EL = U * NB * RP;
+  __shared__ __align__(16) uint16_t Is[IS_EL];
+  __shared__ __align__(16) uint16_t Gs[2][GS_EL];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wc = wave & 1, wn = wave >> 1;
+  const int grp = wave >> 2, gw = wave & 3;      // k-step group, wave within it
+  const int wc = gw & 1, wn = gw >> 1;
   const int fr = lane & 15, fk = (lane >> 4) * 8;
   // block -> (strip, output tile, channel tile); consecutive blocks of one
-  // XCD (the hardware deals blocks round-robin over 8) share a strip
+  // XCD share a strip
   const int tcn = a.ci / 32, ton = a.co / NB;
   const int id = xcd_block(blockIdx.x, gridDim.x);
   const int z = id / (tcn * ton), cx = id % tcn, ox = (id / tcn) % ton;
@@ -626,29 +646,29 @@ __global__ __launch_bounds__(256) void k_wgrad_rows(ConvArgs a, int rows, float 
       }
     }
   };
+  // rows outside the batch read row 0 and are zeroed (no branch around loads)
   auto fetch = [&](const uint16_t *base, int stride, int row, int quad, uint4 (&r)[4]) {
+    const bool ok = row >= 0 && row < nrow;
+    const uint16_t *src = base + ((size_t)(ok ? row : 0) * W + 4 * quad) * stride;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) r[e] = make_uint4(0, 0, 0, 0);
-    if (row < 0 || row >= nrow) return;
-    const uint16_t *src = base + ((size_t)row * W + 4 * quad) * stride;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) r[e] = *(const uint4 *)(src + (size_t)e * stride);
+    for (int e = 0; e < 4; ++e) {
+      const uint4 v = *(const uint4 *)(src + (size_t)e * stride);
+      r[e] = ok ? v : make_uint4(0, 0, 0, 0);
+    }
   };
   const uint16_t *xb = a.x + a.xo + c0, *gyb = a.g + a.go + o0;
   // ring slot of image row `row`: rows r0 - 1, r0, ... take slots 0, 1, ...
   auto slot_of = [&](int row) { return (row - r0 + 1) % NR; };
 
   // prologue: zero pads, input rows r0 - 1 .. r0 + U, GY rows r0 .. r0 + U - 1
-  for (int i = tid; i < NR * 32 + 1; i += 256)
-    *(uint4 *)&Is[i * RP] = make_uint4(0, 0, 0, 0);
-  __syncthreads();
-  for (int q = tid; q < (U + 2) * W; q += 256) {
+  for (int i = tid; i < NR * 32 + 1; i += NTH) *(uint4 *)&Is[i * RP] = make_uint4(0, 0, 0, 0);
+  for (int q = tid; q < (U + 2) * W; q += NTH) {
     const int cg = q & 3, quad = (q >> 2) % (W / 4), u = (q >> 2) / (W / 4);
     uint4 r[4];
     fetch(xb + 8 * cg, a.xs, r0 - 1 + u, quad, r);
     put(&Is[(slot_of(r0 - 1 + u) * 32 + 8 * cg) * RP + 8 + 4 * quad], r);
   }
-  for (int q = tid; q < NGO; q += 256) {
+  for (int q = tid; q < NGO; q += NTH) {
     const int cg = q % GCG, quad = (q / GCG) % (W / 4), u = q / GCG / (W / 4);
     uint4 r[4];
     fetch(gyb + 8 * cg, a.gs, r0 + u, quad, r);
@@ -670,7 +690,7 @@ __global__ __launch_bounds__(256) void k_wgrad_rows(ConvArgs a, int rows, float 
     if (more) {   // rows of the next iteration: input rb + U + 1 .., GY rb + U ..
 #pragma unroll
       for (int j = 0; j < IN_T; ++j) {
-        const int q = tid + 256 * j;
+        const int q = tid + NTH * j;
         if (q < NIN) {
           const int cg = q & 3, quad = (q >> 2) % (W / 4), u = (q >> 2) / (W / 4);
           fetch(xb + 8 * cg, a.xs, rb + U + 1 + u, quad, rin[j]);
@@ -678,7 +698,7 @@ __global__ __launch_bounds__(256) void k_wgrad_rows(ConvArgs a, int rows, float 
       }
 #pragma unroll
       for (int j = 0; j < GO_T; ++j) {
-        const int q = tid + 256 * j;
+        const int q = tid + NTH * j;
         if (q < NGO) {
           const int cg = q % GCG, quad = (q / GCG) % (W / 4), u = q / GCG / (W / 4);
           fetch(gyb + 8 * cg, a.gs, rb + U + u, quad, rgo[j]);
@@ -687,7 +707,8 @@ __global__ __launch_bounds__(256) void k_wgrad_rows(ConvArgs a, int rows, float 
     }
     const int yb = rb % a.h, sb = (it * U) % NR;
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
+    for (int kk = 0; kk < KS / KW; ++kk) {
+      const int ks = kk * KW + grp;
       const int j0 = ks * 32 + fk, u = j0 / W, x0 = j0 % W;
       int y = yb + u;
       if (y >= a.h) y -= a.h;
@@ -727,7 +748,7 @@ __global__ __launch_bounds__(256) void k_wgrad_rows(ConvArgs a, int rows, float 
     if (more) {
 #pragma unroll
       for (int j = 0; j < IN_T; ++j) {
-        const int q = tid + 256 * j;
+        const int q = tid + NTH * j;
         if (q < NIN) {
           const int cg = q & 3, quad = (q >> 2) % (W / 4), u = (q >> 2) / (W / 4);
           put(&Is[(slot_of(rb + U + 1 + u) * 32 + 8 * cg) * RP + 8 + 4 * quad], rin[j]);
@@ -735,7 +756,7 @@ __global__ __launch_bounds__(256) void k_wgrad_rows(ConvArgs a, int rows, float 
       }
 #pragma unroll
       for (int j = 0; j < GO_T; ++j) {
-        const int q = tid + 256 * j;
+        const int q = tid + NTH * j;
         if (q < NGO) {
           const int cg = q % GCG, quad = (q / GCG) % (W / 4), u = q / GCG / (W / 4);
           put(&Gs[buf ^ 1][(u * NB + 8 * cg) * RP + 4 * quad], rgo[j]);
@@ -746,24 +767,57 @@ __global__ __launch_bounds__(256) void k_wgrad_rows(ConvArgs a, int rows, float 
     __syncthreads();
   }
 
+  // groups 1 .. KW - 1 hand their sums to group 0 through LDS, three taps
+  // at a time (the ring is free after the loop's last barrier)
+  if (KW > 1) {
+    float *xch = (float *)Is;   // [group - 1][3 taps][NT][4][256 lanes]
+    static_assert((KW - 1) * 3 * NT * 4 * 256 * 4 <= IS_EL * 2, "exchange fits the ring");
+#pragma unroll
+    for (int t0 = 0; t0 < 9; t0 += 3) {
+      if (grp > 0)
+#pragma unroll
+        for (int t = 0; t < 3; ++t)
+#pragma unroll
+          for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              xch[((((grp - 1) * 3 + t) * NT + nt) * 4 + e) * 256 + (tid & 255)] =
+                  acc[t0 + t][nt][e];
+      __syncthreads();
+      if (grp == 0)
+#pragma unroll
+        for (int g = 1; g < KW; ++g)
+#pragma unroll
+          for (int t = 0; t < 3; ++t)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+              for (int e = 0; e < 4; ++e)
+                acc[t0 + t][nt][e] += xch[((((g - 1) * 3 + t) * NT + nt) * 4 + e) * 256 + tid];
+      __syncthreads();
+    }
+  }
   const int N = a.co;
-  float *dst = a.part + (size_t)z * 9 * a.ci * N;
+  if (grp == 0) {
+    float *dst = a.part + (size_t)z * 9 * a.ci * N;
 #pragma unroll
-  for (int t = 0; t < 9; ++t)
+    for (int t = 0; t < 9; ++t)
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt)
+      for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int c = c0 + wc * 16 + (lane >> 4) * 4 + e;
-        const int o = o0 + wn * 16 * NT + nt * 16 + (lane & 15);
-        dst[(size_t)(t * a.ci + c) * N + o] = acc[t][nt][e];
-      }
+        for (int e = 0; e < 4; ++e) {
+          const int c = c0 + wc * 16 + (lane >> 4) * 4 + e;
+          const int o = o0 + wn * 16 * NT + nt * 16 + (lane & 15);
+          dst[(size_t)(t * a.ci + c) * N + o] = acc[t][nt][e];
+        }
+  }
   if (do_bias) {   // threads tid = g (mod GCG) hold channel group g
-    float *red = (float *)Is;   // 256 x 9 floats; the loop ended on a barrier
+    float *red = (float *)Is;   // NTH x 9 floats; the last barrier has passed
+    static_assert(NTH * 9 * 4 <= IS_EL * 2, "bias tree fits the ring");
 #pragma unroll
     for (int j = 0; j < 8; ++j) red[tid * 9 + j] = bs[j];
     __syncthreads();
-    for (int h = 256 / GCG / 2; h > 0; h >>= 1) {
+    for (int h = NTH / GCG / 2; h > 0; h >>= 1) {
       if (tid / GCG < h)
 #pragma unroll
         for (int j = 0; j < 8; ++j) red[tid * 9 + j] += red[(tid + h * GCG) * 9 + j];
@@ -813,6 +867,7 @@ __global__ __launch_bounds__(256) void k_sum_parts(const float *part, int nparts
   const long long i = blockIdx.x * (long long)kSumOut + o;
   float s = 0.f;
   if (i < n)
+#pragma unroll 8
     for (int k = g; k < nparts; k += kSumGroups) s += part[(size_t)k * n + i];
   __shared__ float sh[kSumGroups][kSumOut];
   sh[g][o] = s;
@@ -825,29 +880,64 @@ __global__ __launch_bounds__(256) void k_sum_parts(const float *part, int nparts
   }
 }
 
-// Two k_sum_parts in one launch (the weight and the bias partials of a
-// layer): blocks below nb1 add part1 into out1, the others part2 into out2,
-// so the bias gradient's short sums run beside the weights' long ones.
-__global__ __launch_bounds__(256) void k_sum_parts2(const float *part1, long long n1, float *out1,
-                                                    int nb1, const float *part2, long long n2,
-                                                    float *out2, int nparts) {
-  const bool first = (int)blockIdx.x < nb1;
-  const float *part = first ? part1 : part2;
-  const long long n = first ? n1 : n2;
-  float *out = first ? out1 : out2;
-  const int o = threadIdx.x % kSumOut, g = threadIdx.x / kSumOut;
-  const long long i = (first ? blockIdx.x : blockIdx.x - nb1) * (long long)kSumOut + o;
-  float s = 0.f;
-  if (i < n)
-    for (int k = g; k < nparts; k += kSumGroups) s += part[(size_t)k * n + i];
-  __shared__ float sh[kSumGroups][kSumOut];
-  sh[g][o] = s;
+// Partial sums of a layer's weight and bias gradients in one launch:
+// out[i] (+)= sum over k of part[k][i] for each of two segments (blocks below
+// s1.blocks take segment 1).  A thread adds 4 consecutive outputs (16-byte
+// loads); the block's `groups` thread groups (a power of two dividing 256)
+// take k = g, g + groups, ... in order and the group sums are added in
+// group order, so the result is fixed for a given shape.  Many groups
+// serve few outputs with many partials, one group many outputs.  n, the
+// pointers' element offsets: multiples of 4.
+struct SumSeg {
+  const float *part;
+  long long n;
+  float *out;
+  int groups, blocks;
+  int add;   // 1: out += sum, 0: out = sum
+};
+__global__ __launch_bounds__(256) void k_sum_parts_v4(SumSeg s1, SumSeg s2, int nparts) {
+  const bool first = (int)blockIdx.x < s1.blocks;
+  const float *part = first ? s1.part : s2.part;
+  float *out = first ? s1.out : s2.out;
+  const long long n4 = (first ? s1.n : s2.n) / 4;
+  const int G = first ? s1.groups : s2.groups, V = 256 / G;
+  const bool add = first ? s1.add : s2.add;
+  const int b = first ? blockIdx.x : blockIdx.x - s1.blocks;
+  const int g = threadIdx.x / V, vi = threadIdx.x - g * V;
+  const long long i = (long long)b * V + vi;   // vector index
+  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+  if (i < n4) {
+    const float4 *p4 = (const float4 *)part + i;
+#pragma unroll 4
+    for (int k = g; k < nparts; k += G) {
+      const float4 v = p4[(size_t)k * n4];
+      acc.x += v.x;
+      acc.y += v.y;
+      acc.z += v.z;
+      acc.w += v.w;
+    }
+  }
+  __shared__ float4 sh[256];
+  sh[threadIdx.x] = acc;
   __syncthreads();
-  if (g == 0 && i < n) {
-    float t = 0.f;
-#pragma unroll
-    for (int q = 0; q < kSumGroups; ++q) t += sh[q][o];
-    out[i] += t;
+  if (g == 0 && i < n4) {
+    float4 t = sh[vi];
+    for (int q = 1; q < G; ++q) {
+      const float4 v = sh[q * V + vi];
+      t.x += v.x;
+      t.y += v.y;
+      t.z += v.z;
+      t.w += v.w;
+    }
+    float4 *o = (float4 *)out + i;
+    if (add) {
+      const float4 r = *o;
+      t.x += r.x;
+      t.y += r.y;
+      t.z += r.z;
+      t.w += r.w;
+    }
+    *o = t;
   }
 }
 
@@ -928,8 +1018,11 @@ __global__ void k_pool_fwd(const uint16_t *x, int xs, int xo, int n, int h, int 
   st8(y + pix * c + 8 * g, r);
 }
 
+// Gradient of the pooling, written into (or added to) a slice of gx; with
+// mask set, zero where mask <= 0 (mask has gx's stride and offset: the ReLU
+// of the layer that produced the pooled input; k_up_bwd likewise).
 __global__ void k_pool_bwd(const uint16_t *gy, int n, int h, int w, int c, uint16_t *gx, int gxs,
-                           int gxo, int accumulate) {
+                           int gxo, int accumulate, const uint16_t *mask) {
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   const int cg = c / 8;
   if (i >= (long long)n * h * w * cg) return;
@@ -941,11 +1034,14 @@ __global__ void k_pool_bwd(const uint16_t *gy, int n, int h, int w, int c, uint1
   uint16_t *o = gx + (size_t)pix * gxs + gxo + 8 * g;
   Bf8 old{};
   if (accumulate) old = ld8(o);
+  Bf8 mk{};
+  if (mask) mk = ld8(mask + (o - gx));
   Bf8 r;
 #pragma unroll
   for (int j = 0; j < 8; ++j) {
     float t = 0.25f * bf2f(v.v[j]);
     if (accumulate) t += bf2f(old.v[j]);
+    if (mask && !(bf2f(mk.v[j]) > 0.f)) t = 0.f;
     r.v[j] = f2bf(t);
   }
   st8(o, r);
@@ -965,7 +1061,7 @@ __global__ void k_up_fwd(const uint16_t *x, int n, int h, int w, int c, uint16_t
 }
 
 __global__ void k_up_bwd(const uint16_t *gy, int gys, int gyo, int n, int h, int w, int c,
-                         uint16_t *gx) {
+                         uint16_t *gx, const uint16_t *mask) {
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   const int cg = c / 8;
   if (i >= (long long)n * h * w * cg) return;
@@ -983,6 +1079,12 @@ __global__ void k_up_bwd(const uint16_t *gy, int gys, int gyo, int n, int h, int
 #pragma unroll
       for (int j = 0; j < 8; ++j) s[j] += bf2f(v.v[j]);
     }
+  if (mask) {
+    const Bf8 mk = ld8(mask + pix * c + 8 * g);
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (!(bf2f(mk.v[j]) > 0.f)) s[j] = 0.f;
+  }
   Bf8 r;
 #pragma unroll
   for (int j = 0; j < 8; ++j) r.v[j] = f2bf(s[j]);
@@ -1006,10 +1108,12 @@ __global__ void k_relu_bwd(const uint16_t *y, int ys, int yo, uint16_t *g, int g
   st8(gp, gv);
 }
 
-// Masked mean-squared error over the first `cu` channels of pred (stride
-// ps): loss[block] = the block's sum of mask (pred - t)^2 / count (k_sum_parts
-// adds the blocks); grad = 2 mask (pred - t) / count (bf16, stride gs, zero
-// elsewhere).  t: FP32 [npix][cu]; mask FP32 [npix].
+// Masked mean-squared error over the first `cu` (<= 8) channels of pred
+// (stride ps): loss[block] = the block's sum of mask (pred - t)^2 / count
+// (k_sum_parts adds the blocks); grad = 2 mask (pred - t) / count (bf16,
+// stride gs, zero elsewhere).  t: FP32 [npix][cu]; mask FP32 [npix].  Strides
+// are multiples of 8 and the tensors 16-byte aligned: a thread reads the
+// first 8 channels of its pixel as one vector and writes gs / 8 vectors.
 __global__ __launch_bounds__(256) void k_mse(const uint16_t *pred, int ps, const float *t,
                                              const float *mask, long long npix, int cu,
                                              float inv_count, uint16_t *grad, int gs,
@@ -1018,15 +1122,20 @@ __global__ __launch_bounds__(256) void k_mse(const uint16_t *pred, int ps, const
   float l = 0.f;
   if (p < npix) {
     const float mk = mask[p];
-    for (int ch = 0; ch < gs; ++ch) {
-      float gv = 0.f;
+    const Bf8 pv = ld8(pred + p * ps);
+    Bf8 gv;
+#pragma unroll
+    for (int ch = 0; ch < 8; ++ch) {
+      float g = 0.f;
       if (ch < cu) {
-        const float d = bf2f(pred[p * ps + ch]) - t[p * cu + ch];
+        const float d = bf2f(pv.v[ch]) - t[p * cu + ch];
         l += mk * d * d;
-        gv = 2.f * mk * d * inv_count;
+        g = 2.f * mk * d * inv_count;
       }
-      grad[p * gs + ch] = f2bf(gv);
+      gv.v[ch] = f2bf(g);
     }
+    st8(grad + p * gs, gv);
+    for (int k = 8; k < gs; k += 8) *(uint4 *)(grad + p * gs + k) = make_uint4(0, 0, 0, 0);
   }
   for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off, 64);
   __shared__ float part[4];
