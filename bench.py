@@ -96,7 +96,7 @@ def parse():
     ap.add_argument("--aux", type=int, default=0,
                     help="instead time the kernels off the metric (non-equilibrium-"
                          "extrapolation step, vortex extraction, surrogate convolutions, "
-                         "series classifier); prints one JSON line")
+                         "series classifier; 2: the surrogate alone); prints one JSON line")
     ap.add_argument("--precision", type=int, default=0,
                     help="instead compare FP32 f - w storage with FP64 on the nine "
                          "500 x (500 Ar) cavities (Ar 0.4/1.0/2.0 x Re 1000/4000/8000) after "
@@ -399,7 +399,7 @@ def main():
     if args.flowmap:
         return run_flowmap(args)
     if args.aux:
-        return run_aux()
+        return run_aux(surrogate_only=args.aux == 2)
     if args.precision:
         return run_precision()
     if not torch.cuda.is_available():
@@ -535,13 +535,19 @@ def run_precision():
     print(json.dumps({"precision": rows}), flush=True)
 
 
-def run_aux():
+def run_aux(surrogate_only=False):
     """Timings of the kernels off the metric, for profiling (one JSON line)."""
     import torch
     import numpy as np
     from paper_2211_05009_amd import lbm, warmstart
     from cavity_inputs import normal_draws
     out = {}
+    if surrogate_only:
+        sur = warmstart.make_surrogate(normal_draws(lbm.Surrogate(1).num_params, seed=0))
+        out["surrogate"] = warmstart.surrogate_throughput(sur)
+        sur.close()
+        print(json.dumps({"aux": out}), flush=True)
+        return
     for dt in ("f64", "f32s"):           # the paper's walls, 256 x 256 validation lattice
         c = lbm.Cavity(257, 257, re=1000.0, u_lid=0.1, dtype=dt, wall="nee")
         c.autotune(chunks=5)

@@ -125,6 +125,13 @@ void conv_patch(const ConvArgs &a, int M, int N, hipStream_t st) {
   hipLaunchKernelGGL((k_conv_patch<MODE, W, BN>), dim3(grid), dim3(256), 0, st, a, ntiles);
 }
 
+// Whether conv_fd takes the patch kernel for a w x h image: whole-row tiles
+// (2 rows at widths 128 and 64, 4 at 32 and 16) and 16-byte output vectors.
+inline bool patch_path(int w, int h, int os, int oo) {
+  if (os % 8 || oo % 8) return false;
+  return ((w == 128 || w == 64) && h % 2 == 0) || ((w == 32 || w == 16) && h % 4 == 0);
+}
+
 template <int MODE>
 void conv_fd(const ConvArgs &a, hipStream_t st) {
   const int M = a.n * a.h * a.w, N = MODE == FWD ? a.co : a.ci;
@@ -132,7 +139,7 @@ void conv_fd(const ConvArgs &a, hipStream_t st) {
   // 32 channels on 128-wide images, 128-pixel tiles on 64- and 32-wide
   // ones, 64-pixel tiles on 16-wide ones (64 channels where N allows)
   // (the forward patch kernel reads the transposed weight copy a.wtt)
-  const bool out_ok = a.os % 8 == 0 && a.oo % 8 == 0 && (MODE != FWD || a.wtt);
+  const bool out_ok = patch_path(a.w, a.h, a.os, a.oo) && (MODE != FWD || a.wtt);
   const bool n64 = N % 64 == 0;
   if (out_ok && a.w == 128 && a.h % 2 == 0) {
     conv_patch<MODE, 128, 32>(a, M, N, st);
@@ -315,6 +322,10 @@ struct lbm_surrogate {
   // relu_fused[p] set for such a conv p (its separate ReLU pass is skipped)
   std::vector<int> mask_of;
   std::vector<char> relu_fused;
+  // forward: pool / upsample ops written by the epilogue of the conv before
+  // them (fwd_into[p] = that op for conv p, else -1; fwd_fused[j] set)
+  std::vector<int> fwd_into;
+  std::vector<char> fwd_fused;
   double *rearr = nullptr;                       // [2 nmax] (Re, Ar)
   double *field = nullptr;                       // warm-start fields
   size_t field_doubles = 0;
@@ -407,21 +418,25 @@ uint16_t *bptr(lbm_surrogate *s, uint16_t *base, const View &v) {
 // Encode (Re, Ar) pairs into the input canvas: channel 0 = cavity mask
 // (rows y < round(128 Ar)), 1 = (x + 1/2)/128, 2 = (y + 1/2)/128,
 // 3 = Re / 3000, 4 = Ar / 2, channels 5-31 zero.
+// One thread per 16-byte vector (8 channels) of a pixel, so a wavefront
+// stores 1 KB of contiguous memory: vector 0 holds channels 0-4, vectors 1-3
+// are zero.
 __global__ void k_encode(const double *ra, int n, uint16_t *x) {
-  const long long i = blockIdx.x * 256LL + threadIdx.x;
-  if (i >= (long long)n * kH * kW) return;
-  const int b = i / (kH * kW), r = i % (kH * kW), y = r / kW, xx = r % kW;
-  const double re = ra[2 * b], ar = ra[2 * b + 1];
-  const int ny = (int)rint(128.0 * ar);
-  float ch[kInCh] = {y < ny ? 1.f : 0.f, (xx + 0.5f) / 128.f, (y + 0.5f) / 128.f,
-                     (float)(re / 3000.0), (float)(ar / 2.0)};
-  static_assert(kInCh == 5, "channels 0-4 packed below");
-  uint4 *o = (uint4 *)(x + i * 32);   // channels 0-7, then three vectors of zeros
-  o[0] = make_uint4(f2bf(ch[0]) | ((uint32_t)f2bf(ch[1]) << 16),
-                    f2bf(ch[2]) | ((uint32_t)f2bf(ch[3]) << 16), f2bf(ch[4]), 0);
-  o[1] = make_uint4(0, 0, 0, 0);
-  o[2] = make_uint4(0, 0, 0, 0);
-  o[3] = make_uint4(0, 0, 0, 0);
+  const long long t = blockIdx.x * 256LL + threadIdx.x;
+  if (t >= (long long)n * kH * kW * 4) return;
+  const long long i = t >> 2;   // pixel
+  uint4 v = make_uint4(0, 0, 0, 0);
+  if ((t & 3) == 0) {
+    const int b = i / (kH * kW), r = i % (kH * kW), y = r / kW, xx = r % kW;
+    const double re = ra[2 * b], ar = ra[2 * b + 1];
+    const int ny = (int)rint(128.0 * ar);
+    const float ch[kInCh] = {y < ny ? 1.f : 0.f, (xx + 0.5f) / 128.f, (y + 0.5f) / 128.f,
+                             (float)(re / 3000.0), (float)(ar / 2.0)};
+    static_assert(kInCh == 5, "channels 0-4 packed below");
+    v = make_uint4(f2bf(ch[0]) | ((uint32_t)f2bf(ch[1]) << 16),
+                   f2bf(ch[2]) | ((uint32_t)f2bf(ch[3]) << 16), f2bf(ch[4]), 0);
+  }
+  ((uint4 *)x)[t] = v;   // the canvas is dense, 32 channels
 }
 
 // Head output channels 0..2 -> FP32 [n][H][W][3].
@@ -481,7 +496,17 @@ int forward(lbm_surrogate *s, int n) {
       a.out = bptr(s, s->act, o.out);
       a.os = o.out.cs;
       a.oo = o.out.co;
+      const int j = s->fwd_into[&o - s->ops.data()];
+      if (j >= 0 && s->ops[j].type == OP_POOL) {
+        a.pool_out = bptr(s, s->act, s->ops[j].out);
+      } else if (j >= 0) {
+        a.up_out = bptr(s, s->act, s->ops[j].out);
+        a.ups = s->ops[j].out.cs;
+        a.upo = s->ops[j].out.co;
+      }
       HIPC(conv_launch(FWD, a, st));
+    } else if (s->fwd_fused[&o - s->ops.data()]) {
+      continue;   // written by the conv before it
     } else if (o.type == OP_POOL) {
       hipLaunchKernelGGL(k_pool_fwd, dim3(blocks_for((long long)n * h * w * o.ci / 32)), dim3(256),
                          0, st, bptr(s, s->act, o.in), o.in.cs, o.in.co, n, h, w, o.ci,
@@ -520,6 +545,27 @@ void plan_relu_masks(lbm_surrogate *s) {
       s->mask_of[last] = p;
       s->relu_fused[p] = 1;
     }
+  }
+}
+
+// A pool or upsample op that reads exactly the output of the conv just
+// before it is done by that conv's forward epilogue (patch kernel only).
+void plan_fwd_fusion(lbm_surrogate *s) {
+  const int nop = (int)s->ops.size();
+  s->fwd_into.assign(nop, -1);
+  s->fwd_fused.assign(nop, 0);
+  for (int p = 0; p + 1 < nop; ++p) {
+    const Op &o = s->ops[p], &q = s->ops[p + 1];
+    if (o.type != OP_CONV || q.type == OP_CONV) continue;
+    if (!patch_path(level_w(o.level), level_h(o.level), o.out.cs, o.out.co)) continue;
+    if (q.in.buf != o.out.buf || q.in.cs != o.out.cs || q.in.co != o.out.co || q.ci != o.co)
+      continue;
+    // the pool writes a dense tensor of the conv's channels; the upsample
+    // writes 16-byte vectors of a slice
+    if (q.type == OP_POOL && (q.out.cs != o.co || q.out.co != 0)) continue;
+    if (q.type == OP_UP && (q.out.cs % 8 || q.out.co % 8)) continue;
+    s->fwd_into[p] = p + 1;
+    s->fwd_fused[p + 1] = 1;
   }
 }
 
@@ -613,7 +659,7 @@ int encode(lbm_surrogate *s, int n, const double *re, const double *ar) {
   HIPC(hipMemcpyAsync(s->rearr, ra.data(), 2 * n * sizeof(double), hipMemcpyHostToDevice,
                       s->stream));
   const View x0{0, 32, 0};
-  hipLaunchKernelGGL(k_encode, dim3(blocks_for((long long)n * kH * kW)), dim3(256), 0, s->stream,
+  hipLaunchKernelGGL(k_encode, dim3(blocks_for((long long)n * kH * kW * 4)), dim3(256), 0, s->stream,
                      s->rearr, n, bptr(s, s->act, x0));
   HIPC(hipGetLastError());
   return LBM_OK;
@@ -766,6 +812,7 @@ int lbm_sur_create(int max_batch, lbm_sur_t *out) {
   s->nmax = max_batch;
   build_net(s);
   plan_relu_masks(s);
+  plan_fwd_fusion(s);
   for (const Op &o : s->ops) {   // the convs are laid out one after another
     if (o.type != OP_CONV) continue;
     const int k = s->convs.count++;
@@ -794,7 +841,7 @@ int lbm_sur_create(int max_batch, lbm_sur_t *out) {
   for (int i = 0; i < 12 && e == hipSuccess; ++i) e = hipMalloc(allocs[i], sizes[i]);
   // partials of the split reductions: the largest weight / bias gradient, or
   // the loss's per-block sums
-  size_t part_floats = blocks_for((long long)npix);
+  size_t part_floats = blocks_for((long long)npix * (s->ops.back().out.cs / 8));
   for (const Op &o : s->ops)
     if (o.type == OP_CONV)
       part_floats = std::max(part_floats, wgrad_part_floats(max_batch, level_h(o.level),
@@ -907,11 +954,14 @@ int lbm_sur_train_step(lbm_sur_t s, int n, const double *re, const double *ar,
   HIPC(hipMemsetAsync(s->loss_dev, 0, sizeof(float), s->stream));
   const View &hv = head_view(s);
   static_assert(kOutCh <= 8, "k_mse reads the head's first 8 channels");
-  hipLaunchKernelGGL(k_mse, dim3(blocks_for(npix)), dim3(256), 0, s->stream,
+  // the head's output is a dense buffer (channel offset 0): k_mse writes its
+  // gradient as hv.cs / 8 vectors per pixel
+  const unsigned mse_blocks = blocks_for(npix * (hv.cs / 8));
+  hipLaunchKernelGGL(k_mse, dim3(mse_blocks), dim3(256), 0, s->stream,
                      bptr(s, s->act, hv), hv.cs, target_dev, mask_dev, npix, kOutCh,
                      (float)(1.0 / count), bptr(s, s->gact, hv), hv.cs, s->part);
-  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s->stream, s->part,
-                     (int)blocks_for(npix), 1LL, s->loss_dev);
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s->stream, s->part, (int)mse_blocks,
+                     1LL, s->loss_dev);
   HIPC(hipGetLastError());
   rc = backward(s, n);
   if (rc) return rc;

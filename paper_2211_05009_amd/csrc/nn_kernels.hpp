@@ -55,6 +55,11 @@ struct ConvArgs {
   const uint16_t *mask;  // DGRAD (optional): zero GX where mask <= 0 (the
                          // ReLU of the layer that produced the input; same
                          // stride and offset as out), before the bf16 rounding
+  // FWD, patch kernel (optional): the layer's output also goes, as the next
+  // op would write it, to
+  uint16_t *pool_out;  // its 2 x 2 average pool, dense [n][h/2][w/2][co]
+  uint16_t *up_out;    // its nearest 2x upsampling, a slice (ups, upo) of
+  int ups, upo;        // [n][2h][2w]
   int kchunk;          // WGRAD: pixels per block (multiple of 32)
   float *part;         // WGRAD: per-chunk partials [gridDim.z][9 ci][co], added
                        // into GW in chunk order by k_sum_parts (deterministic)
@@ -229,6 +234,9 @@ __global__ __launch_bounds__(256) void k_conv_mn(ConvArgs a) {
 // weights) and writes whole 16-byte vectors of 8 channels.  Patch pixels
 // and FP32 rows are padded in LDS so that neither the MFMA operand reads
 // nor the epilogue's writes conflict on banks.
+// In the forward pass the epilogue can also write the output's 2 x 2 average
+// pool or its nearest 2x upsampling (ConvArgs pool_out, up_out), the next
+// op of the network, from the tile it holds.
 // The blocks are persistent: block b takes tiles b, b + G, b + 2 G, ... (G
 // blocks, numbered so that each XCD holds a contiguous range of tiles) and
 // walks their (tile, chunk) steps in order, loading the next step's patch
@@ -396,6 +404,41 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void k
 #pragma unroll
       for (int j = 0; j < 8; ++j) pv[j] = f2bf(r[j]);
       *(uint4 *)o = pk;
+      if (MODE == FWD && a.up_out) {   // the 2 x 2 copies at twice the resolution
+        const int p = m0 + pl, img = p / HW, y = (p - img * HW) / W, x = p % W;
+        uint16_t *u = a.up_out + ((size_t)(img * 2 * a.h + 2 * y) * (2 * W) + 2 * x) * a.ups +
+                      a.upo + n0 + nq;
+        *(uint4 *)u = pk;
+        *(uint4 *)(u + a.ups) = pk;
+        *(uint4 *)(u + (size_t)2 * W * a.ups) = pk;
+        *(uint4 *)(u + (size_t)(2 * W + 1) * a.ups) = pk;
+      }
+    }
+    if (MODE == FWD && a.pool_out) {   // 2 x 2 means of the rounded outputs, in
+      // k_pool_fwd's order; the tile's R rows (R even) start at an even row
+      const int img = m0 / HW, y0 = (m0 - img * HW) / W;
+      for (int v = tid; v < TPIX / 4 * (BN / 8); v += 256) {
+        const int pp = v / (BN / 8), oy = pp / (W / 2), ox = pp % (W / 2);
+        float sm[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+          for (int dx = 0; dx < 2; ++dx) {
+            const float *src = Os + ((2 * oy + dy) * W + 2 * ox + dx) * OS + nq;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+              float r = src[j] + bv[j];
+              if (a.relu) r = fmaxf(r, 0.f);
+              sm[j] += bf2f(f2bf(r));
+            }
+          }
+        uint4 pk;
+        uint16_t *pv = (uint16_t *)&pk;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) pv[j] = f2bf(0.25f * sm[j]);
+        *(uint4 *)(a.pool_out +
+                   ((size_t)(img * (a.h / 2) + y0 / 2 + oy) * (W / 2) + ox) * a.co + n0 + nq) = pk;
+      }
     }
   };
 
@@ -1111,31 +1154,37 @@ __global__ void k_relu_bwd(const uint16_t *y, int ys, int yo, uint16_t *g, int g
 // Masked mean-squared error over the first `cu` (<= 8) channels of pred
 // (stride ps): loss[block] = the block's sum of mask (pred - t)^2 / count
 // (k_sum_parts adds the blocks); grad = 2 mask (pred - t) / count (bf16,
-// stride gs, zero elsewhere).  t: FP32 [npix][cu]; mask FP32 [npix].  Strides
-// are multiples of 8 and the tensors 16-byte aligned: a thread reads the
-// first 8 channels of its pixel as one vector and writes gs / 8 vectors.
+// dense: gs channels, zero beyond cu).  t: FP32 [npix][cu]; mask FP32
+// [npix].  One thread per 16-byte vector of grad (gs / 8 per pixel, so a
+// wavefront stores contiguous memory); the first of a pixel reads its first
+// 8 channels of pred (ps a multiple of 8, 16-byte aligned) and does the sums.
 __global__ __launch_bounds__(256) void k_mse(const uint16_t *pred, int ps, const float *t,
                                              const float *mask, long long npix, int cu,
                                              float inv_count, uint16_t *grad, int gs,
                                              float *loss) {
-  const long long p = blockIdx.x * 256LL + threadIdx.x;
+  const int vp = gs / 8;   // vectors per pixel
+  const long long q = blockIdx.x * 256LL + threadIdx.x;
   float l = 0.f;
-  if (p < npix) {
-    const float mk = mask[p];
-    const Bf8 pv = ld8(pred + p * ps);
-    Bf8 gv;
+  if (q < npix * vp) {
+    const long long p = q / vp;
+    uint4 out = make_uint4(0, 0, 0, 0);
+    if (q - p * vp == 0) {
+      const float mk = mask[p];
+      const Bf8 pv = ld8(pred + p * ps);
+      Bf8 gv;
 #pragma unroll
-    for (int ch = 0; ch < 8; ++ch) {
-      float g = 0.f;
-      if (ch < cu) {
-        const float d = bf2f(pv.v[ch]) - t[p * cu + ch];
-        l += mk * d * d;
-        g = 2.f * mk * d * inv_count;
+      for (int ch = 0; ch < 8; ++ch) {
+        float g = 0.f;
+        if (ch < cu) {
+          const float d = bf2f(pv.v[ch]) - t[p * cu + ch];
+          l += mk * d * d;
+          g = 2.f * mk * d * inv_count;
+        }
+        gv.v[ch] = f2bf(g);
       }
-      gv.v[ch] = f2bf(g);
+      out = *(const uint4 *)gv.v;
     }
-    st8(grad + p * gs, gv);
-    for (int k = 8; k < gs; k += 8) *(uint4 *)(grad + p * gs + k) = make_uint4(0, 0, 0, 0);
+    ((uint4 *)grad)[q] = out;
   }
   for (int off = 32; off > 0; off >>= 1) l += __shfl_xor(l, off, 64);
   __shared__ float part[4];
