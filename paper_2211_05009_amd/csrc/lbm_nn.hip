@@ -960,8 +960,8 @@ int lbm_sur_train_step(lbm_sur_t s, int n, const double *re, const double *ar,
   hipLaunchKernelGGL(k_mse, dim3(mse_blocks), dim3(256), 0, s->stream,
                      bptr(s, s->act, hv), hv.cs, target_dev, mask_dev, npix, kOutCh,
                      (float)(1.0 / count), bptr(s, s->gact, hv), hv.cs, s->part);
-  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s->stream, s->part, (int)mse_blocks,
-                     1LL, s->loss_dev);
+  hipLaunchKernelGGL(k_sum_scalar, dim3(1), dim3(256), 0, s->stream, s->part, (int)mse_blocks,
+                     s->loss_dev);
   HIPC(hipGetLastError());
   rc = backward(s, n);
   if (rc) return rc;

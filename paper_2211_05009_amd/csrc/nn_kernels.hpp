@@ -923,6 +923,23 @@ __global__ __launch_bounds__(256) void k_sum_parts(const float *part, int nparts
   }
 }
 
+// out[0] += the sum of part[0 .. nparts): one block, thread t adding
+// part[t], part[t + 256], ... (loads in flight together), then a fixed LDS
+// tree; the loss's per-block sums.
+__global__ __launch_bounds__(256) void k_sum_scalar(const float *part, int nparts, float *out) {
+  float s = 0.f;
+#pragma unroll 8
+  for (int k = threadIdx.x; k < nparts; k += 256) s += part[k];
+  __shared__ float sh[256];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] += sh[0];
+}
+
 // Partial sums of a layer's weight and bias gradients in one launch:
 // out[i] (+)= sum over k of part[k][i] for each of two segments (blocks below
 // s1.blocks take segment 1).  A thread adds 4 consecutive outputs (16-byte
