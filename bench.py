@@ -134,10 +134,18 @@ def events(torch):
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
-def time_single(lbm, torch, nx, ny, re, dtype, steps, warmup, variant=-1, record=None):
+def time_single(lbm, torch, nx, ny, re, dtype, steps, warmup, variant=-1, record=None,
+                sync=None):
     """Seconds for `steps` steps (HIP events on the library's stream), the
-    shape used and its steps per launch.  `record`, a dict, receives what the
-    timed lbm_step call launched (lbm_last_launches)."""
+    shape used and its steps per launch.  The timed lbm_step call runs with
+    LBM_OPT_SYNC 0: a call with no monitor point returns once its launches
+    are issued, and the region ends when the device is synchronised (calls
+    that reach a monitor point finish before returning either way).
+    `record`, a dict, receives what the timed call launched
+    (lbm_last_launches); `sync`, a dict, receives the seconds of the same
+    call from the same place on the 100-step grid with LBM_OPT_SYNC 1 (the
+    call returning after its work has finished: its host wake-up and the
+    event record after it fall inside the region)."""
     stream = torch.cuda.Stream()
     c = lbm.Cavity(nx, ny, re=re, u_lid=0.1, dtype=dtype)
     c.set_stream(stream)
@@ -159,15 +167,24 @@ def time_single(lbm, torch, nx, ny, re, dtype, steps, warmup, variant=-1, record
             c.step(100 - w)
     t_start = c.steps_done
     e0, e1 = events(torch)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    c.step(steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    sec = e0.elapsed_time(e1) / 1e3
+
+    def timed_call(sync_calls):
+        c.set_option(lbm.LBM_OPT_SYNC, sync_calls)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        c.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        c.set_option(lbm.LBM_OPT_SYNC, 1)
+        return e0.elapsed_time(e1) / 1e3
+
+    sec = timed_call(0)
     assert c.steps_done == t_start + steps
     if record is not None:
         record.update(c.last_launches())
+    if sync is not None:
+        c.step((100 - steps % 100) % 100)    # back onto the 100-step grid
+        sync["seconds"] = timed_call(1)
     mass = c.mass()
     c.close()
     return sec, (v, k), mass
@@ -415,9 +432,9 @@ def main():
     sites = nx * ny
 
     progress(f"headline {nx}x{ny} {args.dtype}, {args.steps} steps")
-    rec = {}
+    rec, sync = {}, {}
     sec, (variant, k), mass = time_single(lbm, torch, nx, ny, args.re, args.dtype, args.steps,
-                                          args.warmup, args.variant, record=rec)
+                                          args.warmup, args.variant, record=rec, sync=sync)
     mlups = sites * args.steps / sec / 1e6
     per_step = sec / args.steps
     out = {
@@ -432,6 +449,10 @@ def main():
                                f"from rest", "nx": nx, "ny": ny, "re": args.re,
                    "storage": args.dtype, "monitors_every": 100},
         "roofline": roofline(rec, sec, sites, args.dtype, nx, ny),
+        # the same call with LBM_OPT_SYNC 1 (returning after its work has
+        # finished), from the same place on the 100-step grid
+        "sync_call": {"value": round(sites * args.steps / sync["seconds"] / 1e6, 2),
+                      "ms_per_step": round(sync["seconds"] / args.steps * 1e3, 6)},
         "final_mass": mass,
         "source_hash": source_hash(),
     }

@@ -157,6 +157,15 @@ int lbm_info(lbm_t h, lbm_info_t *info);
  *   LBM_OPT_TILE_X, LBM_OPT_TILE_Y  read-only: sites along x and y that one
  *                         block of the current shape updates (a K-step
  *                         shape reads a region K sites wider on every side).
+ *   LBM_OPT_SYNC          1 (default): lbm_step returns after its work has
+ *                         finished; 0: a call that reaches no monitor point
+ *                         returns once its launches are issued on the
+ *                         handle's stream, like an asynchronous GPU library
+ *                         call (the caller synchronises the stream before
+ *                         reading results through other APIs; a fault of
+ *                         that work surfaces at the next synchronising
+ *                         call).  Calls that reach a monitor point still
+ *                         finish before returning.
  * LBM_EINVAL for an unknown option or an out-of-range value.
  */
 enum {
@@ -167,7 +176,8 @@ enum {
                               multiple of 100 in [100, 100000] (default 1000) */
   LBM_OPT_STEPS_PER_LAUNCH = 5,
   LBM_OPT_TILE_X = 6,
-  LBM_OPT_TILE_Y = 7
+  LBM_OPT_TILE_Y = 7,
+  LBM_OPT_SYNC = 8
 };
 int lbm_set_option(lbm_t h, int option, int64_t value);
 int lbm_get_option(lbm_t h, int option, int64_t *value);
@@ -199,7 +209,8 @@ int lbm_autotune(lbm_t h, int chunks, int use_cache, int *best_variant,
  * run as launches of the current shape's K steps while t is a multiple of K
  * and K steps remain, and as one-step launches otherwise (a multi-step
  * shape is used only if its K divides a probe cadence of at most 100).
- * Returns after the work has finished; LBM_EUNSTABLE if the last monitor
+ * Returns after the work has finished (with LBM_OPT_SYNC 0 and no monitor
+ * point in the call: once it is issued); LBM_EUNSTABLE if the last monitor
  * (or the final state's mass) is not finite.
  */
 int lbm_step(lbm_t h, int64_t n);

@@ -734,6 +734,9 @@ int lbm_set_option(lbm_t h, int option, int64_t value) {
     case LBM_OPT_USE_GRAPH:
       h->use_graph = value ? 1 : 0;
       return LBM_OK;
+    case LBM_OPT_SYNC:
+      h->sync_calls = value ? 1 : 0;
+      return LBM_OK;
     case LBM_OPT_STEP_VARIANT:
       if (value < 0 || value >= num_variants(h))
         return lbm_fail(LBM_EINVAL, "variant %lld outside [0, %d)", (long long)value,
@@ -750,6 +753,7 @@ int lbm_get_option(lbm_t h, int option, int64_t *value) {
   if (!h || !value) return lbm_fail(LBM_EINVAL, "NULL argument");
   switch (option) {
     case LBM_OPT_USE_GRAPH: *value = h->use_graph; return LBM_OK;
+    case LBM_OPT_SYNC: *value = h->sync_calls; return LBM_OK;
     case LBM_OPT_STEP_VARIANT: *value = h->variant; return LBM_OK;
     case LBM_OPT_NUM_VARIANTS: *value = num_variants(h); return LBM_OK;
     case LBM_OPT_STEPS_PER_LAUNCH: *value = launch_steps(h, h->variant); return LBM_OK;
@@ -910,6 +914,7 @@ static int step_impl(lbm_t h, int64_t n) {
     const int rc = monitor_now();
     if (rc != LBM_OK) return rc;
   }
+  if (!monitored && !h->sync_calls) return LBM_OK;   // issued; nothing to read back
   if (monitored) {
     HIPC(hipMemcpyAsync(h->mon_host, h->mon_dev, 3 * sizeof(double),
                         hipMemcpyDeviceToHost, h->stream));

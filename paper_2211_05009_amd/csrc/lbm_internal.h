@@ -80,6 +80,7 @@ struct lbm_cavity {
   hipStream_t stream = nullptr, own_stream = nullptr, cap_stream = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   int variant = 0, use_graph = 1;
+  int sync_calls = 1;   // LBM_OPT_SYNC
   // counters
   int64_t t = 0, snap_t = 0, mon_t = -1;
   bool mon_valid = false;

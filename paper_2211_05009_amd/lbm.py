@@ -24,7 +24,7 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_EIO, LBM_ESTATE 
     0, -1, -2, -3, -4, -5, -6
 LBM_F64, LBM_F32_SHIFTED = 0, 1
 LBM_OPT_USE_GRAPH, LBM_OPT_STEP_VARIANT, LBM_OPT_NUM_VARIANTS, LBM_OPT_GRAPH_STEPS = 1, 2, 3, 4
-LBM_OPT_STEPS_PER_LAUNCH, LBM_OPT_TILE_X, LBM_OPT_TILE_Y = 5, 6, 7
+LBM_OPT_STEPS_PER_LAUNCH, LBM_OPT_TILE_X, LBM_OPT_TILE_Y, LBM_OPT_SYNC = 5, 6, 7, 8
 LBM_INIT_RENORMALISE_MASS, LBM_INIT_ZERO_STAGGERED = 1, 2
 LBM_WALL_BOUNCE_BACK, LBM_WALL_NEE = 0, 1
 WALLS = {"bounce-back": LBM_WALL_BOUNCE_BACK, "nee": LBM_WALL_NEE}

@@ -142,6 +142,41 @@ def test_variants_graph_and_direct_launch_agree_bitwise(lbm, dtype, nx, ny):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32s"])
+def test_calls_that_return_once_issued(lbm, dtype):
+    """LBM_OPT_SYNC 0: calls without a monitor point return once their
+    launches are issued; after a device synchronisation the populations
+    equal those of synchronous calls bit for bit, calls that reach a
+    monitor point still return the same monitors, and the launch record is
+    the same."""
+    import torch
+    nx, ny, tau = 131, 77, 0.56
+    f0 = W[:, None, None] + random_shift(nx, ny, 37)
+    calls = [20, 37, 43, 100, 45, 5, 250]
+    runs = {}
+    for sync in (1, 0):
+        c = lbm.Cavity(nx, ny, tau=tau, u_lid=U_LID, dtype=dtype)
+        c.set_option(lbm.LBM_OPT_STEP_VARIANT, 24 if dtype == "f32s" else 22)
+        c.set_populations(f0)
+        c.set_option(lbm.LBM_OPT_SYNC, sync)
+        assert c.get_option(lbm.LBM_OPT_SYNC) == sync
+        states, mons, recs = [], [], []
+        for n in calls:
+            c.step(n)
+            recs.append(c.last_launches())
+            torch.cuda.synchronize()
+            states.append(c.get_populations())
+            mons.append((c.mass(), *c.residual()))
+        runs[sync] = (states, mons, recs)
+        c.close()
+    for a, b in zip(runs[1][0], runs[0][0]):
+        assert np.array_equal(a, b)
+    for a, b in zip(runs[1][1], runs[0][1]):
+        assert a[2] == b[2] and (a[1] == b[1] or (math.isinf(a[1]) and math.isinf(b[1])))
+        assert a[0] == b[0]
+    assert runs[1][2] == runs[0][2]
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32s"])
 @pytest.mark.parametrize("variant", [22, 12, 20, 14])
 def test_short_and_unaligned_calls(lbm, dtype, variant):
     """Calls shorter than or off the 100-step chunk grid run the multi-step
