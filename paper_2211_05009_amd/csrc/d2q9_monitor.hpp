@@ -40,20 +40,31 @@ __device__ __forceinline__ int cys(int i) {
   return t[i];
 }
 
-// rho - 1 and rho u of the stored populations at element offset o, in FP64
-// (Eq. 3; a collision leaves both unchanged, so they are also the moments of
-// the pre-collision f).
+// rho - 1 and rho u of one site's nine stored populations, in FP64 (Eq. 3;
+// a collision leaves both unchanged, so they are also the moments of the
+// pre-collision f).  One order of operations wherever the values come from,
+// so the monitors' sums do not depend on the path that took them.
 template <typename T, bool SHIFT>
-__device__ __forceinline__ void site_moments(const T *__restrict__ s, int plane,
-                                             int o, double &drho, double &jx,
-                                             double &jy) {
+__device__ __forceinline__ void moments_of(const T (&v)[9], double &drho, double &jx,
+                                           double &jy) {
   double f[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) f[i] = (double)s[i * plane + o];
+  for (int i = 0; i < 9; ++i) f[i] = (double)v[i];
   double sum = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
   drho = SHIFT ? sum : sum - 1.0;
   jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
   jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+}
+
+// The same at element offset o of planes `plane` apart.
+template <typename T, bool SHIFT>
+__device__ __forceinline__ void site_moments(const T *__restrict__ s, int plane,
+                                             int o, double &drho, double &jx,
+                                             double &jy) {
+  T v[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) v[i] = s[i * plane + o];
+  moments_of<T, SHIFT>(v, drho, jx, jy);
 }
 
 template <int N>

@@ -25,13 +25,16 @@ namespace lbm {
 // The Eq. 6 monitor of the state a chunk starts from, carried by the chunk's
 // first two launches instead of a separate pass.  The first launch (MON = 1)
 // takes the per-site FP64 sums of k_monitor (sum (rho - 1), sum |u -
-// u_ref|^2, sum |u_ref|^2, then u_ref <- u) over each block's core sites,
-// from the region the block has just loaded into LDS, and stores one triple
-// of partials per block.  The second launch (MON = 2, same grid) adds them in
-// block order in its block 0 (deterministic) and writes out[3]; the kernel
-// boundary between the two makes the partials visible, so no block waits on
-// another.  Each thread's u_ref entries and block 0's partials are loaded
-// before the region, so their latency overlaps the region load.
+// u_ref|^2, sum |u_ref|^2, then u_ref <- u) over each block's core sites
+// and stores one triple of partials per block: each thread loads its core
+// sites' nine start-state values and u_ref entries together with step 1's
+// pulls (from the same cache lines; after the steps where they would take
+// too many registers), runs the K steps like any launch, and takes the sums
+// at the end (the launch writes the other buffer, so the start state is
+// intact).  The second launch (MON = 2, same grid) adds the partials in
+// block order in the block of the last tile (deterministic) and writes
+// out[3]; the kernel boundary between the two makes them visible, so no
+// block waits on another.
 struct TbMonitor {
   double2 *uref;      // dense [ny][nx] reference velocity
   double *partials;   // [gridDim.x][3]
@@ -83,8 +86,35 @@ __device__ __forceinline__ bool tb_core(int q, int X0, int Y0, int nx, int ny, i
   return rx >= K && rx < K + TX && ry >= K && ry < K + TY && gx < nx && gy < ny;
 }
 
+// The monitor sums of a block's core sites from their start-state values
+// fv[j] (region site q = threadIdx.x + j NT; cr[j]: a core site, dense
+// index kd[j]) and u_ref entries ur[j].
+template <typename T, bool SHIFT, int J, int NT>
+__device__ __forceinline__ void tb_monitor_sums(const T (&fv)[J][9], const double2 (&ur)[J],
+                                                const bool (&cr)[J], const int (&kd)[J],
+                                                const TbMonBlock &m) {
+  double acc[kNumSums] = {0.0, 0.0, 0.0};
+#pragma unroll
+  for (int j = 0; j < J; ++j) {
+    if (cr[j]) {
+      double drho, jx, jy;
+      moments_of<T, SHIFT>(fv[j], drho, jx, jy);
+      const double rho = 1.0 + drho;
+      const double ux = jx / rho, uy = jy / rho;
+      const double dx = ux - ur[j].x, dy = uy - ur[j].y;
+      acc[0] += drho;
+      acc[1] += dx * dx + dy * dy;
+      acc[2] += ur[j].x * ur[j].x + ur[j].y * ur[j].y;
+      m.uref[kd[j]] = make_double2(ux, uy);
+    }
+  }
+  block_sum_nt<NT, kNumSums>(acc, m.part);
+}
+
+// The same sums from the start state loaded into LDS (region layout), u_ref
+// entries ur[j] prefetched.
 template <typename T, bool SHIFT, int K, int TX, int TY, int NT>
-__device__ __forceinline__ void tb_monitor_sums(const T *lds, int X0, int Y0, int nx, int ny,
+__device__ __forceinline__ void tb_monitor_sums_lds(const T *lds, int X0, int Y0, int nx, int ny,
                                                 const TbMonBlock &m,
                                                 const double2 (&ur)[(
                                                     (TX + 2 * K) * (TY + 2 * K) + NT - 1) / NT]) {
@@ -249,10 +279,15 @@ __device__ __forceinline__ void tb_first_step(T *lds, const T *__restrict__ src,
 }
 
 // One tile (tile_x, tile_y) of TX x TY core sites advanced K steps; src and
-// dst point at plane 0 of the cavity.  The launch that takes the monitor
-// sums (MON = 1) loads the region into LDS, since the sums need the start
-// state of every core site; the others take step 1 from global memory.
+// dst point at plane 0 of the cavity.
 // MON: 0, or 1 / 2 for the first / second launch of a monitored chunk.
+// MON = 1 takes the monitor sums of the start state.  Where a thread's core
+// sites fit in 18 registers (PRE) it loads their nine values and u_ref
+// entries with step 1's pulls (the same cache lines), runs the steps like
+// any launch and takes the sums at the end (the launch writes the other
+// buffer, so the start state is intact).  Otherwise it loads the whole
+// region into LDS first, takes the sums from there and runs step 1 out of
+// LDS, so that a lattice beyond the caches is still read once.
 template <typename T, bool SHIFT, int K, int TX, int TY, int NT, int MON, bool PP = false,
           bool NTS = true>
 __device__ __forceinline__ void tb_tile(T *lds, const T *__restrict__ src, T *__restrict__ dst,
@@ -264,34 +299,44 @@ __device__ __forceinline__ void tb_tile(T *lds, const T *__restrict__ src, T *__
   const int X0 = tile_x * TX - K;             // global x of region column 0
   const int Y0 = tile_y * TY - K;
 
-  // monitor inputs, loaded ahead of the region
-  double2 ur[J];
+  constexpr bool PRE = J * 9 * (int)(sizeof(T) / 4) <= 18;
+  constexpr int JM = MON == 1 ? J : 1;
+  T fv[PRE ? JM : 1][9];
+  double2 ur[JM];
+  bool cr[JM];
+  int kd[JM];
   double fin[kNumSums] = {0.0, 0.0, 0.0};
   if (MON == 1) {
 #pragma unroll
-    for (int j = 0; j < J; ++j) {
+    for (int j = 0; j < JM; ++j) {
       const int q = threadIdx.x + j * NT;
-      int k;
-      ur[j] = (q < RS && tb_core<K, TX, TY>(q, X0, Y0, nx, ny, k)) ? mon.uref[k]
-                                                                  : make_double2(0.0, 0.0);
+      cr[j] = q < RS && tb_core<K, TX, TY>(q, X0, Y0, nx, ny, kd[j]);
+      ur[j] = cr[j] ? mon.uref[kd[j]] : make_double2(0.0, 0.0);
+      if constexpr (PRE) {
+        if (cr[j]) {
+          const int ry = q / RW, o = (Y0 + ry) * pitch + X0 + (q - ry * RW);
+#pragma unroll
+          for (int i = 0; i < 9; ++i) fv[j][i] = src[i * P + o];
+        }
+      }
     }
   }
   if (MON == 2 && threadIdx.x < mon.nfin) {
 #pragma unroll
     for (int k = 0; k < kNumSums; ++k) fin[k] = mon.fin[threadIdx.x * kNumSums + k];
   }
+  if (MON == 2 && mon.nfin > 0) {
+    for (int b = threadIdx.x + NT; b < mon.nfin; b += NT)
+#pragma unroll
+      for (int k = 0; k < kNumSums; ++k) fin[k] += mon.fin[b * kNumSums + k];
+    block_sum_nt<NT, kNumSums>(fin, mon.out);
+  }
 
   // Tiles whose region lies inside the cavity (no wall within reach) take a
   // branch-free pull with constant offsets; the rest test the walls.  The
   // last step stores the core.
   const bool interior = X0 >= 0 && X0 + RW <= nx && Y0 >= 0 && Y0 + RH <= ny;
-  if (MON != 1) {
-    if (MON == 2 && mon.nfin > 0) {
-      for (int b = threadIdx.x + NT; b < mon.nfin; b += NT)
-#pragma unroll
-        for (int k = 0; k < kNumSums; ++k) fin[k] += mon.fin[b * kNumSums + k];
-      block_sum_nt<NT, kNumSums>(fin, mon.out);
-    }
+  if constexpr (MON != 1 || PRE) {
     if (interior) {
       tb_first_step<T, SHIFT, K, RW, RH, NT, true>(lds, src, pitch, P, X0, Y0, nx, ny, omega, u6);
       tb_steps<T, SHIFT, K, RW, RH, NT, 2, true, PP, NTS>(lds, dst, pitch, P, X0, Y0, nx, ny,
@@ -302,42 +347,42 @@ __device__ __forceinline__ void tb_tile(T *lds, const T *__restrict__ src, T *__
       tb_steps<T, SHIFT, K, RW, RH, NT, 2, false, PP, NTS>(lds, dst, pitch, P, X0, Y0, nx, ny,
                                                            omega, u6);
     }
-    return;
-  }
-
-  // Load the region (sites inside the cavity) straight from global memory
-  // into LDS: global_load_lds_dword writes lane l's word at the wavefront's
-  // LDS base + 4 l, with no round trip through registers and no LDS stores.
-  // Thread c takes word c of each plane's region: site c in FP32, the low
-  // (c even) or high half of site c / 2 in FP64, so the 64 lanes of a
-  // wavefront fill 64 consecutive LDS words.
-  constexpr int WPS = sizeof(T) / 4;             // words per site
-  constexpr int JW = (WPS * RS + NT - 1) / NT;   // words per thread and plane
+    if constexpr (MON == 1) tb_monitor_sums<T, SHIFT, JM, NT>(fv, ur, cr, kd, mon);
+  } else {
+    // Load the region (sites inside the cavity) straight from global memory
+    // into LDS: global_load_lds_dword writes lane l's word at the wavefront's
+    // LDS base + 4 l, with no round trip through registers and no LDS stores.
+    // Thread c takes word c of each plane's region: site c in FP32, the low
+    // (c even) or high half of site c / 2 in FP64, so the 64 lanes of a
+    // wavefront fill 64 consecutive LDS words.
+    constexpr int WPS = sizeof(T) / 4;             // words per site
+    constexpr int JW = (WPS * RS + NT - 1) / NT;   // words per thread and plane
 #pragma unroll
-  for (int j = 0; j < JW; ++j) {
-    const int c = threadIdx.x + j * NT;
-    const int q = c / WPS;
-    if (q < RS) {
-      const int ry = q / RW, rx = q - ry * RW;
-      const int gx = X0 + rx, gy = Y0 + ry;
-      if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-        const float *g = reinterpret_cast<const float *>(src + gy * pitch + gx) + c % WPS;
-        float *w0 = reinterpret_cast<float *>(lds) + (c - (threadIdx.x & 63));
+    for (int j = 0; j < JW; ++j) {
+      const int c = threadIdx.x + j * NT;
+      const int q = c / WPS;
+      if (q < RS) {
+        const int ry = q / RW, rx = q - ry * RW;
+        const int gx = X0 + rx, gy = Y0 + ry;
+        if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+          const float *g = reinterpret_cast<const float *>(src + gy * pitch + gx) + c % WPS;
+          float *w0 = reinterpret_cast<float *>(lds) + (c - (threadIdx.x & 63));
 #pragma unroll
-        for (int i = 0; i < 9; ++i)
-          __builtin_amdgcn_global_load_lds(g + WPS * i * P, w0 + WPS * i * RS, 4, 0, 0);
+          for (int i = 0; i < 9; ++i)
+            __builtin_amdgcn_global_load_lds(g + WPS * i * P, w0 + WPS * i * RS, 4, 0, 0);
+        }
       }
     }
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    tb_monitor_sums_lds<T, SHIFT, K, TX, TY, NT>(lds, X0, Y0, nx, ny, mon, ur);
+    if (interior)
+      tb_steps<T, SHIFT, K, RW, RH, NT, 1, true, PP, NTS>(lds, dst, pitch, P, X0, Y0, nx, ny, omega,
+                                                         u6);
+    else
+      tb_steps<T, SHIFT, K, RW, RH, NT, 1, false, PP, NTS>(lds, dst, pitch, P, X0, Y0, nx, ny,
+                                                          omega, u6);
   }
-  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-  __syncthreads();
-  tb_monitor_sums<T, SHIFT, K, TX, TY, NT>(lds, X0, Y0, nx, ny, mon, ur);
-  if (interior)
-    tb_steps<T, SHIFT, K, RW, RH, NT, 1, true, PP, NTS>(lds, dst, pitch, P, X0, Y0, nx, ny, omega,
-                                                       u6);
-  else
-    tb_steps<T, SHIFT, K, RW, RH, NT, 1, false, PP, NTS>(lds, dst, pitch, P, X0, Y0, nx, ny,
-                                                        omega, u6);
 }
 
 // MON: 1 / 2 for the first / second launch of a chunk that carries the
@@ -347,9 +392,11 @@ template <typename T, bool SHIFT, int K, int TX, int TY, int NT, int MON = 0, bo
 __global__ __launch_bounds__(NT) void k_step_tb(StepParams<T> p, int tiles_x, TbMonitor mon) {
   __shared__ T lds[(PP ? 18 : 9) * (TX + 2 * K) * (TY + 2 * K)];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  // block b stores partial triple b; block 0 adds all of them
+  // block b stores partial triple b; the block of the last tile (a ragged
+  // edge tile where the lattice is not a multiple of the tile: less work to
+  // hide the sum behind) adds all of them, in block order
   const TbMonBlock mb{mon.uref, mon.partials + blockIdx.x * kNumSums, mon.partials,
-                      blockIdx.x == 0 ? (int)gridDim.x : 0, mon.out};
+                      tile == (int)gridDim.x - 1 ? (int)gridDim.x : 0, mon.out};
   tb_tile<T, SHIFT, K, TX, TY, NT, MON, PP, NTS>(lds, p.src, p.dst, p.nx, p.ny, p.pitch, p.plane,
                                         p.omega, p.u6, tile % tiles_x, tile / tiles_x, mb);
 }
