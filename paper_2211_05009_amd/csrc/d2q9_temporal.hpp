@@ -285,11 +285,12 @@ __device__ __forceinline__ void tb_first_step(T *lds, const T *__restrict__ src,
 // sites fit in 18 registers (PRE) it loads their nine values and u_ref
 // entries with step 1's pulls (the same cache lines), runs the steps like
 // any launch and takes the sums at the end (the launch writes the other
-// buffer, so the start state is intact).  Otherwise it loads the whole
-// region into LDS first, takes the sums from there and runs step 1 out of
-// LDS, so that a lattice beyond the caches is still read once.
+// buffer, so the start state is intact).  Otherwise (or with MON_LDS) it
+// loads the whole region into LDS first, takes the sums from there and runs
+// step 1 out of LDS, so that a lattice beyond the caches is still read once
+// and the u_ref traffic comes before the steps rather than after them.
 template <typename T, bool SHIFT, int K, int TX, int TY, int NT, int MON, bool PP = false,
-          bool NTS = true>
+          bool NTS = true, bool MON_LDS = false>
 __device__ __forceinline__ void tb_tile(T *lds, const T *__restrict__ src, T *__restrict__ dst,
                                         int nx, int ny, int pitch, int P, T omega, T u6,
                                         int tile_x, int tile_y, const TbMonBlock &mon) {
@@ -299,7 +300,7 @@ __device__ __forceinline__ void tb_tile(T *lds, const T *__restrict__ src, T *__
   const int X0 = tile_x * TX - K;             // global x of region column 0
   const int Y0 = tile_y * TY - K;
 
-  constexpr bool PRE = J * 9 * (int)(sizeof(T) / 4) <= 18;
+  constexpr bool PRE = !MON_LDS && J * 9 * (int)(sizeof(T) / 4) <= 18;
   constexpr int JM = MON == 1 ? J : 1;
   T fv[PRE ? JM : 1][9];
   double2 ur[JM];
