@@ -210,7 +210,8 @@ def test_blow_up_is_reported(lbm):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32s"])
-@pytest.mark.parametrize("nx,ny,variant", [(131, 77, 22), (600, 520, 19), (64, 64, 21)])
+@pytest.mark.parametrize("nx,ny,variant", [(131, 77, 22), (600, 520, 19), (64, 64, 21),
+                                           (131, 77, 24)])
 def test_fused_monitor_matches_separate_pass(lbm, dtype, nx, ny, variant):
     """Multi-step shapes take the Eq. 6 monitor inside the first launch of
     each 100-step chunk (of the state the chunk starts from); the one-step
@@ -219,7 +220,8 @@ def test_fused_monitor_matches_separate_pass(lbm, dtype, nx, ny, variant):
     both report the same mass, residual and residual step (to rounding: the
     sums are split differently), and their states agree bit for bit.
     600 x 520 on 16 x 16 tiles has more tiles (1,254) than the separate
-    pass has blocks."""
+    pass has blocks.  Shapes 22 and 24 in FP32 take the sums from registers
+    after the steps, the others from the region in LDS before them."""
     f0 = W[:, None, None] + random_shift(nx, ny, 17)
     a = lbm.Cavity(nx, ny, re=700.0, u_lid=U_LID, dtype=dtype)
     b = lbm.Cavity(nx, ny, re=700.0, u_lid=U_LID, dtype=dtype)
