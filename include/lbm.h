@@ -603,7 +603,7 @@ int lbm_batch_autotune(lbm_batch_t b, int chunks, int use_cache,
                        int *best_variant, double *ms_per_step);
 
 /* ------------------------------------------------------------------------
- * Learned warm start (spec pattern 4; no counterpart in the paper).
+ * Learned warm start (an extension of the method; no counterpart in the paper).
  *
  * A convolutional surrogate maps (Re, Ar) to the steady field of the cavity
  * so the lattice can start near its steady state instead of at rest
