@@ -48,13 +48,15 @@ inline int wgrad_chunks(const ConvArgs &a) {
 }
 
 // Strips of the row-streamed weight gradient (k_wgrad_rows): widths 16,
-// 32, 64 and 128 (an iteration is 128 pixels = U rows, U <= h), NT = 2
-// (64-channel output tiles) where co allows; strips of whole iterations,
-// about kRowsBlocks blocks of kRowsKW four-wave groups over the (ci / 32) x
-// (co / 32 NT) tiles: two groups per block halve the strips (and the
-// partials) at the same number of waves as 512 one-group blocks.
+// 32, 64 and 128, an iteration of 256 pixels = U rows (U <= h), NT = 2
+// (64-channel output tiles) where co allows.  A block of kRowsKW four-wave
+// groups holds 170-180 VGPRs per lane, so one block fits per CU: strips
+// of whole iterations, at most kRowsBlocks (the CU count) blocks over the
+// (ci / 32) x (co / 32 NT) tiles where the tiles allow, as evenly filled as
+// whole iterations allow (a 257th block would run after the others).
 constexpr int kRowsKW = 2;
-constexpr long long kRowsBlocks = 512 / kRowsKW;
+constexpr int kRowsPix = 256;
+constexpr long long kRowsBlocks = 256;
 struct RowsPlan {
   bool ok;
   int nt, rows, nz;
@@ -63,12 +65,12 @@ struct RowsPlan {
 inline RowsPlan wgrad_rows_plan(int n, int h, int w, int ci, int co) {
   RowsPlan p{false, 1, 0, 0, 0};
   if (!(w == 16 || w == 32 || w == 64 || w == 128) || ci % 32 || co % 32) return p;
-  const int U = 128 / w;
+  const int U = kRowsPix / w;
   if (h < U) return p;
   p.nt = co % 64 == 0 ? 2 : 1;
   const long long tiles = (long long)(ci / 32) * (co / (32 * p.nt));
   const long long nrow = (long long)n * h;
-  long long nz = std::max(1LL, (kRowsBlocks + tiles - 1) / tiles);
+  long long nz = std::max(1LL, kRowsBlocks / tiles);
   nz = std::min(nz, (nrow + U - 1) / U);   // grows with n; p.nz <= it
   p.nz_bound = (int)nz;
   long long rows = (nrow + nz - 1) / nz;
@@ -243,10 +245,10 @@ hipError_t wgrad_launch(const ConvArgs &a, float *gbias, hipStream_t st, bool ad
   const long long mn = 9LL * a.ci * a.co;
   float *bpart = gbias ? a.part + (size_t)p.nz * mn : nullptr;
   switch (a.w) {
-    case 16: wgrad_rows<16, 8>(a, p, bpart, st); break;
-    case 32: wgrad_rows<32, 4>(a, p, bpart, st); break;
-    case 64: wgrad_rows<64, 2>(a, p, bpart, st); break;
-    default: wgrad_rows<128, 1>(a, p, bpart, st); break;
+    case 16: wgrad_rows<16, kRowsPix / 16>(a, p, bpart, st); break;
+    case 32: wgrad_rows<32, kRowsPix / 32>(a, p, bpart, st); break;
+    case 64: wgrad_rows<64, kRowsPix / 64>(a, p, bpart, st); break;
+    default: wgrad_rows<128, kRowsPix / 128>(a, p, bpart, st); break;
   }
   if (v4) {   // mn and co are multiples of 4 (channel counts multiples of 32)
     const SumSeg s1 = sum_seg(a.part, mn, (float *)a.out, p.nz, add);
@@ -331,6 +333,12 @@ struct lbm_surrogate {
   size_t field_doubles = 0;
   int64_t adam_t = 0;
   hipStream_t stream = nullptr, own_stream = nullptr;
+  // weight gradients run on a stream of their own, forked from `stream`
+  // once a layer's output gradient is complete and joined at the end of the
+  // backward pass: no later kernel reads them before the join, and the
+  // input-gradient chain does not wait for them
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace {
@@ -571,6 +579,14 @@ void plan_fwd_fusion(lbm_surrogate *s) {
 
 int backward(lbm_surrogate *s, int n) {
   hipStream_t st = s->stream;
+  // the main stream waits for the side stream however the pass ends
+  struct Join {
+    lbm_surrogate *s;
+    ~Join() {
+      if (hipEventRecord(s->join, s->side) == hipSuccess)
+        (void)hipStreamWaitEvent(s->stream, s->join, 0);
+    }
+  } join{s};
   // every conv's weight and bias gradients are written once (not added)
   for (int k = (int)s->ops.size() - 1; k >= 0; --k) {
     const Op &o = s->ops[k];
@@ -598,8 +614,10 @@ int backward(lbm_surrogate *s, int n) {
       a.go = o.out.co;
       a.out = s->gw + o.woff;
       a.kchunk = wgrad_kchunk(n, h, w, o.ci, o.co);
-      a.part = s->part;
-      HIPC(wgrad_launch(a, s->gw + o.boff, st, false));
+      a.part = s->part;   // used by the side stream only until the join
+      HIPC(hipEventRecord(s->fork, st));
+      HIPC(hipStreamWaitEvent(s->side, s->fork, 0));
+      HIPC(wgrad_launch(a, s->gw + o.boff, s->side, false));
       if (k > 0) {   // the network input needs no gradient
         ConvArgs d{};
         d.n = n;
@@ -792,12 +810,16 @@ int lbm_nn_up2(int backward, int n, int h, int w, int c, const void *in, int is,
 int lbm_sur_destroy(lbm_sur_t s) {
   if (!s) return LBM_OK;
   if (s->stream) (void)hipStreamSynchronize(s->stream);
+  if (s->side) (void)hipStreamSynchronize(s->side);
   void *ptrs[] = {s->act, s->gact, s->w, s->m, s->v, s->gw, s->wb, s->wbt, s->target, s->mask,
                   s->out3, s->loss_dev, s->rearr, s->field, s->part};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (s->loss_host) (void)hipHostFree(s->loss_host);
   if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
+  if (s->side) (void)hipStreamDestroy(s->side);
+  if (s->fork) (void)hipEventDestroy(s->fork);
+  if (s->join) (void)hipEventDestroy(s->join);
   delete s;
   return LBM_OK;
 }
@@ -831,6 +853,12 @@ int lbm_sur_create(int max_batch, lbm_sur_t *out) {
   };
   hipError_t e = hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking);
   s->stream = s->own_stream;
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->side, hipStreamNonBlocking);
+  // the events only order two streams of this device: a device-scope release
+  // (the default system-scope one writes back and invalidates the caches)
+  const unsigned evf = hipEventDisableTiming | hipEventReleaseToDevice;
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork, evf);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&s->join, evf);
   void **allocs[] = {(void **)&s->act,    (void **)&s->gact,  (void **)&s->w,
                      (void **)&s->m,      (void **)&s->v,     (void **)&s->gw,
                      (void **)&s->wb,     (void **)&s->target, (void **)&s->mask,

@@ -629,10 +629,10 @@ __global__ __launch_bounds__(256) void k_wgrad(ConvArgs a) {
 // Per tap row the three x offsets come from one aligned 16-byte read and
 // two 4-byte reads by funnel shifts (v_alignbit); rows above the top or
 // below the bottom of a pixel's image give zero operands.  An iteration
-// covers U rows (U W = 128 pixels, 4 k-steps): the next iteration's rows
-// are loaded into registers while the current one is multiplied out, then
-// written into ring slots the current iteration does not read, so one
-// barrier per iteration suffices.  KW groups of four waves split each
+// covers U rows (U W pixels, a multiple of 128: U W / 32 k-steps; U <= h):
+// the next iteration's rows are loaded into registers while the current
+// one is multiplied out, then written into ring slots the current
+// iteration does not read, so one barrier per iteration suffices.  KW groups of four waves split each
 // iteration's k-steps and add their sums in LDS at the end (fixed order),
 // so a block does KW times the work of one group and the strips, hence the
 // partials, are KW times fewer.  With bpart set, blocks of the first
@@ -640,7 +640,7 @@ __global__ __launch_bounds__(256) void k_wgrad(ConvArgs a) {
 // partial bpart[z][o] (fixed order: per thread, then a fixed LDS tree).
 template <int W, int U, int NT, int KW>
 __global__ __launch_bounds__(256 * KW) void k_wgrad_rows(ConvArgs a, int rows, float *bpart) {
-  static_assert(U * W == 128 && W % 16 == 0, "an iteration is 128 pixels");
+  static_assert(U * W % 128 == 0 && W % 16 == 0, "an iteration is a multiple of 128 pixels");
   constexpr int NTH = 256 * KW;
   constexpr int RP = W + 8, NR = 2 * U + 2, NB = 32 * NT, KS = U * W / 32;
   static_assert(KS % KW == 0, "groups share the k-steps evenly");

@@ -38,7 +38,9 @@ def f64(t):
                                          (4, 128, 128, 32, 64), (4, 64, 64, 64, 128),
                                          (16, 64, 64, 64, 128), (2, 4, 128, 96, 32),
                                          (2, 6, 64, 192, 64), (2, 8, 32, 64, 128),
-                                         (3, 8, 16, 128, 256), (2, 12, 16, 96, 32)])
+                                         (3, 8, 16, 128, 256), (2, 12, 16, 96, 32),
+                                         (2, 16, 16, 128, 256), (3, 20, 16, 96, 32),
+                                         (2, 9, 32, 64, 128)])
 def test_conv_forward_dgrad_wgrad(env, n, h, w, ci, co):
     """Each pass against the FP64 reference on bf16-rounded inputs.  The
     shapes cover every kernel of the forward / input-gradient passes: the
