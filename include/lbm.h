@@ -629,6 +629,11 @@ typedef struct lbm_surrogate *lbm_sur_t;
  * start at zero (load them with lbm_sur_set_params). */
 int lbm_sur_create(int max_batch, lbm_sur_t *out);
 int lbm_sur_destroy(lbm_sur_t s);
+/* Work is issued on hip_stream (NULL: a stream of the handle's own).  The
+ * training step's weight gradients run on a second stream of the handle,
+ * ordered after the work on hip_stream that produces their inputs; before
+ * the backward pass returns, hip_stream waits for them, so every later
+ * operation on hip_stream sees them (both joins are events). */
 int lbm_sur_set_stream(lbm_sur_t s, void *hip_stream);
 int lbm_sur_num_params(lbm_sur_t s, int64_t *n);
 
