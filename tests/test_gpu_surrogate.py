@@ -208,6 +208,42 @@ def test_training_is_bit_reproducible(env):
     assert np.array_equal(out[0][1], out[1][1])
 
 
+def test_training_on_a_caller_stream_matches_the_own_stream(env):
+    """The weight gradients run on a second stream of the handle, forked
+    from and joined back into the stream the caller set: training on a
+    caller's stream, with unrelated work queued on it, gives the same
+    losses, weights and gradients, bit for bit, as on the handle's own."""
+    torch, lbm = env
+    re, ar = np.array([400.0, 2500.0, 1200.0]), np.array([0.6, 1.2, 1.8])
+    x = S.encode(re, ar)
+    mask = torch.tensor(x[..., 0], dtype=torch.float32).cuda()
+    yy = x[..., 2:3]
+    tgt = torch.tensor(np.concatenate([0.2 * yy, np.cos(2 * yy), x[..., 1:2]], axis=-1),
+                       dtype=torch.float32).cuda()
+    torch.cuda.synchronize()
+    out = []
+    for own in (True, False):
+        sur = lbm.Surrogate(max_batch=3)
+        sur.set_params(S.he_init(5))
+        st = None
+        if not own:
+            st = torch.cuda.Stream()
+            sur.set_stream(st)
+        losses = []
+        for _ in range(4):
+            if st is not None:   # work of the caller's own ahead of each step
+                with torch.cuda.stream(st):
+                    big = torch.ones(1 << 22, device="cuda")
+                    big.mul_(2.0).add_(1.0)
+            losses.append(sur.train_step(re, ar, tgt, mask, lr=1e-3))
+        params, grads = sur.get_params(with_grads=True)
+        out.append((np.array(losses), params, grads))
+        sur.close()
+        torch.cuda.synchronize()
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+
+
 def test_warm_start_maps_prediction_onto_the_lattice(env):
     """lbm_sur_warm_start = bilinear map of the prediction onto site
     centres, mass renormalised, staggered momenta removed, f = f^eq
