@@ -26,6 +26,7 @@
 #include "../../include/lbm.h"
 #include "d2q9_monitor.hpp"
 #include "d2q9_nee.hpp"
+#include "d2q9_nee_tb.hpp"
 #include "d2q9_series.hpp"
 #include "d2q9_step.hpp"
 #include "d2q9_temporal.hpp"
@@ -166,15 +167,38 @@ static void tile_of(int v, int dtype, int &tx, int &ty) {
   }
 }
 
-// Non-equilibrium extrapolation handles have their own one-step shapes.
-static const int kNumNeeVariants = 4;
+// Non-equilibrium extrapolation handles have their own shapes: four
+// one-step ones (k_step_nee, 64 x (BY RY) nodes) and three multi-step ones
+// (k_step_nee_tb): 16 x 16, K = 4; K = 5 on 32 x 16 (FP64 16 x 16); K = 4
+// on 32 x 32 (FP64 16 x 32).
+static const int kNumNeeVariants = 7;
+static const int kDefaultNeeVariant = 6;   // the fastest untuned at 257^2 and 501^2
 
 static int num_variants(const lbm_cavity *h) {
   return h->wall == LBM_WALL_NEE ? kNumNeeVariants : kNumVariants;
 }
 
 static int launch_steps(const lbm_cavity *h, int v) {
-  return h->wall == LBM_WALL_NEE ? 1 : steps_per_launch(v);
+  if (h->wall == LBM_WALL_NEE) return v == 5 ? 5 : v >= 4 && v < kNumNeeVariants ? 4 : 1;
+  return steps_per_launch(v);
+}
+
+// Tile (nodes along x, along y) of NEE variant v.
+static void nee_tile_of(int v, int dtype, int &tx, int &ty) {
+  static const int one[4] = {4, 8, 8, 8};   // k_step_nee: 64 x (BY RY)
+  const bool f64 = dtype == LBM_F64;
+  if (v >= 0 && v < 4) {
+    tx = 64;
+    ty = one[v];
+  } else if (v == 4) {
+    tx = ty = 16;
+  } else if (v == 5) {
+    tx = f64 ? 16 : 32;
+    ty = 16;
+  } else {
+    tx = f64 ? 16 : 32;
+    ty = 32;
+  }
 }
 
 template <typename T, bool S, int BY, int RY>
@@ -197,13 +221,45 @@ static hipError_t launch_nee_t(const lbm_cavity *h, const void *src, void *dst,
   return hipGetLastError();
 }
 
+template <typename T, bool S, int K, int TX, int TY, int NT>
+static hipError_t launch_nee_tb_t(const lbm_cavity *h, const void *src, void *dst,
+                                  hipStream_t st) {
+  StepParams<T> p;
+  p.src = (const T *)src;
+  p.dst = (T *)dst;
+  p.nx = h->nx;
+  p.ny = h->ny;
+  p.pitch = h->pitch;
+  p.plane = h->plane;
+  p.tiles_x = (h->nx + TX - 1) / TX;
+  p.omega = (T)h->omega;
+  p.u6 = (T)(h->u_lid / 6.0);
+  p.ulid = (T)h->u_lid;
+  const int tiles_y = (h->ny + TY - 1) / TY;
+  hipLaunchKernelGGL((k_step_nee_tb<T, S, K, TX, TY, NT>), dim3(p.tiles_x * tiles_y), dim3(NT),
+                     0, st, p);
+  return hipGetLastError();
+}
+
 template <typename T, bool S>
 static hipError_t launch_nee_variant(const lbm_cavity *h, int v, const void *src, void *dst,
                                      hipStream_t st) {
+  constexpr bool f64 = sizeof(T) == 8;
   switch (v) {
     case 1: return launch_nee_t<T, S, 4, 2>(h, src, dst, st);
     case 2: return launch_nee_t<T, S, 8, 1>(h, src, dst, st);
     case 3: return launch_nee_t<T, S, 2, 4>(h, src, dst, st);
+    case 4: return launch_nee_tb_t<T, S, 4, 16, 16, 256>(h, src, dst, st);
+    case 5:
+      if constexpr (f64)
+        return launch_nee_tb_t<T, S, 5, 16, 16, 256>(h, src, dst, st);
+      else
+        return launch_nee_tb_t<T, S, 5, 32, 16, 512>(h, src, dst, st);
+    case 6:
+      if constexpr (f64)
+        return launch_nee_tb_t<T, S, 4, 16, 32, 512>(h, src, dst, st);
+      else
+        return launch_nee_tb_t<T, S, 4, 32, 32, 1024>(h, src, dst, st);
     default: return launch_nee_t<T, S, 4, 1>(h, src, dst, st);
   }
 }
@@ -589,7 +645,7 @@ static int create_impl(int nx, int ny, double tau, double re, double u_lid,
   h->u_lid = u_lid;
   h->tau = tau;
   h->omega = 1.0 / tau;
-  h->variant = wall == LBM_WALL_NEE ? 0 : kDefaultVariant;
+  h->variant = wall == LBM_WALL_NEE ? kDefaultNeeVariant : kDefaultVariant;
   h->use_graph = 1;
   const size_t esz = dtype == LBM_F64 ? 8 : 4;
   h->buf_bytes = (size_t)plane * 9 * esz;
@@ -761,8 +817,7 @@ int lbm_get_option(lbm_t h, int option, int64_t *value) {
     case LBM_OPT_TILE_Y: {
       int tx = 64, ty = 4;
       if (h->wall == LBM_WALL_NEE) {
-        static const int nee[4] = {4, 8, 8, 8};              // k_step_nee: 64 x (BY RY)
-        ty = nee[h->variant];
+        nee_tile_of(h->variant, h->dtype, tx, ty);
       } else {
         tile_of(h->variant, h->dtype, tx, ty);
       }

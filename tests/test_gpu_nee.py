@@ -37,8 +37,9 @@ def test_create_reports_the_scheme_and_tau(lbm):
     info = c.info
     assert info["wall"] == lbm.LBM_WALL_NEE
     assert math.isclose(info["tau"], nee.relaxation_time(257, 400.0, U_LID), rel_tol=1e-15)
-    assert c.get_option(lbm.LBM_OPT_NUM_VARIANTS) == 4
-    assert c.get_option(lbm.LBM_OPT_STEPS_PER_LAUNCH) == 1
+    assert c.get_option(lbm.LBM_OPT_NUM_VARIANTS) == 7
+    assert c.get_option(lbm.LBM_OPT_STEP_VARIANT) == 6     # K-step shape by default
+    assert c.get_option(lbm.LBM_OPT_STEPS_PER_LAUNCH) == 4
     with pytest.raises(lbm.LbmError):
         lbm.lbm_create_wall(2, 10, 100.0, U_LID, "f64", "nee")
     with pytest.raises(lbm.LbmError):
@@ -63,7 +64,9 @@ def test_initial_state_moves_the_top_row(lbm, dtype):
                                            ((3, 3), 10.0, 4), ((5, 131), 50.0, 5)])
 def test_fp64_parity_after_1000_steps(lbm, shape, re, seed):
     """Moments and stored populations within 1e-12 of the oracle after 1000
-    steps, every tile shape bit-identical (ragged tiles: 67 = 64 + 3)."""
+    steps, every tile shape bit-identical (one-step shapes and the K-step
+    shapes, whose 100-step chunks are 20 or 25 launches; ragged tiles: 67 =
+    64 + 3)."""
     nx, ny = shape
     ref, c = _pair(lbm, nx, ny, re, "f64", seed)
     f0 = ref.f.copy()
@@ -71,8 +74,9 @@ def test_fp64_parity_after_1000_steps(lbm, shape, re, seed):
     r0, ux0, uy0 = ref.moments()
     fs0 = ref.post_collision()
     results = []
-    for v in range(4):
+    for v in range(c.get_option(lbm.LBM_OPT_NUM_VARIANTS)):
         c.set_option(lbm.LBM_OPT_STEP_VARIANT, v)
+        assert (c.get_option(lbm.LBM_OPT_STEPS_PER_LAUNCH) > 1) == (v >= 4)
         c.set_populations(f0)
         c.step(1000)
         results.append(c.get_populations())
@@ -108,6 +112,35 @@ def test_graph_and_direct_launches_agree(lbm, dtype):
     assert a.residual() == b.residual()
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32s"])
+@pytest.mark.parametrize("nx,ny", [(65, 33), (3, 3), (4, 70), (97, 17), (130, 49)])
+def test_multistep_shapes_agree_bitwise(lbm, dtype, nx, ny):
+    """The K-step NEE shapes against the one-step one, bit for bit, over
+    237 steps (two graph chunks, then K-step launches off the chunk grid and
+    single steps for the rest) and with direct launches; the Eq. 6 monitor
+    is the same pass over the same state.  65 x 33 and 97 x 17 leave tiles
+    one node wide or high at the right and top walls, whose wall nodes read
+    two nodes inward; 3 x 3 is all walls but one node."""
+    f0 = W[:, None, None] + random_shift(nx, ny, 23)
+    c = lbm.Cavity(nx, ny, re=300.0, u_lid=U_LID, dtype=dtype, wall="nee")
+    c.set_populations(f0)
+    c.step(237)
+    ref, ref_res = c.get_populations(), c.residual()
+    for v in range(4, c.get_option(lbm.LBM_OPT_NUM_VARIANTS)):
+        c.set_option(lbm.LBM_OPT_STEP_VARIANT, v)
+        k = c.get_option(lbm.LBM_OPT_STEPS_PER_LAUNCH)
+        for graph in (1, 0):
+            c.set_option(lbm.LBM_OPT_USE_GRAPH, graph)
+            c.set_populations(f0)
+            c.step(237)
+            rec = c.last_launches()
+            assert rec["multi_variant"] == v and rec["steps_per_launch"] == k, rec
+            assert rec["multi_launches"] * k + rec["single_launches"] == 237, rec
+            assert np.array_equal(c.get_populations(), ref), (v, graph)
+            assert c.residual() == ref_res
+    c.close()
 
 
 def test_monitors_on_nodes(lbm):
@@ -151,7 +184,7 @@ def test_checkpoint_records_the_wall_scheme(lbm, tmp_path):
 def test_autotune_picks_a_nee_shape(lbm):
     c = lbm.Cavity(300, 200, re=1000.0, u_lid=U_LID, dtype="f32s", wall="nee")
     best, ms = c.autotune(chunks=2, use_cache=False)
-    assert 0 <= best < 4 and c.get_option(lbm.LBM_OPT_STEP_VARIANT) == best
+    assert 0 <= best < 7 and c.get_option(lbm.LBM_OPT_STEP_VARIANT) == best
     assert c.info["steps_done"] == 0
     c.close()
 
@@ -234,8 +267,9 @@ def test_rectangular_cavity_against_table2_re4000(lbm):
     c.close()
 
 
+@pytest.mark.parametrize("variant", [0, 5])
 @pytest.mark.parametrize("dtype", ["f64", "f32s"])
-def test_full_size_light_cone(lbm, dtype):
+def test_full_size_light_cone(lbm, dtype, variant):
     """The 501 x 601 node lattice of the Table 2 run (Re 4000) from a random
     state: two 100-step graph chunks, the second checked against the oracle
     on 240 x 240 windows cut from the GPU's state after the first.  The
@@ -243,11 +277,13 @@ def test_full_size_light_cone(lbm, dtype):
     wall of the cavity its effect moves one node per step, so nodes more
     than 102 nodes from such an edge are exact after 100 steps.  Windows:
     the two lid corners, the two bottom corners, the centre.  Bars: FP64
-    populations <= 1e-12, FP32 velocity <= 1e-5 U."""
+    populations <= 1e-12, FP32 velocity <= 1e-5 U.  Variant 0 takes one step
+    per launch, variant 5 five (K-step tiles in LDS)."""
     nx, ny, n, w = 501, 601, 100, 240
     m = n + 2
     tau = nee.relaxation_time(nx, 4000.0, U_LID)
     c = lbm.Cavity(nx, ny, re=4000.0, u_lid=U_LID, dtype=dtype, wall="nee")
+    c.set_option(lbm.LBM_OPT_STEP_VARIANT, variant)
     c.set_populations(nee.CavityNEE(nx, ny, tau=tau, u_lid=U_LID).f + random_shift(nx, ny, 41))
     c.step(n)
     f_start = c.get_populations()
