@@ -125,10 +125,11 @@ int lbm_create_tau(int nx, int ny, double tau, double u_lid, int dtype,
  * elsewhere.  Mass, Eq. 6 and moments cover all nodes; probes, Psi and
  * vortex positions use node positions x / (nx - 1) in units of L, and Psi
  * is the trapezoid rule up each column from Psi = 0 on the bottom row.  NEE
- * handles have LBM_OPT_NUM_VARIANTS = 7 tile shapes: 0-3 take one step per
- * launch (64 x {4, 8} nodes), 4-6 take K steps per launch on a tile kept
+ * handles have LBM_OPT_NUM_VARIANTS = 8 tile shapes: 0-3 take one step per
+ * launch (64 x {4, 8} nodes), 4-7 take K steps per launch on a tile kept
  * in LDS (16 x 16, K = 4; 32 x 16, K = 5, FP64 16 x 16; 32 x 32, K = 4,
- * FP64 16 x 32).  Every shape gives the same bits.
+ * FP64 16 x 32; 32 x 32, K = 5, FP64 16 x 32 with K = 2).  Every shape
+ * gives the same bits.
  * Errors: as lbm_create; LBM_EINVAL for an unknown wall, or NEE with nx or
  * ny < 3.
  */

@@ -168,10 +168,10 @@ static void tile_of(int v, int dtype, int &tx, int &ty) {
 }
 
 // Non-equilibrium extrapolation handles have their own shapes: four
-// one-step ones (k_step_nee, 64 x (BY RY) nodes) and three multi-step ones
+// one-step ones (k_step_nee, 64 x (BY RY) nodes) and four multi-step ones
 // (k_step_nee_tb): 16 x 16, K = 4; K = 5 on 32 x 16 (FP64 16 x 16); K = 4
-// on 32 x 32 (FP64 16 x 32).
-static const int kNumNeeVariants = 7;
+// on 32 x 32 (FP64 16 x 32); K = 5 on 32 x 32 (FP64 K = 2 on 16 x 32).
+static const int kNumNeeVariants = 8;
 static const int kDefaultNeeVariant = 6;   // the fastest untuned at 257^2 and 501^2
 
 static int num_variants(const lbm_cavity *h) {
@@ -179,7 +179,11 @@ static int num_variants(const lbm_cavity *h) {
 }
 
 static int launch_steps(const lbm_cavity *h, int v) {
-  if (h->wall == LBM_WALL_NEE) return v == 5 ? 5 : v >= 4 && v < kNumNeeVariants ? 4 : 1;
+  if (h->wall == LBM_WALL_NEE) {
+    static const int k[kNumNeeVariants] = {1, 1, 1, 1, 4, 5, 4, 5};
+    if (v == 7 && h->dtype == LBM_F64) return 2;
+    return (v >= 0 && v < kNumNeeVariants) ? k[v] : 1;
+  }
   return steps_per_launch(v);
 }
 
@@ -195,7 +199,7 @@ static void nee_tile_of(int v, int dtype, int &tx, int &ty) {
   } else if (v == 5) {
     tx = f64 ? 16 : 32;
     ty = 16;
-  } else {
+  } else {   // shapes 6 and 7
     tx = f64 ? 16 : 32;
     ty = 32;
   }
@@ -260,6 +264,11 @@ static hipError_t launch_nee_variant(const lbm_cavity *h, int v, const void *src
         return launch_nee_tb_t<T, S, 4, 16, 32, 512>(h, src, dst, st);
       else
         return launch_nee_tb_t<T, S, 4, 32, 32, 1024>(h, src, dst, st);
+    case 7:
+      if constexpr (f64)
+        return launch_nee_tb_t<T, S, 2, 16, 32, 512>(h, src, dst, st);
+      else
+        return launch_nee_tb_t<T, S, 5, 32, 32, 1024>(h, src, dst, st);
     default: return launch_nee_t<T, S, 4, 1>(h, src, dst, st);
   }
 }

@@ -37,7 +37,7 @@ def test_create_reports_the_scheme_and_tau(lbm):
     info = c.info
     assert info["wall"] == lbm.LBM_WALL_NEE
     assert math.isclose(info["tau"], nee.relaxation_time(257, 400.0, U_LID), rel_tol=1e-15)
-    assert c.get_option(lbm.LBM_OPT_NUM_VARIANTS) == 7
+    assert c.get_option(lbm.LBM_OPT_NUM_VARIANTS) == 8
     assert c.get_option(lbm.LBM_OPT_STEP_VARIANT) == 6     # K-step shape by default
     assert c.get_option(lbm.LBM_OPT_STEPS_PER_LAUNCH) == 4
     with pytest.raises(lbm.LbmError):
@@ -184,7 +184,7 @@ def test_checkpoint_records_the_wall_scheme(lbm, tmp_path):
 def test_autotune_picks_a_nee_shape(lbm):
     c = lbm.Cavity(300, 200, re=1000.0, u_lid=U_LID, dtype="f32s", wall="nee")
     best, ms = c.autotune(chunks=2, use_cache=False)
-    assert 0 <= best < 7 and c.get_option(lbm.LBM_OPT_STEP_VARIANT) == best
+    assert 0 <= best < 8 and c.get_option(lbm.LBM_OPT_STEP_VARIANT) == best
     assert c.info["steps_done"] == 0
     c.close()
 
