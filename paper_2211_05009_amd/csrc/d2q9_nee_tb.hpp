@@ -78,7 +78,8 @@ __device__ __forceinline__ void nee_tb_pull(const StepParams<T> &p, T *lds) {
       if (s == K) {
         const int o = gy * p.pitch + gx;
 #pragma unroll
-        for (int i = 0; i < 9; ++i) p.dst[(size_t)i * p.plane + o] = f[i];
+        for (int i = 0; i < 9; ++i)   // not read again in this launch
+          __builtin_nontemporal_store(f[i], p.dst + (size_t)i * p.plane + o);
       } else {
 #pragma unroll
         for (int i = 0; i < 9; ++i) out[i * RS + ly * RW + lx] = f[i];
