@@ -96,7 +96,8 @@ def parse():
     ap.add_argument("--aux", type=int, default=0,
                     help="instead time the kernels off the metric (non-equilibrium-"
                          "extrapolation step, vortex extraction, surrogate convolutions, "
-                         "series classifier; 2: the surrogate alone); prints one JSON line")
+                         "series classifier; 2: the surrogate alone; 3: the "
+                         "non-equilibrium-extrapolation step alone); prints one JSON line")
     ap.add_argument("--precision", type=int, default=0,
                     help="instead compare FP32 f - w storage with FP64 on the nine "
                          "500 x (500 Ar) cavities (Ar 0.4/1.0/2.0 x Re 1000/4000/8000) after "
@@ -416,7 +417,7 @@ def main():
     if args.flowmap:
         return run_flowmap(args)
     if args.aux:
-        return run_aux(surrogate_only=args.aux == 2)
+        return run_aux(surrogate_only=args.aux == 2, nee_only=args.aux == 3)
     if args.precision:
         return run_precision()
     if not torch.cuda.is_available():
@@ -556,7 +557,7 @@ def run_precision():
     print(json.dumps({"precision": rows}), flush=True)
 
 
-def run_aux(surrogate_only=False):
+def run_aux(surrogate_only=False, nee_only=False):
     """Timings of the kernels off the metric, for profiling (one JSON line)."""
     import torch
     import numpy as np
@@ -569,17 +570,22 @@ def run_aux(surrogate_only=False):
         sur.close()
         print(json.dumps({"aux": out}), flush=True)
         return
-    for dt in ("f64", "f32s"):           # the paper's walls, 256 x 256 validation lattice
-        c = lbm.Cavity(257, 257, re=1000.0, u_lid=0.1, dtype=dt, wall="nee")
-        c.autotune(chunks=5)
-        c.step(2000)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        c.step(20000)
-        sec = time.perf_counter() - t0
-        out[f"nee_257_{dt}"] = {"MLUPS": round(257 * 257 * 20000 / sec / 1e6, 1),
-                                "variant": c.get_option(lbm.LBM_OPT_STEP_VARIANT)}
-        c.close()
+    # the paper's walls: the 256 x 256 validation lattice and a 500 x 500 one
+    for n, steps in ((257, 20000), (501, 10000)):
+        for dt in ("f64", "f32s"):
+            c = lbm.Cavity(n, n, re=1000.0, u_lid=0.1, dtype=dt, wall="nee")
+            c.autotune(chunks=5)
+            c.step(2000)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            c.step(steps)
+            sec = time.perf_counter() - t0
+            out[f"nee_{n}_{dt}"] = {"MLUPS": round(n * n * steps / sec / 1e6, 1),
+                                    "variant": c.get_option(lbm.LBM_OPT_STEP_VARIANT)}
+            c.close()
+    if nee_only:
+        print(json.dumps({"aux": out}), flush=True)
+        return
     progress("vortex extraction")
     c = lbm.Cavity(500, 600, re=6000.0, u_lid=0.1, dtype="f32s")
     c.step(20000)
