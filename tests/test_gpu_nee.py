@@ -115,7 +115,7 @@ def test_graph_and_direct_launches_agree(lbm, dtype):
 
 
 @pytest.mark.parametrize("dtype", ["f64", "f32s"])
-@pytest.mark.parametrize("nx,ny", [(65, 33), (3, 3), (4, 70), (97, 17), (130, 49)])
+@pytest.mark.parametrize("nx,ny", [(65, 33), (3, 3), (4, 70), (97, 17), (130, 49), (200, 150)])
 def test_multistep_shapes_agree_bitwise(lbm, dtype, nx, ny):
     """The K-step NEE shapes against the one-step one, bit for bit, over
     237 steps (two graph chunks, then K-step launches off the chunk grid and
@@ -125,8 +125,10 @@ def test_multistep_shapes_agree_bitwise(lbm, dtype, nx, ny):
     two nodes inward; 3 x 3 is all walls but one node."""
     f0 = W[:, None, None] + random_shift(nx, ny, 23)
     c = lbm.Cavity(nx, ny, re=300.0, u_lid=U_LID, dtype=dtype, wall="nee")
+    c.set_option(lbm.LBM_OPT_STEP_VARIANT, 0)     # one step per launch
     c.set_populations(f0)
     c.step(237)
+    assert c.last_launches()["multi_launches"] == 0
     ref, ref_res = c.get_populations(), c.residual()
     for v in range(4, c.get_option(lbm.LBM_OPT_NUM_VARIANTS)):
         c.set_option(lbm.LBM_OPT_STEP_VARIANT, v)
