@@ -172,7 +172,10 @@ static void tile_of(int v, int dtype, int &tx, int &ty) {
 // (k_step_nee_tb): 16 x 16, K = 4; K = 5 on 32 x 16 (FP64 16 x 16); K = 4
 // on 32 x 32 (FP64 16 x 32); K = 5 on 32 x 32 (FP64 K = 2 on 16 x 32).
 static const int kNumNeeVariants = 8;
-static const int kDefaultNeeVariant = 6;   // the fastest untuned at 257^2 and 501^2
+// default NEE shape before lbm_autotune: within 5 % of the best at 501^2
+// in both precisions and the best in FP64 at 257^2 (FP32 at 257^2: 30
+// against 36 GLUPS for shape 5)
+static const int kDefaultNeeVariant = 6;
 
 static int num_variants(const lbm_cavity *h) {
   return h->wall == LBM_WALL_NEE ? kNumNeeVariants : kNumVariants;
