@@ -735,8 +735,11 @@ int lbm_nn_up2(int backward, int n, int h, int w, int c, const void *in,
  * Storage LBM_F64 or LBM_F32_SHIFTED as in two dimensions; monitors (mass,
  * Eq. 6 over the three velocity components) every 100 steps in FP64; aligned
  * 100-step chunks replayed from HIP graphs.  Options LBM_OPT_USE_GRAPH,
- * LBM_OPT_STEP_VARIANT (3 tile shapes 64 x {1, 2, 4}), LBM_OPT_NUM_VARIANTS,
- * LBM_OPT_STEPS_PER_LAUNCH (1).
+ * LBM_OPT_STEP_VARIANT (6 tile shapes: 0-2 one step per launch, 64 x {1,
+ * 2, 4} sites of a z plane; 3-5 two steps per launch on a 3-D tile kept in
+ * LDS, FP32 32 x 8 x 4, 32 x 4 x 4, 16 x 16 x 4, FP64 16 x 4 x 4, 8 x 8 x 4,
+ * 16 x 8 x 2; every shape gives the same bits), LBM_OPT_NUM_VARIANTS,
+ * LBM_OPT_STEPS_PER_LAUNCH (1 or 2).
  * ------------------------------------------------------------------------ */
 typedef struct lbm_cube *lbm3d_t;
 

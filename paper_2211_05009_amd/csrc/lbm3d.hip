@@ -11,12 +11,17 @@
 
 #include "../../include/lbm.h"
 #include "d3q19_step.hpp"
+#include "d3q19_tb2.hpp"
 #include "lbm_internal.h"
 
 using namespace lbm;
 
 namespace {
-constexpr int kNum3Variants = 3;   // tile 64 x BY, BY in {1, 2, 4}
+// tile shapes: 0-2 one step per launch (64 x BY sites of one z plane, BY
+// in {1, 2, 4}); 3-5 two steps per launch (k_step3_tb2, a TX x TY x TZ tile:
+// FP32 32 x 8 x 4, 32 x 4 x 4, 16 x 16 x 4; FP64 16 x 4 x 4, 8 x 8 x 4,
+// 16 x 8 x 2)
+constexpr int kNum3Variants = 6;
 }  // namespace
 
 struct lbm_cube {
@@ -63,19 +68,63 @@ hipError_t launch3_t(const lbm_cube *h, const void *src, void *dst, hipStream_t 
   return hipGetLastError();
 }
 
+template <typename T, bool S, int TX, int TY, int TZ, int NT>
+hipError_t launch3_tb2_t(const lbm_cube *h, const void *src, void *dst, hipStream_t st) {
+  Step3Params<T> p;
+  p.src = (const T *)src;
+  p.dst = (T *)dst;
+  p.nx = h->nx;
+  p.ny = h->ny;
+  p.nz = h->nz;
+  p.pitch = h->pitch;
+  p.plane = h->plane;
+  p.tiles_x = (h->nx + TX - 1) / TX;
+  p.tiles_y = (h->ny + TY - 1) / TY;
+  p.omega = (T)h->omega;
+  p.u6 = (T)(h->u_lid / 6.0);
+  const int tiles_z = (h->nz + TZ - 1) / TZ;
+  hipLaunchKernelGGL((k_step3_tb2<T, S, TX, TY, TZ, NT>), dim3(p.tiles_x * p.tiles_y * tiles_z),
+                     dim3(NT), 0, st, p);
+  return hipGetLastError();
+}
+
+// Steps of Eq. 1 one launch of shape v applies.
+int steps3(int v) { return v >= 3 ? 2 : 1; }
+
 template <typename T, bool S>
-hipError_t launch3_variant(const lbm_cube *h, const void *src, void *dst, hipStream_t st) {
-  switch (h->variant) {
+hipError_t launch3_variant(int v, const lbm_cube *h, const void *src, void *dst,
+                           hipStream_t st) {
+  constexpr bool f64 = sizeof(T) == 8;
+  switch (v) {
     case 0: return launch3_t<T, S, 1>(h, src, dst, st);
     case 2: return launch3_t<T, S, 4>(h, src, dst, st);
+    case 3:
+      if constexpr (f64)
+        return launch3_tb2_t<T, S, 16, 4, 4, 256>(h, src, dst, st);
+      else
+        return launch3_tb2_t<T, S, 32, 8, 4, 1024>(h, src, dst, st);
+    case 4:
+      if constexpr (f64)
+        return launch3_tb2_t<T, S, 8, 8, 4, 256>(h, src, dst, st);
+      else
+        return launch3_tb2_t<T, S, 32, 4, 4, 512>(h, src, dst, st);
+    case 5:
+      if constexpr (f64)
+        return launch3_tb2_t<T, S, 16, 8, 2, 256>(h, src, dst, st);
+      else
+        return launch3_tb2_t<T, S, 16, 16, 4, 1024>(h, src, dst, st);
     default: return launch3_t<T, S, 2>(h, src, dst, st);
   }
 }
 
-hipError_t launch3(const lbm_cube *h, const void *src, void *dst, hipStream_t st) {
-  if (h->dtype == LBM_F64) return launch3_variant<double, false>(h, src, dst, st);
-  return launch3_variant<float, true>(h, src, dst, st);
+// One launch of shape v: steps3(v) steps from src into dst.
+hipError_t launch3(const lbm_cube *h, int v, const void *src, void *dst, hipStream_t st) {
+  if (h->dtype == LBM_F64) return launch3_variant<double, false>(v, h, src, dst, st);
+  return launch3_variant<float, true>(v, h, src, dst, st);
 }
+
+// The one-step shape single steps take: the chosen one, or shape 1.
+int one_step3(const lbm_cube *h) { return steps3(h->variant) == 1 ? h->variant : 1; }
 
 int reduce_blocks(const lbm_cube *h) {
   return (int)std::min<long long>(kRedBlocks, (sites(h) + kRedThreads - 1) / kRedThreads);
@@ -103,11 +152,13 @@ hipError_t monitor3(const lbm_cube *h, const void *src, bool update, double *out
   return monitor3_t<float, true>(h, src, update, out, st);
 }
 
-// 100 steps from buf[c] (even: the state ends in buf[c]) and the monitor.
+// 100 steps from buf[c] (100 / K launches, an even number: the state ends
+// in buf[c]) and the monitor.
 hipError_t issue_chunk3(lbm_cube *h, int c, hipStream_t st) {
   int cur = c;
-  for (int k = 0; k < kChunk; ++k) {
-    hipError_t e = launch3(h, h->buf[cur], h->buf[1 - cur], st);
+  const int K = steps3(h->variant);
+  for (int k = 0; k < kChunk; k += K) {
+    hipError_t e = launch3(h, h->variant, h->buf[cur], h->buf[1 - cur], st);
     if (e != hipSuccess) return e;
     cur = 1 - cur;
   }
@@ -293,7 +344,7 @@ int lbm3d_get_option(lbm3d_t h, int option, int64_t *value) {
     case LBM_OPT_USE_GRAPH: *value = h->use_graph; return LBM_OK;
     case LBM_OPT_STEP_VARIANT: *value = h->variant; return LBM_OK;
     case LBM_OPT_NUM_VARIANTS: *value = kNum3Variants; return LBM_OK;
-    case LBM_OPT_STEPS_PER_LAUNCH: *value = 1; return LBM_OK;
+    case LBM_OPT_STEPS_PER_LAUNCH: *value = steps3(h->variant); return LBM_OK;
     default: return lbm_fail(LBM_EINVAL, "unknown option %d", option);
   }
 }
@@ -315,17 +366,21 @@ int lbm3d_step(lbm3d_t h, int64_t n) {
         e = issue_chunk3(h, h->cur, h->stream);
         if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "launch: %s", hipGetErrorString(e));
       }
-      h->t += kChunk;            // 100 launches: the state is back in buf[cur]
+      h->t += kChunk;            // an even number of launches: the state is back in buf[cur]
       n -= kChunk;
       note_monitor3(h);
       monitored = true;
       continue;
     }
-    e = launch3(h, h->buf[h->cur], h->buf[1 - h->cur], h->stream);
+    // off the 100-step grid: two-step launches of a two-step shape while t
+    // is even (100 is, so none crosses a monitor point), else single steps
+    const int K = steps3(h->variant) == 2 && h->t % 2 == 0 && n >= 2 ? 2 : 1;
+    e = launch3(h, K == 2 ? h->variant : one_step3(h), h->buf[h->cur], h->buf[1 - h->cur],
+                h->stream);
     if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "step launch: %s", hipGetErrorString(e));
     h->cur = 1 - h->cur;
-    h->t += 1;
-    n -= 1;
+    h->t += K;
+    n -= K;
     if (h->t % kChunk == 0) {
       e = monitor3(h, h->buf[h->cur], true, h->mon_dev, h->stream);
       if (e != hipSuccess) return lbm_fail(LBM_EDEVICE, "monitor: %s", hipGetErrorString(e));

@@ -93,6 +93,31 @@ def test_graph_direct_and_monitors(lbm, dtype):
     b.close()
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32s"])
+def test_two_step_shapes_agree_bitwise(lbm, dtype):
+    """The two-step shapes against a one-step one, bit for bit, on a box
+    ragged for every tile: 137 steps (a graph or direct 100-step chunk, then
+    18 two-step launches and one single step), and the Eq. 6 monitor."""
+    nx, ny, nz = 37, 23, 13
+    rng = np.random.default_rng(31)
+    f0 = D.W[:, None, None, None] + rng.uniform(-4e-3, 4e-3, (19, nz, ny, nx))
+    c = lbm.Cube(nx, ny, nz, re=200.0, u_lid=U, dtype=dtype)
+    c.set_option(lbm.LBM_OPT_STEP_VARIANT, 0)
+    c.set_populations(f0)
+    c.step(137)
+    ref, ref_res = c.get_populations(), c.residual()
+    for v in range(3, c.get_option(lbm.LBM_OPT_NUM_VARIANTS)):
+        c.set_option(lbm.LBM_OPT_STEP_VARIANT, v)
+        assert c.get_option(lbm.LBM_OPT_STEPS_PER_LAUNCH) == 2
+        for graph in (1, 0):
+            c.set_option(lbm.LBM_OPT_USE_GRAPH, graph)
+            c.set_populations(f0)
+            c.step(137)
+            assert np.array_equal(c.get_populations(), ref), (v, graph)
+            assert c.residual() == ref_res
+    c.close()
+
+
 def test_mirror_symmetry_in_z(lbm):
     c = lbm.Cube(24, 20, 9, re=300.0, u_lid=U, dtype="f64")
     c.step(1500)
@@ -106,7 +131,8 @@ def test_autotune_keeps_the_state(lbm):
     c.step(200)
     f = c.get_populations()
     best, ms = c.autotune(2)
-    assert 0 <= best < 3 and ms > 0 and c.steps_done() == 200
+    assert 0 <= best < c.get_option(lbm.LBM_OPT_NUM_VARIANTS) and ms > 0
+    assert c.steps_done() == 200
     assert np.array_equal(c.get_populations(), f)
     c.close()
 
@@ -119,11 +145,13 @@ def test_errors(lbm):
         assert e.value.code == lbm.LBM_EINVAL
 
 
-@pytest.mark.parametrize("dtype,n,variant", [("f32s", 256, 2), ("f64", 192, 1)])
+@pytest.mark.parametrize("dtype,n,variant", [("f32s", 256, 2), ("f64", 192, 1),
+                                             ("f32s", 256, 3), ("f64", 192, 3)])
 def test_full_size_box_light_cone(lbm, dtype, n, variant):
-    """The boxes the benchmark times (256^3 FP32, 192^3 FP64, in the tile
-    shape it picks) from a random state: one 100-step graph chunk, then ten
-    direct launches, checked against the oracle on 42^3 windows cut from the
+    """The boxes the benchmark times (256^3 FP32, 192^3 FP64, in a one-step
+    and a two-step tile shape) from a random state: one 100-step graph chunk,
+    then ten steps of direct launches, checked against the oracle on 42^3
+    windows cut from the
     GPU's state.  In ten steps information moves at most ten sites, so sites
     more than eleven sites from a cut face are exact.  Windows: the lid
     corner at x = z = 0, the opposite bottom corner, the centre.  Bars: FP64
