@@ -737,8 +737,8 @@ int lbm_nn_up2(int backward, int n, int h, int w, int c, const void *in,
  * 100-step chunks replayed from HIP graphs.  Options LBM_OPT_USE_GRAPH,
  * LBM_OPT_STEP_VARIANT (6 tile shapes: 0-2 one step per launch, 64 x {1,
  * 2, 4} sites of a z plane; 3-5 two steps per launch on a 3-D tile kept in
- * LDS, FP32 32 x 8 x 4, 32 x 4 x 4, 16 x 16 x 4, FP64 16 x 4 x 4, 8 x 8 x 4,
- * 16 x 8 x 2; every shape gives the same bits), LBM_OPT_NUM_VARIANTS,
+ * LDS, FP32 32 x 8 x 4, 32 x 4 x 4, 16 x 16 x 4, FP64 32 x 4 x 3, 16 x 6 x 4,
+ * 16 x 5 x 5; every shape gives the same bits), LBM_OPT_NUM_VARIANTS,
  * LBM_OPT_STEPS_PER_LAUNCH (1 or 2).
  * ------------------------------------------------------------------------ */
 typedef struct lbm_cube *lbm3d_t;

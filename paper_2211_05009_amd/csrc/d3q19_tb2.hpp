@@ -17,6 +17,34 @@
 
 namespace lbm {
 
+// The 19 inputs of site (x, y, z), at element o of an array with plane,
+// row and slab strides ps, rs, ss: a link from outside the box reflects,
+// with the lid's term where it crosses the lid, as in k_step3.  Sites whose
+// every link comes from inside the box (all but the box's outer shell) take
+// the unchecked pulls; the values are the same either way.
+template <typename T>
+__device__ __forceinline__ void pull19(const T *a, int ps, int rs, int ss, int o, int x, int y,
+                                       int z, int nx, int ny, int nz, T u6, T (&f)[19]) {
+  if (x >= 1 && x < nx - 1 && y >= 1 && y < ny - 1 && z >= 1 && z < nz - 1) {
+#pragma unroll
+    for (int i = 0; i < 19; ++i) f[i] = a[i * ps + o - cx19(i) - cy19(i) * rs - cz19(i) * ss];
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const int xs = x - cx19(i), ys = y - cy19(i), zs = z - cz19(i);
+    if (xs >= 0 && xs < nx && ys >= 0 && ys < ny && zs >= 0 && zs < nz) {
+      f[i] = a[i * ps + o - cx19(i) - cy19(i) * rs - cz19(i) * ss];
+    } else {
+      f[i] = a[opp19(i) * ps + o];
+      if (ys >= ny) {
+        if (i == 8) f[i] -= u6;
+        else if (i == 9) f[i] += u6;
+      }
+    }
+  }
+}
+
 template <typename T, bool SHIFT, int TX, int TY, int TZ, int NT>
 __global__ __launch_bounds__(NT) void k_step3_tb2(Step3Params<T> p) {
   constexpr int WX = TX + 2, WY = TY + 2, WZ = TZ + 2, WS = WX * WY * WZ;
@@ -34,21 +62,8 @@ __global__ __launch_bounds__(NT) void k_step3_tb2(Step3Params<T> p) {
     const int lx = q % WX, t = q / WX, ly = t % WY, lz = t / WY;
     const int x = X0 + lx, y = Y0 + ly, z = Z0 + lz;
     if (x < 0 || x >= nx || y < 0 || y >= ny || z < 0 || z >= nz) continue;
-    const int o = z * slab + y * rowp + x;
     T f[19];
-#pragma unroll
-    for (int i = 0; i < 19; ++i) {
-      const int xs = x - cx19(i), ys = y - cy19(i), zs = z - cz19(i);
-      if (xs >= 0 && xs < nx && ys >= 0 && ys < ny && zs >= 0 && zs < nz) {
-        f[i] = p.src[i * p.plane + o - cx19(i) - cy19(i) * rowp - cz19(i) * slab];
-      } else {   // reflected, plus the lid's term where the link crosses it
-        f[i] = p.src[opp19(i) * p.plane + o];
-        if (ys >= ny) {
-          if (i == 8) f[i] -= p.u6;
-          else if (i == 9) f[i] += p.u6;
-        }
-      }
-    }
+    pull19<T>(p.src, p.plane, rowp, slab, z * slab + y * rowp + x, x, y, z, nx, ny, nz, p.u6, f);
     bgk_collide19<T, SHIFT>(f, p.omega);
 #pragma unroll
     for (int i = 0; i < 19; ++i) lds[i * WS + q] = f[i];
@@ -60,21 +75,8 @@ __global__ __launch_bounds__(NT) void k_step3_tb2(Step3Params<T> p) {
     const int lx = 1 + q % TX, t = q / TX, ly = 1 + t % TY, lz = 1 + t / TY;
     const int x = X0 + lx, y = Y0 + ly, z = Z0 + lz;
     if (x >= nx || y >= ny || z >= nz) continue;
-    const int l = (lz * WY + ly) * WX + lx;
     T f[19];
-#pragma unroll
-    for (int i = 0; i < 19; ++i) {
-      const int xs = x - cx19(i), ys = y - cy19(i), zs = z - cz19(i);
-      if (xs >= 0 && xs < nx && ys >= 0 && ys < ny && zs >= 0 && zs < nz) {
-        f[i] = lds[i * WS + l - cx19(i) - cy19(i) * WX - cz19(i) * WX * WY];
-      } else {
-        f[i] = lds[opp19(i) * WS + l];
-        if (ys >= ny) {
-          if (i == 8) f[i] -= p.u6;
-          else if (i == 9) f[i] += p.u6;
-        }
-      }
-    }
+    pull19<T>(lds, WS, WX, WX * WY, (lz * WY + ly) * WX + lx, x, y, z, nx, ny, nz, p.u6, f);
     bgk_collide19<T, SHIFT>(f, p.omega);
     const int o = z * slab + y * rowp + x;
 #pragma unroll

@@ -19,8 +19,10 @@ using namespace lbm;
 namespace {
 // tile shapes: 0-2 one step per launch (64 x BY sites of one z plane, BY
 // in {1, 2, 4}); 3-5 two steps per launch (k_step3_tb2, a TX x TY x TZ tile:
-// FP32 32 x 8 x 4, 32 x 4 x 4, 16 x 16 x 4; FP64 16 x 4 x 4, 8 x 8 x 4,
-// 16 x 8 x 2)
+// FP32 32 x 8 x 4, 32 x 4 x 4, 16 x 16 x 4; FP64 32 x 4 x 3, 16 x 6 x 4,
+// 16 x 5 x 5).  A two-step window takes most of the LDS, so one block runs per
+// CU: FP64 tiles run in 1024-thread blocks (16 waves per CU) to hide the
+// latency that four waves of 256 threads left exposed.
 constexpr int kNum3Variants = 6;
 }  // namespace
 
@@ -100,17 +102,17 @@ hipError_t launch3_variant(int v, const lbm_cube *h, const void *src, void *dst,
     case 2: return launch3_t<T, S, 4>(h, src, dst, st);
     case 3:
       if constexpr (f64)
-        return launch3_tb2_t<T, S, 16, 4, 4, 256>(h, src, dst, st);
+        return launch3_tb2_t<T, S, 32, 4, 3, 1024>(h, src, dst, st);
       else
         return launch3_tb2_t<T, S, 32, 8, 4, 1024>(h, src, dst, st);
     case 4:
       if constexpr (f64)
-        return launch3_tb2_t<T, S, 8, 8, 4, 256>(h, src, dst, st);
+        return launch3_tb2_t<T, S, 16, 6, 4, 1024>(h, src, dst, st);
       else
         return launch3_tb2_t<T, S, 32, 4, 4, 512>(h, src, dst, st);
     case 5:
       if constexpr (f64)
-        return launch3_tb2_t<T, S, 16, 8, 2, 256>(h, src, dst, st);
+        return launch3_tb2_t<T, S, 16, 5, 5, 1024>(h, src, dst, st);
       else
         return launch3_tb2_t<T, S, 16, 16, 4, 1024>(h, src, dst, st);
     default: return launch3_t<T, S, 2>(h, src, dst, st);
