@@ -273,13 +273,15 @@ def time_sweep(lbm, torch, re_cases, dtype, steps, sequential=True):
 
 
 def time_cube(lbm, torch, n, dtype, steps):
-    """D3Q19 lid-driven box of n^3 sites (Re 1000): MLUPS and the HBM
-    roofline at 19 populations read and written per site update (152 B in
-    FP32, 304 B in FP64), timed with HIP events on the handle's stream."""
+    """D3Q19 lid-driven box of n^3 sites (Re 1000): MLUPS and the
+    algorithmic bytes at 19 populations read and written per site update
+    (152 B in FP32, 304 B in FP64; a two-step launch counts two updates),
+    timed with HIP events on the handle's stream."""
     c = lbm.Cube(n, n, n, re=1000.0, u_lid=0.1, dtype=dtype)
     stream = torch.cuda.Stream()
     lbm.lbm3d_set_stream(c.h, stream)
     best, _ = c.autotune(2)
+    k = c.get_option(lbm.LBM_OPT_STEPS_PER_LAUNCH)
     c.step(200)
     e0, e1 = events(torch)
     torch.cuda.synchronize()
@@ -292,7 +294,7 @@ def time_cube(lbm, torch, n, dtype, steps):
     mlups = n ** 3 * steps / sec / 1e6
     bps = 152 if dtype == "f32s" else 304
     return {"sites": f"{n}^3", "storage": dtype, "steps": steps, "variant": best,
-            "MLUPS": round(mlups, 1), "GB/s": round(mlups * bps / 1e3, 1),
+            "steps_per_launch": k, "MLUPS": round(mlups, 1), "GB/s": round(mlups * bps / 1e3, 1),
             "frac_hbm": round(mlups * bps / 1e3 / HBM_PEAK_GBS, 4)}
 
 

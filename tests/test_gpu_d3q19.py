@@ -146,7 +146,7 @@ def test_errors(lbm):
 
 
 @pytest.mark.parametrize("dtype,n,variant", [("f32s", 256, 2), ("f64", 192, 1),
-                                             ("f32s", 256, 3), ("f64", 192, 3)])
+                                             ("f32s", 256, 3), ("f64", 192, 4)])
 def test_full_size_box_light_cone(lbm, dtype, n, variant):
     """The boxes the benchmark times (256^3 FP32, 192^3 FP64, in a one-step
     and a two-step tile shape) from a random state: one 100-step graph chunk,
