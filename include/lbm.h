@@ -735,10 +735,12 @@ int lbm_nn_up2(int backward, int n, int h, int w, int c, const void *in,
  * Storage LBM_F64 or LBM_F32_SHIFTED as in two dimensions; monitors (mass,
  * Eq. 6 over the three velocity components) every 100 steps in FP64; aligned
  * 100-step chunks replayed from HIP graphs.  Options LBM_OPT_USE_GRAPH,
- * LBM_OPT_STEP_VARIANT (6 tile shapes: 0-2 one step per launch, 64 x {1,
- * 2, 4} sites of a z plane; 3-5 two steps per launch on a 3-D tile kept in
- * LDS, FP32 32 x 8 x 4, 32 x 4 x 4, 16 x 16 x 4, FP64 32 x 4 x 3, 16 x 6 x 4,
- * 16 x 5 x 5; every shape gives the same bits), LBM_OPT_NUM_VARIANTS,
+ * LBM_OPT_STEP_VARIANT (8 tile shapes: 0-2 one step per launch, 64 x {1,
+ * 2, 4} sites of a z plane; 3-7 two steps per launch: 3 a 3-D tile kept in
+ * LDS, FP32 32 x 8 x 4, FP64 16 x 6 x 4; 4-7 a column marching through z
+ * with three planes of step-1 results in LDS, FP32 64 x 8, 64 x 12,
+ * 32 x 16, 32 x 24, FP64 32 x 12, 32 x 8, 16 x 16, 24 x 16; every shape
+ * gives the same bits), LBM_OPT_NUM_VARIANTS,
  * LBM_OPT_STEPS_PER_LAUNCH (1 or 2).
  * ------------------------------------------------------------------------ */
 typedef struct lbm_cube *lbm3d_t;

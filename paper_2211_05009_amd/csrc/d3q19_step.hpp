@@ -48,6 +48,7 @@ struct Step3Params {
   int nx, ny, nz, pitch;
   int plane;        // elements per population plane
   int tiles_x, tiles_y;
+  int zc;           // planes per block in the z-marching kernel (k_step3_zs2)
   T omega, u6;      // 1/tau, u_lid / 6 (the lid term of links 8 and 9)
 };
 

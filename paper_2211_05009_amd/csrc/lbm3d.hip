@@ -18,12 +18,12 @@ using namespace lbm;
 
 namespace {
 // tile shapes: 0-2 one step per launch (64 x BY sites of one z plane, BY
-// in {1, 2, 4}); 3-5 two steps per launch (k_step3_tb2, a TX x TY x TZ tile:
-// FP32 32 x 8 x 4, 32 x 4 x 4, 16 x 16 x 4; FP64 32 x 4 x 3, 16 x 6 x 4,
-// 16 x 5 x 5).  A two-step window takes most of the LDS, so one block runs per
-// CU: FP64 tiles run in 1024-thread blocks (16 waves per CU) to hide the
-// latency that four waves of 256 threads left exposed.
-constexpr int kNum3Variants = 6;
+// in {1, 2, 4}); 3-7 two steps per launch: 3 a TX x TY x TZ tile in LDS
+// (k_step3_tb2; FP32 32 x 8 x 4, FP64 16 x 6 x 4, 1024 threads: the window
+// takes most of the LDS, one block per CU, so large blocks hide latency),
+// 4-7 a TX x TY column marching through z (k_step3_zs2; FP32 64 x 8,
+// 64 x 12, 32 x 16, 32 x 24; FP64 32 x 12, 32 x 8, 16 x 16, 24 x 16)
+constexpr int kNum3Variants = 8;
 }  // namespace
 
 struct lbm_cube {
@@ -53,7 +53,7 @@ long long sites(const lbm_cube *h) { return (long long)h->nx * h->ny * h->nz; }
 
 template <typename T, bool S, int BY>
 hipError_t launch3_t(const lbm_cube *h, const void *src, void *dst, hipStream_t st) {
-  Step3Params<T> p;
+  Step3Params<T> p{};
   p.src = (const T *)src;
   p.dst = (T *)dst;
   p.nx = h->nx;
@@ -72,7 +72,7 @@ hipError_t launch3_t(const lbm_cube *h, const void *src, void *dst, hipStream_t 
 
 template <typename T, bool S, int TX, int TY, int TZ, int NT>
 hipError_t launch3_tb2_t(const lbm_cube *h, const void *src, void *dst, hipStream_t st) {
-  Step3Params<T> p;
+  Step3Params<T> p{};
   p.src = (const T *)src;
   p.dst = (T *)dst;
   p.nx = h->nx;
@@ -90,6 +90,39 @@ hipError_t launch3_tb2_t(const lbm_cube *h, const void *src, void *dst, hipStrea
   return hipGetLastError();
 }
 
+template <typename T, bool S, int TX, int TY, int NT>
+hipError_t launch3_zs2_t(const lbm_cube *h, const void *src, void *dst, hipStream_t st) {
+  Step3Params<T> p{};
+  p.src = (const T *)src;
+  p.dst = (T *)dst;
+  p.nx = h->nx;
+  p.ny = h->ny;
+  p.nz = h->nz;
+  p.pitch = h->pitch;
+  p.plane = h->plane;
+  p.tiles_x = (h->nx + TX - 1) / TX;
+  p.tiles_y = (h->ny + TY - 1) / TY;
+  p.omega = (T)h->omega;
+  p.u6 = (T)(h->u_lid / 6.0);
+  // about 1024 blocks, at least 4 planes each (each block computes step 1
+  // on one plane below and one above its range as well)
+  const int cols = p.tiles_x * p.tiles_y;
+  const int want = (1024 + cols - 1) / cols;
+  p.zc = std::max(4, (h->nz + want - 1) / want);
+  const int chunks = (h->nz + p.zc - 1) / p.zc;
+  // FP64 states below 2^31 bytes through raw buffers (+2.6 % at 192^3;
+  // FP32 measured 5.5 % slower that way at 256^3)
+  bool buf = false;
+  if constexpr (sizeof(T) == 8) buf = 19LL * h->plane * (long long)sizeof(T) <= INT32_MAX;
+  if (buf)
+    hipLaunchKernelGGL((k_step3_zs2<T, S, TX, TY, NT, sizeof(T) == 8>), dim3(cols * chunks),
+                       dim3(NT), 0, st, p);
+  else
+    hipLaunchKernelGGL((k_step3_zs2<T, S, TX, TY, NT, false>), dim3(cols * chunks), dim3(NT), 0,
+                       st, p);
+  return hipGetLastError();
+}
+
 // Steps of Eq. 1 one launch of shape v applies.
 int steps3(int v) { return v >= 3 ? 2 : 1; }
 
@@ -102,19 +135,29 @@ hipError_t launch3_variant(int v, const lbm_cube *h, const void *src, void *dst,
     case 2: return launch3_t<T, S, 4>(h, src, dst, st);
     case 3:
       if constexpr (f64)
-        return launch3_tb2_t<T, S, 32, 4, 3, 1024>(h, src, dst, st);
+        return launch3_tb2_t<T, S, 16, 6, 4, 1024>(h, src, dst, st);
       else
         return launch3_tb2_t<T, S, 32, 8, 4, 1024>(h, src, dst, st);
     case 4:
       if constexpr (f64)
-        return launch3_tb2_t<T, S, 16, 6, 4, 1024>(h, src, dst, st);
+        return launch3_zs2_t<T, S, 32, 12, 512>(h, src, dst, st);
       else
-        return launch3_tb2_t<T, S, 32, 4, 4, 512>(h, src, dst, st);
+        return launch3_zs2_t<T, S, 64, 8, 704>(h, src, dst, st);
     case 5:
       if constexpr (f64)
-        return launch3_tb2_t<T, S, 16, 5, 5, 1024>(h, src, dst, st);
+        return launch3_zs2_t<T, S, 32, 8, 384>(h, src, dst, st);
       else
-        return launch3_tb2_t<T, S, 16, 16, 4, 1024>(h, src, dst, st);
+        return launch3_zs2_t<T, S, 64, 12, 960>(h, src, dst, st);
+    case 6:
+      if constexpr (f64)
+        return launch3_zs2_t<T, S, 16, 16, 384>(h, src, dst, st);
+      else
+        return launch3_zs2_t<T, S, 32, 16, 640>(h, src, dst, st);
+    case 7:
+      if constexpr (f64)
+        return launch3_zs2_t<T, S, 24, 16, 512>(h, src, dst, st);
+      else
+        return launch3_zs2_t<T, S, 32, 24, 896>(h, src, dst, st);
     default: return launch3_t<T, S, 2>(h, src, dst, st);
   }
 }

@@ -118,6 +118,24 @@ def test_two_step_shapes_agree_bitwise(lbm, dtype):
     c.close()
 
 
+def test_fp64_z_marching_beyond_buffer_range(lbm):
+    """FP64 z-marching shapes read and write states below 2^31 bytes as raw
+    buffers and larger ones through pointers: a 128 x 130 x 864 box (2.19 GB
+    of populations) takes the pointer path; 101 steps from rest (a graph
+    chunk and a single step) equal a one-step shape's bit for bit."""
+    nx, ny, nz = 128, 130, 864
+    assert 19 * nx * ny * nz * 8 > 2 ** 31
+    out = []
+    for v in (1, 4):
+        c = lbm.Cube(nx, ny, nz, re=400.0, u_lid=U, dtype="f64")
+        c.set_option(lbm.LBM_OPT_STEP_VARIANT, v)
+        c.step(101)
+        out.append((c.get_populations(), c.residual()))
+        c.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1]
+
+
 def test_mirror_symmetry_in_z(lbm):
     c = lbm.Cube(24, 20, 9, re=300.0, u_lid=U, dtype="f64")
     c.step(1500)
@@ -146,10 +164,11 @@ def test_errors(lbm):
 
 
 @pytest.mark.parametrize("dtype,n,variant", [("f32s", 256, 2), ("f64", 192, 1),
-                                             ("f32s", 256, 3), ("f64", 192, 4)])
+                                             ("f32s", 256, 3), ("f32s", 256, 6),
+                                             ("f64", 192, 4)])
 def test_full_size_box_light_cone(lbm, dtype, n, variant):
     """The boxes the benchmark times (256^3 FP32, 192^3 FP64, in a one-step
-    and a two-step tile shape) from a random state: one 100-step graph chunk,
+    shape, a 3-D two-step tile and a z-marching one) from a random state: one 100-step graph chunk,
     then ten steps of direct launches, checked against the oracle on 42^3
     windows cut from the
     GPU's state.  In ten steps information moves at most ten sites, so sites
