@@ -61,30 +61,39 @@ struct Step3Params {
 // every collision).
 template <typename T, bool SHIFT>
 __device__ __forceinline__ void bgk_collide19(T (&f)[19], T omega) {
-  T s = T(0), jx = T(0), jy = T(0), jz = T(0);
+  T s = f[0];
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
-    s += f[i];
-    jx += T(cx19(i)) * f[i];
-    jy += T(cy19(i)) * f[i];
-    jz += T(cz19(i)) * f[i];
-  }
+  for (int i = 1; i < 19; ++i) s += f[i];
+  // momentum from the differences of opposite links (each odd link is
+  // followed by its opposite), no term with a zero velocity component
+  const T d1 = f[1] - f[2], d3 = f[3] - f[4], d5 = f[5] - f[6];
+  const T d7 = f[7] - f[8], d9 = f[9] - f[10], d11 = f[11] - f[12];
+  const T d13 = f[13] - f[14], d15 = f[15] - f[16], d17 = f[17] - f[18];
+  const T jx = d1 + d7 + d9 + d11 + d13;
+  const T jy = d3 + d7 - d9 + d15 + d17;
+  const T jz = d5 + d11 - d13 + d15 - d17;
   const T rho = SHIFT ? T(1) + s : s;
   const T rinv = recip<T>(rho);
   const T b = SHIFT ? s : rho;
   const T od = omega * T(1.0 / 36.0);
   const T jsq = T(1.5) * (jx * jx + jy * jy + jz * jz);
-#pragma unroll
-  for (int i = 0; i < 19; ++i) {
-    const T cj = T(cx19(i)) * jx + T(cy19(i)) * jy + T(cz19(i)) * jz;
-    const T e = (b + rinv * (T(4.5) * cj * cj - jsq)) + T(3) * cj;
-    if (i == 0)
-      f[i] += (T(4) * od) * (T(3) * e - T(9) * f[i]);
-    else if (i < 7)
-      f[i] += (T(2) * od) * (e - T(18) * f[i]);
-    else
-      f[i] += od * (e - T(36) * f[i]);
-  }
+  f[0] += (T(4) * od) * (T(3) * (b - rinv * jsq) - T(9) * f[0]);
+  // link a and its opposite a + 1: c_a . j = cj and -cj share E's even part
+  auto pair = [&](int a, T cj, T w, T k) {
+    const T q = b + rinv * (T(4.5) * cj * cj - jsq), e = T(3) * cj;
+    f[a] += w * ((q + e) - k * f[a]);
+    f[a + 1] += w * ((q - e) - k * f[a + 1]);
+  };
+  const T oa = T(2) * od;
+  pair(1, jx, oa, T(18));
+  pair(3, jy, oa, T(18));
+  pair(5, jz, oa, T(18));
+  pair(7, jx + jy, od, T(36));
+  pair(9, jx - jy, od, T(36));
+  pair(11, jx + jz, od, T(36));
+  pair(13, jx - jz, od, T(36));
+  pair(15, jy + jz, od, T(36));
+  pair(17, jy - jz, od, T(36));
 }
 
 // One step: block 64 x BY threads = one tile of 64 x BY sites of one z
