@@ -1,15 +1,21 @@
 // d3q19_tb2.hpp -- two D3Q19 steps per launch for the lid-driven box (the
-// three-dimensional extension of Sec. 4 of arXiv 2211.05009).
+// three-dimensional extension of Sec. 4 of arXiv 2211.05009).  Two forms:
 //
-// A block owns a TX x TY x TZ tile of sites.  Step 1 updates the tile and
-// the one-site shell around it (the window, clipped to the box), pulling
-// each site's inputs from the state f*(t) in global memory exactly as
-// k_step3 does, and leaves the results in LDS; step 2 updates the tile's
+// k_step3_tb2: a block owns a TX x TY x TZ tile.  Step 1 updates the tile
+// and the one-site shell around it (the window, clipped to the box),
+// pulling each site's inputs from the state f*(t) in global memory exactly
+// as k_step3 does, and leaves the results in LDS; step 2 updates the tile's
 // sites out of LDS (a link from outside the box reflects, with the lid's
-// term, as in k_step3) and stores them.  The per-site arithmetic is
-// k_step3's in the same order, so the result is bit-identical to two
-// one-step launches, and each launch reads and writes the state once for
-// two steps: the one-step kernel runs at the rate of a plain device copy.
+// term, as in k_step3) and stores them.
+//
+// k_step3_zs2: a block owns a TX x TY column over a range of planes and
+// marches through z, keeping step-1 results of three planes in LDS, so only
+// the x-y shell is computed twice.
+//
+// Per site both use k_step3's pulls and collision in the same order, so the
+// result is bit-identical to two one-step launches, and each launch reads
+// and writes the state once for two steps: the one-step kernel runs at the
+// rate of a plain device copy.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -26,7 +32,9 @@ struct PtrArray {   // any array: 64-bit addresses
   __device__ __forceinline__ T at(int d, int o) const { return a[d + o]; }
 };
 // Arrays below 2^31 bytes as raw buffers: the lane's byte offset in a VGPR,
-// the uniform one in an SGPR, no per-access 64-bit address arithmetic.
+// the uniform one in an SGPR, no per-access 64-bit address arithmetic.  The
+// descriptor: stride 0 (raw), num_records = the array's bytes, and
+// 0x00020000 as its last word (data format 32 bits) for gfx9-family GPUs.
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void *p, long long bytes) {
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, (int)bytes, 0x00020000);
 }
