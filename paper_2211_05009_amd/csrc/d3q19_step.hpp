@@ -137,12 +137,12 @@ __device__ __forceinline__ void site_moments19(const T *__restrict__ s, int plan
                                                double &jz) {
   double sum = 0.0, a = 0.0, b = 0.0, c = 0.0;
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
+  for (int i = 0; i < 19; ++i) {   // the zero components skipped (constants here)
     const double v = (double)s[i * plane + o];
     sum += v;
-    a += cx19(i) * v;
-    b += cy19(i) * v;
-    c += cz19(i) * v;
+    if (cx19(i)) a += cx19(i) > 0 ? v : -v;
+    if (cy19(i)) b += cy19(i) > 0 ? v : -v;
+    if (cz19(i)) c += cz19(i) > 0 ? v : -v;
   }
   drho = SHIFT ? sum : sum - 1.0;
   jx = a;

@@ -24,6 +24,9 @@ namespace {
 // 4-7 a TX x TY column marching through z (k_step3_zs2; FP32 64 x 8,
 // 64 x 12, 32 x 16, 32 x 24; FP64 32 x 12, 32 x 8, 16 x 16, 24 x 16)
 constexpr int kNum3Variants = 8;
+// blocks of the monitor and mass reductions (each thread takes a few sites:
+// more waves in flight than the two-dimensional handles' 1024 blocks give)
+constexpr int kRed3Blocks = 8192;
 }  // namespace
 
 struct lbm_cube {
@@ -33,7 +36,7 @@ struct lbm_cube {
   size_t buf_bytes = 0;
   int cur = 0;
   double *uref = nullptr;       // [3][n] Eq. 6 reference velocity
-  double *partials = nullptr;   // [kRedBlocks][kNumSums]
+  double *partials = nullptr;   // [kRed3Blocks][kNumSums]
   double *mon_dev = nullptr;    // chunk monitor sums
   double *aux_dev = nullptr;    // on-demand sums
   double *mon_host = nullptr;   // pinned
@@ -172,7 +175,7 @@ hipError_t launch3(const lbm_cube *h, int v, const void *src, void *dst, hipStre
 int one_step3(const lbm_cube *h) { return steps3(h->variant) == 1 ? h->variant : 1; }
 
 int reduce_blocks(const lbm_cube *h) {
-  return (int)std::min<long long>(kRedBlocks, (sites(h) + kRedThreads - 1) / kRedThreads);
+  return (int)std::min<long long>(kRed3Blocks, (sites(h) + kRedThreads - 1) / kRedThreads);
 }
 
 template <typename T, bool S>
@@ -332,7 +335,7 @@ int lbm3d_create(int nx, int ny, int nz, double re, double u_lid, int dtype, lbm
   TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
   for (int c = 0; c < 2; ++c) TRY(hipMalloc(&h->buf[c], h->buf_bytes));
   TRY(hipMalloc(&h->uref, sizeof(double) * 3 * (size_t)sites(h)));
-  TRY(hipMalloc(&h->partials, sizeof(double) * kRedBlocks * kNumSums));
+  TRY(hipMalloc(&h->partials, sizeof(double) * kRed3Blocks * kNumSums));
   TRY(hipMalloc(&h->mon_dev, sizeof(double) * 4));
   TRY(hipMalloc(&h->aux_dev, sizeof(double) * 4));
   TRY(hipHostMalloc(&h->mon_host, sizeof(double) * 8, hipHostMallocDefault));
