@@ -45,6 +45,8 @@ struct lbm_cube {
   hipStream_t stream = nullptr, own_stream = nullptr, cap_stream = nullptr;
   hipGraphExec_t graph[2] = {nullptr, nullptr};
   int variant = 1, use_graph = 1;
+  int cus = 256;                       // compute units of the handle's GPU
+  mutable int zs2_zc[kNum3Variants] = {};   // planes per block of a z-marching shape
   int64_t t = 0, snap_t = 0, mon_t = -1;
   bool mon_valid = false;
   double last_res = INFINITY, last_mass = NAN;
@@ -93,8 +95,28 @@ hipError_t launch3_tb2_t(const lbm_cube *h, const void *src, void *dst, hipStrea
   return hipGetLastError();
 }
 
+// Planes per block of the z-marching kernel over nz planes and cols
+// columns, `slots` blocks resident on the GPU at once: the length whose
+// chunk count minimises rounds x (planes + 2), a round being `slots` blocks
+// and a block's time about proportional to its planes plus the two extra
+// planes its step 1 computes (ties: the longer chunks, fewer blocks).
+int zs2_planes(int nz, long long cols, long long slots) {
+  int best = nz;
+  long long best_cost = -1;
+  for (int zc = nz; zc >= 1; --zc) {
+    const long long chunks = (nz + zc - 1) / zc;
+    const long long rounds = (cols * chunks + slots - 1) / slots;
+    const long long cost = rounds * (zc + 2);
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best = zc;
+    }
+  }
+  return best;
+}
+
 template <typename T, bool S, int TX, int TY, int NT>
-hipError_t launch3_zs2_t(const lbm_cube *h, const void *src, void *dst, hipStream_t st) {
+hipError_t launch3_zs2_t(const lbm_cube *h, int v, const void *src, void *dst, hipStream_t st) {
   Step3Params<T> p{};
   p.src = (const T *)src;
   p.dst = (T *)dst;
@@ -107,11 +129,15 @@ hipError_t launch3_zs2_t(const lbm_cube *h, const void *src, void *dst, hipStrea
   p.tiles_y = (h->ny + TY - 1) / TY;
   p.omega = (T)h->omega;
   p.u6 = (T)(h->u_lid / 6.0);
-  // about 1024 blocks, at least 4 planes each (each block computes step 1
-  // on one plane below and one above its range as well)
+  // the chunk length, once per handle and shape: blocks per CU as the LDS
+  // window (43 values per window site) and 2048 threads allow
   const int cols = p.tiles_x * p.tiles_y;
-  const int want = (1024 + cols - 1) / cols;
-  p.zc = std::max(4, (h->nz + want - 1) / want);
+  if (h->zs2_zc[v] <= 0) {
+    const long long lds = 43LL * (TX + 2) * (TY + 2) * (long long)sizeof(T);
+    const long long per_cu = std::max(1LL, std::min(160LL * 1024 / lds, 2048LL / NT));
+    h->zs2_zc[v] = zs2_planes(h->nz, cols, per_cu * std::max(1, h->cus));
+  }
+  p.zc = h->zs2_zc[v];
   const int chunks = (h->nz + p.zc - 1) / p.zc;
   // FP64 states below 2^31 bytes through raw buffers (+2.6 % at 192^3;
   // FP32 measured 5.5 % slower that way at 256^3)
@@ -143,24 +169,24 @@ hipError_t launch3_variant(int v, const lbm_cube *h, const void *src, void *dst,
         return launch3_tb2_t<T, S, 32, 8, 4, 1024>(h, src, dst, st);
     case 4:
       if constexpr (f64)
-        return launch3_zs2_t<T, S, 32, 12, 512>(h, src, dst, st);
+        return launch3_zs2_t<T, S, 32, 12, 512>(h, v, src, dst, st);
       else
-        return launch3_zs2_t<T, S, 64, 8, 704>(h, src, dst, st);
+        return launch3_zs2_t<T, S, 64, 8, 704>(h, v, src, dst, st);
     case 5:
       if constexpr (f64)
-        return launch3_zs2_t<T, S, 32, 8, 384>(h, src, dst, st);
+        return launch3_zs2_t<T, S, 32, 8, 384>(h, v, src, dst, st);
       else
-        return launch3_zs2_t<T, S, 64, 12, 960>(h, src, dst, st);
+        return launch3_zs2_t<T, S, 64, 12, 960>(h, v, src, dst, st);
     case 6:
       if constexpr (f64)
-        return launch3_zs2_t<T, S, 16, 16, 384>(h, src, dst, st);
+        return launch3_zs2_t<T, S, 16, 16, 384>(h, v, src, dst, st);
       else
-        return launch3_zs2_t<T, S, 32, 16, 640>(h, src, dst, st);
+        return launch3_zs2_t<T, S, 32, 16, 640>(h, v, src, dst, st);
     case 7:
       if constexpr (f64)
-        return launch3_zs2_t<T, S, 24, 16, 512>(h, src, dst, st);
+        return launch3_zs2_t<T, S, 24, 16, 512>(h, v, src, dst, st);
       else
-        return launch3_zs2_t<T, S, 32, 24, 896>(h, src, dst, st);
+        return launch3_zs2_t<T, S, 32, 24, 896>(h, v, src, dst, st);
     default: return launch3_t<T, S, 2>(h, src, dst, st);
   }
 }
@@ -331,6 +357,11 @@ int lbm3d_create(int nx, int ny, int nz, double re, double u_lid, int dtype, lbm
                            #call, hipGetErrorString(e)));                                  \
   } while (0)
   TRY(hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking));
+  {
+    int dev = 0;
+    TRY(hipGetDevice(&dev));
+    TRY(hipDeviceGetAttribute(&h->cus, hipDeviceAttributeMultiprocessorCount, dev));
+  }
   h->stream = h->own_stream;
   TRY(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
   for (int c = 0; c < 2; ++c) TRY(hipMalloc(&h->buf[c], h->buf_bytes));

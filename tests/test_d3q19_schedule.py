@@ -11,9 +11,11 @@ site; a second barrier separates it from the next step 1.  pop() keeps the
 (43 values per window site).  Checked: every LDS index lies in the array,
 every step-2 read finds the value step 1 computed for that population,
 site and plane (nothing overwrote it in between), and every site of the box
-is stored exactly once per launch.  The velocity tables, the population
-order inside each c_z group and the tile shapes are read from the sources.
+is stored exactly once per launch, for chunks of 1, 2, 3, 5 and all planes
+per block.  The velocity tables, the population order inside each c_z
+group and the tile shapes are read from the sources.
 """
+import itertools
 import os
 import re
 
@@ -44,7 +46,7 @@ def _opp(i):
     return 0 if i == 0 else (i + 1 if i % 2 else i - 1)
 
 
-def _schedule(nx, ny, nz, tx_, ty_, nt):
+def _schedule(nx, ny, nz, tx_, ty_, nt, zc):
     wx_, wy_ = tx_ + 2, ty_ + 2
     wp, tp = wx_ * wy_, tx_ * ty_
     dn, mid = 0, 2 * 5 * wp
@@ -62,7 +64,6 @@ def _schedule(nx, ny, nz, tx_, ty_, nt):
 
     tiles_x, tiles_y = -(-nx // tx_), -(-ny // ty_)
     cols = tiles_x * tiles_y
-    zc = max(4, -(-nz // -(-1024 // cols)))
     chunks = -(-nz // zc)
     stored = set()
     for b in range(cols * chunks):
@@ -111,5 +112,6 @@ def test_tables_read_from_the_sources():
 
 @pytest.mark.parametrize("box", [(37, 23, 13), (3, 3, 3), (2, 66, 4), (67, 9, 5)])
 def test_z_marching_schedule(box):
-    for tx_, ty_, nt in SHAPES:
-        _schedule(*box, tx_, ty_, nt)
+    # any chunk length (planes per block) the launcher may choose
+    for (tx_, ty_, nt), zc in itertools.product(SHAPES, sorted({1, 2, 3, 5, box[2]})):
+        _schedule(*box, tx_, ty_, nt, zc)
