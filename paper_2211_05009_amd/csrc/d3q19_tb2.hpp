@@ -25,11 +25,12 @@ namespace lbm {
 
 // Element reads and writes of a state array.  `at(d, o)` is element d + o,
 // where d is the same for every lane (a population plane and a fixed
-// neighbour offset) and o the lane's site.
+// neighbour offset) and o the lane's site; `elem(e)` is element e.
 template <typename T>
 struct PtrArray {   // any array: 64-bit addresses
   const T *a;
   __device__ __forceinline__ T at(int d, int o) const { return a[d + o]; }
+  __device__ __forceinline__ T elem(int e) const { return a[e]; }
 };
 // Arrays below 2^31 bytes as raw buffers: the lane's byte offset in a VGPR,
 // the uniform one in an SGPR, no per-access 64-bit address arithmetic.  The
@@ -47,6 +48,7 @@ struct BufArray {
     else
       return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(r, o * 8, d * 8, 0));
   }
+  __device__ __forceinline__ T elem(int e) const { return at(0, e); }
   // non-temporal store (cache policy NT)
   __device__ __forceinline__ void put(int d, int o, T v) const {
     if constexpr (sizeof(T) == 4)
@@ -57,31 +59,44 @@ struct BufArray {
   }
 };
 
+// Link i of site (x, y, z) comes from a site of the box (only the nonzero
+// velocity components are tested).
+__device__ __forceinline__ bool from_box(int i, int x, int y, int z, int nx, int ny, int nz) {
+  return (cx19(i) == 0 || (unsigned)(x - cx19(i)) < (unsigned)nx) &&
+         (cy19(i) == 0 || (unsigned)(y - cy19(i)) < (unsigned)ny) &&
+         (cz19(i) == 0 || (unsigned)(z - cz19(i)) < (unsigned)nz);
+}
+
+// The lid's term on a reflected link through the lid (links 8 and 9 of the
+// top row y = ny - 1), as in k_step3.
+template <typename T>
+__device__ __forceinline__ T lid19(int i, T f, int y, int ny, T u6) {
+  if (i == 8) return y == ny - 1 ? f - u6 : f;
+  if (i == 9) return y == ny - 1 ? f + u6 : f;
+  return f;
+}
+
 // The 19 inputs of site (x, y, z), at element o of an array with plane,
 // row and slab strides ps, rs, ss: a link from outside the box reflects,
-// with the lid's term where it crosses the lid, as in k_step3.  Sites whose
-// every link comes from inside the box (all but the box's outer shell) take
-// the unchecked pulls; the values are the same either way.
+// with the lid's term where it crosses the lid, as in k_step3.  A wavefront
+// whose sites all lie off the box's outer shell takes unchecked pulls; any
+// other selects each link's element (the neighbour's, or the site's own
+// opposite population) and loads it, without branches, so the wavefronts of
+// a column at a face do not run two paths.  The values are the same.
 template <typename T, typename A>
 __device__ __forceinline__ void pull19(const A &a, int ps, int rs, int ss, int o, int x, int y,
                                        int z, int nx, int ny, int nz, T u6, T (&f)[19]) {
-  if (x >= 1 && x < nx - 1 && y >= 1 && y < ny - 1 && z >= 1 && z < nz - 1) {
+  if (__all(x >= 1 && x < nx - 1 && y >= 1 && y < ny - 1 && z >= 1 && z < nz - 1)) {
 #pragma unroll
     for (int i = 0; i < 19; ++i) f[i] = a.at(i * ps - cx19(i) - cy19(i) * rs - cz19(i) * ss, o);
     return;
   }
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
-    const int xs = x - cx19(i), ys = y - cy19(i), zs = z - cz19(i);
-    if (xs >= 0 && xs < nx && ys >= 0 && ys < ny && zs >= 0 && zs < nz) {
-      f[i] = a.at(i * ps - cx19(i) - cy19(i) * rs - cz19(i) * ss, o);
-    } else {
-      f[i] = a.at(opp19(i) * ps, o);
-      if (ys >= ny) {
-        if (i == 8) f[i] -= u6;
-        else if (i == 9) f[i] += u6;
-      }
-    }
+    const int e = from_box(i, x, y, z, nx, ny, nz)
+                      ? o + i * ps - cx19(i) - cy19(i) * rs - cz19(i) * ss
+                      : o + opp19(i) * ps;
+    f[i] = lid19<T>(i, a.elem(e), y, ny, u6);
   }
 }
 
@@ -134,23 +149,16 @@ template <typename T, int WX, typename P>
 __device__ __forceinline__ void pull19_planes(const P &pop, int l, int x, int y, int z, int nx,
                                               int ny, int nz, T u6, T (&f)[19]) {
   // a link moving +z comes from the plane below, -z from the plane above
-  if (x >= 1 && x < nx - 1 && y >= 1 && y < ny - 1 && z >= 1 && z < nz - 1) {
+  if (__all(x >= 1 && x < nx - 1 && y >= 1 && y < ny - 1 && z >= 1 && z < nz - 1)) {
 #pragma unroll
     for (int i = 0; i < 19; ++i) f[i] = pop(i, z - cz19(i))[l - cx19(i) - cy19(i) * WX];
     return;
   }
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
-    const int xs = x - cx19(i), ys = y - cy19(i), zs = z - cz19(i);
-    if (xs >= 0 && xs < nx && ys >= 0 && ys < ny && zs >= 0 && zs < nz) {
-      f[i] = pop(i, zs)[l - cx19(i) - cy19(i) * WX];
-    } else {
-      f[i] = pop(opp19(i), z)[l];
-      if (ys >= ny) {
-        if (i == 8) f[i] -= u6;
-        else if (i == 9) f[i] += u6;
-      }
-    }
+    const T *e = from_box(i, x, y, z, nx, ny, nz) ? pop(i, z - cz19(i)) + l - cx19(i) - cy19(i) * WX
+                                                  : pop(opp19(i), z) + l;
+    f[i] = lid19<T>(i, *e, y, ny, u6);
   }
 }
 
