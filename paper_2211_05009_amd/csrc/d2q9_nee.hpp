@@ -68,22 +68,43 @@ __device__ __forceinline__ void equilibrium9(T base, T rho, T ux, T uy, T (&e)[9
   e[8] = bd + sm - am;
 }
 
-// Wall node from its reference node's streamed populations f (in place):
-// f <- f^eq(rho_r, (uw, 0)) + (1 - omega) (f - f^eq(rho_r, u_r)).
+// Node update from the populations streamed to it (a fluid node) or to its
+// reference node (a wall node), in place.  A fluid node takes the BGK
+// collision.  A wall node takes f^eq(rho_r, (uw, 0)) + (1 - omega)(f -
+// f^eq(rho_r, u_r)) with rho_r, u_r the moments of f: since the BGK update
+// of f is f^eq(rho_r, u_r) + (1 - omega)(f - f^eq(rho_r, u_r)), that is the
+// BGK update plus f^eq(rho_r, (uw, 0)) - f^eq(rho_r, u_r).  So a wavefront
+// holding both kinds runs the collision once, and its wall lanes add only
+// the moments before it and that difference after it.
 template <typename T, bool SHIFT>
-__device__ __forceinline__ void nee_wall(T (&f)[9], T omega, T uw) {
-  const T s = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
-  const T jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
-  const T jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
-  const T rho = SHIFT ? T(1) + s : s;
-  const T rinv = recip<T>(rho);
-  const T base = SHIFT ? s : rho;
-  T er[9], ew[9];
-  equilibrium9<T>(base, rho, jx * rinv, jy * rinv, er);
-  equilibrium9<T>(base, rho, uw, T(0), ew);
-  const T keep = T(1) - omega;
-#pragma unroll
-  for (int i = 0; i < 9; ++i) f[i] = ew[i] + keep * (f[i] - er[i]);
+__device__ __forceinline__ void nee_collide(T (&f)[9], T omega, bool wall, T uw) {
+  T rho = T(1), ux = T(0), uy = T(0);
+  if (wall) {
+    const T s = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+    const T jx = (f[1] - f[3]) + (f[5] - f[6]) + (f[8] - f[7]);
+    const T jy = (f[2] - f[4]) + (f[5] + f[6]) - (f[7] + f[8]);
+    rho = SHIFT ? T(1) + s : s;
+    const T rinv = recip<T>(rho);
+    ux = jx * rinv;
+    uy = jy * rinv;
+  }
+  bgk_collide<T, SHIFT>(f, omega);
+  if (wall) {
+    // w_i rho [3 c.(uw - u) + 4.5 ((c.uw)^2 - (c.u)^2) - 1.5 (uw^2 - u^2)],
+    // a link and its opposite sharing the even part
+    const T du = T(1.5) * (uw * uw - (ux * ux + uy * uy));
+    const T ra = T(LBM_WA) * rho, rd = T(LBM_WD) * rho;
+    f[0] -= (T(LBM_W0) * rho) * du;
+    auto pair = [&](int a, int b, T r, T cw, T cu) {
+      const T odd = T(3) * (cw - cu), even = T(4.5) * (cw * cw - cu * cu) - du;
+      f[a] += r * (even + odd);
+      f[b] += r * (even - odd);
+    };
+    pair(1, 3, ra, uw, ux);            // (1, 0), (-1, 0)
+    pair(2, 4, ra, T(0), uy);          // (0, 1), (0, -1)
+    pair(5, 7, rd, uw, ux + uy);       // (1, 1), (-1, -1)
+    pair(6, 8, rd, -uw, uy - ux);      // (-1, 1), (1, -1)
+  }
 }
 
 // One step over a tile of 64 x (BY * RY) nodes (block 64 x BY threads,
@@ -103,10 +124,7 @@ __global__ __launch_bounds__(64 * BY) void k_step_nee(StepParams<T> p) {
     const int yr = min(max(y, 1), p.ny - 2);
     T f[9];
     pull_fluid<T>(p.src, p.plane, p.pitch, yr * p.pitch + xr, f);
-    if (xr == x && yr == y)
-      bgk_collide<T, SHIFT>(f, p.omega);
-    else
-      nee_wall<T, SHIFT>(f, p.omega, y == p.ny - 1 ? p.ulid : T(0));
+    nee_collide<T, SHIFT>(f, p.omega, xr != x || yr != y, y == p.ny - 1 ? p.ulid : T(0));
     const int o = y * p.pitch + x;
 #pragma unroll
     for (int i = 0; i < 9; ++i) p.dst[i * p.plane + o] = f[i];

@@ -6,7 +6,7 @@
 // steps run between two LDS buffers (one barrier per step) and the last
 // one stores the tile's nodes from registers.  Per node the arithmetic is
 // k_step_nee's, in the same order (pull at the node's reference node, then
-// bgk_collide or nee_wall), so any number of steps per launch gives the
+// nee_collide), so any number of steps per launch gives the
 // same bits as one-step launches.  Two forms, each the faster one measured
 // for its precision:
 //   FP32 (nee_tb_pull): step 1 pulls its nodes' inputs straight from the
@@ -44,10 +44,7 @@ __device__ __forceinline__ void nee_tb_pull(const StepParams<T> &p, T *lds) {
   auto update = [&](const T *src, int P, int pitch, int x0, int y0, int gx, int gy, T(&f)[9]) {
     const int xr = min(max(gx, 1), nx - 2), yr = min(max(gy, 1), ny - 2);
     pull_fluid<T>(src, P, pitch, (yr - y0) * pitch + (xr - x0), f);
-    if (xr == gx && yr == gy)
-      bgk_collide<T, SHIFT>(f, p.omega);
-    else
-      nee_wall<T, SHIFT>(f, p.omega, gy == ny - 1 ? p.ulid : T(0));
+    nee_collide<T, SHIFT>(f, p.omega, xr != gx || yr != gy, gy == ny - 1 ? p.ulid : T(0));
   };
   {  // step 1 from global memory into LDS buffer 0
     constexpr int W = RW - 2, N = W * (RH - 2);
@@ -128,10 +125,7 @@ __device__ __forceinline__ void nee_tb_load(const StepParams<T> &p, T *lds) {
       const int xr = min(max(gx, 1), nx - 2), yr = min(max(gy, 1), ny - 2);
       T f[9];
       pull_fluid<T>(in, RS, RW, (yr - Y0) * RW + (xr - X0), f);
-      if (xr == gx && yr == gy)
-        bgk_collide<T, SHIFT>(f, p.omega);
-      else
-        nee_wall<T, SHIFT>(f, p.omega, gy == ny - 1 ? p.ulid : T(0));
+      nee_collide<T, SHIFT>(f, p.omega, xr != gx || yr != gy, gy == ny - 1 ? p.ulid : T(0));
       if (s == K) {
         const int o = gy * p.pitch + gx;
 #pragma unroll
