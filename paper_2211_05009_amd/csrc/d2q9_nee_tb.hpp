@@ -6,24 +6,17 @@
 // steps run between two LDS buffers (one barrier per step) and the last
 // one stores the tile's nodes from registers.  Per node the arithmetic is
 // k_step_nee's, in the same order (pull at the node's reference node, then
-// nee_collide), so any number of steps per launch gives the
-// same bits as one-step launches.  Two forms, each the faster one measured
-// for its precision:
-//   FP32 (nee_tb_pull): step 1 pulls its nodes' inputs straight from the
-//     state f*(t) in global memory; step s updates the region's nodes s or
-//     more sites from its border, [s, RW - s) x [s, RH - s) in region
-//     coordinates (a constant width: the step loop is unrolled), skipping
-//     those outside the lattice; the last step takes the tile alone.
-//   FP64 (nee_tb_load): the block first loads the region's nodes inside
-//     the lattice into LDS; windows are clipped to the lattice: sides that
-//     face other tiles lose one node per step, sides on the lattice's edge
-//     none.
-// Either way a fluid node reads its eight neighbours at the previous step
-// and a wall node its reference node's, one node inward; every such node is
-// inside the lattice and inside the previous step's window.  The extra node
-// below and left is for a tile that starts at the last column (or row): its
-// right (top) wall node reads two nodes to its left (below), which the
-// previous step's window then still holds.
+// nee_collide), so any number of steps per launch gives the same bits as
+// one-step launches.  Step 1 pulls its nodes' inputs straight from the state
+// f*(t) in global memory; step s updates the region's nodes s or more sites
+// from its border, [s, RW - s) x [s, RH - s) in region coordinates (a
+// constant width: the step loop is unrolled), skipping those outside the
+// lattice; the last step takes the tile alone.  A fluid node reads its eight
+// neighbours at the previous step and a wall node its reference node's, one
+// node inward; every such node is inside the lattice and inside the previous
+// step's window.  The extra node below and left is for a tile that starts at
+// the last column (or row): its right (top) wall node reads two nodes to its
+// left (below), which the previous step's window then still holds.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -89,67 +82,12 @@ __device__ __forceinline__ void nee_tb_pull(const StepParams<T> &p, T *lds) {
 }
 
 template <typename T, bool SHIFT, int K, int TX, int TY, int NT>
-__device__ __forceinline__ void nee_tb_load(const StepParams<T> &p, T *lds) {
-  constexpr int RW = TX + 2 * K + 1, RH = TY + 2 * K + 1, RS = RW * RH;
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int tx = tile % p.tiles_x, ty = tile / p.tiles_x;
-  const int nx = p.nx, ny = p.ny;
-  // region origin (node coordinates of LDS site (0, 0); may be negative)
-  // and the part of the region inside the lattice
-  const int X0 = tx * TX - K - 1, Y0 = ty * TY - K - 1;
-  const int cx0 = max(X0, 0), cx1 = min(X0 + RW, nx);
-  const int cy0 = max(Y0, 0), cy1 = min(Y0 + RH, ny);
-  {  // load f*(t) on the region
-    const int cw = cx1 - cx0, n = cw * (cy1 - cy0);
-    for (int q = threadIdx.x; q < n; q += NT) {
-      const int gy = cy0 + q / cw, gx = cx0 + q % cw;
-      const int o = gy * p.pitch + gx, l = (gy - Y0) * RW + (gx - X0);
-#pragma unroll
-      for (int i = 0; i < 9; ++i) lds[i * RS + l] = p.src[(size_t)i * p.plane + o];
-    }
-  }
-  __syncthreads();
-  const bool el = cx0 == 0, er = cx1 == nx, eb = cy0 == 0, et = cy1 == ny;
-#pragma unroll 1
-  for (int s = 1; s <= K; ++s) {
-    const T *in = lds + ((s - 1) & 1) * 9 * RS;
-    T *out = lds + (s & 1) * 9 * RS;
-    const int wx0 = el ? 0 : cx0 + s, wx1 = er ? nx : cx1 - s;
-    const int wy0 = eb ? 0 : cy0 + s, wy1 = et ? ny : cy1 - s;
-    // the last step keeps only the tile's own nodes
-    const int sx0 = s == K ? max(wx0, tx * TX) : wx0, sx1 = s == K ? min(wx1, tx * TX + TX) : wx1;
-    const int sy0 = s == K ? max(wy0, ty * TY) : wy0, sy1 = s == K ? min(wy1, ty * TY + TY) : wy1;
-    const int ww = sx1 - sx0, n = ww * (sy1 - sy0);
-    for (int q = threadIdx.x; q < n; q += NT) {
-      const int gy = sy0 + q / ww, gx = sx0 + q % ww;
-      const int xr = min(max(gx, 1), nx - 2), yr = min(max(gy, 1), ny - 2);
-      T f[9];
-      pull_fluid<T>(in, RS, RW, (yr - Y0) * RW + (xr - X0), f);
-      nee_collide<T, SHIFT>(f, p.omega, xr != gx || yr != gy, gy == ny - 1 ? p.ulid : T(0));
-      if (s == K) {
-        const int o = gy * p.pitch + gx;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) p.dst[(size_t)i * p.plane + o] = f[i];
-      } else {
-        const int l = (gy - Y0) * RW + (gx - X0);
-#pragma unroll
-        for (int i = 0; i < 9; ++i) out[i * RS + l] = f[i];
-      }
-    }
-    if (s < K) __syncthreads();
-  }
-}
-
-template <typename T, bool SHIFT, int K, int TX, int TY, int NT>
 __global__ __launch_bounds__(NT) void k_step_nee_tb(StepParams<T> p) {
   constexpr int RS = (TX + 2 * K + 1) * (TY + 2 * K + 1);
   static_assert(K >= 2, "one-step launches take k_step_nee");
   static_assert(2 * 9 * RS * sizeof(T) <= 160 * 1024, "two region buffers fit the LDS");
   __shared__ T lds[2 * 9 * RS];
-  if constexpr (sizeof(T) == 4)
-    nee_tb_pull<T, SHIFT, K, TX, TY, NT>(p, lds);
-  else
-    nee_tb_load<T, SHIFT, K, TX, TY, NT>(p, lds);
+  nee_tb_pull<T, SHIFT, K, TX, TY, NT>(p, lds);
 }
 
 }  // namespace lbm
