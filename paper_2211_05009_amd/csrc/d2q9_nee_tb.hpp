@@ -67,9 +67,15 @@ __device__ __forceinline__ void nee_tb_pull(const StepParams<T> &p, T *lds) {
       update(in, RS, RW, X0, Y0, gx, gy, f);
       if (s == K) {
         const int o = gy * p.pitch + gx;
+        // not read again in this launch: FP32 with non-temporal stores (+3 %
+        // at 501 x 501), FP64 with plain ones (+2.7 % at 501 x 501)
 #pragma unroll
-        for (int i = 0; i < 9; ++i)   // not read again in this launch
-          __builtin_nontemporal_store(f[i], p.dst + (size_t)i * p.plane + o);
+        for (int i = 0; i < 9; ++i) {
+          if constexpr (sizeof(T) == 4)
+            __builtin_nontemporal_store(f[i], p.dst + (size_t)i * p.plane + o);
+          else
+            p.dst[(size_t)i * p.plane + o] = f[i];
+        }
       } else {
 #pragma unroll
         for (int i = 0; i < 9; ++i) out[i * RS + ly * RW + lx] = f[i];
