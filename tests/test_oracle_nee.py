@@ -9,7 +9,7 @@ import pytest
 
 from cavity_inputs import random_shift
 from oracle import nee
-from oracle.d2q9 import W, equilibrium, macroscopic
+from oracle.d2q9 import W, collide, equilibrium, macroscopic
 from oracle.naive import naive_steps_nee
 
 U = 0.1
@@ -122,7 +122,9 @@ def test_mirror_symmetry():
 def test_post_collision_of_a_wall_node():
     """The stored (post-collision) value of a wall node is
     f^eq(rho_f, u_w) + (1 - 1/tau)(f_f - f^eq_f): the form a fused kernel
-    computes from the streamed reference node alone."""
+    computes from the streamed reference node alone; and that equals the
+    BGK update of f_f plus f^eq(rho_f, u_w) - f^eq_f, the form in which the
+    library runs wall nodes through the fluid nodes' collision."""
     nx, ny = 9, 8
     c = nee.CavityNEE(nx, ny, re=120.0, u_lid=U)
     c.set_state(c.f + random_shift(nx, ny, 5))
@@ -136,6 +138,8 @@ def test_post_collision_of_a_wall_node():
         feq_w = equilibrium(rho[yr, xr], U if y == ny - 1 else 0.0, 0.0)
         want = feq_w + (1 - 1 / c.tau) * (ff - feq_f)
         assert np.allclose(fs[:, y, x], want, rtol=0, atol=5e-16)
+        via_bgk = collide(ff, c.tau) + (feq_w - feq_f)
+        assert np.allclose(fs[:, y, x], via_bgk, rtol=0, atol=5e-16)
 
 
 # -- mutations -------------------------------------------------------------
